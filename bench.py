@@ -1,0 +1,225 @@
+"""RACE SymmSpMV benchmark on one MI355X.
+
+One step = one product y = A x of the whole RACE path (every phase launch)
+on the 3D 27-point stencil with a 128^3 grid (N = 2,097,152, 28,920,060
+stored upper entries, float64), inputs resident in HBM.  Vectors rotate
+through two ring buffers larger than the last-level caches (the paper's
+measurement protocol: two rings, one vector pair per product, mean time).
+
+Also timed the same way on the same GPU: full-matrix CRS SpMV (the
+yardstick) and SymmSpMV with global float64 atomics.  The CPU baseline is
+the plain serial oracle on one host core over a bounded sample.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SymmSpMV GFLOP/s + % peak HBM GB/s vs CRS SpMV, same GPU, FP64 rel err ≤1e-12"
+PEAK_HBM_GBS = 8000.0
+RING_BYTES = 576 << 20  # each ring >= 2 x (256 MB last-level cache + L2s)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import matgen
+    if name == "3d27pt_128":
+        return matgen.config_3d_128(), "3D 27-point stencil 128^3, lexicographic, FP64, seed 2"
+    if name == "2d5pt_100":
+        return matgen.config_2d_small(), "2D 5-point Laplacian 100x100, FP64, seed 1"
+    if name == "banded_4m":
+        return matgen.config_banded_4m(), "irregular banded 2^22 rows, bandwidth 2^16, FP64, seed 3"
+    if name == "3d27pt_160":
+        return matgen.config_3d_160(), "3D 27-point stencil 160^3, FP64, seed 2000"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_ring(fn, xs, ys, steps, warmup, torch):
+    nr = len(xs)
+    for i in range(warmup):
+        fn(xs[i % nr], ys[i % nr])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        fn(xs[i % nr], ys[(i + 1) % nr])
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(m, budget_s):
+    import numpy as np
+
+    import matgen
+    from oracle import build as ob
+    from oracle import symmspmv as O
+    ob.build(force=False)
+    x = matgen.rhs(m.n, 99)
+    y = np.empty(m.n)
+    O.symm_spmv_c(m.n, m.row_ptr, m.col, m.val, x, y)  # warm
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        O.symm_spmv_c(m.n, m.row_ptr, m.col, m.val, x, y)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return dt, reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="3d27pt_128")
+    ap.add_argument("--n-workers", type=int, default=256)
+    ap.add_argument("--max-stages", type=int, default=4)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--window", type=int, default=4096)
+    ap.add_argument("--value-type", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--sweep", default="", help="n_workers:block list, e.g. 256:256,512:512 (extra lines on stderr)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
+              "not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1907_06487_amd as R
+    from oracle import symmspmv as O
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m, desc = workload(args.workload)
+    log(f"workload {args.workload}: n={m.n} nnz_upper={m.nnz}")
+    t0 = time.perf_counter()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
+                   block_threads=args.block, window_max=args.window, value_type=args.value_type)
+    t_build = time.perf_counter() - t0
+    st = s.stats()
+    log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
+        "n_levels0", "depth", "n_leaves", "n_phases_used", "n_units", "max_window", "eta", "halo_total",
+        "sell_elems", "bytes_min", "bytes_kernel")}))
+
+    nring = max(2, -(-RING_BYTES // (8 * m.n)))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(12345)
+    xs = [torch.rand(m.n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1 for _ in range(nring)]
+    ys = [torch.empty(m.n, dtype=torch.float64, device=dev) for _ in range(nring)]
+
+    # correctness of the timed configuration against the oracle (input order)
+    x0 = xs[0].cpu().numpy()
+    perm = s.perm()
+    x_orig = np.empty(m.n)
+    x_orig[perm] = x0
+    s.spmv(xs[0], ys[0])
+    torch.cuda.synchronize()
+    y_perm = ys[0].cpu().numpy()
+    y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x_orig)
+    err_norm, err_comp = O.errors(y_perm, y_ref[perm], O.abs_product(m.n, m.row_ptr, m.col, m.val, x_orig)[perm])
+    log(f"error vs oracle: norm {err_norm:.3e} comp {err_comp:.3e}")
+
+    ms = time_ring(lambda x, y: s.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
+    flops = 2 * st["nnz_full"]
+    gflops = flops / (ms * 1e-3) / 1e9
+    achieved = st["bytes_min"] / (ms * 1e-3) / 1e9
+    launches = st["n_phases_used"]
+    log(f"RACE: {ms * 1e3:.2f} us/product, {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s algorithmic "
+        f"({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes {st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
+
+    for item in filter(None, args.sweep.split(",")):
+        nt, blk = (int(v) for v in item.split(":"))
+        s2 = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=nt, max_stages=args.max_stages, block_threads=blk,
+                        window_max=args.window, value_type=args.value_type)
+        st2 = s2.stats()
+        ms2 = time_ring(lambda x, y: s2.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
+        log(f"sweep n_workers={nt} block={blk}: {ms2 * 1e3:.2f} us, "
+            f"{st2['bytes_min'] / (ms2 * 1e-3) / 1e9 / PEAK_HBM_GBS * 100:.1f}% peak, phases={st2['n_phases_used']} "
+            f"leaves={st2['n_leaves']} units={st2['n_units']} kernel bytes={st2['bytes_kernel']}")
+        s2.close()
+
+    baselines = {}
+    if not args.no_baselines:
+        rp, c, v = O.expand_full(m.n, m.row_ptr, m.col, m.val)
+        best = None
+        for order in ("input", "race"):
+            if order == "race":
+                import scipy.sparse as sp
+                a = sp.csr_matrix((v, c, rp), shape=(m.n, m.n))[perm][:, perm].tocsr()
+                a.sort_indices()
+                brp, bc, bv = a.indptr.astype(np.int32), a.indices.astype(np.int32), a.data
+            else:
+                brp, bc, bv = rp, c, v
+            h = R.race_csr_create(m.n, brp, bc, bv, 0)
+            t = time_ring(lambda x, y: R.race_csr_spmv(h, x, y), xs, ys, args.steps, args.warmup, torch)
+            R.race_csr_destroy(h)
+            log(f"CRS SpMV ({order} order): {t * 1e3:.2f} us")
+            if best is None or t < best[0]:
+                best = (t, order)
+        bytes_spmv = 12 * int(rp[-1]) + 20 * m.n + 4
+        baselines["crs_spmv"] = {"us": best[0] * 1e3, "order": best[1], "gflops": flops / (best[0] * 1e-3) / 1e9,
+                                 "algorithmic_GBs": bytes_spmv / (best[0] * 1e-3) / 1e9}
+        h = R.race_atomic_create(m.n, m.row_ptr, m.col, m.val)
+        t = time_ring(lambda x, y: R.race_symm_spmv_atomic(h, x, y), xs, ys, args.steps, args.warmup, torch)
+        R.race_csr_destroy(h)
+        log(f"atomic SymmSpMV (input order): {t * 1e3:.2f} us")
+        baselines["atomic_symmspmv"] = {"us": t * 1e3, "gflops": flops / (t * 1e-3) / 1e9}
+        baselines["race_speedup_vs_crs"] = best[0] / ms
+
+    cpu = None
+    if not args.no_cpu:
+        dt, reps = cpu_baseline(m, args.cpu_seconds)
+        cpu = {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full products of the same matrix with the serial C oracle (-O2), "
+                         f"{dt * 1e3:.1f} ms each"}
+        log(f"CPU oracle: {dt * 1e3:.1f} ms/product ({cpu['value']:.3f} GFLOP/s)")
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    if os.path.exists(tpath):
+        try:
+            tr = json.load(open(tpath))
+            if tr.get("bytes_kernel") == st["bytes_kernel"] and tr.get("n_workers") == args.n_workers:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": METRIC, "value": round(gflops, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.value_type == "f64" else "f32-values/f64-accumulate", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_upper": m.nnz,
+                   "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
+                   "window_max": args.window, "phases": launches, "leaves": st["n_leaves"], "eta": st["eta"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "launches_per_step": launches,
+                     "bytes_per_step": st["bytes_min"], "kernel_format_bytes_per_step": st["bytes_kernel"]},
+        "error": {"norm": err_norm, "componentwise": err_comp},
+        "baselines": baselines,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * race.h -- C ABI of the MI355X RACE SymmSpMV library (librace.so).
+ *
+ * Problem (Alappat et al., "A Recursive Algebraic Coloring Technique for
+ * Hardware-Efficient Symmetric Sparse Matrix-Vector Multiplication"):
+ * y = A x for a real symmetric sparse A stored as its upper triangle
+ * (diagonal included) in CRS (Section 3.2, Algorithm "SymmSpMV").  Every
+ * stored off-diagonal A[r,c] both gathers x[c] into y[r] and scatters
+ * A[r,c] x[r] into y[c], so rows whose touch sets meet must not run at the
+ * same time.  RACE (Section 4) builds a recursive distance-2 coloring of
+ * level groups of BFS levels; same-colored groups run concurrently.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success, a negative RACE_E* code on failure; the message
+ *    of the last failure on the calling thread is race_last_error().  No C++
+ *    exception crosses this interface.
+ *  - "host" pointers are ordinary CPU memory, borrowed for the duration of
+ *    the call.  "device" pointers are HIP device memory on the device that is
+ *    current on the calling thread; the caller owns them.
+ *  - stream arguments are hipStream_t values passed as void* (NULL = the
+ *    default stream).  Device work is enqueued on that stream and the call
+ *    returns without synchronising.
+ *  - Index arrays are int32; the number of stored entries must be < 2^31.
+ *  - Vectors passed to the products are in the schedule's PERMUTED order
+ *    (race_permute converts); the permutation is the RACE level ordering
+ *    (Sections 4.1 and 4.4.2).
+ */
+#ifndef RACE_H
+#define RACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RACE_OK 0
+#define RACE_EINVAL (-1)       /* malformed input: bad CRS, bad sizes, NULL pointers */
+#define RACE_ENOMEM (-2)       /* host or device allocation failed */
+#define RACE_EHIP (-3)         /* a HIP runtime call failed (message holds hipGetErrorString) */
+#define RACE_EUNSUPPORTED (-4) /* valid input this build cannot run (dist_k != 2, a row whose window does not fit, k > 16) */
+#define RACE_ESTATE (-5)       /* wrong object state (e.g. product before race_schedule_upload) */
+#define RACE_EINTERNAL (-6)    /* an internal consistency check failed (e.g. two concurrent units touch one index) */
+
+typedef struct race_schedule* race_schedule_t;
+typedef struct race_csr* race_csr_t;
+typedef struct race_batch* race_batch_t;
+
+/* Parameters of the schedule (Section 5: {eps_s}, N_t; Section 4.3: rows or
+ * nonzeros as load; Section 4.2: distance k). */
+typedef struct {
+  int32_t dist_k;        /* distance of the coloring; SymmSpMV needs 2 (the only value accepted) */
+  int32_t n_workers;     /* N_t: concurrent workers the tree is built for (>= 1) */
+  int32_t max_stages;    /* recursion stages including stage 0 (1..16) */
+  int32_t balance_by;    /* 0: nonzeros of the full row, 1: rows, 2: learned cost model (cost_model) */
+  int32_t global_lb;     /* 1: run Algorithm "Load Balancing" over all children after the pair split */
+  int32_t value_type;    /* 0: float64 matrix values, 1: float32 values (promoted; FP64 accumulation) */
+  int32_t window_max;    /* max LDS window entries (rows + halo) of one unit; 0 = 4096 */
+  int32_t block_threads; /* workgroup size of the RACE kernel: 64, 128, 256, 512 or 1024; 0 = 256 */
+  double eps[8];         /* eps_s per stage (stages past 7 use eps[7]); each in [0, 1) */
+  const float* cost_model; /* host: weights of the cost-model network (balance_by == 2), else NULL */
+  int32_t cost_model_len;  /* number of floats in cost_model */
+  int32_t reserved;
+} race_params;
+
+/* Summary of a built schedule (Section 5 terms where they exist). */
+typedef struct {
+  int32_t n;                 /* rows */
+  int32_t n_levels0;         /* stage-0 BFS levels N_l */
+  int32_t depth;             /* deepest stage of any leaf (-1: the root is a leaf) */
+  int32_t n_nodes;           /* tree nodes including the root */
+  int32_t n_leaves;
+  int32_t n_phases;          /* 2^(depth+1) */
+  int32_t n_phases_used;     /* phases holding at least one leaf */
+  int32_t n_units;           /* LDS-window units (a leaf is split into units processed in order) */
+  int32_t max_window;        /* largest unit window (rows + halo) */
+  int32_t n_chunks;          /* 64-row chunks of the kernel's sliced layout */
+  int32_t n_eff_root;        /* effective row count of the root */
+  int32_t n_workers;
+  double eta;                /* parallel efficiency N / (N_eff(root) * N_t) */
+  int64_t nnz_upper;         /* stored upper entries, diagonal included */
+  int64_t nnz_full;          /* entries of the full symmetric matrix */
+  int64_t n_diag;            /* rows with a stored diagonal */
+  int64_t sell_elems;        /* off-diagonal slots of the sliced layout incl. padding */
+  int64_t halo_total;        /* sum over units of halo entries */
+  int64_t rows_rmw;          /* own rows that an earlier unit already wrote */
+  int64_t halo_rmw;          /* halo entries that an earlier unit already wrote */
+  int64_t bytes_min;         /* 12 nnz_u + 20 N + 4: minimum bytes of one product in upper CRS with FP64 values */
+  int64_t bytes_kernel;      /* bytes one product of the RACE kernel moves by its own format, counted once each */
+  int64_t device_bytes;      /* device memory held by the schedule */
+} race_stats;
+
+/* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
+ * nonzeros, no global pass, float64 values, window 4096, 256 threads,
+ * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice). */
+int race_params_default(race_params* p);
+
+/* Build the RACE schedule and the kernel's data layout on the host.
+ * n: rows; row_ptr (n+1), col (nnz), val (nnz): host, the upper triangle in
+ * CRS, columns strictly ascending within a row and >= the row (the diagonal,
+ * when stored, is the row's first entry); val may be NULL (pattern only: the
+ * schedule can be inspected but not uploaded).  Disconnected matrices are
+ * accepted (islands).  *out receives a new schedule owned by the caller
+ * (race_schedule_destroy).  No device is needed.
+ * Errors: RACE_EINVAL for malformed CRS or parameters, RACE_EUNSUPPORTED when
+ * dist_k != 2 or one row alone exceeds the window, RACE_EINTERNAL if the
+ * built-in independence check finds two concurrent units touching one index. */
+int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                        const race_params* p, race_schedule_t* out);
+
+/* Copy the permuted matrix and schedule to the current device (hipMalloc +
+ * hipMemcpy).  Needed once before any product; repeated calls are no-ops. */
+int race_schedule_upload(race_schedule_t s);
+
+void race_schedule_destroy(race_schedule_t s);
+
+int race_schedule_stats(race_schedule_t s, race_stats* out);
+
+/* new2old (host, n): row i of the permuted matrix is row new2old[i] of the input. */
+int race_schedule_perm(race_schedule_t s, int32_t* new2old);
+
+/* The level-group tree in preorder (Section 4.4.3 tree; node 0 = the root,
+ * stage -1).  Call with all arrays NULL to get *n_nodes; then each non-NULL
+ * host array of n_nodes entries is filled: stage, color (0 first, 1 second),
+ * parent (-1 for the root), row range [lo, hi) in permuted order, workers b. */
+int race_schedule_tree(race_schedule_t s, int32_t* n_nodes, int32_t* stage, int32_t* color, int32_t* parent,
+                       int32_t* lo, int32_t* hi, int32_t* workers);
+
+/* Leaves in execution order (sorted by phase, then first row): node id and
+ * phase; *n_leaves as above. */
+int race_schedule_leaves(race_schedule_t s, int32_t* n_leaves, int32_t* node, int32_t* phase);
+
+/* Units in execution order: leaf index (into the leaves list), own rows
+ * [row_lo, row_hi), halo count; and the concatenated halo lists (global
+ * indices in permuted order, ascending per unit) with their first-touch flags
+ * (1: this unit is the first to write that y entry), and the first-touch flag
+ * of every row.  Sizes via NULL arrays: *n_units, *n_halo.  Host arrays. */
+int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, int32_t* unit_leaf, int32_t* row_lo,
+                        int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_first, uint8_t* row_first);
+
+/* y = A x (Algorithm "SymmSpMV"): x, y device float64 arrays of n in
+ * permuted order, y overwritten (no clearing needed), x and y must not
+ * overlap.  One launch per non-empty phase on `stream`, in phase order. */
+int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream);
+
+/* Y = A X for k right-hand sides, X and Y device float64 row-major n x k
+ * (k in 1..16), permuted order, Y overwritten. */
+int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream);
+
+/* Reorder device float64 row-major n x k arrays between input order and the
+ * permuted order: to_permuted != 0: out[i] = in[new2old[i]]; else
+ * out[new2old[i]] = in[i]. */
+int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, int32_t to_permuted, void* stream);
+
+/* ---- same-GPU baselines (not RACE; the yardsticks of Section 6) ---- */
+
+/* Full-matrix CRS SpMV (Algorithm "SpMV"): takes the FULL symmetric matrix in
+ * CRS (host arrays, copied to the current device).  lanes_per_row 0 = choose. */
+int race_csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                    int32_t lanes_per_row, race_csr_t* out);
+/* b = A x, device float64 arrays of n. */
+int race_csr_spmv(race_csr_t h, const double* x, double* y, void* stream);
+
+/* SymmSpMV with global float64 atomics: takes the UPPER triangle (host,
+ * copied to the device); y is cleared on the stream, then every scatter and
+ * every row total is an atomic add. */
+int race_atomic_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, race_csr_t* out);
+int race_symm_spmv_atomic(race_csr_t h, const double* x, double* y, void* stream);
+void race_csr_destroy(race_csr_t h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* race_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RACE_H */

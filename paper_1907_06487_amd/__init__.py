@@ -1,0 +1,85 @@
+"""RACE-scheduled symmetric SpMV for AMD MI355X (gfx950).
+
+The work happens in librace.so (C ABI, include/race.h): the host builds the
+recursive distance-2 coloring of the matrix graph (Section 4 of Alappat et
+al.) and the kernels' data layout; gfx950 kernels run the product one
+phase at a time.  This package only marshals arguments (``_lib``) and adds
+a small owning wrapper (``Schedule``).  PyTorch supplies device memory and
+streams.
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import (RaceError, race_atomic_create, race_build_schedule, race_csr_create, race_csr_destroy,
+                   race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_destroy,
+                   race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
+                   race_schedule_units, race_schedule_upload, race_symm_spmm, race_symm_spmv,
+                   race_symm_spmv_atomic)
+
+BALANCE = {"nnz": 0, "rows": 1}
+
+
+def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=4096,
+                block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5)):
+    p = race_params_default()
+    p.n_workers = int(n_workers)
+    p.max_stages = int(max_stages)
+    p.balance_by = BALANCE[balance]
+    p.global_lb = int(bool(global_lb))
+    p.value_type = {"f64": 0, "f32": 1}[value_type]
+    p.window_max = int(window_max)
+    p.block_threads = int(block_threads)
+    eps = list(eps) + [eps[-1]] * (8 - len(eps))
+    for i in range(8):
+        p.eps[i] = float(eps[i])
+    return p
+
+
+class Schedule:
+    """Owning wrapper around a race_schedule_t."""
+
+    def __init__(self, n, row_ptr, col, val, upload=True, **params):
+        self.n = int(n)
+        self.params = make_params(**params)
+        self.handle = race_build_schedule(self.n, row_ptr, col, val, self.params)
+        if upload:
+            race_schedule_upload(self.handle)
+
+    def upload(self):
+        race_schedule_upload(self.handle)
+
+    def stats(self):
+        return race_schedule_stats(self.handle)
+
+    def perm(self):
+        return race_schedule_perm(self.handle, self.n)
+
+    def tree(self):
+        return race_schedule_tree(self.handle)
+
+    def leaves(self):
+        return race_schedule_leaves(self.handle)
+
+    def units(self):
+        return race_schedule_units(self.handle, self.n)
+
+    def spmv(self, x, y, stream=None):
+        race_symm_spmv(self.handle, x, y, stream)
+
+    def spmm(self, X, Y, stream=None):
+        race_symm_spmm(self.handle, X.shape[1] if X.dim() == 2 else 1, X, Y, stream)
+
+    def permute(self, inp, out, to_permuted=True, stream=None):
+        k = inp.shape[1] if inp.dim() == 2 else 1
+        race_permute(self.handle, k, inp, out, to_permuted, stream)
+
+    def close(self):
+        if self.handle is not None:
+            race_schedule_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,264 @@
+"""ctypes binding of librace.so (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name declared
+in include/race.h.  Device arrays are passed as torch CUDA tensors (their
+data pointers), streams as torch streams or raw hipStream_t integers.  The
+library must have been built (paper_1907_06487_amd/build.py); importing it
+fails loudly otherwise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librace.so")
+
+RACE_OK = 0
+ERRORS = {-1: "RACE_EINVAL", -2: "RACE_ENOMEM", -3: "RACE_EHIP", -4: "RACE_EUNSUPPORTED", -5: "RACE_ESTATE",
+          -6: "RACE_EINTERNAL"}
+
+# every symbol the header declares
+EXPORTS = [
+    "race_params_default", "race_build_schedule", "race_schedule_upload", "race_schedule_destroy",
+    "race_schedule_stats", "race_schedule_perm", "race_schedule_tree", "race_schedule_leaves",
+    "race_schedule_units", "race_symm_spmv", "race_symm_spmm", "race_permute", "race_csr_create",
+    "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
+]
+
+
+class RaceError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class race_params(ctypes.Structure):
+    _fields_ = [
+        ("dist_k", ctypes.c_int32), ("n_workers", ctypes.c_int32), ("max_stages", ctypes.c_int32),
+        ("balance_by", ctypes.c_int32), ("global_lb", ctypes.c_int32), ("value_type", ctypes.c_int32),
+        ("window_max", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("eps", ctypes.c_double * 8),
+        ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class race_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_levels0", ctypes.c_int32), ("depth", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+        ("n_leaves", ctypes.c_int32), ("n_phases", ctypes.c_int32), ("n_phases_used", ctypes.c_int32),
+        ("n_units", ctypes.c_int32), ("max_window", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+        ("n_eff_root", ctypes.c_int32), ("n_workers", ctypes.c_int32), ("eta", ctypes.c_double),
+        ("nnz_upper", ctypes.c_int64), ("nnz_full", ctypes.c_int64), ("n_diag", ctypes.c_int64),
+        ("sell_elems", ctypes.c_int64), ("halo_total", ctypes.c_int64), ("rows_rmw", ctypes.c_int64),
+        ("halo_rmw", ctypes.c_int64), ("bytes_min", ctypes.c_int64), ("bytes_kernel", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_U8P = ctypes.POINTER(ctypes.c_uint8)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"librace.so is not built ({LIB_PATH}); run paper_1907_06487_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "race_params_default": ([ctypes.POINTER(race_params)], ctypes.c_int),
+        "race_build_schedule": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.POINTER(race_params), ctypes.POINTER(_P)],
+                                ctypes.c_int),
+        "race_schedule_upload": ([_P], ctypes.c_int),
+        "race_schedule_destroy": ([_P], None),
+        "race_schedule_stats": ([_P, ctypes.POINTER(race_stats)], ctypes.c_int),
+        "race_schedule_perm": ([_P, _I32P], ctypes.c_int),
+        "race_schedule_tree": ([_P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
+        "race_schedule_leaves": ([_P, _I32P, _I32P, _I32P], ctypes.c_int),
+        "race_schedule_units": ([_P, _I32P, _I64P, _I32P, _I32P, _I32P, _I64P, _I32P, _U8P, _U8P], ctypes.c_int),
+        "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
+        "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+        "race_permute": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+        "race_csr_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
+        "race_csr_spmv": ([_P, _P, _P, _P], ctypes.c_int),
+        "race_atomic_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.POINTER(_P)], ctypes.c_int),
+        "race_symm_spmv_atomic": ([_P, _P, _P, _P], ctypes.c_int),
+        "race_csr_destroy": ([_P], None),
+        "race_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != RACE_OK:
+        raise RaceError(rc, lib().race_last_error().decode())
+    return rc
+
+
+def _np_ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# same names as the C ABI
+
+def race_params_default():
+    p = race_params()
+    check(lib().race_params_default(ctypes.byref(p)))
+    return p
+
+
+def race_build_schedule(n, row_ptr, col, val, params=None):
+    """Host CRS arrays (upper triangle); returns an opaque handle (c_void_p)."""
+    rp, c = _i32(row_ptr), _i32(col)
+    v = None if val is None else np.ascontiguousarray(val, dtype=np.float64)
+    h = _P()
+    p = params if params is not None else race_params_default()
+    check(lib().race_build_schedule(int(n), _np_ptr(rp, ctypes.c_int32), _np_ptr(c, ctypes.c_int32),
+                                    None if v is None else _np_ptr(v, ctypes.c_double), ctypes.byref(p),
+                                    ctypes.byref(h)))
+    return h
+
+
+def race_schedule_upload(h):
+    check(lib().race_schedule_upload(h))
+
+
+def race_schedule_destroy(h):
+    lib().race_schedule_destroy(h)
+
+
+def race_schedule_stats(h):
+    st = race_stats()
+    check(lib().race_schedule_stats(h, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def race_schedule_perm(h, n):
+    out = np.empty(n, dtype=np.int32)
+    check(lib().race_schedule_perm(h, _np_ptr(out, ctypes.c_int32)))
+    return out
+
+
+def race_schedule_tree(h):
+    cnt = ctypes.c_int32()
+    check(lib().race_schedule_tree(h, ctypes.byref(cnt), None, None, None, None, None, None))
+    k = cnt.value
+    arrs = [np.empty(k, dtype=np.int32) for _ in range(6)]
+    check(lib().race_schedule_tree(h, ctypes.byref(cnt), *[_np_ptr(a, ctypes.c_int32) for a in arrs]))
+    return dict(zip(["stage", "color", "parent", "lo", "hi", "workers"], arrs))
+
+
+def race_schedule_leaves(h):
+    cnt = ctypes.c_int32()
+    check(lib().race_schedule_leaves(h, ctypes.byref(cnt), None, None))
+    node = np.empty(cnt.value, dtype=np.int32)
+    phase = np.empty(cnt.value, dtype=np.int32)
+    check(lib().race_schedule_leaves(h, ctypes.byref(cnt), _np_ptr(node, ctypes.c_int32),
+                                     _np_ptr(phase, ctypes.c_int32)))
+    return node, phase
+
+
+def race_schedule_units(h, n):
+    nu = ctypes.c_int32()
+    nh = ctypes.c_int64()
+    check(lib().race_schedule_units(h, ctypes.byref(nu), ctypes.byref(nh), *([None] * 7)))
+    u, hcount = nu.value, nh.value
+    unit_leaf = np.empty(u, dtype=np.int32)
+    lo = np.empty(u, dtype=np.int32)
+    hi = np.empty(u, dtype=np.int32)
+    hptr = np.empty(u + 1, dtype=np.int64)
+    halo = np.empty(hcount, dtype=np.int32)
+    hfirst = np.empty(hcount, dtype=np.uint8)
+    rfirst = np.empty(n, dtype=np.uint8)
+    check(lib().race_schedule_units(h, ctypes.byref(nu), ctypes.byref(nh), _np_ptr(unit_leaf, ctypes.c_int32),
+                                    _np_ptr(lo, ctypes.c_int32), _np_ptr(hi, ctypes.c_int32),
+                                    _np_ptr(hptr, ctypes.c_int64), _np_ptr(halo, ctypes.c_int32),
+                                    _np_ptr(hfirst, ctypes.c_uint8), _np_ptr(rfirst, ctypes.c_uint8)))
+    return {"unit_leaf": unit_leaf, "lo": lo, "hi": hi, "halo_ptr": hptr, "halo": halo, "halo_first": hfirst,
+            "row_first": rfirst}
+
+
+def race_symm_spmv(h, x, y, stream=None):
+    check(lib().race_symm_spmv(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
+
+
+def race_symm_spmm(h, k, X, Y, stream=None):
+    check(lib().race_symm_spmm(h, int(k), _dev_ptr(X), _dev_ptr(Y), _stream_ptr(stream)))
+
+
+def race_permute(h, k, inp, out, to_permuted, stream=None):
+    check(lib().race_permute(h, int(k), _dev_ptr(inp), _dev_ptr(out), int(bool(to_permuted)), _stream_ptr(stream)))
+
+
+def race_csr_create(n, row_ptr, col, val, lanes_per_row=0):
+    rp, c = _i32(row_ptr), _i32(col)
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    h = _P()
+    check(lib().race_csr_create(int(n), _np_ptr(rp, ctypes.c_int32), _np_ptr(c, ctypes.c_int32),
+                                _np_ptr(v, ctypes.c_double), int(lanes_per_row), ctypes.byref(h)))
+    return h
+
+
+def race_csr_spmv(h, x, y, stream=None):
+    check(lib().race_csr_spmv(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
+
+
+def race_atomic_create(n, row_ptr, col, val):
+    rp, c = _i32(row_ptr), _i32(col)
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    h = _P()
+    check(lib().race_atomic_create(int(n), _np_ptr(rp, ctypes.c_int32), _np_ptr(c, ctypes.c_int32),
+                                   _np_ptr(v, ctypes.c_double), ctypes.byref(h)))
+    return h
+
+
+def race_symm_spmv_atomic(h, x, y, stream=None):
+    check(lib().race_symm_spmv_atomic(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
+
+
+def race_csr_destroy(h):
+    lib().race_csr_destroy(h)
+
+
+def race_last_error():
+    return lib().race_last_error().decode()

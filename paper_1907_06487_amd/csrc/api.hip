@@ -1,0 +1,469 @@
+// C ABI of librace.so (declared in include/race.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/race.h"
+#include "kernels.hpp"
+#include "layout.hpp"
+#include "schedule.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return RACE_EHIP;
+}
+
+// Upper-triangle CRS: row_ptr[0] == 0, non-decreasing, columns strictly
+// ascending inside a row and in [row, n).  `upper` false: any column in [0, n).
+int validate_crs(int32_t n, const int32_t* row_ptr, const int32_t* col, bool upper) {
+  if (n < 0) return fail(RACE_EINVAL, "n must be >= 0");
+  if (!row_ptr) return fail(RACE_EINVAL, "row_ptr is NULL");
+  if (row_ptr[0] != 0) return fail(RACE_EINVAL, "row_ptr[0] must be 0");
+  for (int32_t r = 0; r < n; ++r)
+    if (row_ptr[r + 1] < row_ptr[r]) return fail(RACE_EINVAL, "row_ptr decreases at row " + std::to_string(r));
+  if (n > 0 && row_ptr[n] > 0 && !col) return fail(RACE_EINVAL, "col is NULL");
+  for (int32_t r = 0; r < n; ++r) {
+    for (int32_t i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
+      const int32_t c = col[i];
+      if (c < (upper ? r : 0) || c >= n)
+        return fail(RACE_EINVAL, "column " + std::to_string(c) + " of row " + std::to_string(r) +
+                                     (upper ? " is not in [row, n)" : " is out of range"));
+      if (i > row_ptr[r] && c <= col[i - 1])
+        return fail(RACE_EINVAL, "columns of row " + std::to_string(r) + " are not strictly ascending");
+    }
+  }
+  return RACE_OK;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t count = 0;
+};
+
+template <typename T>
+hipError_t upload(DevBuf<T>& b, const T* host, size_t count, int64_t* total) {
+  b.count = count;
+  if (count == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&b.p, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  *total += static_cast<int64_t>(count * sizeof(T));
+  return hipMemcpy(b.p, host, count * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+void release(DevBuf<T>& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.count = 0;
+}
+
+}  // namespace
+
+struct race_schedule {
+  race_params params{};
+  race::Tree tree;
+  race::Layout L;
+  race_stats stats{};
+  bool has_values = false;
+  bool uploaded = false;
+  int device = -1;
+  DevBuf<int32_t> leaf_unit_ptr, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old;
+  DevBuf<uint32_t> halo, row_first_bits, chunk_off;
+  DevBuf<uint16_t> lane_slot, sell_slot;
+  DevBuf<double> lane_diag64, sell_val64;
+  DevBuf<float> lane_diag32, sell_val32;
+
+  void free_device() {
+    release(leaf_unit_ptr); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
+    release(chunk_len); release(new2old); release(halo); release(row_first_bits); release(chunk_off);
+    release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
+    release(sell_val32);
+    uploaded = false;
+  }
+};
+
+struct race_csr {
+  int32_t n = 0;
+  int32_t lpr = 8;
+  bool atomic = false;
+  int device = -1;
+  DevBuf<int32_t> rp, col;
+  DevBuf<double> val;
+};
+
+extern "C" {
+
+const char* race_last_error(void) { return g_err.c_str(); }
+
+int race_params_default(race_params* p) {
+  if (!p) return fail(RACE_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->dist_k = 2;
+  p->n_workers = 1024;
+  p->max_stages = 4;
+  p->balance_by = 0;
+  p->global_lb = 0;
+  p->value_type = 0;
+  p->window_max = 4096;
+  p->block_threads = 256;
+  const double eps[8] = {0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
+  for (int i = 0; i < 8; ++i) p->eps[i] = eps[i];
+  p->cost_model = nullptr;
+  p->cost_model_len = 0;
+  return RACE_OK;
+}
+
+int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                        const race_params* p, race_schedule_t* out) {
+  if (!out) return fail(RACE_EINVAL, "out is NULL");
+  *out = nullptr;
+  race_params prm;
+  if (p) prm = *p;
+  else race_params_default(&prm);
+  if (prm.dist_k != 2) return fail(RACE_EUNSUPPORTED, "only distance-2 coloring (dist_k = 2) is implemented");
+  if (prm.n_workers < 1) return fail(RACE_EINVAL, "n_workers must be >= 1");
+  if (prm.max_stages < 1 || prm.max_stages > 16) return fail(RACE_EINVAL, "max_stages must be in 1..16");
+  if (prm.balance_by < 0 || prm.balance_by > 1)
+    return fail(RACE_EUNSUPPORTED, "balance_by must be 0 (nonzeros) or 1 (rows)");
+  if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
+  if (prm.window_max == 0) prm.window_max = 4096;
+  if (prm.window_max < 2 || prm.window_max > 10240) return fail(RACE_EINVAL, "window_max must be in 2..10240");
+  if (prm.block_threads == 0) prm.block_threads = 256;
+  if (prm.block_threads != 64 && prm.block_threads != 128 && prm.block_threads != 256 && prm.block_threads != 512 &&
+      prm.block_threads != 1024)
+    return fail(RACE_EINVAL, "block_threads must be 64, 128, 256, 512 or 1024");
+  for (int i = 0; i < 8; ++i)
+    if (!(prm.eps[i] >= 0.0 && prm.eps[i] < 1.0)) return fail(RACE_EINVAL, "eps values must be in [0, 1)");
+  int rc = validate_crs(n, row_ptr, col, true);
+  if (rc) return rc;
+  race_schedule* s = new (std::nothrow) race_schedule();
+  if (!s) return fail(RACE_ENOMEM, "out of host memory");
+  try {
+    s->params = prm;
+    race::Graph g;
+    race::build_graph(n, row_ptr, col, g);
+    std::vector<int64_t> m;
+    race::row_loads(n, row_ptr, col, prm.balance_by == 1, m);
+    race::TreeParams tp;
+    tp.n_workers = prm.n_workers;
+    tp.max_stages = prm.max_stages;
+    tp.dist_k = prm.dist_k;
+    tp.global_lb = prm.global_lb != 0;
+    for (int i = 0; i < 8; ++i) tp.eps[i] = prm.eps[i];
+    std::string err = race::build_tree(g, m, tp, s->tree);
+    if (!err.empty()) {
+      delete s;
+      return fail(RACE_EINVAL, err);
+    }
+    int code = RACE_OK;
+    err = race::build_layout(n, row_ptr, col, val, s->tree, prm.window_max, prm.value_type, s->L, &code);
+    if (!err.empty()) {
+      delete s;
+      return fail(code, err);
+    }
+    s->has_values = val != nullptr;
+    race_stats& st = s->stats;
+    const race::Tree& t = s->tree;
+    const race::Layout& L = s->L;
+    st.n = n;
+    st.n_levels0 = t.n_levels0;
+    st.depth = t.depth;
+    st.n_nodes = static_cast<int32_t>(t.nodes.size());
+    st.n_leaves = static_cast<int32_t>(t.leaves.size());
+    st.n_phases = t.n_phases;
+    int32_t used = 0;
+    for (int32_t ph = 0; ph < t.n_phases; ++ph)
+      if (L.phase_leaf_ptr[ph + 1] > L.phase_leaf_ptr[ph]) ++used;
+    st.n_phases_used = used;
+    st.n_units = static_cast<int32_t>(L.unit_lo.size());
+    st.max_window = L.max_window;
+    st.n_chunks = static_cast<int32_t>(L.chunk_len.size());
+    st.n_eff_root = t.n_eff_root;
+    st.n_workers = prm.n_workers;
+    st.eta = t.eta;
+    st.nnz_upper = n > 0 ? row_ptr[n] : 0;
+    st.n_diag = L.n_diag;
+    st.nnz_full = 2 * st.nnz_upper - st.n_diag;
+    st.sell_elems = static_cast<int64_t>(L.sell_val.size());
+    st.halo_total = L.halo_total;
+    st.rows_rmw = L.rows_rmw;
+    st.halo_rmw = L.halo_rmw;
+    st.bytes_min = 12 * st.nnz_upper + 20 * static_cast<int64_t>(n) + 4;
+    const int64_t vb = prm.value_type == 1 ? 4 : 8;
+    // slices: value + 2-byte slot per element; per lane: slot + diagonal;
+    // per slice: offset + length; per unit: 4 ints; halo: index;
+    // x: own rows + halo read once; y: own rows + halo written, RMW read.
+    st.bytes_kernel = st.sell_elems * (vb + 2) + static_cast<int64_t>(st.n_chunks) * (8 + race::kSlice * (2 + vb)) +
+                      static_cast<int64_t>(st.n_units) * 16 + st.halo_total * 4 +
+                      (static_cast<int64_t>(n) + 31) / 32 * 4 +
+                      8 * (static_cast<int64_t>(n) + st.halo_total) + 8 * (static_cast<int64_t>(n) + st.halo_total) +
+                      8 * (st.rows_rmw + st.halo_rmw);
+    st.device_bytes = 0;
+  } catch (const std::bad_alloc&) {
+    delete s;
+    return fail(RACE_ENOMEM, "out of host memory while building the schedule");
+  } catch (const std::exception& ex) {
+    delete s;
+    return fail(RACE_EINTERNAL, ex.what());
+  }
+  *out = s;
+  return RACE_OK;
+}
+
+int race_schedule_upload(race_schedule_t s) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->uploaded) return RACE_OK;
+  if (!s->has_values) return fail(RACE_ESTATE, "schedule was built from a pattern without values");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const race::Layout& L = s->L;
+  int64_t total = 0;
+#define UP(buf, vec)                                               \
+  e = upload(s->buf, (vec).data(), (vec).size(), &total);          \
+  if (e != hipSuccess) {                                           \
+    s->free_device();                                              \
+    return hip_fail(e, "upload of " #buf);                         \
+  }
+  UP(leaf_unit_ptr, L.leaf_unit_ptr)
+  UP(unit_lo, L.unit_lo)
+  UP(unit_hi, L.unit_hi)
+  UP(unit_halo_ptr, L.unit_halo_ptr)
+  UP(unit_chunk_ptr, L.unit_chunk_ptr)
+  UP(chunk_len, L.chunk_len)
+  UP(new2old, s->tree.perm)
+  UP(halo, L.halo)
+  UP(row_first_bits, L.row_first_bits)
+  UP(chunk_off, L.chunk_off)
+  UP(lane_slot, L.lane_slot)
+  UP(sell_slot, L.sell_slot)
+  if (s->params.value_type == 0) {
+    UP(lane_diag64, L.lane_diag)
+    UP(sell_val64, L.sell_val)
+  } else {
+    std::vector<float> d32(L.lane_diag.begin(), L.lane_diag.end());
+    std::vector<float> v32(L.sell_val.begin(), L.sell_val.end());
+    UP(lane_diag32, d32)
+    UP(sell_val32, v32)
+  }
+#undef UP
+  s->device = dev;
+  s->uploaded = true;
+  s->stats.device_bytes = total;
+  return RACE_OK;
+}
+
+void race_schedule_destroy(race_schedule_t s) {
+  if (!s) return;
+  if (s->uploaded) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s->device);
+    s->free_device();
+    (void)hipSetDevice(cur);
+  }
+  delete s;
+}
+
+int race_schedule_stats(race_schedule_t s, race_stats* out) {
+  if (!s || !out) return fail(RACE_EINVAL, "NULL argument");
+  *out = s->stats;
+  return RACE_OK;
+}
+
+int race_schedule_perm(race_schedule_t s, int32_t* new2old) {
+  if (!s || !new2old) return fail(RACE_EINVAL, "NULL argument");
+  std::copy(s->tree.perm.begin(), s->tree.perm.end(), new2old);
+  return RACE_OK;
+}
+
+int race_schedule_tree(race_schedule_t s, int32_t* n_nodes, int32_t* stage, int32_t* color, int32_t* parent,
+                       int32_t* lo, int32_t* hi, int32_t* workers) {
+  if (!s || !n_nodes) return fail(RACE_EINVAL, "NULL argument");
+  const auto& nodes = s->tree.nodes;
+  *n_nodes = static_cast<int32_t>(nodes.size());
+  for (size_t i = 0; i < nodes.size(); ++i) {
+    if (stage) stage[i] = nodes[i].stage;
+    if (color) color[i] = nodes[i].color;
+    if (parent) parent[i] = nodes[i].parent;
+    if (lo) lo[i] = nodes[i].lo;
+    if (hi) hi[i] = nodes[i].hi;
+    if (workers) workers[i] = nodes[i].workers;
+  }
+  return RACE_OK;
+}
+
+int race_schedule_leaves(race_schedule_t s, int32_t* n_leaves, int32_t* node, int32_t* phase) {
+  if (!s || !n_leaves) return fail(RACE_EINVAL, "NULL argument");
+  *n_leaves = static_cast<int32_t>(s->tree.leaves.size());
+  if (node) std::copy(s->tree.leaves.begin(), s->tree.leaves.end(), node);
+  if (phase) std::copy(s->tree.leaf_phase.begin(), s->tree.leaf_phase.end(), phase);
+  return RACE_OK;
+}
+
+int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, int32_t* unit_leaf, int32_t* row_lo,
+                        int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_first, uint8_t* row_first) {
+  if (!s || !n_units || !n_halo) return fail(RACE_EINVAL, "NULL argument");
+  const race::Layout& L = s->L;
+  *n_units = static_cast<int32_t>(L.unit_lo.size());
+  *n_halo = static_cast<int64_t>(L.halo.size());
+  for (size_t u = 0; u < L.unit_lo.size(); ++u) {
+    if (unit_leaf) unit_leaf[u] = L.unit_leaf[u];
+    if (row_lo) row_lo[u] = L.unit_lo[u];
+    if (row_hi) row_hi[u] = L.unit_hi[u];
+  }
+  if (halo_ptr)
+    for (size_t u = 0; u < L.unit_halo_ptr.size(); ++u) halo_ptr[u] = L.unit_halo_ptr[u];
+  for (size_t j = 0; j < L.halo.size(); ++j) {
+    if (halo) halo[j] = static_cast<int32_t>(L.halo[j] & 0x7fffffffu);
+    if (halo_first) halo_first[j] = (L.halo[j] >> 31) ? 1 : 0;
+  }
+  if (row_first)
+    for (int32_t r = 0; r < L.n; ++r) row_first[r] = (L.row_first_bits[r >> 5] >> (r & 31)) & 1u;
+  return RACE_OK;
+}
+
+static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
+  if (s->tree.n == 0) return RACE_OK;
+  if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
+  const size_t lds_limit = 160 * 1024;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const race::Layout& L = s->L;
+  for (int32_t ph = 0; ph < s->tree.n_phases; ++ph) {
+    const int32_t l0 = L.phase_leaf_ptr[ph], l1 = L.phase_leaf_ptr[ph + 1];
+    if (l1 == l0) continue;
+    const int32_t wmax = std::max(1, L.phase_max_window[ph]);
+    if (2 * static_cast<size_t>(wmax) * k * sizeof(double) > lds_limit)
+      return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
+                                         " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
+    hipError_t e;
+    if (s->params.value_type == 0) {
+      race::UnitArgs<double> a{s->leaf_unit_ptr.p, s->unit_lo.p, s->unit_hi.p, s->unit_halo_ptr.p, s->halo.p,
+                               s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p, s->chunk_len.p,
+                               s->lane_slot.p, s->lane_diag64.p, s->sell_val64.p, s->sell_slot.p};
+      e = race::launch_race_phase<double>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, st);
+    } else {
+      race::UnitArgs<float> a{s->leaf_unit_ptr.p, s->unit_lo.p, s->unit_hi.p, s->unit_halo_ptr.p, s->halo.p,
+                              s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p, s->chunk_len.p,
+                              s->lane_slot.p, s->lane_diag32.p, s->sell_val32.p, s->sell_slot.p};
+      e = race::launch_race_phase<float>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "RACE phase launch");
+  }
+  return RACE_OK;
+}
+
+int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream) {
+  return run_products(s, 1, x, y, stream);
+}
+
+int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream) {
+  return run_products(s, k, X, Y, stream);
+}
+
+int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, int32_t to_permuted, void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  if (k < 1) return fail(RACE_EINVAL, "k must be >= 1");
+  if (s->tree.n == 0) return RACE_OK;
+  if (!in || !out) return fail(RACE_EINVAL, "in or out is NULL");
+  hipError_t e = race::launch_permute(s->tree.n, k, s->new2old.p, in, out, to_permuted, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "permute launch");
+  return RACE_OK;
+}
+
+static int pick_lpr(int32_t n, int64_t nnz) {
+  const double mean = n > 0 ? static_cast<double>(nnz) / n : 1.0;
+  int lpr = 1;
+  while (lpr < 64 && lpr < mean / 2.0) lpr *= 2;
+  return lpr;
+}
+
+static int csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, int32_t lpr,
+                      bool upper, race_csr_t* out) {
+  if (!out) return fail(RACE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_crs(n, row_ptr, col, upper);
+  if (rc) return rc;
+  const int64_t nnz = n > 0 ? row_ptr[n] : 0;
+  if (nnz > 0 && !val) return fail(RACE_EINVAL, "val is NULL");
+  if (lpr == 0) lpr = pick_lpr(n, nnz);
+  if (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8 && lpr != 16 && lpr != 32 && lpr != 64)
+    return fail(RACE_EINVAL, "lanes_per_row must be a power of two in 1..64");
+  race_csr* h = new (std::nothrow) race_csr();
+  if (!h) return fail(RACE_ENOMEM, "out of host memory");
+  h->n = n;
+  h->lpr = lpr;
+  h->atomic = upper;
+  hipError_t e = hipGetDevice(&h->device);
+  int64_t total = 0;
+  if (e == hipSuccess) e = upload(h->rp, row_ptr, static_cast<size_t>(n) + 1, &total);
+  if (e == hipSuccess) e = upload(h->col, col, static_cast<size_t>(nnz), &total);
+  if (e == hipSuccess) e = upload(h->val, val, static_cast<size_t>(nnz), &total);
+  if (e != hipSuccess) {
+    race_csr_destroy(h);
+    return hip_fail(e, "baseline upload");
+  }
+  *out = h;
+  return RACE_OK;
+}
+
+int race_csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, int32_t lanes_per_row,
+                    race_csr_t* out) {
+  return csr_create(n, row_ptr, col, val, lanes_per_row, false, out);
+}
+
+int race_atomic_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, race_csr_t* out) {
+  return csr_create(n, row_ptr, col, val, 0, true, out);
+}
+
+int race_csr_spmv(race_csr_t h, const double* x, double* y, void* stream) {
+  if (!h) return fail(RACE_EINVAL, "handle is NULL");
+  if (h->atomic) return fail(RACE_ESTATE, "handle holds an upper triangle; use race_symm_spmv_atomic");
+  if (h->n > 0 && (!x || !y)) return fail(RACE_EINVAL, "x or y is NULL");
+  hipError_t e = race::launch_csr_spmv(h->n, h->rp.p, h->col.p, h->val.p, x, y, h->lpr, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "CSR SpMV launch");
+  return RACE_OK;
+}
+
+int race_symm_spmv_atomic(race_csr_t h, const double* x, double* y, void* stream) {
+  if (!h) return fail(RACE_EINVAL, "handle is NULL");
+  if (!h->atomic) return fail(RACE_ESTATE, "handle holds a full matrix; use race_csr_spmv");
+  if (h->n > 0 && (!x || !y)) return fail(RACE_EINVAL, "x or y is NULL");
+  hipError_t e =
+      race::launch_atomic_symm(h->n, h->rp.p, h->col.p, h->val.p, x, y, h->lpr, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "atomic SymmSpMV launch");
+  return RACE_OK;
+}
+
+void race_csr_destroy(race_csr_t h) {
+  if (!h) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (h->device >= 0) (void)hipSetDevice(h->device);
+  release(h->rp);
+  release(h->col);
+  release(h->val);
+  (void)hipSetDevice(cur);
+  delete h;
+}
+
+}  // extern "C"

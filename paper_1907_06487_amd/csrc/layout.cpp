@@ -1,0 +1,223 @@
+// Device data layout of a RACE schedule (see layout.hpp).
+#include "layout.hpp"
+
+#include <algorithm>
+#include <numeric>
+
+#include "../../include/race.h"
+
+namespace race {
+
+static void permute_upper(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                          const std::vector<int32_t>& perm, Layout& L) {
+  std::vector<int32_t> old2new(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) old2new[perm[i]] = i;
+  const int64_t nnz = row_ptr[n];
+  L.prow_ptr.assign(static_cast<size_t>(n) + 1, 0);
+  for (int32_t r = 0; r < n; ++r)
+    for (int32_t i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
+      const int32_t a = old2new[r], b = old2new[col[i]];
+      ++L.prow_ptr[std::min(a, b) + 1];
+    }
+  for (int32_t i = 0; i < n; ++i) L.prow_ptr[i + 1] += L.prow_ptr[i];
+  L.pcol.resize(static_cast<size_t>(nnz));
+  L.pval.resize(static_cast<size_t>(nnz));
+  std::vector<int32_t> fill(L.prow_ptr.begin(), L.prow_ptr.end() - 1);
+  for (int32_t r = 0; r < n; ++r)
+    for (int32_t i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
+      const int32_t a = old2new[r], b = old2new[col[i]];
+      const int32_t lo = std::min(a, b), hi = std::max(a, b);
+      const int32_t at = fill[lo]++;
+      L.pcol[at] = hi;
+      L.pval[at] = val ? val[i] : 0.0;
+    }
+  std::vector<std::pair<int32_t, double>> tmp;
+  L.n_diag = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t s = L.prow_ptr[r], e = L.prow_ptr[r + 1];
+    tmp.clear();
+    for (int32_t i = s; i < e; ++i) tmp.emplace_back(L.pcol[i], L.pval[i]);
+    std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (int32_t i = s; i < e; ++i) {
+      L.pcol[i] = tmp[i - s].first;
+      L.pval[i] = tmp[i - s].second;
+    }
+    if (s < e && L.pcol[s] == r) ++L.n_diag;
+  }
+}
+
+std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, const Tree& tree,
+                         int32_t window_max, int32_t value_type, Layout& L, int* code) {
+  *code = RACE_OK;
+  L = Layout();
+  L.n = n;
+  L.value_type = value_type;
+  permute_upper(n, row_ptr, col, val, tree.perm, L);
+  const std::vector<int32_t>& rp = L.prow_ptr;
+  const std::vector<int32_t>& pc = L.pcol;
+
+  // phases -> leaves
+  const int32_t n_leaves = static_cast<int32_t>(tree.leaves.size());
+  L.phase_leaf_ptr.assign(static_cast<size_t>(tree.n_phases) + 1, 0);
+  for (int32_t t = 0; t < n_leaves; ++t) ++L.phase_leaf_ptr[tree.leaf_phase[t] + 1];
+  for (int32_t p = 0; p < tree.n_phases; ++p) L.phase_leaf_ptr[p + 1] += L.phase_leaf_ptr[p];
+
+  // units: greedy row ranges of each leaf whose window fits
+  std::vector<uint8_t> marked(static_cast<size_t>(n), 0);
+  std::vector<int32_t> mark_list;
+  std::vector<int32_t> slot_of(static_cast<size_t>(n), -1);
+  L.leaf_unit_ptr.assign(1, 0);
+  L.unit_halo_ptr.assign(1, 0);
+  L.unit_chunk_ptr.assign(1, 0);
+  std::vector<int32_t> rows_sorted;
+  uint64_t elems = 0;
+  for (int32_t t = 0; t < n_leaves; ++t) {
+    const TreeNode& leaf = tree.nodes[tree.leaves[t]];
+    int32_t a = leaf.lo;
+    while (a < leaf.hi) {
+      int64_t w = 0;
+      int32_t b = a;
+      while (b < leaf.hi) {
+        const int32_t r = b;
+        int64_t new_h = 0;
+        for (int32_t i = rp[r]; i < rp[r + 1]; ++i)
+          if (pc[i] > r && !marked[pc[i]]) ++new_h;
+        const int64_t w_new = w + (marked[r] ? 0 : 1) + new_h;
+        if (w_new > window_max) {
+          if (b == a) {
+            *code = RACE_EUNSUPPORTED;
+            return "row " + std::to_string(r) + " alone needs a window of " + std::to_string(w_new) +
+                   " entries, more than window_max " + std::to_string(window_max);
+          }
+          break;
+        }
+        if (!marked[r]) { marked[r] = 1; mark_list.push_back(r); }
+        for (int32_t i = rp[r]; i < rp[r + 1]; ++i)
+          if (!marked[pc[i]]) { marked[pc[i]] = 1; mark_list.push_back(pc[i]); }
+        w = w_new;
+        ++b;
+      }
+      // unit [a, b): halo = marked indices >= b, ascending
+      const int32_t R = b - a;
+      const size_t h0 = L.halo.size();
+      for (int32_t v : mark_list)
+        if (v >= b) L.halo.push_back(static_cast<uint32_t>(v));
+      std::sort(L.halo.begin() + h0, L.halo.end());
+      const int32_t H = static_cast<int32_t>(L.halo.size() - h0);
+      for (int32_t v : mark_list) marked[v] = 0;
+      mark_list.clear();
+      for (int32_t j = 0; j < H; ++j) slot_of[L.halo[h0 + j]] = R + j;
+      L.max_window = std::max<int32_t>(L.max_window, R + H);
+      L.unit_leaf.push_back(t);
+      L.unit_lo.push_back(a);
+      L.unit_hi.push_back(b);
+      L.unit_halo_ptr.push_back(static_cast<int32_t>(L.halo.size()));
+      // slices, rows by descending off-diagonal count (stable)
+      rows_sorted.resize(static_cast<size_t>(R));
+      std::iota(rows_sorted.begin(), rows_sorted.end(), a);
+      auto offd = [&](int32_t r) {
+        const int32_t len = rp[r + 1] - rp[r];
+        return len - ((len > 0 && pc[rp[r]] == r) ? 1 : 0);
+      };
+      std::stable_sort(rows_sorted.begin(), rows_sorted.end(), [&](int32_t x, int32_t y) { return offd(x) > offd(y); });
+      for (int32_t c0 = 0; c0 < R; c0 += kSlice) {
+        const int32_t cn = std::min(kSlice, R - c0);
+        int32_t len = 0;
+        for (int32_t l = 0; l < cn; ++l) len = std::max(len, offd(rows_sorted[c0 + l]));
+        L.chunk_off.push_back(static_cast<uint32_t>(elems));
+        L.chunk_len.push_back(len | (cn << 16));
+        const size_t base = L.sell_val.size();
+        L.sell_val.resize(base + static_cast<size_t>(len) * cn, 0.0);
+        L.sell_slot.resize(base + static_cast<size_t>(len) * cn, 0);
+        for (int32_t l = 0; l < kSlice; ++l) {
+          if (l >= cn) {
+            L.lane_slot.push_back(kNoRow);
+            L.lane_diag.push_back(0.0);
+            continue;
+          }
+          const int32_t r = rows_sorted[c0 + l];
+          const uint16_t own = static_cast<uint16_t>(r - a);
+          L.lane_slot.push_back(own);
+          int32_t i = rp[r];
+          double d = 0.0;
+          if (i < rp[r + 1] && pc[i] == r) {
+            d = L.pval[i];
+            ++i;
+          }
+          L.lane_diag.push_back(d);
+          int32_t j = 0;
+          for (; i < rp[r + 1]; ++i, ++j) {
+            const int32_t c = pc[i];
+            const int32_t s = c < b ? c - a : slot_of[c];
+            L.sell_val[base + static_cast<size_t>(j) * cn + l] = L.pval[i];
+            L.sell_slot[base + static_cast<size_t>(j) * cn + l] = static_cast<uint16_t>(s);
+          }
+          for (; j < len; ++j) L.sell_slot[base + static_cast<size_t>(j) * cn + l] = own;
+        }
+        elems += static_cast<uint64_t>(len) * cn;
+        if (elems >= (1ull << 32)) {
+          *code = RACE_EUNSUPPORTED;
+          return "sliced layout exceeds 2^32 elements";
+        }
+      }
+      L.unit_chunk_ptr.push_back(static_cast<int32_t>(L.chunk_len.size()));
+      for (int32_t j = 0; j < H; ++j) slot_of[L.halo[h0 + j]] = -1;
+      a = b;
+    }
+    L.leaf_unit_ptr.push_back(static_cast<int32_t>(L.unit_lo.size()));
+  }
+  if (L.halo.size() >= static_cast<size_t>(INT32_MAX)) {
+    *code = RACE_EUNSUPPORTED;
+    return "halo lists exceed 2^31 entries";
+  }
+
+  // first writer of every y entry, and the independence check: units of
+  // different leaves in one phase must never touch the same index
+  L.row_first_bits.assign((static_cast<size_t>(n) + 31) / 32, 0u);
+  std::vector<int32_t> last_phase(static_cast<size_t>(n), -1), last_leaf(static_cast<size_t>(n), -1);
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  for (int32_t u = 0; u < n_units; ++u) {
+    const int32_t t = L.unit_leaf[u];
+    const int32_t ph = tree.leaf_phase[t];
+    auto touch = [&](int32_t g) -> int {
+      if (last_phase[g] < 0) {
+        last_phase[g] = ph;
+        last_leaf[g] = t;
+        return 1;
+      }
+      if (last_phase[g] == ph && last_leaf[g] != t) return -1;
+      last_phase[g] = ph;
+      last_leaf[g] = t;
+      return 0;
+    };
+    for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) {
+      const int f = touch(g);
+      if (f < 0) {
+        *code = RACE_EINTERNAL;
+        return "phase " + std::to_string(ph) + ": row " + std::to_string(g) + " is touched by two leaves";
+      }
+      if (f) L.row_first_bits[g >> 5] |= 1u << (g & 31);
+      else ++L.rows_rmw;
+    }
+    for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j) {
+      const int32_t g = static_cast<int32_t>(L.halo[j]);
+      const int f = touch(g);
+      if (f < 0) {
+        *code = RACE_EINTERNAL;
+        return "phase " + std::to_string(ph) + ": index " + std::to_string(g) + " is touched by two leaves";
+      }
+      if (f) L.halo[j] |= kFirstBit;
+      else ++L.halo_rmw;
+    }
+  }
+  L.halo_total = static_cast<int64_t>(L.halo.size());
+  L.phase_max_window.assign(static_cast<size_t>(tree.n_phases), 0);
+  for (int32_t u = 0; u < n_units; ++u) {
+    const int32_t ph = tree.leaf_phase[L.unit_leaf[u]];
+    const int32_t w = (L.unit_hi[u] - L.unit_lo[u]) + (L.unit_halo_ptr[u + 1] - L.unit_halo_ptr[u]);
+    L.phase_max_window[ph] = std::max(L.phase_max_window[ph], w);
+  }
+  return std::string();
+}
+
+}  // namespace race

@@ -1,0 +1,185 @@
+"""Host-side checks of librace.so (CPU only, no device calls).
+
+* the library loads and exports every entry point include/race.h declares;
+* the native schedule is bit-exact against the oracle (permutation, tree,
+  leaf order, phases, N_eff, eta);
+* the kernel layout (units, halos, first-writer flags) is consistent with an
+  independent derivation from the exported schedule, and every schedule
+  passes the brute-force conflict checker;
+* malformed inputs return the documented error codes.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import matgen
+import paper_1907_06487_amd as R
+from paper_1907_06487_amd import _lib
+from oracle import checker as C
+from oracle import schedule as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "race.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(race_\w+)\s*\(", hdr, flags=re.M))
+    assert declared == set(_lib.EXPORTS)
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _oracle(m, nt, **kw):
+    return S.build_schedule(m.n, m.row_ptr, m.col, nt, eps=kw.get("eps", S.DEFAULT_EPS),
+                            balance=kw.get("balance", "nnz"), max_stages=kw.get("max_stages", 4),
+                            global_lb=kw.get("global_lb", False))
+
+
+def _compare(m, nt, **kw):
+    ref = _oracle(m, nt, **kw)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, n_workers=nt, **kw)
+    try:
+        assert np.array_equal(s.perm(), ref.perm)
+        tr = s.tree()
+        assert len(tr["lo"]) == len(ref.nodes)
+        for key, attr in [("stage", "stage"), ("color", "color"), ("parent", "parent"), ("lo", "lo"), ("hi", "hi"),
+                          ("workers", "b")]:
+            assert np.array_equal(tr[key], [getattr(nd, attr) for nd in ref.nodes]), key
+        node, phase = s.leaves()
+        assert np.array_equal(node, ref.leaves)
+        assert np.array_equal(phase, ref.leaf_phase)
+        st = s.stats()
+        assert st["eta"] == ref.eta and st["n_eff_root"] == ref.n_eff_root
+        assert st["n_phases"] == ref.n_phases and st["n_levels0"] == ref.stage0_levels
+        return s, ref
+    except Exception:
+        s.close()
+        raise
+
+
+CASES = [
+    ("worked_16x16", lambda: matgen.stencil2d_7pt(16), 8, dict(eps=(0.6, 0.6), balance="rows")),
+    ("worked_16x16_global", lambda: matgen.stencil2d_7pt(16), 8, dict(eps=(0.6, 0.6), balance="rows", global_lb=True)),
+    ("2d5pt_100", matgen.config_2d_small, 64, {}),
+    ("2d5pt_100_rows", matgen.config_2d_small, 200, dict(balance="rows")),
+    ("3d27pt_20", lambda: matgen.stencil3d_27pt(20, seed=4), 128, {}),
+    ("3d27pt_20_global", lambda: matgen.stencil3d_27pt(20, seed=4), 96, dict(global_lb=True, max_stages=6)),
+    ("banded_30k", lambda: matgen.banded_irregular(30000, seed=6, band=3000), 256, {}),
+    ("rand_islands", lambda: matgen.random_symmetric(400, 0.003, seed=8), 16, {}),
+    ("rand_nodiag", lambda: matgen.random_symmetric(300, 0.02, seed=9, with_diag=False), 12, {}),
+    ("one_row", lambda: matgen.UpperCSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.ones(1)), 4, {}),
+    ("empty", lambda: matgen.UpperCSR(0, np.array([0], np.int32), np.array([], np.int32), np.zeros(0)), 4, {}),
+]
+
+
+@pytest.mark.parametrize("name,make,nt,kw", CASES, ids=[c[0] for c in CASES])
+def test_schedule_bit_exact_vs_oracle(name, make, nt, kw):
+    m = make()
+    s, ref = _compare(m, nt, **kw)
+    s.close()
+
+
+@pytest.mark.slow
+def test_schedule_bit_exact_3d27pt_128():
+    m = matgen.config_3d_128()
+    s, ref = _compare(m, 1024)
+    s.close()
+
+
+def first_writers(n, unit_leaf, leaf_phase, lo, hi, halo_ptr, halo):
+    """Independent derivation: walk units in execution order; the first unit
+    touching an index writes it; two leaves of one phase must not share one."""
+    seen_phase = np.full(n, -1, dtype=np.int64)
+    seen_leaf = np.full(n, -1, dtype=np.int64)
+    row_first = np.zeros(n, dtype=np.uint8)
+    halo_first = np.zeros(len(halo), dtype=np.uint8)
+    for u in range(len(lo)):
+        leaf = unit_leaf[u]
+        ph = leaf_phase[leaf]
+        idx = np.concatenate([np.arange(lo[u], hi[u]), halo[halo_ptr[u]:halo_ptr[u + 1]]])
+        clash = (seen_phase[idx] == ph) & (seen_leaf[idx] != leaf)
+        assert not clash.any()
+        fresh = seen_phase[idx] < 0
+        r = hi[u] - lo[u]
+        row_first[lo[u]:hi[u]] = fresh[:r]
+        halo_first[halo_ptr[u]:halo_ptr[u + 1]] = fresh[r:]
+        seen_phase[idx] = ph
+        seen_leaf[idx] = leaf
+    return row_first, halo_first
+
+
+@pytest.mark.parametrize("name,make,nt,kw", CASES[:9], ids=[c[0] for c in CASES[:9]])
+def test_layout_consistent(name, make, nt, kw):
+    m = make()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, n_workers=nt, window_max=256, **kw)
+    try:
+        u = s.units()
+        node, phase = s.leaves()
+        tr = s.tree()
+        # units tile each leaf in order
+        for t, nd in enumerate(node):
+            sel = np.flatnonzero(u["unit_leaf"] == t)
+            if tr["hi"][nd] == tr["lo"][nd]:
+                assert sel.size == 0
+                continue
+            assert u["lo"][sel[0]] == tr["lo"][nd] and u["hi"][sel[-1]] == tr["hi"][nd]
+            assert np.array_equal(u["lo"][sel[1:]], u["hi"][sel[:-1]])
+        # halo = distinct columns at or beyond the unit's end, ascending
+        perm = s.perm()
+        rp, cols, _ = S.permute_upper(m.n, m.row_ptr, m.col, m.val, perm)
+        for k in range(len(u["lo"])):
+            a, b = u["lo"][k], u["hi"][k]
+            want = np.unique(cols[rp[a]:rp[b]])
+            want = want[want >= b]
+            got = u["halo"][u["halo_ptr"][k]:u["halo_ptr"][k + 1]]
+            assert np.array_equal(got, want)
+            assert (b - a) + got.size <= 256
+        rf, hf = first_writers(m.n, u["unit_leaf"], phase, u["lo"], u["hi"], u["halo_ptr"], u["halo"])
+        assert np.array_equal(rf, u["row_first"])
+        assert np.array_equal(hf, u["halo_first"])
+        # the schedule itself passes the brute-force checker
+        C.check_schedule(m.n, m.row_ptr, m.col, perm, tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase)
+    finally:
+        s.close()
+
+
+def _expect(code, fn):
+    with pytest.raises(_lib.RaceError) as ei:
+        fn()
+    assert ei.value.code == code, str(ei.value)
+
+
+def test_error_codes():
+    ok_rp = np.array([0, 2, 3], np.int32)
+    ok_col = np.array([0, 1, 1], np.int32)
+    v = np.ones(3)
+    h = R.race_build_schedule(2, ok_rp, ok_col, v)
+    R.race_schedule_destroy(h)
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, np.array([1, 0, 1], np.int32), v))       # unsorted
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, np.array([0, 1, 0], np.int32), v))       # col < row
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, np.array([0, 2, 1], np.int32), v))       # out of range
+    _expect(-1, lambda: R.race_build_schedule(2, np.array([1, 2, 3], np.int32), ok_col, v))       # row_ptr[0]
+    _expect(-1, lambda: R.race_build_schedule(2, np.array([0, 2, 1], np.int32), ok_col, v))       # decreasing
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, np.array([0, 0, 1], np.int32), v))       # duplicate
+    p = R.make_params()
+    p.dist_k = 1
+    _expect(-4, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params(n_workers=0)
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params(window_max=100000)
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params(block_threads=100)
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    # a row whose window alone exceeds the budget
+    n = 40
+    rp = np.array([0, n] + [n + i for i in range(1, n)], np.int32)
+    col = np.concatenate([np.arange(n), np.arange(1, n)]).astype(np.int32)
+    _expect(-4, lambda: R.race_build_schedule(n, rp, col, np.ones(col.size), R.make_params(window_max=16)))
+    # products need an uploaded schedule with values
+    h = R.race_build_schedule(2, ok_rp, ok_col, None)
+    _expect(-5, lambda: R.race_schedule_upload(h))
+    R.race_schedule_destroy(h)
