@@ -87,13 +87,15 @@ def main():
     ap.add_argument("--workload", default="3d27pt_128")
     ap.add_argument("--n-workers", type=int, default=256)
     ap.add_argument("--max-stages", type=int, default=4)
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--window", type=int, default=4096)
     ap.add_argument("--value-type", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--exec-mode", default="flow", choices=["flow", "phases"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
-    ap.add_argument("--sweep", default="", help="n_workers:block list, e.g. 256:256,512:512 (extra lines on stderr)")
+    ap.add_argument("--sweep", default="",
+                    help="n_workers:block[:window[:mode]] list, e.g. 256:256,512:512:2048:phases (stderr)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
@@ -112,7 +114,8 @@ def main():
     log(f"workload {args.workload}: n={m.n} nnz_upper={m.nnz}")
     t0 = time.perf_counter()
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
-                   block_threads=args.block, window_max=args.window, value_type=args.value_type)
+                   block_threads=args.block, window_max=args.window, value_type=args.value_type,
+                   exec_mode=args.exec_mode)
     t_build = time.perf_counter() - t0
     st = s.stats()
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
@@ -138,6 +141,7 @@ def main():
     log(f"error vs oracle: norm {err_norm:.3e} comp {err_comp:.3e}")
 
     ms = time_ring(lambda x, y: s.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
+    s.check()
     flops = 2 * st["nnz_full"]
     gflops = flops / (ms * 1e-3) / 1e9
     achieved = st["bytes_min"] / (ms * 1e-3) / 1e9
@@ -146,12 +150,16 @@ def main():
         f"({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes {st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
 
     for item in filter(None, args.sweep.split(",")):
-        nt, blk = (int(v) for v in item.split(":"))
+        nt, blk = (int(v) for v in item.split(":")[:2])
+        parts = item.split(":")
+        win = int(parts[2]) if len(parts) > 2 else args.window
+        mode = parts[3] if len(parts) > 3 else args.exec_mode
         s2 = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=nt, max_stages=args.max_stages, block_threads=blk,
-                        window_max=args.window, value_type=args.value_type)
+                        window_max=win, value_type=args.value_type, exec_mode=mode)
         st2 = s2.stats()
         ms2 = time_ring(lambda x, y: s2.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
-        log(f"sweep n_workers={nt} block={blk}: {ms2 * 1e3:.2f} us, "
+        s2.check()
+        log(f"sweep n_workers={nt} block={blk} window={win} mode={mode}: {ms2 * 1e3:.2f} us, "
             f"{st2['bytes_min'] / (ms2 * 1e-3) / 1e9 / PEAK_HBM_GBS * 100:.1f}% peak, phases={st2['n_phases_used']} "
             f"leaves={st2['n_leaves']} units={st2['n_units']} kernel bytes={st2['bytes_kernel']}")
         s2.close()
@@ -208,7 +216,7 @@ def main():
         "dtype": "f64" if args.value_type == "f64" else "f32-values/f64-accumulate", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_upper": m.nnz,
                    "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
-                   "window_max": args.window, "phases": launches, "leaves": st["n_leaves"], "eta": st["eta"]},
+                   "window_max": args.window, "exec_mode": args.exec_mode, "phases": launches, "leaves": st["n_leaves"], "eta": st["eta"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "launches_per_step": launches,

@@ -60,7 +60,8 @@ typedef struct {
   double eps[8];         /* eps_s per stage (stages past 7 use eps[7]); each in [0, 1) */
   const float* cost_model; /* host: weights of the cost-model network (balance_by == 2), else NULL */
   int32_t cost_model_len;  /* number of floats in cost_model */
-  int32_t reserved;
+  int32_t exec_mode;       /* 0: one launch per phase; 1: one persistent dataflow launch (units wait only for the
+                              earlier units they conflict with) */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */
@@ -88,11 +89,14 @@ typedef struct {
   int64_t bytes_min;         /* 12 nnz_u + 20 N + 4: minimum bytes of one product in upper CRS with FP64 values */
   int64_t bytes_kernel;      /* bytes one product of the RACE kernel moves by its own format, counted once each */
   int64_t device_bytes;      /* device memory held by the schedule */
+  int64_t n_deps;            /* conflict edges between units (dataflow mode) */
+  int32_t flow_grid;         /* workgroups of the dataflow launch (0 before the first dataflow product) */
+  int32_t exec_mode;
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
  * nonzeros, no global pass, float64 values, window 4096, 256 threads,
- * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice). */
+ * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice), exec_mode 1. */
 int race_params_default(race_params* p);
 
 /* Build the RACE schedule and the kernel's data layout on the host.
@@ -140,12 +144,21 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
 
 /* y = A x (Algorithm "SymmSpMV"): x, y device float64 arrays of n in
  * permuted order, y overwritten (no clearing needed), x and y must not
- * overlap.  One launch per non-empty phase on `stream`, in phase order. */
+ * overlap.  exec_mode 0: one launch per non-empty phase on `stream`, in
+ * phase order; exec_mode 1: one persistent launch in which every unit waits
+ * only for the earlier units whose touch sets meet its own.  Products on
+ * one schedule must be ordered (one stream, or synchronised): they share the
+ * schedule's dataflow state. */
 int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream);
 
 /* Y = A X for k right-hand sides, X and Y device float64 row-major n x k
  * (k in 1..16), permuted order, Y overwritten. */
 int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream);
+
+/* Synchronise the device and report the dataflow status: RACE_EINTERNAL if a
+ * bounded wait of a dataflow product gave up since the last check (the
+ * product's result is then not reliable); clears the status. */
+int race_schedule_check(race_schedule_t s);
 
 /* Reorder device float64 row-major n x k arrays between input order and the
  * permuted order: to_permuted != 0: out[i] = in[new2old[i]]; else

@@ -11,7 +11,7 @@ from __future__ import annotations
 
 from . import _lib
 from ._lib import (RaceError, race_atomic_create, race_build_schedule, race_csr_create, race_csr_destroy,
-                   race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_destroy,
+                   race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_symm_spmm, race_symm_spmv,
                    race_symm_spmv_atomic)
@@ -20,7 +20,7 @@ BALANCE = {"nnz": 0, "rows": 1}
 
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=4096,
-                block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5)):
+                block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow"):
     p = race_params_default()
     p.n_workers = int(n_workers)
     p.max_stages = int(max_stages)
@@ -29,6 +29,7 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.value_type = {"f64": 0, "f32": 1}[value_type]
     p.window_max = int(window_max)
     p.block_threads = int(block_threads)
+    p.exec_mode = {"phases": 0, "flow": 1}[exec_mode]
     eps = list(eps) + [eps[-1]] * (8 - len(eps))
     for i in range(8):
         p.eps[i] = float(eps[i])
@@ -47,6 +48,9 @@ class Schedule:
 
     def upload(self):
         race_schedule_upload(self.handle)
+
+    def check(self):
+        race_schedule_check(self.handle)
 
     def stats(self):
         return race_schedule_stats(self.handle)

@@ -24,7 +24,7 @@ ERRORS = {-1: "RACE_EINVAL", -2: "RACE_ENOMEM", -3: "RACE_EHIP", -4: "RACE_EUNSU
 EXPORTS = [
     "race_params_default", "race_build_schedule", "race_schedule_upload", "race_schedule_destroy",
     "race_schedule_stats", "race_schedule_perm", "race_schedule_tree", "race_schedule_leaves",
-    "race_schedule_units", "race_symm_spmv", "race_symm_spmm", "race_permute", "race_csr_create",
+    "race_schedule_units", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_permute", "race_csr_create",
     "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
 ]
 
@@ -41,7 +41,7 @@ class race_params(ctypes.Structure):
         ("balance_by", ctypes.c_int32), ("global_lb", ctypes.c_int32), ("value_type", ctypes.c_int32),
         ("window_max", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("eps", ctypes.c_double * 8),
         ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("exec_mode", ctypes.c_int32),
     ]
 
 
@@ -54,7 +54,8 @@ class race_stats(ctypes.Structure):
         ("nnz_upper", ctypes.c_int64), ("nnz_full", ctypes.c_int64), ("n_diag", ctypes.c_int64),
         ("sell_elems", ctypes.c_int64), ("halo_total", ctypes.c_int64), ("rows_rmw", ctypes.c_int64),
         ("halo_rmw", ctypes.c_int64), ("bytes_min", ctypes.c_int64), ("bytes_kernel", ctypes.c_int64),
-        ("device_bytes", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
+        ("exec_mode", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -87,6 +88,7 @@ def lib():
         "race_schedule_tree": ([_P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
         "race_schedule_leaves": ([_P, _I32P, _I32P, _I32P], ctypes.c_int),
         "race_schedule_units": ([_P, _I32P, _I64P, _I32P, _I32P, _I32P, _I64P, _I32P, _U8P, _U8P], ctypes.c_int),
+        "race_schedule_check": ([_P], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_permute": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
@@ -216,6 +218,10 @@ def race_schedule_units(h, n):
                                     _np_ptr(hfirst, ctypes.c_uint8), _np_ptr(rfirst, ctypes.c_uint8)))
     return {"unit_leaf": unit_leaf, "lo": lo, "hi": hi, "halo_ptr": hptr, "halo": halo, "halo_first": hfirst,
             "row_first": rfirst}
+
+
+def race_schedule_check(h):
+    check(lib().race_schedule_check(h))
 
 
 def race_symm_spmv(h, x, y, stream=None):

@@ -82,7 +82,11 @@ struct race_schedule {
   bool has_values = false;
   bool uploaded = false;
   int device = -1;
-  DevBuf<int32_t> leaf_unit_ptr, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old;
+  DevBuf<int32_t> leaf_unit_ptr, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old, dep_ptr, dep_idx;
+  DevBuf<uint32_t> flow_state;  // done[n_units], status, padding, counter (64-bit, 8-byte aligned)
+  uint32_t epoch = 0;
+  uint64_t ticket_next = 0;
+  int32_t n_cus = 0;
   DevBuf<uint32_t> halo, row_first_bits, chunk_off;
   DevBuf<uint16_t> lane_slot, sell_slot;
   DevBuf<double> lane_diag64, sell_val64;
@@ -92,7 +96,7 @@ struct race_schedule {
     release(leaf_unit_ptr); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
     release(chunk_len); release(new2old); release(halo); release(row_first_bits); release(chunk_off);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
-    release(sell_val32);
+    release(sell_val32); release(dep_ptr); release(dep_idx); release(flow_state);
     uploaded = false;
   }
 };
@@ -125,6 +129,7 @@ int race_params_default(race_params* p) {
   for (int i = 0; i < 8; ++i) p->eps[i] = eps[i];
   p->cost_model = nullptr;
   p->cost_model_len = 0;
+  p->exec_mode = 1;
   return RACE_OK;
 }
 
@@ -141,6 +146,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (prm.balance_by < 0 || prm.balance_by > 1)
     return fail(RACE_EUNSUPPORTED, "balance_by must be 0 (nonzeros) or 1 (rows)");
   if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
+  if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
   if (prm.window_max == 0) prm.window_max = 4096;
   if (prm.window_max < 2 || prm.window_max > 10240) return fail(RACE_EINVAL, "window_max must be in 2..10240");
   if (prm.block_threads == 0) prm.block_threads = 256;
@@ -214,6 +220,9 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
                       8 * (static_cast<int64_t>(n) + st.halo_total) + 8 * (static_cast<int64_t>(n) + st.halo_total) +
                       8 * (st.rows_rmw + st.halo_rmw);
     st.device_bytes = 0;
+    st.n_deps = static_cast<int64_t>(L.dep_idx.size());
+    st.flow_grid = 0;
+    st.exec_mode = prm.exec_mode;
   } catch (const std::bad_alloc&) {
     delete s;
     return fail(RACE_ENOMEM, "out of host memory while building the schedule");
@@ -252,6 +261,19 @@ int race_schedule_upload(race_schedule_t s) {
   UP(chunk_off, L.chunk_off)
   UP(lane_slot, L.lane_slot)
   UP(sell_slot, L.sell_slot)
+  UP(dep_ptr, L.dep_ptr)
+  UP(dep_idx, L.dep_idx)
+  {
+    // done[] per unit, then status, then an aligned 64-bit counter
+    const size_t words = (L.unit_lo.size() + 2 + 1) / 2 * 2 + 2;
+    std::vector<uint32_t> zeros(words, 0u);
+    UP(flow_state, zeros)
+  }
+  e = hipDeviceGetAttribute(&s->n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    s->free_device();
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
   if (s->params.value_type == 0) {
     UP(lane_diag64, L.lane_diag)
     UP(sell_val64, L.sell_val)
@@ -338,35 +360,96 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
   return RACE_OK;
 }
 
+}  // extern "C"
+
+template <typename ValT>
+static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const ValT* vals) {
+  return race::UnitArgs<ValT>{s->leaf_unit_ptr.p, s->unit_lo.p,    s->unit_hi.p,        s->unit_halo_ptr.p,
+                              s->halo.p,          s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p,
+                              s->chunk_len.p,     s->lane_slot.p,  diag,                vals,
+                              s->sell_slot.p};
+}
+
+template <typename ValT>
+static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
+                    hipStream_t st) {
+  const race::Layout& L = s->L;
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  if (n_units == 0) return RACE_OK;
+  const int32_t wmax = std::max(1, L.max_window);
+  int32_t per_cu = 0;
+  hipError_t e = race::race_flow_occupancy<ValT>(k, s->params.block_threads, wmax, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (per_cu < 1) return fail(RACE_EUNSUPPORTED, "dataflow kernel does not fit a CU with this window and block size");
+  const int32_t grid = std::max(1, std::min(n_units, per_cu * s->n_cus));
+  uint32_t* base = s->flow_state.p;
+  const size_t counter_word = s->flow_state.count - 2;
+  race::FlowArgs f{s->dep_ptr.p, s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word),
+                   base + n_units, n_units};
+  s->epoch += 1;
+  if (s->epoch == 0) {  // wrapped: every done flag must differ from the new epoch
+    e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_units, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    s->epoch = 1;
+  }
+  const uint64_t ticket_base = s->ticket_next;
+  s->ticket_next += static_cast<uint64_t>(n_units) + static_cast<uint64_t>(grid);
+  s->stats.flow_grid = grid;
+  e = race::launch_race_flow<ValT>(a, f, k, x, y, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
+  if (e != hipSuccess) return hip_fail(e, "RACE dataflow launch");
+  return RACE_OK;
+}
+
+template <typename ValT>
+static int run_phases(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
+                      hipStream_t st) {
+  const race::Layout& L = s->L;
+  for (int32_t ph = 0; ph < s->tree.n_phases; ++ph) {
+    const int32_t l0 = L.phase_leaf_ptr[ph], l1 = L.phase_leaf_ptr[ph + 1];
+    if (l1 == l0) continue;
+    const int32_t wmax = std::max(1, L.phase_max_window[ph]);
+    hipError_t e = race::launch_race_phase<ValT>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, st);
+    if (e != hipSuccess) return hip_fail(e, "RACE phase launch");
+  }
+  return RACE_OK;
+}
+
 static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, void* stream) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
   if (s->tree.n == 0) return RACE_OK;
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
-  const size_t lds_limit = 160 * 1024;
+  const size_t lds_limit = 159 * 1024;  // dynamic windows plus the kernels' own few bytes
+  const int32_t wmax = std::max(1, s->L.max_window);
+  if (2 * static_cast<size_t>(wmax) * k * sizeof(double) > lds_limit)
+    return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
+                                       " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const race::Layout& L = s->L;
-  for (int32_t ph = 0; ph < s->tree.n_phases; ++ph) {
-    const int32_t l0 = L.phase_leaf_ptr[ph], l1 = L.phase_leaf_ptr[ph + 1];
-    if (l1 == l0) continue;
-    const int32_t wmax = std::max(1, L.phase_max_window[ph]);
-    if (2 * static_cast<size_t>(wmax) * k * sizeof(double) > lds_limit)
-      return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
-                                         " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
-    hipError_t e;
-    if (s->params.value_type == 0) {
-      race::UnitArgs<double> a{s->leaf_unit_ptr.p, s->unit_lo.p, s->unit_hi.p, s->unit_halo_ptr.p, s->halo.p,
-                               s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p, s->chunk_len.p,
-                               s->lane_slot.p, s->lane_diag64.p, s->sell_val64.p, s->sell_slot.p};
-      e = race::launch_race_phase<double>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, st);
-    } else {
-      race::UnitArgs<float> a{s->leaf_unit_ptr.p, s->unit_lo.p, s->unit_hi.p, s->unit_halo_ptr.p, s->halo.p,
-                              s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p, s->chunk_len.p,
-                              s->lane_slot.p, s->lane_diag32.p, s->sell_val32.p, s->sell_slot.p};
-      e = race::launch_race_phase<float>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, st);
-    }
-    if (e != hipSuccess) return hip_fail(e, "RACE phase launch");
+  if (s->params.value_type == 0) {
+    const auto a = unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p);
+    return s->params.exec_mode == 1 ? run_flow<double>(s, a, k, x, y, st) : run_phases<double>(s, a, k, x, y, st);
+  }
+  const auto a = unit_args<float>(s, s->lane_diag32.p, s->sell_val32.p);
+  return s->params.exec_mode == 1 ? run_flow<float>(s, a, k, x, y, st) : run_phases<float>(s, a, k, x, y, st);
+}
+
+extern "C" {
+
+int race_schedule_check(race_schedule_t s) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!s->uploaded) return RACE_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  const int32_t n_units = static_cast<int32_t>(s->L.unit_lo.size());
+  uint32_t status = 0;
+  e = hipMemcpy(&status, s->flow_state.p + n_units, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (status) {
+    const uint32_t zero = 0;
+    e = hipMemcpy(s->flow_state.p + n_units, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    return fail(RACE_EINTERNAL, "a dataflow wait gave up (bounded spin exceeded)");
   }
   return RACE_OK;
 }

@@ -25,11 +25,33 @@ struct UnitArgs {
   const uint16_t* sell_slot;
 };
 
+// Dataflow state of one schedule: conflict edges between units (CSR over
+// units, every edge pointing to a smaller unit), per-unit completion epochs,
+// the ticket counter and a status word (bit 0: a bounded wait gave up).
+struct FlowArgs {
+  const int32_t* dep_ptr;
+  const int32_t* dep_idx;
+  uint32_t* done;
+  uint64_t* counter;
+  uint32_t* status;
+  int32_t n_units;
+};
+
 // One phase: n_leaves workgroups starting at leaf_base; k right-hand sides
 // (1..16) in row-major x/y; wmax = largest unit window of the phase.
 template <typename ValT>
 hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, int32_t k, const double* x,
                              double* y, int32_t wmax, int32_t threads, hipStream_t st);
+
+// Whole product in one persistent launch of `grid` workgroups; epoch and
+// ticket_base identify the call (see race_flow_kernel).
+template <typename ValT>
+hipError_t launch_race_flow(const UnitArgs<ValT>& a, const FlowArgs& f, int32_t k, const double* x, double* y,
+                            int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
+                            hipStream_t st);
+
+template <typename ValT>
+hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu);
 
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                            double* y, int32_t lanes_per_row, hipStream_t st);

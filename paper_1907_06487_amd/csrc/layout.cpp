@@ -210,6 +210,33 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
       else ++L.halo_rmw;
     }
   }
+  // conflict edges: for every index, each unit touching it waits for the
+  // previous unit (in execution order) that touched it
+  {
+    std::vector<int32_t> last_unit(static_cast<size_t>(n), -1);
+    std::vector<int32_t> deps;
+    L.dep_ptr.assign(1, 0);
+    for (int32_t u = 0; u < n_units; ++u) {
+      deps.clear();
+      auto touch = [&](int32_t g) {
+        if (last_unit[g] >= 0) deps.push_back(last_unit[g]);
+        last_unit[g] = u;
+      };
+      for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) touch(g);
+      for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j)
+        touch(static_cast<int32_t>(L.halo[j] & 0x7fffffffu));
+      std::sort(deps.begin(), deps.end());
+      deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+      for (int32_t v : deps) {
+        if (v >= u) {
+          *code = RACE_EINTERNAL;
+          return "conflict edge does not point to an earlier unit";
+        }
+        L.dep_idx.push_back(v);
+      }
+      L.dep_ptr.push_back(static_cast<int32_t>(L.dep_idx.size()));
+    }
+  }
   L.halo_total = static_cast<int64_t>(L.halo.size());
   L.phase_max_window.assign(static_cast<size_t>(tree.n_phases), 0);
   for (int32_t u = 0; u < n_units; ++u) {

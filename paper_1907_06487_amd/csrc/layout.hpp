@@ -46,6 +46,9 @@ struct Layout {
   std::vector<double> sell_val;         // padded slice elements
   std::vector<uint16_t> sell_slot;
   std::vector<int32_t> phase_max_window;  // per phase, largest unit window
+  // conflict edges for dataflow execution: unit u waits for dep_idx[dep_ptr[u]
+  // .. dep_ptr[u+1]), the latest earlier units touching each of its indices
+  std::vector<int32_t> dep_ptr, dep_idx;
 
   int32_t max_window = 0;
   int64_t halo_total = 0, rows_rmw = 0, halo_rmw = 0;

@@ -2,6 +2,7 @@
 // global-atomic SymmSpMV baselines, and the permutation kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -11,17 +12,226 @@ namespace dev {
 
 constexpr int kSlice = 64;
 constexpr uint16_t kNoRow = 0xFFFF;
+constexpr int kBatch = 16;               // slots per lane loaded before any arithmetic
+constexpr uint32_t kSpinLimit = 1u << 16;  // bounded wait (milliseconds), then report and go on
 
-// One workgroup runs one leaf of a phase: the leaf's units in order.  For a
-// unit with own rows [lo, lo + R) and halo list h[0..H):
-//   1. x window  xw[s] = x[row of slot s], y window yw[s] = 0   (LDS)
-//   2. every 64-row slice is taken by one wavefront, one row per lane:
+// One slice descriptor as held in registers by a wavefront.
+template <typename ValT>
+struct SliceRegs {
+  int32_t len = 0, width = 0;
+  uint32_t off = 0;
+  uint16_t rs = kNoRow;
+  double d = 0.0;
+  double v[kBatch];
+  int32_t sl[kBatch];
+};
+
+template <typename ValT>
+__device__ __forceinline__ void load_slice_head(const UnitArgs<ValT>& a, int32_t c, int32_t lane, SliceRegs<ValT>& r) {
+  const int32_t meta = a.chunk_len[c];
+  r.len = meta & 0xFFFF;
+  r.width = meta >> 16;
+  r.off = a.chunk_off[c];
+  r.rs = a.lane_slot[static_cast<size_t>(c) * kSlice + lane];
+  r.d = static_cast<double>(a.lane_diag[static_cast<size_t>(c) * kSlice + lane]);
+}
+
+template <typename ValT>
+__device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane, int32_t j0, SliceRegs<ValT>& r) {
+  const bool active = r.rs != kNoRow;
+  const ValT* vp = a.sell_val + r.off + lane;
+  const uint16_t* sp = a.sell_slot + r.off + lane;
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b) {
+    const int32_t j = j0 + b;
+    if (active && j < r.len) {
+      r.v[b] = static_cast<double>(vp[j * r.width]);
+      r.sl[b] = sp[j * r.width];
+    } else {
+      r.v[b] = 0.0;
+      r.sl[b] = 0;
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void apply_batch(const double* v, const int32_t* sl, const double* xw, double* yw,
+                                            const double (&xr)[K], double (&acc)[K]) {
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b) {
+    if (v[b] != 0.0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        acc[k] += v[b] * xw[sl[b] * K + k];
+        atomicAdd(&yw[sl[b] * K + k], v[b] * xr[k]);
+      }
+    }
+  }
+}
+
+// One unit with own rows [lo, lo + R) and halo list h[0..H), on one
+// workgroup:
+//   1. x window  xw[s] = x[row of slot s], y window yw[s] = 0   (LDS);
+//      each wavefront's first slice is already being fetched meanwhile
+//   2. every slice (up to 64 rows) is taken by one wavefront, one row per
+//      lane:
 //        acc  = diag * x[r] + sum_j v_j * xw[slot_j]      (the gather)
 //        yw[slot_j] += v_j * x[r]  for every j           (the scatter, LDS atomics)
 //        yw[slot_r] += acc
 //   3. flush the window: y[g] = yw[s] when this unit is the first writer of
-//      y[g], else y[g] += yw[s].  Units of one phase never share an index
-//      (distance-2 coloring), so the flush needs no global atomics.
+//      y[g], else y[g] += yw[s].  Units that may run at the same time never
+//      share an index (distance-2 coloring), so the flush needs no global
+//      atomics.
+template <typename ValT, int K>
+__device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u, const double* __restrict__ x,
+                                             double* xw, double* yw, int32_t tid, int32_t nthr) {
+  constexpr int kStage = K >= 4 ? 1 : 4;  // window entries per thread per staging round
+  const int32_t lane = tid & (kSlice - 1), wave = tid / kSlice, nwaves = nthr / kSlice;
+  const int32_t lo = a.unit_lo[u];
+  const int32_t R = a.unit_hi[u] - lo;
+  const int32_t h0 = a.unit_halo_ptr[u];
+  const int32_t W = R + (a.unit_halo_ptr[u + 1] - h0);
+  const int32_t c1 = a.unit_chunk_ptr[u + 1];
+  int32_t c = a.unit_chunk_ptr[u] + wave;
+  SliceRegs<ValT> cur;
+  if (c < c1) {
+    load_slice_head(a, c, lane, cur);
+    load_batch(a, lane, 0, cur);
+  }
+  // 1. stage the windows while the first slice is in flight
+  for (int32_t base = 0; base < W; base += kStage * nthr) {
+    int32_t g[kStage];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int32_t s = base + q * nthr + tid;
+      g[q] = s < R ? lo + s : (s < W ? static_cast<int32_t>(a.halo[h0 + s - R] & 0x7fffffffu) : -1);
+    }
+    double xv[kStage][K];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q)
+#pragma unroll
+      for (int k = 0; k < K; ++k) xv[q][k] = g[q] >= 0 ? x[static_cast<size_t>(g[q]) * K + k] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int32_t s = base + q * nthr + tid;
+      if (s < W) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          xw[s * K + k] = xv[q][k];
+          yw[s * K + k] = 0.0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // 2. slices: the next slice's descriptor is in flight during this slice's
+  // arithmetic, its elements are requested right after
+  while (c < c1) {
+    const int32_t cn = c + nwaves;
+    int32_t meta_n = 0;
+    uint32_t off_n = 0;
+    uint16_t rs_n = kNoRow;
+    ValT d_n = ValT(0);
+    if (cn < c1) {
+      meta_n = a.chunk_len[cn];
+      off_n = a.chunk_off[cn];
+      rs_n = a.lane_slot[static_cast<size_t>(cn) * kSlice + lane];
+      d_n = a.lane_diag[static_cast<size_t>(cn) * kSlice + lane];
+    }
+    if (cur.rs != kNoRow) {
+      double xr[K], acc[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        xr[k] = xw[cur.rs * K + k];
+        acc[k] = cur.d * xr[k];
+      }
+      apply_batch<K>(cur.v, cur.sl, xw, yw, xr, acc);
+      for (int32_t j0 = kBatch; j0 < cur.len; j0 += kBatch) {
+        load_batch(a, lane, j0, cur);
+        apply_batch<K>(cur.v, cur.sl, xw, yw, xr, acc);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) atomicAdd(&yw[cur.rs * K + k], acc[k]);
+    }
+    if (cn < c1) {
+      cur.len = meta_n & 0xFFFF;
+      cur.width = meta_n >> 16;
+      cur.off = off_n;
+      cur.rs = rs_n;
+      cur.d = static_cast<double>(d_n);
+      load_batch(a, lane, 0, cur);
+    }
+    c = cn;
+  }
+  __syncthreads();
+}
+
+// y entries that another workgroup may later read back go through
+// agent-scope relaxed atomic loads and stores when kCoherent: on this
+// architecture those bypass the non-coherent per-XCD caches, so a unit that
+// waited for a predecessor's completion flag reads the predecessor's y
+// without any cache-wide writeback or invalidation.
+template <bool kCoherent>
+__device__ __forceinline__ double y_load(const double* p) {
+  if constexpr (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+
+template <bool kCoherent>
+__device__ __forceinline__ void y_store(double* p, double v) {
+  if constexpr (kCoherent) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+// Step 3 of a unit: flush the y window.  y[g] = yw[s] when this unit is the
+// first writer of y[g], else y[g] += yw[s].  Units that may run at the same
+// time never share an index (distance-2 coloring), so no global atomics.
+template <typename ValT, int K, bool kCoherent>
+__device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, double* __restrict__ y,
+                                           const double* yw, int32_t tid, int32_t nthr) {
+  constexpr int kStage = K >= 4 ? 1 : 4;
+  const int32_t lo = a.unit_lo[u];
+  const int32_t R = a.unit_hi[u] - lo;
+  const int32_t h0 = a.unit_halo_ptr[u];
+  const int32_t W = R + (a.unit_halo_ptr[u + 1] - h0);
+  for (int32_t base = 0; base < W; base += kStage * nthr) {
+    int32_t g[kStage];
+    bool first[kStage];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int32_t s = base + q * nthr + tid;
+      if (s < R) {
+        g[q] = lo + s;
+        first[q] = (a.row_first_bits[g[q] >> 5] >> (g[q] & 31)) & 1u;
+      } else if (s < W) {
+        const uint32_t h = a.halo[h0 + s - R];
+        g[q] = static_cast<int32_t>(h & 0x7fffffffu);
+        first[q] = (h >> 31) != 0u;
+      } else {
+        g[q] = -1;
+        first[q] = true;
+      }
+    }
+    double old[kStage][K];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        old[q][k] = (g[q] >= 0 && !first[q]) ? y_load<kCoherent>(y + static_cast<size_t>(g[q]) * K + k) : 0.0;
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int32_t s = base + q * nthr + tid;
+      if (g[q] >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          y_store<kCoherent>(y + static_cast<size_t>(g[q]) * K + k, old[q][k] + yw[s * K + k]);
+      }
+    }
+  }
+}
+
+// Phase-by-phase execution: one launch per phase, one workgroup per leaf
+// running the leaf's units in order.
 template <typename ValT, int K>
 __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32_t leaf_base,
                                                          const double* __restrict__ x, double* __restrict__ y,
@@ -32,70 +242,75 @@ __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32
   const int32_t leaf = leaf_base + static_cast<int32_t>(blockIdx.x);
   const int32_t u0 = a.leaf_unit_ptr[leaf], u1 = a.leaf_unit_ptr[leaf + 1];
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
-  const int32_t lane = tid & (kSlice - 1), wave = tid / kSlice, nwaves = nthr / kSlice;
   for (int32_t u = u0; u < u1; ++u) {
-    const int32_t lo = a.unit_lo[u];
-    const int32_t R = a.unit_hi[u] - lo;
-    const int32_t h0 = a.unit_halo_ptr[u];
-    const int32_t W = R + (a.unit_halo_ptr[u + 1] - h0);
-    for (int32_t s = tid; s < W; s += nthr) {
-      const int32_t g = s < R ? lo + s : static_cast<int32_t>(a.halo[h0 + s - R] & 0x7fffffffu);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        xw[s * K + k] = x[static_cast<size_t>(g) * K + k];
-        yw[s * K + k] = 0.0;
+    compute_unit<ValT, K>(a, u, x, xw, yw, tid, nthr);
+    flush_unit<ValT, K, false>(a, u, y, yw, tid, nthr);
+    __syncthreads();
+  }
+}
+
+// Dataflow execution in one persistent launch.  Units are taken in the
+// schedule's order (phase, leaf, unit) from a ticket counter; a unit first
+// waits until every earlier unit whose touch set meets its own has
+// published completion (the conflict edges of the tree's coloring), then
+// runs and publishes.  Only y crosses units, and it does so through
+// coherent (agent-scope atomic) accesses whose completion each thread
+// awaits before the publishing barrier; x and the matrix are read-only.  Waits only point to smaller tickets, which were
+// handed to running workgroups, so the lowest unfinished ticket can always
+// proceed; every wait is bounded and reports through `status` if it gives
+// up, so the grid always drains.
+template <typename ValT, int K>
+__global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowArgs f, const double* __restrict__ x,
+                                                         double* __restrict__ y, int32_t wmax, uint32_t epoch,
+                                                         uint64_t ticket_base) {
+  extern __shared__ double smem[];
+  double* xw = smem;
+  double* yw = smem + static_cast<size_t>(wmax) * K;
+  __shared__ int32_t s_unit;
+  const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
+  // wave 0 as a scalar condition: the lane-0 work below sits in small
+  // diamonds inside a wave-uniform branch, and barriers close them on both
+  // sides, so no lane can run ahead into the next unit's barriers
+  const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < kSlice;
+  for (;;) {
+    __syncthreads();
+    if (wave0) {
+      if (tid == 0) {
+        const uint64_t t = atomicAdd(reinterpret_cast<unsigned long long*>(f.counter), 1ull) - ticket_base;
+        s_unit = t < static_cast<uint64_t>(f.n_units) ? static_cast<int32_t>(t) : -1;
       }
     }
     __syncthreads();
-    const int32_t c1 = a.unit_chunk_ptr[u + 1];
-    for (int32_t c = a.unit_chunk_ptr[u] + wave; c < c1; c += nwaves) {
-      const uint16_t rs = a.lane_slot[static_cast<size_t>(c) * kSlice + lane];
-      if (rs != kNoRow) {
-        const int32_t meta = a.chunk_len[c];
-        const int32_t len = meta & 0xFFFF, width = meta >> 16;
-        const ValT* vp = a.sell_val + a.chunk_off[c] + lane;
-        const uint16_t* sp = a.sell_slot + a.chunk_off[c] + lane;
-        const double d = static_cast<double>(a.lane_diag[static_cast<size_t>(c) * kSlice + lane]);
-        double xr[K], acc[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          xr[k] = xw[rs * K + k];
-          acc[k] = d * xr[k];
+    // the same value in every lane; read into a scalar register so the loop's
+    // exit and the barriers below stay in uniform control flow
+    const int32_t u = __builtin_amdgcn_readfirstlane(s_unit);
+    if (u < 0) break;
+    // the unit's arithmetic needs nothing from other units; only its flush
+    // must follow the earlier units it conflicts with
+    compute_unit<ValT, K>(a, u, x, xw, yw, tid, nthr);
+    const int32_t d0 = f.dep_ptr[u], d1 = f.dep_ptr[u + 1];
+    for (int32_t i = d0 + tid; i < d1; i += nthr) {
+      const int32_t v = f.dep_idx[i];
+      uint32_t spins = 0;
+      while (__hip_atomic_load(f.done + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(f.status, 1u);
+          break;
         }
-        for (int32_t j = 0; j < len; ++j) {
-          const double v = static_cast<double>(vp[j * width]);
-          const int32_t s = sp[j * width];
-          if (v != 0.0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-              acc[k] += v * xw[s * K + k];
-              atomicAdd(&yw[s * K + k], v * xr[k]);
-            }
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) atomicAdd(&yw[rs * K + k], acc[k]);
       }
     }
     __syncthreads();
-    for (int32_t s = tid; s < W; s += nthr) {
-      int32_t g;
-      bool first;
-      if (s < R) {
-        g = lo + s;
-        first = (a.row_first_bits[g >> 5] >> (g & 31)) & 1u;
-      } else {
-        const uint32_t h = a.halo[h0 + s - R];
-        g = static_cast<int32_t>(h & 0x7fffffffu);
-        first = (h >> 31) != 0u;
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        double* dst = y + static_cast<size_t>(g) * K + k;
-        *dst = first ? yw[s * K + k] : *dst + yw[s * K + k];
-      }
-    }
+    flush_unit<ValT, K, true>(a, u, y, yw, tid, nthr);
+    // every thread's coherent y stores complete before the barrier, so the
+    // completion flag written after it is only seen once they are visible
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
+    if (wave0) {
+      if (tid == 0) __hip_atomic_store(f.done + u, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -163,40 +378,108 @@ __global__ void __launch_bounds__(256) permute_kernel(int32_t n, int32_t k, cons
 // launchers
 
 template <typename ValT, int K>
+static hipError_t set_lds_attr(const void* fn) {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+template <typename ValT, int K>
 static hipError_t launch_leaf(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, const double* x, double* y,
                               int32_t wmax, int32_t threads, hipStream_t st) {
   const size_t lds = 2 * static_cast<size_t>(wmax) * K * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::race_leaf_kernel<ValT, K>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = set_lds_attr<ValT, K>(reinterpret_cast<const void*>(&dev::race_leaf_kernel<ValT, K>));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((dev::race_leaf_kernel<ValT, K>), dim3(n_leaves), dim3(threads), lds, st, a, leaf_base, x, y,
                      wmax);
   return hipGetLastError();
 }
 
+template <typename ValT, int K>
+struct FlowTag {};
+
+template <typename ValT, int K>
+static hipError_t launch_flow(const UnitArgs<ValT>& a, const FlowArgs& f, const double* x, double* y, int32_t wmax,
+                              int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base, hipStream_t st) {
+  const size_t lds = 2 * static_cast<size_t>(wmax) * K * sizeof(double);
+  hipError_t e = set_lds_attr<FlowTag<ValT, K>, K>(reinterpret_cast<const void*>(&dev::race_flow_kernel<ValT, K>));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((dev::race_flow_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, a, f, x, y, wmax, epoch,
+                     ticket_base);
+  return hipGetLastError();
+}
+
+// Workgroups of the dataflow kernel one CU holds at once, from the kernel's
+// registers and static LDS, the dynamic windows, 160 KB of LDS and 32
+// wavefronts per CU (512 VGPRs per SIMD lane, allocated in blocks of 8).
+// Only the launch size depends on it: the dataflow scheme itself needs no
+// co-residency.
+template <typename ValT, int K>
+static hipError_t flow_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_per_cu) {
+  const size_t lds = 2 * static_cast<size_t>(wmax) * K * sizeof(double);
+  hipFuncAttributes attr{};
+  hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&dev::race_flow_kernel<ValT, K>));
+  int32_t regs = 128, static_lds = 64;
+  if (e == hipSuccess) {
+    regs = std::max(attr.numRegs, 1);
+    static_lds = static_cast<int32_t>(attr.sharedSizeBytes);
+  } else {
+    (void)hipGetLastError();
+  }
+  const int32_t waves_per_block = std::max(1, threads / 64);
+  const int32_t regs_rounded = (regs + 7) / 8 * 8;
+  const int32_t waves_per_simd = std::max(1, std::min(8, 512 / regs_rounded));
+  const int32_t by_waves = (4 * waves_per_simd) / waves_per_block;
+  const int32_t by_lds = static_cast<int32_t>((160 * 1024) / (lds + static_cast<size_t>(static_lds) + 1));
+  *blocks_per_cu = std::max(0, std::min(by_waves, by_lds));
+  return hipSuccess;
+}
+
+#define RACE_K_SWITCH(CALL)                                                                              \
+  switch (k) {                                                                                           \
+    case 1: return CALL(1);   case 2: return CALL(2);   case 3: return CALL(3);   case 4: return CALL(4); \
+    case 5: return CALL(5);   case 6: return CALL(6);   case 7: return CALL(7);   case 8: return CALL(8); \
+    case 9: return CALL(9);   case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12); \
+    case 13: return CALL(13); case 14: return CALL(14); case 15: return CALL(15); case 16: return CALL(16); \
+    default: return hipErrorInvalidValue;                                                                \
+  }
+
 template <typename ValT>
 hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, int32_t k, const double* x,
                              double* y, int32_t wmax, int32_t threads, hipStream_t st) {
-  switch (k) {
-#define RACE_K(KK) \
-  case KK:         \
-    return launch_leaf<ValT, KK>(a, leaf_base, n_leaves, x, y, wmax, threads, st);
-    RACE_K(1) RACE_K(2) RACE_K(3) RACE_K(4) RACE_K(5) RACE_K(6) RACE_K(7) RACE_K(8)
-    RACE_K(9) RACE_K(10) RACE_K(11) RACE_K(12) RACE_K(13) RACE_K(14) RACE_K(15) RACE_K(16)
-#undef RACE_K
-    default:
-      return hipErrorInvalidValue;
-  }
+#define CALL(KK) launch_leaf<ValT, KK>(a, leaf_base, n_leaves, x, y, wmax, threads, st)
+  RACE_K_SWITCH(CALL)
+#undef CALL
+}
+
+template <typename ValT>
+hipError_t launch_race_flow(const UnitArgs<ValT>& a, const FlowArgs& f, int32_t k, const double* x, double* y,
+                            int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
+                            hipStream_t st) {
+#define CALL(KK) launch_flow<ValT, KK>(a, f, x, y, wmax, threads, grid, epoch, ticket_base, st)
+  RACE_K_SWITCH(CALL)
+#undef CALL
+}
+
+template <typename ValT>
+hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu) {
+#define CALL(KK) flow_occupancy<ValT, KK>(threads, wmax, blocks_per_cu)
+  RACE_K_SWITCH(CALL)
+#undef CALL
 }
 
 template hipError_t launch_race_phase<double>(const UnitArgs<double>&, int32_t, int32_t, int32_t, const double*,
                                               double*, int32_t, int32_t, hipStream_t);
 template hipError_t launch_race_phase<float>(const UnitArgs<float>&, int32_t, int32_t, int32_t, const double*,
                                              double*, int32_t, int32_t, hipStream_t);
+template hipError_t launch_race_flow<double>(const UnitArgs<double>&, const FlowArgs&, int32_t, const double*, double*,
+                                             int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
+template hipError_t launch_race_flow<float>(const UnitArgs<float>&, const FlowArgs&, int32_t, const double*, double*,
+                                            int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
+template hipError_t race_flow_occupancy<double>(int32_t, int32_t, int32_t, int32_t*);
+template hipError_t race_flow_occupancy<float>(int32_t, int32_t, int32_t, int32_t*);
 
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                            double* y, int32_t lpr, hipStream_t st) {

@@ -60,6 +60,7 @@ def run_race(m, x, k=1, **params):
             s.spmm(xp, yp)
         s.permute(yp, y, to_permuted=False)
         torch.cuda.synchronize()
+        s.check()
         return y.cpu().numpy(), s.stats()
     finally:
         s.close()
@@ -81,6 +82,12 @@ SMALL = [
      dict(n_workers=4)),
     ("diag_only", lambda: matgen.UpperCSR(7, np.arange(8, dtype=np.int32), np.arange(7, dtype=np.int32),
                                           np.arange(1.0, 8.0)), dict(n_workers=4)),
+    ("2d5pt_100_phases", matgen.config_2d_small, dict(n_workers=64, exec_mode="phases")),
+    ("3d27pt_24_w128_phases", lambda: matgen.stencil3d_27pt(24, seed=5),
+     dict(n_workers=64, window_max=128, exec_mode="phases")),
+    ("banded_40k_phases", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
+     dict(n_workers=256, exec_mode="phases")),
+    ("rand_islands_phases", lambda: matgen.random_symmetric(500, 0.003, seed=8), dict(n_workers=16, exec_mode="phases")),
 ]
 
 
@@ -189,6 +196,7 @@ def test_race_repeated_calls_and_streams():
             s.permute(yp, y, False, stream=st)
             outs.append(y)
     st.synchronize()
+    s.check()
     for y in outs:
         _check(y.cpu().numpy(), y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), "repeat")
     s.close()
@@ -212,13 +220,13 @@ def _sampled_rows_exact(m, x, rows):
     return np.array([math.fsum(t + cols_i[int(i)]) for t, i in zip(out, rows)])
 
 
-@pytest.mark.parametrize("nt", [256, 1024])
-def test_race_full_size_3d27pt_128(nt):
+@pytest.mark.parametrize("nt,mode", [(256, "flow"), (1024, "flow"), (512, "phases")])
+def test_race_full_size_3d27pt_128(nt, mode):
     m = matgen.config_3d_128()
-    print(f"case 3d27pt_128 n_workers={nt}: n={m.n} nnz={m.nnz}", flush=True)
+    print(f"case 3d27pt_128 n_workers={nt} mode={mode}: n={m.n} nnz={m.nnz}", flush=True)
     x = matgen.rhs(m.n, 2)
     y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
-    y, st = run_race(m, x, n_workers=nt)
+    y, st = run_race(m, x, n_workers=nt, exec_mode=mode)
     _check(y, y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), f"3d27pt_128 nt={nt}")
     rows = np.random.default_rng(0).choice(m.n, size=200, replace=False)
     exact = _sampled_rows_exact(m, x, rows)
