@@ -43,6 +43,16 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def kernel_source_hash():
+    """Hash of the sources that decide what the RACE kernel moves."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ["race_kernels.hip", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp", "api.hip"]:
+        with open(os.path.join(ROOT, "paper_1907_06487_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def time_ring(fn, xs, ys, steps, warmup, torch):
     nr = len(xs)
     for i in range(warmup):
@@ -88,12 +98,14 @@ def main():
     ap.add_argument("--n-workers", type=int, default=256)
     ap.add_argument("--max-stages", type=int, default=4)
     ap.add_argument("--block", type=int, default=512)
-    ap.add_argument("--window", type=int, default=4096)
+    ap.add_argument("--window", type=int, default=3840)
     ap.add_argument("--value-type", default="f64", choices=["f64", "f32"])
     ap.add_argument("--exec-mode", default="flow", choices=["flow", "phases"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run a device copy of this many MiB (reference for the traffic counters)")
     ap.add_argument("--sweep", default="",
                     help="n_workers:block[:window[:mode]] list, e.g. 256:256,512:512:2048:phases (stderr)")
     args = ap.parse_args()
@@ -164,6 +176,17 @@ def main():
             f"leaves={st2['n_leaves']} units={st2['n_units']} kernel bytes={st2['bytes_kernel']}")
         s2.close()
 
+    if args.calibrate_copy:
+        # a compute-kernel copy (elementwise multiply by one) of known size,
+        # larger than every cache: the traffic counters' reference
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration: elementwise copy reading and writing {nbytes} bytes, 3 times")
+
     baselines = {}
     if not args.no_baselines:
         rp, c, v = O.expand_full(m.n, m.row_ptr, m.col, m.val)
@@ -200,15 +223,17 @@ def main():
                          f"{dt * 1e3:.1f} ms each"}
         log(f"CPU oracle: {dt * 1e3:.1f} ms/product ({cpu['value']:.3f} GFLOP/s)")
 
+    # HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    # runs, valid only while the kernel, layout and parameters are unchanged
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if os.path.exists(tpath):
-        try:
-            tr = json.load(open(tpath))
-            if tr.get("bytes_kernel") == st["bytes_kernel"] and tr.get("n_workers") == args.n_workers:
-                traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+        tr = json.load(open(tpath))
+        same = (tr.get("source_hash") == kernel_source_hash() and tr.get("bytes_kernel") == st["bytes_kernel"]
+                and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
+                and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode)
+        if same and args.value_type == "f64":
+            traffic = tr.get("bytes_per_launch")
 
     out = {
         "metric": METRIC, "value": round(gflops, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,

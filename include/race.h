@@ -55,7 +55,8 @@ typedef struct {
   int32_t balance_by;    /* 0: nonzeros of the full row, 1: rows, 2: learned cost model (cost_model) */
   int32_t global_lb;     /* 1: run Algorithm "Load Balancing" over all children after the pair split */
   int32_t value_type;    /* 0: float64 matrix values, 1: float32 values (promoted; FP64 accumulation) */
-  int32_t window_max;    /* max LDS window entries (rows + halo) of one unit; 0 = 4096 */
+  int32_t window_max;    /* max LDS window entries (rows + halo) of one unit, 2..8000; 0 = 3840 (20 B of LDS each per
+                            right-hand side pair of x/y plus the index) */
   int32_t block_threads; /* workgroup size of the RACE kernel: 64, 128, 256, 512 or 1024; 0 = 256 */
   double eps[8];         /* eps_s per stage (stages past 7 use eps[7]); each in [0, 1) */
   const float* cost_model; /* host: weights of the cost-model network (balance_by == 2), else NULL */
@@ -92,10 +93,11 @@ typedef struct {
   int64_t n_deps;            /* conflict edges between units (dataflow mode) */
   int32_t flow_grid;         /* workgroups of the dataflow launch (0 before the first dataflow product) */
   int32_t exec_mode;
+  int64_t wall_clock_hz;     /* rate of the device clock used by traced products (set by race_schedule_upload) */
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
- * nonzeros, no global pass, float64 values, window 4096, 256 threads,
+ * nonzeros, no global pass, float64 values, window 3840, 256 threads,
  * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice), exec_mode 1. */
 int race_params_default(race_params* p);
 
@@ -154,6 +156,13 @@ int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream);
 /* Y = A X for k right-hand sides, X and Y device float64 row-major n x k
  * (k in 1..16), permuted order, Y overwritten. */
 int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream);
+
+/* As race_symm_spmm, and record per unit four device wall-clock stamps into
+ * trace (device uint64 array of 4 * n_units, units in execution order):
+ * [0] work taken, [1] arithmetic done, [2] earlier conflicting units done,
+ * [3] y flushed.  Ticks at race_stats.wall_clock_hz.  These per-unit times
+ * are the measurements the cost model learns from. */
+int race_symm_spmm_traced(race_schedule_t s, int32_t k, const double* X, double* Y, uint64_t* trace, void* stream);
 
 /* Synchronise the device and report the dataflow status: RACE_EINTERNAL if a
  * bounded wait of a dataflow product gave up since the last check (the

@@ -13,13 +13,13 @@ from . import _lib
 from ._lib import (RaceError, race_atomic_create, race_build_schedule, race_csr_create, race_csr_destroy,
                    race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
-                   race_schedule_units, race_schedule_upload, race_symm_spmm, race_symm_spmv,
+                   race_schedule_units, race_schedule_upload, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
                    race_symm_spmv_atomic)
 
 BALANCE = {"nnz": 0, "rows": 1}
 
 
-def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=4096,
+def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow"):
     p = race_params_default()
     p.n_workers = int(n_workers)
@@ -72,6 +72,9 @@ class Schedule:
 
     def spmm(self, X, Y, stream=None):
         race_symm_spmm(self.handle, X.shape[1] if X.dim() == 2 else 1, X, Y, stream)
+
+    def traced(self, X, Y, trace, stream=None):
+        race_symm_spmm_traced(self.handle, X.shape[1] if X.dim() == 2 else 1, X, Y, trace, stream)
 
     def permute(self, inp, out, to_permuted=True, stream=None):
         k = inp.shape[1] if inp.dim() == 2 else 1

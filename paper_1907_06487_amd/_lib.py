@@ -24,7 +24,7 @@ ERRORS = {-1: "RACE_EINVAL", -2: "RACE_ENOMEM", -3: "RACE_EHIP", -4: "RACE_EUNSU
 EXPORTS = [
     "race_params_default", "race_build_schedule", "race_schedule_upload", "race_schedule_destroy",
     "race_schedule_stats", "race_schedule_perm", "race_schedule_tree", "race_schedule_leaves",
-    "race_schedule_units", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_permute", "race_csr_create",
+    "race_schedule_units", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
     "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
 ]
 
@@ -55,7 +55,7 @@ class race_stats(ctypes.Structure):
         ("sell_elems", ctypes.c_int64), ("halo_total", ctypes.c_int64), ("rows_rmw", ctypes.c_int64),
         ("halo_rmw", ctypes.c_int64), ("bytes_min", ctypes.c_int64), ("bytes_kernel", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
-        ("exec_mode", ctypes.c_int32),
+        ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -91,6 +91,7 @@ def lib():
         "race_schedule_check": ([_P], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+        "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
         "race_permute": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
         "race_csr_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
         "race_csr_spmv": ([_P, _P, _P, _P], ctypes.c_int),
@@ -230,6 +231,11 @@ def race_symm_spmv(h, x, y, stream=None):
 
 def race_symm_spmm(h, k, X, Y, stream=None):
     check(lib().race_symm_spmm(h, int(k), _dev_ptr(X), _dev_ptr(Y), _stream_ptr(stream)))
+
+
+def race_symm_spmm_traced(h, k, X, Y, trace, stream=None):
+    """trace: device int64 tensor of 4 * n_units (stamps are unsigned ticks)."""
+    check(lib().race_symm_spmm_traced(h, int(k), _dev_ptr(X), _dev_ptr(Y), _dev_ptr(trace), _stream_ptr(stream)))
 
 
 def race_permute(h, k, inp, out, to_permuted, stream=None):

@@ -82,7 +82,7 @@ struct race_schedule {
   bool has_values = false;
   bool uploaded = false;
   int device = -1;
-  DevBuf<int32_t> leaf_unit_ptr, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old, dep_ptr, dep_idx;
+  DevBuf<int32_t> leaf_units, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old, dep_ptr, dep_idx;
   DevBuf<uint32_t> flow_state;  // done[n_units], status, padding, counter (64-bit, 8-byte aligned)
   uint32_t epoch = 0;
   uint64_t ticket_next = 0;
@@ -93,7 +93,7 @@ struct race_schedule {
   DevBuf<float> lane_diag32, sell_val32;
 
   void free_device() {
-    release(leaf_unit_ptr); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
+    release(leaf_units); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
     release(chunk_len); release(new2old); release(halo); release(row_first_bits); release(chunk_off);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(dep_ptr); release(dep_idx); release(flow_state);
@@ -123,7 +123,7 @@ int race_params_default(race_params* p) {
   p->balance_by = 0;
   p->global_lb = 0;
   p->value_type = 0;
-  p->window_max = 4096;
+  p->window_max = 3840;
   p->block_threads = 256;
   const double eps[8] = {0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
   for (int i = 0; i < 8; ++i) p->eps[i] = eps[i];
@@ -147,8 +147,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     return fail(RACE_EUNSUPPORTED, "balance_by must be 0 (nonzeros) or 1 (rows)");
   if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
   if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
-  if (prm.window_max == 0) prm.window_max = 4096;
-  if (prm.window_max < 2 || prm.window_max > 10240) return fail(RACE_EINVAL, "window_max must be in 2..10240");
+  if (prm.window_max == 0) prm.window_max = 3840;
+  if (prm.window_max < 2 || prm.window_max > 8000) return fail(RACE_EINVAL, "window_max must be in 2..8000");
   if (prm.block_threads == 0) prm.block_threads = 256;
   if (prm.block_threads != 64 && prm.block_threads != 128 && prm.block_threads != 256 && prm.block_threads != 512 &&
       prm.block_threads != 1024)
@@ -249,7 +249,7 @@ int race_schedule_upload(race_schedule_t s) {
     s->free_device();                                              \
     return hip_fail(e, "upload of " #buf);                         \
   }
-  UP(leaf_unit_ptr, L.leaf_unit_ptr)
+  UP(leaf_units, L.leaf_units)
   UP(unit_lo, L.unit_lo)
   UP(unit_hi, L.unit_hi)
   UP(unit_halo_ptr, L.unit_halo_ptr)
@@ -270,10 +270,13 @@ int race_schedule_upload(race_schedule_t s) {
     UP(flow_state, zeros)
   }
   e = hipDeviceGetAttribute(&s->n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int clock_khz = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
   if (e != hipSuccess) {
     s->free_device();
     return hip_fail(e, "hipDeviceGetAttribute");
   }
+  s->stats.wall_clock_hz = static_cast<int64_t>(clock_khz) * 1000;
   if (s->params.value_type == 0) {
     UP(lane_diag64, L.lane_diag)
     UP(sell_val64, L.sell_val)
@@ -364,7 +367,7 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
 
 template <typename ValT>
 static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const ValT* vals) {
-  return race::UnitArgs<ValT>{s->leaf_unit_ptr.p, s->unit_lo.p,    s->unit_hi.p,        s->unit_halo_ptr.p,
+  return race::UnitArgs<ValT>{s->leaf_units.p, s->unit_lo.p,    s->unit_hi.p,        s->unit_halo_ptr.p,
                               s->halo.p,          s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p,
                               s->chunk_len.p,     s->lane_slot.p,  diag,                vals,
                               s->sell_slot.p};
@@ -372,7 +375,7 @@ static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const
 
 template <typename ValT>
 static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
-                    hipStream_t st) {
+                    uint64_t* trace, hipStream_t st) {
   const race::Layout& L = s->L;
   const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
   if (n_units == 0) return RACE_OK;
@@ -381,11 +384,12 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   hipError_t e = race::race_flow_occupancy<ValT>(k, s->params.block_threads, wmax, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(RACE_EUNSUPPORTED, "dataflow kernel does not fit a CU with this window and block size");
-  const int32_t grid = std::max(1, std::min(n_units, per_cu * s->n_cus));
+  const int32_t n_tickets = n_units;
+  const int32_t grid = std::max(1, std::min(n_tickets, per_cu * s->n_cus));
   uint32_t* base = s->flow_state.p;
   const size_t counter_word = s->flow_state.count - 2;
   race::FlowArgs f{s->dep_ptr.p, s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word),
-                   base + n_units, n_units};
+                   base + n_units, trace, n_tickets};
   s->epoch += 1;
   if (s->epoch == 0) {  // wrapped: every done flag must differ from the new epoch
     e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_units, st);
@@ -393,7 +397,7 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
     s->epoch = 1;
   }
   const uint64_t ticket_base = s->ticket_next;
-  s->ticket_next += static_cast<uint64_t>(n_units) + static_cast<uint64_t>(grid);
+  s->ticket_next += static_cast<uint64_t>(n_tickets) + static_cast<uint64_t>(grid);
   s->stats.flow_grid = grid;
   e = race::launch_race_flow<ValT>(a, f, k, x, y, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
   if (e != hipSuccess) return hip_fail(e, "RACE dataflow launch");
@@ -402,19 +406,19 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
 
 template <typename ValT>
 static int run_phases(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
-                      hipStream_t st) {
+                      uint64_t* trace, hipStream_t st) {
   const race::Layout& L = s->L;
   for (int32_t ph = 0; ph < s->tree.n_phases; ++ph) {
     const int32_t l0 = L.phase_leaf_ptr[ph], l1 = L.phase_leaf_ptr[ph + 1];
     if (l1 == l0) continue;
     const int32_t wmax = std::max(1, L.phase_max_window[ph]);
-    hipError_t e = race::launch_race_phase<ValT>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, st);
+    hipError_t e = race::launch_race_phase<ValT>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, trace, st);
     if (e != hipSuccess) return hip_fail(e, "RACE phase launch");
   }
   return RACE_OK;
 }
 
-static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, void* stream) {
+static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, uint64_t* trace, void* stream) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
@@ -422,16 +426,18 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
   const size_t lds_limit = 159 * 1024;  // dynamic windows plus the kernels' own few bytes
   const int32_t wmax = std::max(1, s->L.max_window);
-  if (2 * static_cast<size_t>(wmax) * k * sizeof(double) > lds_limit)
+  if (race::window_lds_bytes(wmax, k) > lds_limit)
     return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
                                        " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (s->params.value_type == 0) {
     const auto a = unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p);
-    return s->params.exec_mode == 1 ? run_flow<double>(s, a, k, x, y, st) : run_phases<double>(s, a, k, x, y, st);
+    return s->params.exec_mode == 1 ? run_flow<double>(s, a, k, x, y, trace, st)
+                                    : run_phases<double>(s, a, k, x, y, trace, st);
   }
   const auto a = unit_args<float>(s, s->lane_diag32.p, s->sell_val32.p);
-  return s->params.exec_mode == 1 ? run_flow<float>(s, a, k, x, y, st) : run_phases<float>(s, a, k, x, y, st);
+  return s->params.exec_mode == 1 ? run_flow<float>(s, a, k, x, y, trace, st)
+                                  : run_phases<float>(s, a, k, x, y, trace, st);
 }
 
 extern "C" {
@@ -455,11 +461,16 @@ int race_schedule_check(race_schedule_t s) {
 }
 
 int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream) {
-  return run_products(s, 1, x, y, stream);
+  return run_products(s, 1, x, y, nullptr, stream);
 }
 
 int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream) {
-  return run_products(s, k, X, Y, stream);
+  return run_products(s, k, X, Y, nullptr, stream);
+}
+
+int race_symm_spmm_traced(race_schedule_t s, int32_t k, const double* X, double* Y, uint64_t* trace, void* stream) {
+  if (!trace) return fail(RACE_EINVAL, "trace is NULL");
+  return run_products(s, k, X, Y, trace, stream);
 }
 
 int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, int32_t to_permuted, void* stream) {

@@ -10,7 +10,7 @@ namespace race {
 // Device pointers of one schedule's layout (see layout.hpp for the meaning).
 template <typename ValT>
 struct UnitArgs {
-  const int32_t* leaf_unit_ptr;
+  const int32_t* leaf_units;  // 2 per leaf: first unit, one past the last
   const int32_t* unit_lo;
   const int32_t* unit_hi;
   const int32_t* unit_halo_ptr;
@@ -25,23 +25,31 @@ struct UnitArgs {
   const uint16_t* sell_slot;
 };
 
-// Dataflow state of one schedule: conflict edges between units (CSR over
-// units, every edge pointing to a smaller unit), per-unit completion epochs,
-// the ticket counter and a status word (bit 0: a bounded wait gave up).
+// Dataflow state of one schedule: tickets are units in execution order,
+// conflict edges between units (CSR over units, every edge pointing to a
+// smaller unit), per-unit completion epochs, the ticket counter and a status
+// word (bit 0: a bounded wait gave up).
 struct FlowArgs {
   const int32_t* dep_ptr;
   const int32_t* dep_idx;
   uint32_t* done;
   uint64_t* counter;
   uint32_t* status;
-  int32_t n_units;
+  uint64_t* trace;  // NULL, or 4 stamps per unit: taken, computed, dependencies met, flushed
+  int32_t n_tickets;  // units, in execution order
 };
+
+// LDS bytes of a unit window of wmax entries with k right-hand sides: the
+// x and y windows (float64) and the window's global indices (int32).
+inline size_t window_lds_bytes(int32_t wmax, int32_t k) {
+  return static_cast<size_t>(wmax) * (16 * static_cast<size_t>(k) + 4);
+}
 
 // One phase: n_leaves workgroups starting at leaf_base; k right-hand sides
 // (1..16) in row-major x/y; wmax = largest unit window of the phase.
 template <typename ValT>
 hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, int32_t k, const double* x,
-                             double* y, int32_t wmax, int32_t threads, hipStream_t st);
+                             double* y, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st);
 
 // Whole product in one persistent launch of `grid` workgroups; epoch and
 // ticket_base identify the call (see race_flow_kernel).

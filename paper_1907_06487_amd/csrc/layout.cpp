@@ -66,13 +66,29 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
   std::vector<uint8_t> marked(static_cast<size_t>(n), 0);
   std::vector<int32_t> mark_list;
   std::vector<int32_t> slot_of(static_cast<size_t>(n), -1);
-  L.leaf_unit_ptr.assign(1, 0);
+  L.leaf_units.assign(2 * static_cast<size_t>(n_leaves), 0);
+  // execution order: phase by phase; inside a phase (no conflicts between its
+  // leaves) the heaviest leaves first, so the large units start early
+  L.unit_order_leaves.resize(static_cast<size_t>(n_leaves));
+  std::iota(L.unit_order_leaves.begin(), L.unit_order_leaves.end(), 0);
+  {
+    std::vector<int64_t> work(static_cast<size_t>(n_leaves));
+    for (int32_t t = 0; t < n_leaves; ++t) {
+      const TreeNode& nd = tree.nodes[tree.leaves[t]];
+      work[t] = static_cast<int64_t>(rp[nd.hi] - rp[nd.lo]) + (nd.hi - nd.lo);
+    }
+    std::stable_sort(L.unit_order_leaves.begin(), L.unit_order_leaves.end(), [&](int32_t a, int32_t b) {
+      if (tree.leaf_phase[a] != tree.leaf_phase[b]) return tree.leaf_phase[a] < tree.leaf_phase[b];
+      return work[a] > work[b];
+    });
+  }
   L.unit_halo_ptr.assign(1, 0);
   L.unit_chunk_ptr.assign(1, 0);
   std::vector<int32_t> rows_sorted;
   uint64_t elems = 0;
-  for (int32_t t = 0; t < n_leaves; ++t) {
+  for (int32_t t : L.unit_order_leaves) {
     const TreeNode& leaf = tree.nodes[tree.leaves[t]];
+    L.leaf_units[2 * static_cast<size_t>(t)] = static_cast<int32_t>(L.unit_lo.size());
     int32_t a = leaf.lo;
     while (a < leaf.hi) {
       int64_t w = 0;
@@ -164,7 +180,7 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
       for (int32_t j = 0; j < H; ++j) slot_of[L.halo[h0 + j]] = -1;
       a = b;
     }
-    L.leaf_unit_ptr.push_back(static_cast<int32_t>(L.unit_lo.size()));
+    L.leaf_units[2 * static_cast<size_t>(t) + 1] = static_cast<int32_t>(L.unit_lo.size());
   }
   if (L.halo.size() >= static_cast<size_t>(INT32_MAX)) {
     *code = RACE_EUNSUPPORTED;

@@ -33,7 +33,8 @@ struct Layout {
 
   // execution structure
   std::vector<int32_t> phase_leaf_ptr;  // n_phases + 1, into the leaves list
-  std::vector<int32_t> leaf_unit_ptr;   // n_leaves + 1
+  std::vector<int32_t> leaf_units;      // 2 per leaf (tree order): first unit, one past the last
+  std::vector<int32_t> unit_order_leaves;  // leaves in execution order (phase, then descending work)
   std::vector<int32_t> unit_leaf, unit_lo, unit_hi;
   std::vector<int32_t> unit_halo_ptr;   // n_units + 1
   std::vector<uint32_t> halo;           // index | kFirstBit when first writer

@@ -84,7 +84,7 @@ __device__ __forceinline__ void apply_batch(const double* v, const int32_t* sl, 
 //      atomics.
 template <typename ValT, int K>
 __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u, const double* __restrict__ x,
-                                             double* xw, double* yw, int32_t tid, int32_t nthr) {
+                                             double* xw, double* yw, uint32_t* gw, int32_t tid, int32_t nthr) {
   constexpr int kStage = K >= 4 ? 1 : 4;  // window entries per thread per staging round
   const int32_t lane = tid & (kSlice - 1), wave = tid / kSlice, nwaves = nthr / kSlice;
   const int32_t lo = a.unit_lo[u];
@@ -100,21 +100,30 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u,
   }
   // 1. stage the windows while the first slice is in flight
   for (int32_t base = 0; base < W; base += kStage * nthr) {
-    int32_t g[kStage];
+    // window index with the first-writer flag in bit 31, kept in LDS for the flush
+    uint32_t h[kStage];
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
-      g[q] = s < R ? lo + s : (s < W ? static_cast<int32_t>(a.halo[h0 + s - R] & 0x7fffffffu) : -1);
+      if (s < R) {
+        const uint32_t r = static_cast<uint32_t>(lo + s);
+        h[q] = r | (((a.row_first_bits[r >> 5] >> (r & 31)) & 1u) << 31);
+      } else {
+        h[q] = s < W ? a.halo[h0 + s - R] : 0u;
+      }
     }
     double xv[kStage][K];
 #pragma unroll
-    for (int q = 0; q < kStage; ++q)
+    for (int q = 0; q < kStage; ++q) {
+      const bool in = base + q * nthr + tid < W;
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv[q][k] = g[q] >= 0 ? x[static_cast<size_t>(g[q]) * K + k] : 0.0;
+      for (int k = 0; k < K; ++k) xv[q][k] = in ? x[static_cast<size_t>(h[q] & 0x7fffffffu) * K + k] : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
       if (s < W) {
+        gw[s] = h[q];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           xw[s * K + k] = xv[q][k];
@@ -188,43 +197,29 @@ __device__ __forceinline__ void y_store(double* p, double v) {
 // time never share an index (distance-2 coloring), so no global atomics.
 template <typename ValT, int K, bool kCoherent>
 __device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, double* __restrict__ y,
-                                           const double* yw, int32_t tid, int32_t nthr) {
-  constexpr int kStage = K >= 4 ? 1 : 4;
-  const int32_t lo = a.unit_lo[u];
-  const int32_t R = a.unit_hi[u] - lo;
-  const int32_t h0 = a.unit_halo_ptr[u];
-  const int32_t W = R + (a.unit_halo_ptr[u + 1] - h0);
+                                           const double* yw, const uint32_t* gw, int32_t tid, int32_t nthr) {
+  constexpr int kStage = K >= 4 ? 2 : 8;
+  const int32_t W = (a.unit_hi[u] - a.unit_lo[u]) + (a.unit_halo_ptr[u + 1] - a.unit_halo_ptr[u]);
   for (int32_t base = 0; base < W; base += kStage * nthr) {
-    int32_t g[kStage];
-    bool first[kStage];
+    uint32_t h[kStage];
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
-      if (s < R) {
-        g[q] = lo + s;
-        first[q] = (a.row_first_bits[g[q] >> 5] >> (g[q] & 31)) & 1u;
-      } else if (s < W) {
-        const uint32_t h = a.halo[h0 + s - R];
-        g[q] = static_cast<int32_t>(h & 0x7fffffffu);
-        first[q] = (h >> 31) != 0u;
-      } else {
-        g[q] = -1;
-        first[q] = true;
-      }
+      h[q] = s < W ? gw[s] : 0x80000000u;
     }
     double old[kStage][K];
 #pragma unroll
     for (int q = 0; q < kStage; ++q)
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        old[q][k] = (g[q] >= 0 && !first[q]) ? y_load<kCoherent>(y + static_cast<size_t>(g[q]) * K + k) : 0.0;
+        old[q][k] = (h[q] >> 31) ? 0.0 : y_load<kCoherent>(y + static_cast<size_t>(h[q] & 0x7fffffffu) * K + k);
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
-      if (g[q] >= 0) {
+      if (s < W) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-          y_store<kCoherent>(y + static_cast<size_t>(g[q]) * K + k, old[q][k] + yw[s * K + k]);
+          y_store<kCoherent>(y + static_cast<size_t>(h[q] & 0x7fffffffu) * K + k, old[q][k] + yw[s * K + k]);
       }
     }
   }
@@ -232,28 +227,41 @@ __device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, d
 
 // Phase-by-phase execution: one launch per phase, one workgroup per leaf
 // running the leaf's units in order.
+// Device wall clock (constant rate, common to all CUs) for unit traces.
+__device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
+
 template <typename ValT, int K>
 __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32_t leaf_base,
                                                          const double* __restrict__ x, double* __restrict__ y,
-                                                         int32_t wmax) {
+                                                         int32_t wmax, uint64_t* trace) {
   extern __shared__ double smem[];
   double* xw = smem;
   double* yw = smem + static_cast<size_t>(wmax) * K;
+  uint32_t* gw = reinterpret_cast<uint32_t*>(smem + 2 * static_cast<size_t>(wmax) * K);
   const int32_t leaf = leaf_base + static_cast<int32_t>(blockIdx.x);
-  const int32_t u0 = a.leaf_unit_ptr[leaf], u1 = a.leaf_unit_ptr[leaf + 1];
+  const int32_t u0 = a.leaf_units[2 * leaf], u1 = a.leaf_units[2 * leaf + 1];
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
   for (int32_t u = u0; u < u1; ++u) {
-    compute_unit<ValT, K>(a, u, x, xw, yw, tid, nthr);
-    flush_unit<ValT, K, false>(a, u, y, yw, tid, nthr);
+    const uint64_t t0 = trace ? wall_clock() : 0;
+    compute_unit<ValT, K>(a, u, x, xw, yw, gw, tid, nthr);
+    const uint64_t t1 = trace ? wall_clock() : 0;
+    flush_unit<ValT, K, false>(a, u, y, yw, gw, tid, nthr);
     __syncthreads();
+    if (trace && tid == 0) {
+      const uint64_t t2 = wall_clock();
+      trace[4 * static_cast<size_t>(u) + 0] = t0;
+      trace[4 * static_cast<size_t>(u) + 1] = t1;
+      trace[4 * static_cast<size_t>(u) + 2] = t1;
+      trace[4 * static_cast<size_t>(u) + 3] = t2;
+    }
   }
 }
 
 // Dataflow execution in one persistent launch.  Units are taken in the
-// schedule's order (phase, leaf, unit) from a ticket counter; a unit first
-// waits until every earlier unit whose touch set meets its own has
-// published completion (the conflict edges of the tree's coloring), then
-// runs and publishes.  Only y crosses units, and it does so through
+// execution order (phase, then heaviest leaf first, a leaf's units in row
+// order) from a ticket counter; a unit computes right away and, before its
+// flush, waits until every earlier unit whose touch set meets its own has
+// published completion (the conflict edges of the tree's coloring).  Only y crosses units, and it does so through
 // coherent (agent-scope atomic) accesses whose completion each thread
 // awaits before the publishing barrier; x and the matrix are read-only.  Waits only point to smaller tickets, which were
 // handed to running workgroups, so the lowest unfinished ticket can always
@@ -266,7 +274,8 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
   extern __shared__ double smem[];
   double* xw = smem;
   double* yw = smem + static_cast<size_t>(wmax) * K;
-  __shared__ int32_t s_unit;
+  uint32_t* gw = reinterpret_cast<uint32_t*>(smem + 2 * static_cast<size_t>(wmax) * K);
+  __shared__ int32_t s_unit[1];
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
   // wave 0 as a scalar condition: the lane-0 work below sits in small
   // diamonds inside a wave-uniform branch, and barriers close them on both
@@ -277,17 +286,20 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
     if (wave0) {
       if (tid == 0) {
         const uint64_t t = atomicAdd(reinterpret_cast<unsigned long long*>(f.counter), 1ull) - ticket_base;
-        s_unit = t < static_cast<uint64_t>(f.n_units) ? static_cast<int32_t>(t) : -1;
+        s_unit[0] = t < static_cast<uint64_t>(f.n_tickets) ? static_cast<int32_t>(t) : -1;
       }
     }
     __syncthreads();
     // the same value in every lane; read into a scalar register so the loop's
-    // exit and the barriers below stay in uniform control flow
-    const int32_t u = __builtin_amdgcn_readfirstlane(s_unit);
+    // exit and the barriers below stay in uniform control flow (a ticket taken
+    // only when the workgroup is free keeps the end of the run balanced)
+    const int32_t u = __builtin_amdgcn_readfirstlane(s_unit[0]);
     if (u < 0) break;
+    const uint64_t t0 = f.trace ? wall_clock() : 0;
     // the unit's arithmetic needs nothing from other units; only its flush
     // must follow the earlier units it conflicts with
-    compute_unit<ValT, K>(a, u, x, xw, yw, tid, nthr);
+    compute_unit<ValT, K>(a, u, x, xw, yw, gw, tid, nthr);
+    const uint64_t t1 = f.trace ? wall_clock() : 0;
     const int32_t d0 = f.dep_ptr[u], d1 = f.dep_ptr[u + 1];
     for (int32_t i = d0 + tid; i < d1; i += nthr) {
       const int32_t v = f.dep_idx[i];
@@ -301,7 +313,8 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
       }
     }
     __syncthreads();
-    flush_unit<ValT, K, true>(a, u, y, yw, tid, nthr);
+    const uint64_t t2 = f.trace ? wall_clock() : 0;
+    flush_unit<ValT, K, true>(a, u, y, yw, gw, tid, nthr);
     // every thread's coherent y stores complete before the barrier, so the
     // completion flag written after it is only seen once they are visible
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -309,7 +322,16 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
     if (wave0) {
-      if (tid == 0) __hip_atomic_store(f.done + u, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) {
+        if (f.trace) {
+          const uint64_t t3 = wall_clock();
+          f.trace[4 * static_cast<size_t>(u) + 0] = t0;
+          f.trace[4 * static_cast<size_t>(u) + 1] = t1;
+          f.trace[4 * static_cast<size_t>(u) + 2] = t2;
+          f.trace[4 * static_cast<size_t>(u) + 3] = t3;
+        }
+        __hip_atomic_store(f.done + u, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }
@@ -388,12 +410,12 @@ static hipError_t set_lds_attr(const void* fn) {
 
 template <typename ValT, int K>
 static hipError_t launch_leaf(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, const double* x, double* y,
-                              int32_t wmax, int32_t threads, hipStream_t st) {
-  const size_t lds = 2 * static_cast<size_t>(wmax) * K * sizeof(double);
+                              int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
+  const size_t lds = window_lds_bytes(wmax, K);
   hipError_t e = set_lds_attr<ValT, K>(reinterpret_cast<const void*>(&dev::race_leaf_kernel<ValT, K>));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((dev::race_leaf_kernel<ValT, K>), dim3(n_leaves), dim3(threads), lds, st, a, leaf_base, x, y,
-                     wmax);
+                     wmax, trace);
   return hipGetLastError();
 }
 
@@ -403,7 +425,7 @@ struct FlowTag {};
 template <typename ValT, int K>
 static hipError_t launch_flow(const UnitArgs<ValT>& a, const FlowArgs& f, const double* x, double* y, int32_t wmax,
                               int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base, hipStream_t st) {
-  const size_t lds = 2 * static_cast<size_t>(wmax) * K * sizeof(double);
+  const size_t lds = window_lds_bytes(wmax, K);
   hipError_t e = set_lds_attr<FlowTag<ValT, K>, K>(reinterpret_cast<const void*>(&dev::race_flow_kernel<ValT, K>));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((dev::race_flow_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, a, f, x, y, wmax, epoch,
@@ -418,7 +440,7 @@ static hipError_t launch_flow(const UnitArgs<ValT>& a, const FlowArgs& f, const 
 // co-residency.
 template <typename ValT, int K>
 static hipError_t flow_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_per_cu) {
-  const size_t lds = 2 * static_cast<size_t>(wmax) * K * sizeof(double);
+  const size_t lds = window_lds_bytes(wmax, K);
   hipFuncAttributes attr{};
   hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&dev::race_flow_kernel<ValT, K>));
   int32_t regs = 128, static_lds = 64;
@@ -448,8 +470,8 @@ static hipError_t flow_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_
 
 template <typename ValT>
 hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, int32_t k, const double* x,
-                             double* y, int32_t wmax, int32_t threads, hipStream_t st) {
-#define CALL(KK) launch_leaf<ValT, KK>(a, leaf_base, n_leaves, x, y, wmax, threads, st)
+                             double* y, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
+#define CALL(KK) launch_leaf<ValT, KK>(a, leaf_base, n_leaves, x, y, wmax, threads, trace, st)
   RACE_K_SWITCH(CALL)
 #undef CALL
 }
@@ -471,9 +493,9 @@ hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t
 }
 
 template hipError_t launch_race_phase<double>(const UnitArgs<double>&, int32_t, int32_t, int32_t, const double*,
-                                              double*, int32_t, int32_t, hipStream_t);
+                                              double*, int32_t, int32_t, uint64_t*, hipStream_t);
 template hipError_t launch_race_phase<float>(const UnitArgs<float>&, int32_t, int32_t, int32_t, const double*,
-                                             double*, int32_t, int32_t, hipStream_t);
+                                             double*, int32_t, int32_t, uint64_t*, hipStream_t);
 template hipError_t launch_race_flow<double>(const UnitArgs<double>&, const FlowArgs&, int32_t, const double*, double*,
                                              int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
 template hipError_t launch_race_flow<float>(const UnitArgs<float>&, const FlowArgs&, int32_t, const double*, double*,
