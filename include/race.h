@@ -174,6 +174,32 @@ int race_schedule_check(race_schedule_t s);
  * out[new2old[i]] = in[i]. */
 int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, int32_t to_permuted, void* stream);
 
+/* ---- batches: many schedules in one persistent launch ---- */
+
+/* Group `count` uploaded schedules (same device and value type) for k
+ * right-hand sides each.  Their units are merged into one ticket sequence
+ * (by phase, keeping every matrix's own order) for a single persistent
+ * dataflow launch.  The schedules are borrowed and must outlive the batch. */
+int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, race_batch_t* out);
+
+/* Set the device arrays of every matrix (host arrays of `count` device
+ * pointers; X[m], Y[m] row-major n_m x k in matrix m's permuted order) and
+ * capture the run -- a state-clearing kernel followed by the persistent
+ * launch -- into a hipGraph for replay.  Call again to change pointers. */
+int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y);
+
+/* Y_m = A_m X_m for every matrix: replay the captured graph on `stream`
+ * (use_graph != 0) or enqueue the same two kernels directly. */
+int race_batch_run(race_batch_t b, int32_t use_graph, void* stream);
+
+/* Synchronise and report whether a bounded wait gave up (RACE_EINTERNAL). */
+int race_batch_check(race_batch_t b);
+
+/* Tickets (units over all matrices), workgroups of the launch, largest window. */
+int race_batch_info(race_batch_t b, int32_t* n_tickets, int32_t* grid, int32_t* wmax);
+
+void race_batch_destroy(race_batch_t b);
+
 /* ---- same-GPU baselines (not RACE; the yardsticks of Section 6) ---- */
 
 /* Full-matrix CRS SpMV (Algorithm "SpMV"): takes the FULL symmetric matrix in

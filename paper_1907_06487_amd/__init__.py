@@ -10,7 +10,8 @@ streams.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import (RaceError, race_atomic_create, race_build_schedule, race_csr_create, race_csr_destroy,
+from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_check, race_batch_create,
+                   race_batch_destroy, race_batch_info, race_batch_run, race_build_schedule, race_csr_create, race_csr_destroy,
                    race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
@@ -83,6 +84,38 @@ class Schedule:
     def close(self):
         if self.handle is not None:
             race_schedule_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owning wrapper around a race_batch_t (the schedules must outlive it)."""
+
+    def __init__(self, schedules, k):
+        self.schedules = list(schedules)
+        self.k = int(k)
+        self.handle = race_batch_create([s.handle for s in self.schedules], self.k)
+
+    def bind(self, xs, ys):
+        race_batch_bind(self.handle, xs, ys)
+
+    def run(self, use_graph=True, stream=None):
+        race_batch_run(self.handle, use_graph, stream)
+
+    def check(self):
+        race_batch_check(self.handle)
+
+    def info(self):
+        return race_batch_info(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            race_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

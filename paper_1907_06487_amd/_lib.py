@@ -26,6 +26,8 @@ EXPORTS = [
     "race_schedule_stats", "race_schedule_perm", "race_schedule_tree", "race_schedule_leaves",
     "race_schedule_units", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
     "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
+    "race_batch_create", "race_batch_bind", "race_batch_run", "race_batch_check", "race_batch_info",
+    "race_batch_destroy",
 ]
 
 
@@ -99,6 +101,12 @@ def lib():
         "race_symm_spmv_atomic": ([_P, _P, _P, _P], ctypes.c_int),
         "race_csr_destroy": ([_P], None),
         "race_last_error": ([], ctypes.c_char_p),
+        "race_batch_create": ([ctypes.c_int32, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
+        "race_batch_bind": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], ctypes.c_int),
+        "race_batch_run": ([_P, ctypes.c_int32, _P], ctypes.c_int),
+        "race_batch_check": ([_P], ctypes.c_int),
+        "race_batch_info": ([_P, _I32P, _I32P, _I32P], ctypes.c_int),
+        "race_batch_destroy": ([_P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -274,3 +282,34 @@ def race_csr_destroy(h):
 
 def race_last_error():
     return lib().race_last_error().decode()
+
+
+def race_batch_create(handles, k):
+    arr = (_P * len(handles))(*[h.value if isinstance(h, _P) else h for h in handles])
+    b = _P()
+    check(lib().race_batch_create(len(handles), arr, int(k), ctypes.byref(b)))
+    return b
+
+
+def race_batch_bind(b, xs, ys):
+    X = (_P * len(xs))(*[_dev_ptr(t).value for t in xs])
+    Y = (_P * len(ys))(*[_dev_ptr(t).value for t in ys])
+    check(lib().race_batch_bind(b, X, Y))
+
+
+def race_batch_run(b, use_graph=True, stream=None):
+    check(lib().race_batch_run(b, int(bool(use_graph)), _stream_ptr(stream)))
+
+
+def race_batch_check(b):
+    check(lib().race_batch_check(b))
+
+
+def race_batch_info(b):
+    t, g, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().race_batch_info(b, ctypes.byref(t), ctypes.byref(g), ctypes.byref(w)))
+    return {"n_tickets": t.value, "grid": g.value, "wmax": w.value}
+
+
+def race_batch_destroy(b):
+    lib().race_batch_destroy(b)

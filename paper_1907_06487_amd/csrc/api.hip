@@ -110,6 +110,26 @@ struct race_csr {
   DevBuf<double> val;
 };
 
+struct race_batch {
+  int32_t count = 0;
+  int32_t k = 1;
+  int32_t value_type = 0;
+  int32_t threads = 256;
+  int32_t grid = 0;
+  int32_t wmax = 1;
+  int32_t n_tickets = 0;
+  int device = -1;
+  std::vector<race_schedule_t> mats;
+  std::vector<int64_t> unit_base;  // offset of each matrix's done flags in the state
+  DevBuf<int32_t> ticket_mat, ticket_unit;
+  DevBuf<uint32_t> state;
+  void* d_mats = nullptr;          // BatchMat<ValT>[count]
+  bool bound = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 extern "C" {
 
 const char* race_last_error(void) { return g_err.c_str(); }
@@ -482,6 +502,200 @@ int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, in
   hipError_t e = race::launch_permute(s->tree.n, k, s->new2old.p, in, out, to_permuted, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "permute launch");
   return RACE_OK;
+}
+
+}  // extern "C"
+
+template <typename ValT>
+static race::BatchMat<ValT> batch_mat(race_schedule_t s, const ValT* diag, const ValT* vals, uint32_t* done,
+                                      const double* x, double* y) {
+  return race::BatchMat<ValT>{unit_args<ValT>(s, diag, vals), s->dep_ptr.p, s->dep_idx.p, done, x, y};
+}
+
+static void batch_release(race_batch_t b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->cap = nullptr;
+  if (b->d_mats) (void)hipFree(b->d_mats);
+  b->d_mats = nullptr;
+  release(b->ticket_mat);
+  release(b->ticket_unit);
+  release(b->state);
+}
+
+static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
+  race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count), b->n_tickets};
+  if (b->value_type == 0)
+    return race::launch_race_batch<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), a, b->k, b->wmax,
+                                           b->threads, b->grid, st);
+  return race::launch_race_batch<float>(static_cast<const race::BatchMat<float>*>(b->d_mats), a, b->k, b->wmax,
+                                        b->threads, b->grid, st);
+}
+
+extern "C" {
+
+int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, race_batch_t* out) {
+  if (!out || !s || count < 1) return fail(RACE_EINVAL, "need count >= 1 schedules and an output handle");
+  *out = nullptr;
+  if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  int32_t wmax = 1, threads = 0, vt = -1;
+  for (int32_t m = 0; m < count; ++m) {
+    if (!s[m] || !s[m]->uploaded) return fail(RACE_ESTATE, "every schedule must be uploaded");
+    if (s[m]->device != dev) return fail(RACE_EINVAL, "schedules live on different devices");
+    if (vt >= 0 && s[m]->params.value_type != vt) return fail(RACE_EINVAL, "schedules mix value types");
+    vt = s[m]->params.value_type;
+    threads = std::max(threads, s[m]->params.block_threads);
+    wmax = std::max(wmax, s[m]->L.max_window);
+  }
+  if (race::window_lds_bytes(wmax, k) > 159 * 1024)
+    return fail(RACE_EUNSUPPORTED, "largest window x k exceeds the LDS; rebuild with a smaller window_max");
+  race_batch* b = new (std::nothrow) race_batch();
+  if (!b) return fail(RACE_ENOMEM, "out of host memory");
+  b->count = count;
+  b->k = k;
+  b->value_type = vt;
+  b->threads = threads;
+  b->wmax = wmax;
+  b->device = dev;
+  b->mats.assign(s, s + count);
+  // tickets: (phase as a fraction of the matrix's phases, matrix, unit); every
+  // matrix keeps its own unit order, so all conflict edges point backwards
+  struct Tk {
+    double key;
+    int32_t m, u;
+  };
+  std::vector<Tk> tk;
+  int64_t total_units = 0;
+  b->unit_base.resize(count);
+  for (int32_t m = 0; m < count; ++m) {
+    const race::Layout& L = s[m]->L;
+    const race::Tree& t = s[m]->tree;
+    b->unit_base[m] = total_units;
+    const int32_t nu = static_cast<int32_t>(L.unit_lo.size());
+    for (int32_t u = 0; u < nu; ++u)
+      tk.push_back({static_cast<double>(t.leaf_phase[L.unit_leaf[u]]) / static_cast<double>(t.n_phases), m, u});
+    total_units += nu;
+  }
+  std::stable_sort(tk.begin(), tk.end(), [](const Tk& a, const Tk& c) {
+    if (a.key != c.key) return a.key < c.key;
+    return a.m < c.m;
+  });
+  std::vector<int32_t> tm(tk.size()), tu(tk.size());
+  for (size_t i = 0; i < tk.size(); ++i) {
+    tm[i] = tk[i].m;
+    tu[i] = tk[i].u;
+  }
+  b->n_tickets = static_cast<int32_t>(tk.size());
+  int64_t total = 0;
+  const size_t words = static_cast<size_t>((total_units + 4 + 1) / 2 * 2);
+  std::vector<uint32_t> zeros(words, 0u);
+  e = upload(b->ticket_mat, tm.data(), tm.size(), &total);
+  if (e == hipSuccess) e = upload(b->ticket_unit, tu.data(), tu.size(), &total);
+  if (e == hipSuccess) e = upload(b->state, zeros.data(), zeros.size(), &total);
+  int32_t per_cu = 0;
+  if (e == hipSuccess)
+    e = vt == 0 ? race::race_flow_occupancy<double>(k, threads, wmax, &per_cu)
+                : race::race_flow_occupancy<float>(k, threads, wmax, &per_cu);
+  if (e != hipSuccess) {
+    batch_release(b);
+    delete b;
+    return hip_fail(e, "batch setup");
+  }
+  b->grid = std::max(1, std::min(b->n_tickets, std::max(1, per_cu) * s[0]->n_cus));
+  *out = b;
+  return RACE_OK;
+}
+
+int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y) {
+  if (!b || !X || !Y) return fail(RACE_EINVAL, "NULL argument");
+  for (int32_t m = 0; m < b->count; ++m)
+    if (!X[m] || !Y[m]) return fail(RACE_EINVAL, "x/y pointer of matrix " + std::to_string(m) + " is NULL");
+  hipError_t e = hipSuccess;
+  const size_t bytes = b->value_type == 0 ? sizeof(race::BatchMat<double>) * b->count
+                                          : sizeof(race::BatchMat<float>) * b->count;
+  if (!b->d_mats) {
+    e = hipMalloc(&b->d_mats, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  }
+  if (b->value_type == 0) {
+    std::vector<race::BatchMat<double>> h(b->count);
+    for (int32_t m = 0; m < b->count; ++m)
+      h[m] = batch_mat<double>(b->mats[m], b->mats[m]->lane_diag64.p, b->mats[m]->sell_val64.p,
+                               b->state.p + b->unit_base[m], X[m], Y[m]);
+    e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<race::BatchMat<float>> h(b->count);
+    for (int32_t m = 0; m < b->count; ++m)
+      h[m] = batch_mat<float>(b->mats[m], b->mats[m]->lane_diag32.p, b->mats[m]->sell_val32.p,
+                              b->state.p + b->unit_base[m], X[m], Y[m]);
+    e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  // capture reset + persistent kernel once; replays reuse it
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (!b->cap) {
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  }
+  e = b->value_type == 0 ? race::prepare_race_batch<double>(b->k) : race::prepare_race_batch<float>(b->k);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel attributes");
+  e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t le = batch_enqueue(b, b->cap);
+  e = hipStreamEndCapture(b->cap, &b->graph);
+  if (le != hipSuccess) return hip_fail(le, "batch launch under capture");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  b->bound = true;
+  return RACE_OK;
+}
+
+int race_batch_run(race_batch_t b, int32_t use_graph, void* stream) {
+  if (!b) return fail(RACE_EINVAL, "batch is NULL");
+  if (!b->bound) return fail(RACE_ESTATE, "race_batch_bind has not been called");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = use_graph ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st);
+  if (e != hipSuccess) return hip_fail(e, use_graph ? "hipGraphLaunch" : "batch launch");
+  return RACE_OK;
+}
+
+int race_batch_check(race_batch_t b) {
+  if (!b) return fail(RACE_EINVAL, "batch is NULL");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  uint32_t status = 0;
+  e = hipMemcpy(&status, b->state.p + b->state.count - 4, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (status) return fail(RACE_EINTERNAL, "a dataflow wait of the batch gave up (bounded spin exceeded)");
+  return RACE_OK;
+}
+
+int race_batch_info(race_batch_t b, int32_t* n_tickets, int32_t* grid, int32_t* wmax) {
+  if (!b) return fail(RACE_EINVAL, "batch is NULL");
+  if (n_tickets) *n_tickets = b->n_tickets;
+  if (grid) *grid = b->grid;
+  if (wmax) *wmax = b->wmax;
+  return RACE_OK;
+}
+
+void race_batch_destroy(race_batch_t b) {
+  if (!b) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  batch_release(b);
+  (void)hipSetDevice(cur);
+  delete b;
 }
 
 static int pick_lpr(int32_t n, int64_t nnz) {

@@ -39,6 +39,29 @@ struct FlowArgs {
   int32_t n_tickets;  // units, in execution order
 };
 
+// One matrix of a batch: its layout, conflict edges, completion flags (a
+// slice of the batch's state) and its x/y (row-major n x k).
+template <typename ValT>
+struct BatchMat {
+  UnitArgs<ValT> a;
+  const int32_t* dep_ptr;
+  const int32_t* dep_idx;
+  uint32_t* done;
+  const double* x;
+  double* y;
+};
+
+// Tickets of a batch: (matrix, unit) pairs, merged so every matrix keeps its
+// own execution order; the counter, status word and all done flags are
+// cleared by a reset kernel at the start of every run.
+struct BatchArgs {
+  const int32_t* ticket_mat;
+  const int32_t* ticket_unit;
+  uint32_t* state;       // all done flags, then status, then the 64-bit counter
+  int64_t state_words;   // length of `state` in 32-bit words (even)
+  int32_t n_tickets;
+};
+
 // LDS bytes of a unit window of wmax entries with k right-hand sides: the
 // x and y windows (float64) and the window's global indices (int32).
 inline size_t window_lds_bytes(int32_t wmax, int32_t k) {
@@ -60,6 +83,15 @@ hipError_t launch_race_flow(const UnitArgs<ValT>& a, const FlowArgs& f, int32_t 
 
 template <typename ValT>
 hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu);
+
+// Kernel attributes of the batch kernel (call once before stream capture).
+template <typename ValT>
+hipError_t prepare_race_batch(int32_t k);
+
+// A batch run: the reset kernel, then one persistent launch over all tickets.
+template <typename ValT>
+hipError_t launch_race_batch(const BatchMat<ValT>* mats, const BatchArgs& b, int32_t k, int32_t wmax, int32_t threads,
+                             int32_t grid, hipStream_t st);
 
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                            double* y, int32_t lanes_per_row, hipStream_t st);

@@ -257,6 +257,54 @@ __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32
   }
 }
 
+// One unit in dataflow order: compute, wait for the earlier units its touch
+// set meets, flush with coherent y accesses, publish completion.
+template <typename ValT, int K>
+__device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, const int32_t* dep_ptr,
+                                          const int32_t* dep_idx, uint32_t* done, uint32_t* status, uint64_t* trace,
+                                          uint32_t epoch, const double* __restrict__ x, double* __restrict__ y,
+                                          double* xw, double* yw, uint32_t* gw, int32_t tid, int32_t nthr,
+                                          bool wave0) {
+  const uint64_t t0 = trace ? wall_clock() : 0;
+  // the unit's arithmetic needs nothing from other units; only its flush
+  // must follow the earlier units it conflicts with
+  compute_unit<ValT, K>(a, u, x, xw, yw, gw, tid, nthr);
+  const uint64_t t1 = trace ? wall_clock() : 0;
+  const int32_t d0 = dep_ptr[u], d1 = dep_ptr[u + 1];
+  for (int32_t i = d0 + tid; i < d1; i += nthr) {
+    const int32_t v = dep_idx[i];
+    uint32_t spins = 0;
+    while (__hip_atomic_load(done + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        atomicOr(status, 1u);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t t2 = trace ? wall_clock() : 0;
+  flush_unit<ValT, K, true>(a, u, y, yw, gw, tid, nthr);
+  // every thread's coherent y stores complete before the barrier, so the
+  // completion flag written after it is only seen once they are visible
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (wave0) {
+    if (tid == 0) {
+      if (trace) {
+        const uint64_t t3 = wall_clock();
+        trace[4 * static_cast<size_t>(u) + 0] = t0;
+        trace[4 * static_cast<size_t>(u) + 1] = t1;
+        trace[4 * static_cast<size_t>(u) + 2] = t2;
+        trace[4 * static_cast<size_t>(u) + 3] = t3;
+      }
+      __hip_atomic_store(done + u, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // Dataflow execution in one persistent launch.  Units are taken in the
 // execution order (phase, then heaviest leaf first, a leaf's units in row
 // order) from a ticket counter; a unit computes right away and, before its
@@ -295,44 +343,49 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
     // only when the workgroup is free keeps the end of the run balanced)
     const int32_t u = __builtin_amdgcn_readfirstlane(s_unit[0]);
     if (u < 0) break;
-    const uint64_t t0 = f.trace ? wall_clock() : 0;
-    // the unit's arithmetic needs nothing from other units; only its flush
-    // must follow the earlier units it conflicts with
-    compute_unit<ValT, K>(a, u, x, xw, yw, gw, tid, nthr);
-    const uint64_t t1 = f.trace ? wall_clock() : 0;
-    const int32_t d0 = f.dep_ptr[u], d1 = f.dep_ptr[u + 1];
-    for (int32_t i = d0 + tid; i < d1; i += nthr) {
-      const int32_t v = f.dep_idx[i];
-      uint32_t spins = 0;
-      while (__hip_atomic_load(f.done + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          atomicOr(f.status, 1u);
-          break;
-        }
-      }
-    }
-    __syncthreads();
-    const uint64_t t2 = f.trace ? wall_clock() : 0;
-    flush_unit<ValT, K, true>(a, u, y, yw, gw, tid, nthr);
-    // every thread's coherent y stores complete before the barrier, so the
-    // completion flag written after it is only seen once they are visible
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    flow_unit<ValT, K>(a, u, f.dep_ptr, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, xw, yw, gw, tid, nthr,
+                       wave0);
+  }
+}
+
+// Clears a batch's dataflow state (done flags, status, ticket counter) with
+// plain stores, so a captured graph can replay the run.
+__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t* state, int64_t words) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < words) state[i] = 0u;
+}
+
+// Many matrices in one persistent launch: tickets are (matrix, unit) pairs
+// merged in phase order with every matrix's own order kept, so the same
+// argument as in race_flow_kernel makes it deadlock-free.
+template <typename ValT, int K>
+__global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* __restrict__ mats, BatchArgs b,
+                                                          int32_t wmax) {
+  extern __shared__ double smem[];
+  double* xw = smem;
+  double* yw = smem + static_cast<size_t>(wmax) * K;
+  uint32_t* gw = reinterpret_cast<uint32_t*>(smem + 2 * static_cast<size_t>(wmax) * K);
+  __shared__ int32_t s_ticket[1];
+  const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
+  const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < kSlice;
+  uint64_t* counter = reinterpret_cast<uint64_t*>(b.state + b.state_words - 2);
+  uint32_t* status = b.state + b.state_words - 4;
+  for (;;) {
     __syncthreads();
     if (wave0) {
       if (tid == 0) {
-        if (f.trace) {
-          const uint64_t t3 = wall_clock();
-          f.trace[4 * static_cast<size_t>(u) + 0] = t0;
-          f.trace[4 * static_cast<size_t>(u) + 1] = t1;
-          f.trace[4 * static_cast<size_t>(u) + 2] = t2;
-          f.trace[4 * static_cast<size_t>(u) + 3] = t3;
-        }
-        __hip_atomic_store(f.done + u, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t = atomicAdd(reinterpret_cast<unsigned long long*>(counter), 1ull);
+        s_ticket[0] = t < static_cast<uint64_t>(b.n_tickets) ? static_cast<int32_t>(t) : -1;
       }
     }
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(s_ticket[0]);
+    if (t < 0) break;
+    const int32_t m = __builtin_amdgcn_readfirstlane(b.ticket_mat[t]);
+    const int32_t u = __builtin_amdgcn_readfirstlane(b.ticket_unit[t]);
+    const BatchMat<ValT> mm = mats[m];
+    flow_unit<ValT, K>(mm.a, u, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u, mm.x, mm.y, xw, yw, gw, tid,
+                       nthr, wave0);
   }
 }
 
@@ -502,6 +555,44 @@ template hipError_t launch_race_flow<float>(const UnitArgs<float>&, const FlowAr
                                             int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
 template hipError_t race_flow_occupancy<double>(int32_t, int32_t, int32_t, int32_t*);
 template hipError_t race_flow_occupancy<float>(int32_t, int32_t, int32_t, int32_t*);
+
+template <typename ValT, int K>
+struct BatchTag {};
+
+template <typename ValT, int K>
+static hipError_t launch_batch_k(const BatchMat<ValT>* mats, const BatchArgs& b, int32_t wmax, int32_t threads,
+                                 int32_t grid, hipStream_t st) {
+  const size_t lds = window_lds_bytes(wmax, K);
+  hipError_t e = set_lds_attr<BatchTag<ValT, K>, K>(reinterpret_cast<const void*>(&dev::race_batch_kernel<ValT, K>));
+  if (e != hipSuccess) return e;
+  const int64_t words = b.state_words;
+  hipLaunchKernelGGL(dev::batch_reset_kernel, dim3(static_cast<uint32_t>((words + 255) / 256)), dim3(256), 0, st,
+                     b.state, words);
+  hipLaunchKernelGGL((dev::race_batch_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, mats, b, wmax);
+  return hipGetLastError();
+}
+
+template <typename ValT>
+hipError_t launch_race_batch(const BatchMat<ValT>* mats, const BatchArgs& b, int32_t k, int32_t wmax, int32_t threads,
+                             int32_t grid, hipStream_t st) {
+#define CALL(KK) launch_batch_k<ValT, KK>(mats, b, wmax, threads, grid, st)
+  RACE_K_SWITCH(CALL)
+#undef CALL
+}
+
+template <typename ValT>
+hipError_t prepare_race_batch(int32_t k) {
+#define CALL(KK) set_lds_attr<BatchTag<ValT, KK>, KK>(reinterpret_cast<const void*>(&dev::race_batch_kernel<ValT, KK>))
+  RACE_K_SWITCH(CALL)
+#undef CALL
+}
+
+template hipError_t prepare_race_batch<double>(int32_t);
+template hipError_t prepare_race_batch<float>(int32_t);
+template hipError_t launch_race_batch<double>(const BatchMat<double>*, const BatchArgs&, int32_t, int32_t, int32_t,
+                                              int32_t, hipStream_t);
+template hipError_t launch_race_batch<float>(const BatchMat<float>*, const BatchArgs&, int32_t, int32_t, int32_t,
+                                             int32_t, hipStream_t);
 
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                            double* y, int32_t lpr, hipStream_t st) {

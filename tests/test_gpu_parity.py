@@ -117,7 +117,7 @@ def test_race_symm_spmm(k):
     m = matgen.stencil3d_27pt(16, seed=7)
     X = matgen.rhs(m.n, 23, k=k).reshape(m.n, k) if k > 1 else matgen.rhs(m.n, 23)
     Y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, X)
-    window = max(64, 4096 // k)
+    window = min(3840, (159 * 1024) // (16 * k + 4) - 16)
     Y, st = run_race(m, X, k=k, n_workers=128, window_max=window)
     absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(X))
     for j in range(k):
@@ -231,3 +231,69 @@ def test_race_full_size_3d27pt_128(nt, mode):
     rows = np.random.default_rng(0).choice(m.n, size=200, replace=False)
     exact = _sampled_rows_exact(m, x, rows)
     assert np.all(np.abs(y[rows] - exact) <= 1e-12 * np.max(np.abs(y_ref)))
+
+
+def _batch_mats():
+    return [matgen.stencil2d_5pt(40, seed=51), matgen.stencil3d_27pt(14, seed=52),
+            matgen.banded_irregular(6000, seed=53, band=600), matgen.stencil2d_5pt(23, seed=54),
+            matgen.random_symmetric(300, 0.02, seed=55), matgen.stencil3d_27pt(9, seed=56)]
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_batch_graph_replays(k):
+    mats = _batch_mats()
+    window = min(3840, (159 * 1024) // (16 * k + 4) - 16)  # x, y windows of k doubles + the index, per entry
+    scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500), window_max=window) for m in mats]
+    batch = R.Batch(scheds, k)
+    info = batch.info()
+    print(f"batch k={k}: {info}", flush=True)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(7 + k)
+    xs = [torch.empty((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=DEV) for m in mats]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    batch.bind(xs, ys)
+    for rep in range(3):
+        for x in xs:  # eager work between replays: new right-hand sides
+            x.uniform_(-1.0, 1.0, generator=gen)
+        for y in ys:
+            y.fill_(float("nan"))
+        batch.run(use_graph=(rep != 1))
+        torch.cuda.synchronize()
+        batch.check()
+        for m, s, x, y in zip(mats, scheds, xs, ys):
+            perm = s.perm()
+            xp = x.cpu().numpy()
+            x_orig = np.empty_like(xp)
+            x_orig[perm] = xp
+            y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x_orig)[perm]
+            absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(x_orig))[perm]
+            yh = y.cpu().numpy()
+            for j in range(k):
+                sl = (slice(None), j) if k > 1 else slice(None)
+                _check(yh[sl], y_ref[sl], absax[sl], _full_row_len(m), f"batch k={k} rep={rep} {m.name} col={j}")
+    batch.close()
+    for s in scheds:
+        s.close()
+
+
+def test_traced_product_stamps():
+    m = matgen.stencil3d_27pt(20, seed=61)
+    x = matgen.rhs(m.n, 61)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=64)
+    st = s.stats()
+    xd = torch.as_tensor(x, device=DEV)
+    xp = torch.empty_like(xd)
+    s.permute(xd, xp, True)
+    yp = torch.full_like(xd, float("nan"))
+    tr = torch.zeros(4 * st["n_units"], dtype=torch.int64, device=DEV)
+    s.traced(xp, yp, tr)
+    torch.cuda.synchronize()
+    s.check()
+    t = tr.cpu().numpy().reshape(-1, 4)
+    assert np.all(t[:, 0] > 0)
+    assert np.all(np.diff(t, axis=1) >= 0)
+    y = torch.empty_like(xd)
+    s.permute(yp, y, False)
+    y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
+    _check(y.cpu().numpy(), y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), "traced")
+    s.close()
