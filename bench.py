@@ -89,6 +89,82 @@ def cpu_baseline(m, budget_s):
     return dt, reps
 
 
+def run_batch(args, k, torch):
+    """64 seeded matrices of uneven size (2D 5-pt / 3D 27-pt / irregular
+    banded, 1e4..5e5 rows) with k right-hand sides: one hipGraph replay of the
+    persistent batch launch with autotuned shapes, against 64 separate
+    product launches with the library's default shapes."""
+    import numpy as np
+
+    import matgen
+    import paper_1907_06487_amd as R
+    from paper_1907_06487_amd import autotune
+    from oracle import symmspmv as O
+
+    t0 = time.perf_counter()
+    mats = matgen.config_batch(64, 100)
+    log(f"batch64 k={k}: generated {len(mats)} matrices, {sum(m.n for m in mats)} rows, "
+        f"{sum(m.nnz for m in mats)} stored entries in {time.perf_counter() - t0:.1f}s")
+    dev = "cuda:0"
+    shape = lambda m: (m.n, k) if k > 1 else (m.n,)
+    xs = [torch.rand(shape(m), dtype=torch.float64, device=dev) * 2 - 1 for m in mats]
+    ys = [torch.empty_like(x) for x in xs]
+    # plain: library defaults (window capped for k), one launch per matrix
+    plain = [R.Schedule(m.n, m.row_ptr, m.col, m.val, window_max=autotune.max_window(k)) for m in mats]
+    stats = [s.stats() for s in plain]
+    flops = sum(2 * st["nnz_full"] * k for st in stats)
+    bytes_min = sum(12 * m.nnz + 4 * (m.n + 1) + 16 * m.n * k for m in mats)
+
+    def run_plain():
+        for s, x, y in zip(plain, xs, ys):
+            if k > 1:
+                s.spmm(x, y)
+            else:
+                s.spmv(x, y)
+
+    ms_plain = time_ring(lambda x, y: run_plain(), [0], [0], args.steps, args.warmup, torch)
+    t0 = time.perf_counter()
+    scheds, batch, chosen = autotune.tune_batch(mats, k, log=log)
+    t_tune = time.perf_counter() - t0
+    batch.bind(xs, ys)
+    ms_graph = time_ring(lambda x, y: batch.run(use_graph=True), [0], [0], args.steps, args.warmup, torch)
+    ms_direct = time_ring(lambda x, y: batch.run(use_graph=False), [0], [0], args.steps, args.warmup, torch)
+    batch.check()
+    # error of every matrix against the oracle (permuted order)
+    batch.run(use_graph=True)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for m, s, x, y in zip(mats, scheds, xs, ys):
+        perm = s.perm()
+        xh = x.cpu().numpy()
+        xo = np.empty_like(xh)
+        xo[perm] = xh
+        y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, xo)[perm]
+        worst = max(worst, O.errors(y.cpu().numpy(), y_ref)[0])
+    log(f"batch64 k={k}: graph {ms_graph * 1e3:.1f} us, direct {ms_direct * 1e3:.1f} us, 64 separate {ms_plain * 1e3:.1f} us, "
+        f"tuning {t_tune:.1f}s, worst error {worst:.2e}")
+    out = {
+        "metric": "batched SymmSpMM GFLOP/s, 64 matrices in one hipGraph replay", "value": round(flops / (ms_graph * 1e-3) / 1e9, 3),
+        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch64_k{k}", "matrices": 64, "rows": sum(m.n for m in mats), "k": k,
+                   "block_threads": chosen["block_threads"],
+                   "n_workers": [p["n_workers"] for p in chosen["params"]],
+                   "window_max": [p["window_max"] for p in chosen["params"]]},
+        "roofline": {"bound": "hbm", "achieved": round(bytes_min / (ms_graph * 1e-3) / 1e9, 3), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(bytes_min / (ms_graph * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": None},
+        "separate_launches": {"ms": ms_plain, "gflops": flops / (ms_plain * 1e-3) / 1e9},
+        "batch_direct_launch": {"ms": ms_direct},
+        "speedup_vs_separate": ms_plain / ms_graph,
+        "error": {"norm_worst": worst},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
+    for s in scheds + plain:
+        s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +180,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--k", default="1", help="batch64 workload: right-hand sides, e.g. 1,4,16")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a device copy of this many MiB (reference for the traffic counters)")
     ap.add_argument("--sweep", default="",
@@ -122,6 +199,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batch64":
+        for k in (int(v) for v in args.k.split(",")):
+            run_batch(args, k, torch)
+        return
     m, desc = workload(args.workload)
     log(f"workload {args.workload}: n={m.n} nnz_upper={m.nnz}")
     t0 = time.perf_counter()

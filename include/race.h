@@ -179,8 +179,10 @@ int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, in
 /* Group `count` uploaded schedules (same device and value type) for k
  * right-hand sides each.  Their units are merged into one ticket sequence
  * (by phase, keeping every matrix's own order) for a single persistent
- * dataflow launch.  The schedules are borrowed and must outlive the batch. */
-int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, race_batch_t* out);
+ * dataflow launch of `threads` threads per workgroup (0: the largest
+ * block_threads of the schedules).  The schedules are borrowed and must
+ * outlive the batch. */
+int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_t threads, race_batch_t* out);
 
 /* Set the device arrays of every matrix (host arrays of `count` device
  * pointers; X[m], Y[m] row-major n_m x k in matrix m's permuted order) and

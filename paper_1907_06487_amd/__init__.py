@@ -96,10 +96,10 @@ class Schedule:
 class Batch:
     """Owning wrapper around a race_batch_t (the schedules must outlive it)."""
 
-    def __init__(self, schedules, k):
+    def __init__(self, schedules, k, threads=0):
         self.schedules = list(schedules)
         self.k = int(k)
-        self.handle = race_batch_create([s.handle for s in self.schedules], self.k)
+        self.handle = race_batch_create([s.handle for s in self.schedules], self.k, threads)
 
     def bind(self, xs, ys):
         race_batch_bind(self.handle, xs, ys)

@@ -101,7 +101,8 @@ def lib():
         "race_symm_spmv_atomic": ([_P, _P, _P, _P], ctypes.c_int),
         "race_csr_destroy": ([_P], None),
         "race_last_error": ([], ctypes.c_char_p),
-        "race_batch_create": ([ctypes.c_int32, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
+        "race_batch_create": ([ctypes.c_int32, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
+                              ctypes.c_int),
         "race_batch_bind": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], ctypes.c_int),
         "race_batch_run": ([_P, ctypes.c_int32, _P], ctypes.c_int),
         "race_batch_check": ([_P], ctypes.c_int),
@@ -284,10 +285,10 @@ def race_last_error():
     return lib().race_last_error().decode()
 
 
-def race_batch_create(handles, k):
+def race_batch_create(handles, k, threads=0):
     arr = (_P * len(handles))(*[h.value if isinstance(h, _P) else h for h in handles])
     b = _P()
-    check(lib().race_batch_create(len(handles), arr, int(k), ctypes.byref(b)))
+    check(lib().race_batch_create(len(handles), arr, int(k), int(threads), ctypes.byref(b)))
     return b
 
 

@@ -1,0 +1,82 @@
+"""Schedule-shape autotuner.
+
+Picks, per matrix and number of right-hand sides k, the RACE worker count
+(N_t, Section 5), the unit window and the workgroup size by timing candidate
+schedules on the device (HIP events around the library's own product
+calls).  A batch needs one workgroup size for all matrices; `tune_batch`
+chooses it by timing the whole batch.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import Batch, Schedule
+
+
+def max_window(k: int) -> int:
+    """Largest unit window whose LDS (x and y windows of k doubles plus a
+    4-byte index per entry) fits a 159 KiB workgroup allocation."""
+    return min(3840, (159 * 1024) // (16 * k + 4) - 16)
+
+
+def candidates(n: int, k: int, block: int):
+    """Worker counts of 8000, 4000 and 2000 rows per worker at the largest
+    window that fits for k."""
+    wm = max_window(k)
+    nts = sorted({int(min(4096, max(4, n // r))) for r in (8000, 4000, 2000)})
+    return [dict(n_workers=nt, window_max=wm, block_threads=block) for nt in nts]
+
+
+def _time(fn, reps):
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0"):
+    """Best shape for one matrix: returns (params, ms, all results)."""
+    shape = (m.n, k) if k > 1 else (m.n,)
+    x = torch.rand(shape, dtype=torch.float64, device=device)
+    y = torch.empty_like(x)
+    results = []
+    for c in candidates(m.n, k, block):
+        s = Schedule(m.n, m.row_ptr, m.col, m.val, **c)
+        ms = _time(lambda: s.spmm(x, y) if k > 1 else s.spmv(x, y), reps)
+        s.close()
+        results.append((ms, c))
+    results.sort(key=lambda r: r[0])
+    return results[0][1], results[0][0], results
+
+
+def tune_batch(mats, k: int, blocks=(256, 512, 1024), reps: int = 5, device: str = "cuda:0", log=None):
+    """Per-matrix shapes (timed at 512 threads), then the workgroup size
+    whose whole batch replay runs fastest.  Returns (schedules, batch, chosen)."""
+    params = []
+    for i, m in enumerate(mats):
+        params.append(tune_matrix(m, k, 512, reps=3, device=device)[0])
+        if log and i % 16 == 15:
+            log(f"autotune k={k}: {i + 1}/{len(mats)} matrices")
+    scheds = [Schedule(m.n, m.row_ptr, m.col, m.val, **p) for m, p in zip(mats, params)]
+    xs = [torch.rand((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=device) for m in mats]
+    ys = [torch.empty_like(x) for x in xs]
+    best = None
+    for blk in blocks:
+        batch = Batch(scheds, k, threads=blk)
+        batch.bind(xs, ys)
+        ms = _time(lambda: batch.run(use_graph=True), reps)
+        if best is None or ms < best[0]:
+            if best is not None:
+                best[1].close()
+            best = (ms, batch, blk)
+        else:
+            batch.close()
+    ms, batch, blk = best
+    return scheds, batch, {"block_threads": blk, "params": params, "ms": ms}

@@ -537,7 +537,8 @@ static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
 
 extern "C" {
 
-int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, race_batch_t* out) {
+int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_t threads_override,
+                      race_batch_t* out) {
   if (!out || !s || count < 1) return fail(RACE_EINVAL, "need count >= 1 schedules and an output handle");
   *out = nullptr;
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
@@ -555,6 +556,12 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, race_b
   }
   if (race::window_lds_bytes(wmax, k) > 159 * 1024)
     return fail(RACE_EUNSUPPORTED, "largest window x k exceeds the LDS; rebuild with a smaller window_max");
+  if (threads_override != 0) {
+    if (threads_override != 64 && threads_override != 128 && threads_override != 256 && threads_override != 512 &&
+        threads_override != 1024)
+      return fail(RACE_EINVAL, "threads must be 0 (largest of the schedules) or 64, 128, 256, 512, 1024");
+    threads = threads_override;
+  }
   race_batch* b = new (std::nothrow) race_batch();
   if (!b) return fail(RACE_ENOMEM, "out of host memory");
   b->count = count;
