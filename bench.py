@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--window", type=int, default=3840)
     ap.add_argument("--value-type", default="f64", choices=["f64", "f32"])
     ap.add_argument("--exec-mode", default="flow", choices=["flow", "phases"])
+    ap.add_argument("--shared-atomics", type=int, default=1, choices=[0, 1],
+                    help="units of one leaf run concurrently, combining shared y entries atomically (1) or in order (0)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
@@ -184,7 +186,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a device copy of this many MiB (reference for the traffic counters)")
     ap.add_argument("--sweep", default="",
-                    help="n_workers:block[:window[:mode]] list, e.g. 256:256,512:512:2048:phases (stderr)")
+                    help="n_workers:block[:window[:mode[:shared]]] list, e.g. 256:256,512:512:2048:phases:0 (stderr)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
@@ -208,12 +210,12 @@ def main():
     t0 = time.perf_counter()
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
                    block_threads=args.block, window_max=args.window, value_type=args.value_type,
-                   exec_mode=args.exec_mode)
+                   exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics))
     t_build = time.perf_counter() - t0
     st = s.stats()
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
         "n_levels0", "depth", "n_leaves", "n_phases_used", "n_units", "max_window", "eta", "halo_total",
-        "sell_elems", "bytes_min", "bytes_kernel")}))
+        "sell_elems", "bytes_min", "bytes_kernel", "n_deps", "shared_touches", "n_zeroed")}))
 
     nring = max(2, -(-RING_BYTES // (8 * m.n)))
     gen = torch.Generator(device=dev)
@@ -238,7 +240,7 @@ def main():
     flops = 2 * st["nnz_full"]
     gflops = flops / (ms * 1e-3) / 1e9
     achieved = st["bytes_min"] / (ms * 1e-3) / 1e9
-    launches = st["n_phases_used"]
+    launches = (1 if args.exec_mode == "flow" else st["n_phases_used"]) + (1 if st["n_zeroed"] else 0)
     log(f"RACE: {ms * 1e3:.2f} us/product, {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s algorithmic "
         f"({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes {st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
 
@@ -247,12 +249,13 @@ def main():
         parts = item.split(":")
         win = int(parts[2]) if len(parts) > 2 else args.window
         mode = parts[3] if len(parts) > 3 else args.exec_mode
+        shared = bool(int(parts[4])) if len(parts) > 4 else bool(args.shared_atomics)
         s2 = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=nt, max_stages=args.max_stages, block_threads=blk,
-                        window_max=win, value_type=args.value_type, exec_mode=mode)
+                        window_max=win, value_type=args.value_type, exec_mode=mode, shared_atomics=shared)
         st2 = s2.stats()
         ms2 = time_ring(lambda x, y: s2.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
         s2.check()
-        log(f"sweep n_workers={nt} block={blk} window={win} mode={mode}: {ms2 * 1e3:.2f} us, "
+        log(f"sweep n_workers={nt} block={blk} window={win} mode={mode} shared={int(shared)}: {ms2 * 1e3:.2f} us, "
             f"{st2['bytes_min'] / (ms2 * 1e-3) / 1e9 / PEAK_HBM_GBS * 100:.1f}% peak, phases={st2['n_phases_used']} "
             f"leaves={st2['n_leaves']} units={st2['n_units']} kernel bytes={st2['bytes_kernel']}")
         s2.close()
@@ -312,7 +315,8 @@ def main():
         tr = json.load(open(tpath))
         same = (tr.get("source_hash") == kernel_source_hash() and tr.get("bytes_kernel") == st["bytes_kernel"]
                 and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
-                and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode)
+                and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode
+                and tr.get("shared_atomics", 0) == args.shared_atomics)
         if same and args.value_type == "f64":
             traffic = tr.get("bytes_per_launch")
 
@@ -322,7 +326,8 @@ def main():
         "dtype": "f64" if args.value_type == "f64" else "f32-values/f64-accumulate", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_upper": m.nnz,
                    "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
-                   "window_max": args.window, "exec_mode": args.exec_mode, "phases": launches, "leaves": st["n_leaves"], "eta": st["eta"]},
+                   "window_max": args.window, "exec_mode": args.exec_mode, "shared_atomics": args.shared_atomics,
+                   "phases": st["n_phases_used"], "leaves": st["n_leaves"], "eta": st["eta"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "launches_per_step": launches,

@@ -63,6 +63,9 @@ typedef struct {
   int32_t cost_model_len;  /* number of floats in cost_model */
   int32_t exec_mode;       /* 0: one launch per phase; 1: one persistent dataflow launch (units wait only for the
                               earlier units they conflict with) */
+  int32_t shared_atomics;  /* a leaf whose rows need several LDS windows is cut into several units.  0: those units
+                              run one after another; 1: they run concurrently and combine the y entries they share
+                              with global float64 atomic adds (other entries stay atomic-free) */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */
@@ -94,11 +97,14 @@ typedef struct {
   int32_t flow_grid;         /* workgroups of the dataflow launch (0 before the first dataflow product) */
   int32_t exec_mode;
   int64_t wall_clock_hz;     /* rate of the device clock used by traced products (set by race_schedule_upload) */
+  int64_t shared_touches;    /* (unit, index) touches combined by atomic adds (shared_atomics) */
+  int64_t n_zeroed;          /* y entries cleared before each product (first touched by a shared unit) */
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
  * nonzeros, no global pass, float64 values, window 3840, 256 threads,
- * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice), exec_mode 1. */
+ * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice), exec_mode 1,
+ * shared_atomics 1. */
 int race_params_default(race_params* p);
 
 /* Build the RACE schedule and the kernel's data layout on the host.
@@ -138,11 +144,17 @@ int race_schedule_leaves(race_schedule_t s, int32_t* n_leaves, int32_t* node, in
 
 /* Units in execution order: leaf index (into the leaves list), own rows
  * [row_lo, row_hi), halo count; and the concatenated halo lists (global
- * indices in permuted order, ascending per unit) with their first-touch flags
- * (1: this unit is the first to write that y entry), and the first-touch flag
- * of every row.  Sizes via NULL arrays: *n_units, *n_halo.  Host arrays. */
+ * indices in permuted order, ascending per unit) with their flags, and the
+ * flags of every row as touched by its own unit.  Flag bit 0: this unit is
+ * the first to write that y entry (it stores); bit 1: the entry is shared
+ * with other units of the same leaf (atomic add, shared_atomics).  Sizes via
+ * NULL arrays: *n_units, *n_halo.  Host arrays. */
 int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, int32_t* unit_leaf, int32_t* row_lo,
-                        int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_first, uint8_t* row_first);
+                        int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_flags, uint8_t* row_flags);
+
+/* The y entries cleared before every product (ascending, permuted order):
+ * those whose first toucher is a shared touch.  idx NULL: only *count. */
+int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx);
 
 /* y = A x (Algorithm "SymmSpMV"): x, y device float64 arrays of n in
  * permuted order, y overwritten (no clearing needed), x and y must not

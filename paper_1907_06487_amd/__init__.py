@@ -14,14 +14,15 @@ from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_ch
                    race_batch_destroy, race_batch_info, race_batch_run, race_build_schedule, race_csr_create, race_csr_destroy,
                    race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
-                   race_schedule_units, race_schedule_upload, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
+                   race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
                    race_symm_spmv_atomic)
 
 BALANCE = {"nnz": 0, "rows": 1}
 
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
-                block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow"):
+                block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
+                shared_atomics=True):
     p = race_params_default()
     p.n_workers = int(n_workers)
     p.max_stages = int(max_stages)
@@ -31,6 +32,7 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.window_max = int(window_max)
     p.block_threads = int(block_threads)
     p.exec_mode = {"phases": 0, "flow": 1}[exec_mode]
+    p.shared_atomics = int(bool(shared_atomics))
     eps = list(eps) + [eps[-1]] * (8 - len(eps))
     for i in range(8):
         p.eps[i] = float(eps[i])
@@ -67,6 +69,9 @@ class Schedule:
 
     def units(self):
         return race_schedule_units(self.handle, self.n)
+
+    def zero_list(self):
+        return race_schedule_zero_list(self.handle)
 
     def spmv(self, x, y, stream=None):
         race_symm_spmv(self.handle, x, y, stream)

@@ -24,7 +24,7 @@ ERRORS = {-1: "RACE_EINVAL", -2: "RACE_ENOMEM", -3: "RACE_EHIP", -4: "RACE_EUNSU
 EXPORTS = [
     "race_params_default", "race_build_schedule", "race_schedule_upload", "race_schedule_destroy",
     "race_schedule_stats", "race_schedule_perm", "race_schedule_tree", "race_schedule_leaves",
-    "race_schedule_units", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
+    "race_schedule_units", "race_schedule_zero_list", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
     "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
     "race_batch_create", "race_batch_bind", "race_batch_run", "race_batch_check", "race_batch_info",
     "race_batch_destroy",
@@ -43,7 +43,7 @@ class race_params(ctypes.Structure):
         ("balance_by", ctypes.c_int32), ("global_lb", ctypes.c_int32), ("value_type", ctypes.c_int32),
         ("window_max", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("eps", ctypes.c_double * 8),
         ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
-        ("exec_mode", ctypes.c_int32),
+        ("exec_mode", ctypes.c_int32), ("shared_atomics", ctypes.c_int32),
     ]
 
 
@@ -57,7 +57,8 @@ class race_stats(ctypes.Structure):
         ("sell_elems", ctypes.c_int64), ("halo_total", ctypes.c_int64), ("rows_rmw", ctypes.c_int64),
         ("halo_rmw", ctypes.c_int64), ("bytes_min", ctypes.c_int64), ("bytes_kernel", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
-        ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64),
+        ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64), ("shared_touches", ctypes.c_int64),
+        ("n_zeroed", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -90,6 +91,7 @@ def lib():
         "race_schedule_tree": ([_P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
         "race_schedule_leaves": ([_P, _I32P, _I32P, _I32P], ctypes.c_int),
         "race_schedule_units": ([_P, _I32P, _I64P, _I32P, _I32P, _I32P, _I64P, _I32P, _U8P, _U8P], ctypes.c_int),
+        "race_schedule_zero_list": ([_P, _I64P, _I32P], ctypes.c_int),
         "race_schedule_check": ([_P], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
@@ -220,14 +222,22 @@ def race_schedule_units(h, n):
     hi = np.empty(u, dtype=np.int32)
     hptr = np.empty(u + 1, dtype=np.int64)
     halo = np.empty(hcount, dtype=np.int32)
-    hfirst = np.empty(hcount, dtype=np.uint8)
-    rfirst = np.empty(n, dtype=np.uint8)
+    hflags = np.empty(hcount, dtype=np.uint8)
+    rflags = np.empty(n, dtype=np.uint8)
     check(lib().race_schedule_units(h, ctypes.byref(nu), ctypes.byref(nh), _np_ptr(unit_leaf, ctypes.c_int32),
                                     _np_ptr(lo, ctypes.c_int32), _np_ptr(hi, ctypes.c_int32),
                                     _np_ptr(hptr, ctypes.c_int64), _np_ptr(halo, ctypes.c_int32),
-                                    _np_ptr(hfirst, ctypes.c_uint8), _np_ptr(rfirst, ctypes.c_uint8)))
-    return {"unit_leaf": unit_leaf, "lo": lo, "hi": hi, "halo_ptr": hptr, "halo": halo, "halo_first": hfirst,
-            "row_first": rfirst}
+                                    _np_ptr(hflags, ctypes.c_uint8), _np_ptr(rflags, ctypes.c_uint8)))
+    return {"unit_leaf": unit_leaf, "lo": lo, "hi": hi, "halo_ptr": hptr, "halo": halo, "halo_flags": hflags,
+            "row_flags": rflags}
+
+
+def race_schedule_zero_list(h):
+    cnt = ctypes.c_int64()
+    check(lib().race_schedule_zero_list(h, ctypes.byref(cnt), None))
+    out = np.empty(cnt.value, dtype=np.int32)
+    check(lib().race_schedule_zero_list(h, ctypes.byref(cnt), _np_ptr(out, ctypes.c_int32)))
+    return out
 
 
 def race_schedule_check(h):

@@ -87,14 +87,16 @@ struct race_schedule {
   uint32_t epoch = 0;
   uint64_t ticket_next = 0;
   int32_t n_cus = 0;
-  DevBuf<uint32_t> halo, row_first_bits, chunk_off;
+  DevBuf<uint32_t> halo, row_flags, chunk_off;
+  DevBuf<int32_t> zero_idx;
   DevBuf<uint16_t> lane_slot, sell_slot;
   DevBuf<double> lane_diag64, sell_val64;
   DevBuf<float> lane_diag32, sell_val32;
 
   void free_device() {
     release(leaf_units); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
-    release(chunk_len); release(new2old); release(halo); release(row_first_bits); release(chunk_off);
+    release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
+    release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(dep_ptr); release(dep_idx); release(flow_state);
     uploaded = false;
@@ -121,7 +123,7 @@ struct race_batch {
   int device = -1;
   std::vector<race_schedule_t> mats;
   std::vector<int64_t> unit_base;  // offset of each matrix's done flags in the state
-  DevBuf<int32_t> ticket_mat, ticket_unit;
+  DevBuf<int32_t> ticket_mat, ticket_unit, zero_mat, zero_idx;
   DevBuf<uint32_t> state;
   void* d_mats = nullptr;          // BatchMat<ValT>[count]
   bool bound = false;
@@ -150,6 +152,7 @@ int race_params_default(race_params* p) {
   p->cost_model = nullptr;
   p->cost_model_len = 0;
   p->exec_mode = 1;
+  p->shared_atomics = 1;
   return RACE_OK;
 }
 
@@ -167,6 +170,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     return fail(RACE_EUNSUPPORTED, "balance_by must be 0 (nonzeros) or 1 (rows)");
   if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
   if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
+  if (prm.shared_atomics < 0 || prm.shared_atomics > 1) return fail(RACE_EINVAL, "shared_atomics must be 0 or 1");
   if (prm.window_max == 0) prm.window_max = 3840;
   if (prm.window_max < 2 || prm.window_max > 8000) return fail(RACE_EINVAL, "window_max must be in 2..8000");
   if (prm.block_threads == 0) prm.block_threads = 256;
@@ -197,7 +201,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
       return fail(RACE_EINVAL, err);
     }
     int code = RACE_OK;
-    err = race::build_layout(n, row_ptr, col, val, s->tree, prm.window_max, prm.value_type, s->L, &code);
+    err = race::build_layout(n, row_ptr, col, val, s->tree, prm.window_max, prm.value_type, prm.shared_atomics != 0,
+                             s->L, &code);
     if (!err.empty()) {
       delete s;
       return fail(code, err);
@@ -233,12 +238,15 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     const int64_t vb = prm.value_type == 1 ? 4 : 8;
     // slices: value + 2-byte slot per element; per lane: slot + diagonal;
     // per slice: offset + length; per unit: 4 ints; halo: index;
-    // x: own rows + halo read once; y: own rows + halo written, RMW read.
+    // x: own rows + halo read once; y: own rows + halo written, RMW and
+    // atomic touches read; cleared entries: index read, zero written.
+    st.shared_touches = L.shared_touches;
+    st.n_zeroed = static_cast<int64_t>(L.zero_idx.size());
     st.bytes_kernel = st.sell_elems * (vb + 2) + static_cast<int64_t>(st.n_chunks) * (8 + race::kSlice * (2 + vb)) +
                       static_cast<int64_t>(st.n_units) * 16 + st.halo_total * 4 +
-                      (static_cast<int64_t>(n) + 31) / 32 * 4 +
+                      (static_cast<int64_t>(n) + 15) / 16 * 4 +
                       8 * (static_cast<int64_t>(n) + st.halo_total) + 8 * (static_cast<int64_t>(n) + st.halo_total) +
-                      8 * (st.rows_rmw + st.halo_rmw);
+                      8 * (st.rows_rmw + st.halo_rmw + st.shared_touches) + 12 * st.n_zeroed;
     st.device_bytes = 0;
     st.n_deps = static_cast<int64_t>(L.dep_idx.size());
     st.flow_grid = 0;
@@ -277,7 +285,8 @@ int race_schedule_upload(race_schedule_t s) {
   UP(chunk_len, L.chunk_len)
   UP(new2old, s->tree.perm)
   UP(halo, L.halo)
-  UP(row_first_bits, L.row_first_bits)
+  UP(row_flags, L.row_flags)
+  UP(zero_idx, L.zero_idx)
   UP(chunk_off, L.chunk_off)
   UP(lane_slot, L.lane_slot)
   UP(sell_slot, L.sell_slot)
@@ -362,7 +371,7 @@ int race_schedule_leaves(race_schedule_t s, int32_t* n_leaves, int32_t* node, in
 }
 
 int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, int32_t* unit_leaf, int32_t* row_lo,
-                        int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_first, uint8_t* row_first) {
+                        int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_flags, uint8_t* row_flags) {
   if (!s || !n_units || !n_halo) return fail(RACE_EINVAL, "NULL argument");
   const race::Layout& L = s->L;
   *n_units = static_cast<int32_t>(L.unit_lo.size());
@@ -375,11 +384,19 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
   if (halo_ptr)
     for (size_t u = 0; u < L.unit_halo_ptr.size(); ++u) halo_ptr[u] = L.unit_halo_ptr[u];
   for (size_t j = 0; j < L.halo.size(); ++j) {
-    if (halo) halo[j] = static_cast<int32_t>(L.halo[j] & 0x7fffffffu);
-    if (halo_first) halo_first[j] = (L.halo[j] >> 31) ? 1 : 0;
+    if (halo) halo[j] = static_cast<int32_t>(L.halo[j] & race::kIndexMask);
+    if (halo_flags)
+      halo_flags[j] = static_cast<uint8_t>(((L.halo[j] & race::kFirstBit) ? 1 : 0) | ((L.halo[j] & race::kSharedBit) ? 2 : 0));
   }
-  if (row_first)
-    for (int32_t r = 0; r < L.n; ++r) row_first[r] = (L.row_first_bits[r >> 5] >> (r & 31)) & 1u;
+  if (row_flags)
+    for (int32_t r = 0; r < L.n; ++r) row_flags[r] = static_cast<uint8_t>(race::row_flag(L.row_flags, r));
+  return RACE_OK;
+}
+
+int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx) {
+  if (!s || !count) return fail(RACE_EINVAL, "NULL argument");
+  *count = static_cast<int64_t>(s->L.zero_idx.size());
+  if (idx) std::copy(s->L.zero_idx.begin(), s->L.zero_idx.end(), idx);
   return RACE_OK;
 }
 
@@ -388,7 +405,7 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
 template <typename ValT>
 static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const ValT* vals) {
   return race::UnitArgs<ValT>{s->leaf_units.p, s->unit_lo.p,    s->unit_hi.p,        s->unit_halo_ptr.p,
-                              s->halo.p,          s->row_first_bits.p, s->unit_chunk_ptr.p, s->chunk_off.p,
+                              s->halo.p,          s->row_flags.p,    s->unit_chunk_ptr.p, s->chunk_off.p,
                               s->chunk_len.p,     s->lane_slot.p,  diag,                vals,
                               s->sell_slot.p};
 }
@@ -428,11 +445,16 @@ template <typename ValT>
 static int run_phases(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
                       uint64_t* trace, hipStream_t st) {
   const race::Layout& L = s->L;
+  // a leaf's units run on one workgroup in order, or each on its own
+  // workgroup when they combine their shared entries atomically
+  const int32_t per_unit = s->params.shared_atomics;
   for (int32_t ph = 0; ph < s->tree.n_phases; ++ph) {
-    const int32_t l0 = L.phase_leaf_ptr[ph], l1 = L.phase_leaf_ptr[ph + 1];
-    if (l1 == l0) continue;
+    const std::vector<int32_t>& ptr = per_unit ? L.phase_unit_ptr : L.phase_leaf_ptr;
+    const int32_t i0 = ptr[ph], i1 = ptr[ph + 1];
+    if (i1 == i0) continue;
     const int32_t wmax = std::max(1, L.phase_max_window[ph]);
-    hipError_t e = race::launch_race_phase<ValT>(a, l0, l1 - l0, k, x, y, wmax, s->params.block_threads, trace, st);
+    hipError_t e =
+        race::launch_race_phase<ValT>(a, i0, i1 - i0, per_unit, k, x, y, wmax, s->params.block_threads, trace, st);
     if (e != hipSuccess) return hip_fail(e, "RACE phase launch");
   }
   return RACE_OK;
@@ -450,6 +472,8 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
     return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
                                        " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t ze = race::launch_zero_entries(y, k, s->zero_idx.p, static_cast<int64_t>(s->L.zero_idx.size()), st);
+  if (ze != hipSuccess) return hip_fail(ze, "clearing shared entries");
   if (s->params.value_type == 0) {
     const auto a = unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p);
     return s->params.exec_mode == 1 ? run_flow<double>(s, a, k, x, y, trace, st)
@@ -523,11 +547,14 @@ static void batch_release(race_batch_t b) {
   b->d_mats = nullptr;
   release(b->ticket_mat);
   release(b->ticket_unit);
+  release(b->zero_mat);
+  release(b->zero_idx);
   release(b->state);
 }
 
 static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
-  race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count), b->n_tickets};
+  race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count), b->n_tickets,
+                    b->zero_mat.p, b->zero_idx.p, static_cast<int64_t>(b->zero_idx.count)};
   if (b->value_type == 0)
     return race::launch_race_batch<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), a, b->k, b->wmax,
                                            b->threads, b->grid, st);
@@ -598,6 +625,13 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     tm[i] = tk[i].m;
     tu[i] = tk[i].u;
   }
+  // y entries to clear at the start of a run, of every matrix
+  std::vector<int32_t> zm, zi;
+  for (int32_t m = 0; m < count; ++m)
+    for (int32_t g : s[m]->L.zero_idx) {
+      zm.push_back(m);
+      zi.push_back(g);
+    }
   b->n_tickets = static_cast<int32_t>(tk.size());
   int64_t total = 0;
   const size_t words = static_cast<size_t>((total_units + 4 + 1) / 2 * 2);
@@ -605,6 +639,8 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   e = upload(b->ticket_mat, tm.data(), tm.size(), &total);
   if (e == hipSuccess) e = upload(b->ticket_unit, tu.data(), tu.size(), &total);
   if (e == hipSuccess) e = upload(b->state, zeros.data(), zeros.size(), &total);
+  if (e == hipSuccess) e = upload(b->zero_mat, zm.data(), zm.size(), &total);
+  if (e == hipSuccess) e = upload(b->zero_idx, zi.data(), zi.size(), &total);
   int32_t per_cu = 0;
   if (e == hipSuccess)
     e = vt == 0 ? race::race_flow_occupancy<double>(k, threads, wmax, &per_cu)

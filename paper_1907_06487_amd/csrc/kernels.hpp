@@ -15,7 +15,7 @@ struct UnitArgs {
   const int32_t* unit_hi;
   const int32_t* unit_halo_ptr;
   const uint32_t* halo;
-  const uint32_t* row_first_bits;
+  const uint32_t* row_flags;  // 2 bits per row: first writer, shared
   const int32_t* unit_chunk_ptr;
   const uint32_t* chunk_off;
   const int32_t* chunk_len;
@@ -53,13 +53,17 @@ struct BatchMat {
 
 // Tickets of a batch: (matrix, unit) pairs, merged so every matrix keeps its
 // own execution order; the counter, status word and all done flags are
-// cleared by a reset kernel at the start of every run.
+// cleared by a reset kernel at the start of every run, and the y entries the
+// matrices' shared units touch first are cleared with them.
 struct BatchArgs {
   const int32_t* ticket_mat;
   const int32_t* ticket_unit;
   uint32_t* state;       // all done flags, then status, then the 64-bit counter
   int64_t state_words;   // length of `state` in 32-bit words (even)
   int32_t n_tickets;
+  const int32_t* zero_mat;  // per cleared entry: matrix
+  const int32_t* zero_idx;  // and y index
+  int64_t n_zero;
 };
 
 // LDS bytes of a unit window of wmax entries with k right-hand sides: the
@@ -68,11 +72,18 @@ inline size_t window_lds_bytes(int32_t wmax, int32_t k) {
   return static_cast<size_t>(wmax) * (16 * static_cast<size_t>(k) + 4);
 }
 
-// One phase: n_leaves workgroups starting at leaf_base; k right-hand sides
+// One phase: `count` workgroups starting at `base`, each running one leaf's
+// units in order (per_unit 0; base and count index the leaves list) or one
+// unit (per_unit 1; base and count index the units); k right-hand sides
 // (1..16) in row-major x/y; wmax = largest unit window of the phase.
 template <typename ValT>
-hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, int32_t k, const double* x,
-                             double* y, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st);
+hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t base, int32_t count, int32_t per_unit, int32_t k,
+                             const double* x, double* y, int32_t wmax, int32_t threads, uint64_t* trace,
+                             hipStream_t st);
+
+// y[idx[i] * k + c] = 0 for i < count, c < k (entries whose first toucher
+// is a shared unit).
+hipError_t launch_zero_entries(double* y, int32_t k, const int32_t* idx, int64_t count, hipStream_t st);
 
 // Whole product in one persistent launch of `grid` workgroups; epoch and
 // ticket_base identify the call (see race_flow_kernel).

@@ -47,9 +47,13 @@ static void permute_upper(int32_t n, const int32_t* row_ptr, const int32_t* col,
 }
 
 std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, const Tree& tree,
-                         int32_t window_max, int32_t value_type, Layout& L, int* code) {
+                         int32_t window_max, int32_t value_type, bool shared_atomics, Layout& L, int* code) {
   *code = RACE_OK;
   L = Layout();
+  if (n >= (1 << 30)) {
+    *code = RACE_EUNSUPPORTED;
+    return "n must be below 2^30";
+  }
   L.n = n;
   L.value_type = value_type;
   permute_upper(n, row_ptr, col, val, tree.perm, L);
@@ -187,11 +191,38 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
     return "halo lists exceed 2^31 entries";
   }
 
-  // first writer of every y entry, and the independence check: units of
-  // different leaves in one phase must never touch the same index
-  L.row_first_bits.assign((static_cast<size_t>(n) + 31) / 32, 0u);
-  std::vector<int32_t> last_phase(static_cast<size_t>(n), -1), last_leaf(static_cast<size_t>(n), -1);
   const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  L.row_flags.assign((static_cast<size_t>(n) + 15) / 16, 0u);
+  // shared indices: touched by two or more units of one leaf
+  if (shared_atomics) {
+    std::vector<int32_t> cnt(static_cast<size_t>(n), 0), stamp(static_cast<size_t>(n), -1);
+    for (int32_t t = 0; t < n_leaves; ++t) {
+      const int32_t u0 = L.leaf_units[2 * static_cast<size_t>(t)], u1 = L.leaf_units[2 * static_cast<size_t>(t) + 1];
+      if (u1 - u0 < 2) continue;
+      auto count = [&](int32_t g) {
+        if (stamp[g] != t) {
+          stamp[g] = t;
+          cnt[g] = 0;
+        }
+        ++cnt[g];
+      };
+      for (int32_t u = u0; u < u1; ++u) {
+        for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) count(g);
+        for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j) count(static_cast<int32_t>(L.halo[j]));
+      }
+      for (int32_t u = u0; u < u1; ++u) {
+        for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g)
+          if (cnt[g] > 1) L.row_flags[static_cast<size_t>(g) >> 4] |= 2u << (2 * (g & 15));
+        for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j)
+          if (cnt[static_cast<int32_t>(L.halo[j])] > 1) L.halo[j] |= kSharedBit;
+      }
+    }
+  }
+
+  // first writer of every y entry, and the independence check: units of
+  // different leaves in one phase must never touch the same index.  A first
+  // touch that is shared is replaced by clearing y[g] before the product.
+  std::vector<int32_t> last_phase(static_cast<size_t>(n), -1), last_leaf(static_cast<size_t>(n), -1);
   for (int32_t u = 0; u < n_units; ++u) {
     const int32_t t = L.unit_leaf[u];
     const int32_t ph = tree.leaf_phase[t];
@@ -212,35 +243,58 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
         *code = RACE_EINTERNAL;
         return "phase " + std::to_string(ph) + ": row " + std::to_string(g) + " is touched by two leaves";
       }
-      if (f) L.row_first_bits[g >> 5] |= 1u << (g & 31);
-      else ++L.rows_rmw;
+      const bool shared = row_flag(L.row_flags, g) & 2u;
+      if (shared) {
+        ++L.shared_touches;
+        if (f) L.zero_idx.push_back(g);
+      } else if (f) {
+        L.row_flags[static_cast<size_t>(g) >> 4] |= 1u << (2 * (g & 15));
+      } else {
+        ++L.rows_rmw;
+      }
     }
     for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j) {
-      const int32_t g = static_cast<int32_t>(L.halo[j]);
+      const int32_t g = static_cast<int32_t>(L.halo[j] & kIndexMask);
       const int f = touch(g);
       if (f < 0) {
         *code = RACE_EINTERNAL;
         return "phase " + std::to_string(ph) + ": index " + std::to_string(g) + " is touched by two leaves";
       }
-      if (f) L.halo[j] |= kFirstBit;
-      else ++L.halo_rmw;
+      if (L.halo[j] & kSharedBit) {
+        ++L.shared_touches;
+        if (f) L.zero_idx.push_back(g);
+      } else if (f) {
+        L.halo[j] |= kFirstBit;
+      } else {
+        ++L.halo_rmw;
+      }
     }
   }
-  // conflict edges: for every index, each unit touching it waits for the
-  // previous unit (in execution order) that touched it
+  std::sort(L.zero_idx.begin(), L.zero_idx.end());
+  // conflict edges: a plain touch of y[g] waits for the last plain toucher and
+  // every shared toucher since; a shared touch waits for the last plain
+  // toucher only (atomic adds of shared touches commute)
   {
-    std::vector<int32_t> last_unit(static_cast<size_t>(n), -1);
-    std::vector<int32_t> deps;
+    std::vector<int32_t> last_plain(static_cast<size_t>(n), -1), deps, pool_unit;
+    std::vector<int64_t> shared_head(static_cast<size_t>(n), -1), pool_next;
     L.dep_ptr.assign(1, 0);
     for (int32_t u = 0; u < n_units; ++u) {
       deps.clear();
-      auto touch = [&](int32_t g) {
-        if (last_unit[g] >= 0) deps.push_back(last_unit[g]);
-        last_unit[g] = u;
+      auto touch = [&](int32_t g, bool shared) {
+        if (last_plain[g] >= 0) deps.push_back(last_plain[g]);
+        if (shared) {
+          pool_unit.push_back(u);
+          pool_next.push_back(shared_head[g]);
+          shared_head[g] = static_cast<int64_t>(pool_unit.size()) - 1;
+        } else {
+          for (int64_t q = shared_head[g]; q >= 0; q = pool_next[q]) deps.push_back(pool_unit[q]);
+          shared_head[g] = -1;
+          last_plain[g] = u;
+        }
       };
-      for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) touch(g);
+      for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) touch(g, row_flag(L.row_flags, g) & 2u);
       for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j)
-        touch(static_cast<int32_t>(L.halo[j] & 0x7fffffffu));
+        touch(static_cast<int32_t>(L.halo[j] & kIndexMask), L.halo[j] & kSharedBit);
       std::sort(deps.begin(), deps.end());
       deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
       for (int32_t v : deps) {
@@ -254,6 +308,9 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
     }
   }
   L.halo_total = static_cast<int64_t>(L.halo.size());
+  L.phase_unit_ptr.assign(static_cast<size_t>(tree.n_phases) + 1, 0);
+  for (int32_t u = 0; u < n_units; ++u) ++L.phase_unit_ptr[tree.leaf_phase[L.unit_leaf[u]] + 1];
+  for (int32_t p = 0; p < tree.n_phases; ++p) L.phase_unit_ptr[p + 1] += L.phase_unit_ptr[p];
   L.phase_max_window.assign(static_cast<size_t>(tree.n_phases), 0);
   for (int32_t u = 0; u < n_units; ++u) {
     const int32_t ph = tree.leaf_phase[L.unit_leaf[u]];

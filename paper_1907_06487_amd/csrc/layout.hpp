@@ -9,6 +9,16 @@
 // window-local 16-bit column slots:
 //   slot < R      -> own row  lo + slot
 //   slot >= R     -> halo[slot - R]  (a row after the unit, written by it)
+//
+// Every y index a unit touches carries two flags:
+//   first  - the unit is the first (in execution order) to write y[g]: it
+//            stores instead of read-modify-write;
+//   shared - (shared_atomics mode) two or more units of the unit's own leaf
+//            touch g.  Those units run concurrently and combine their
+//            contributions to y[g] with global atomic adds; y[g] is cleared
+//            before the product when such a unit is its first toucher.
+// Without shared entries the units of a leaf follow each other through
+// conflict edges instead.
 #pragma once
 
 #include <cstdint>
@@ -22,6 +32,8 @@ namespace race {
 constexpr int32_t kSlice = 64;           // rows per slice (one wavefront)
 constexpr uint16_t kNoRow = 0xFFFF;      // padding lane
 constexpr uint32_t kFirstBit = 0x80000000u;
+constexpr uint32_t kSharedBit = 0x40000000u;
+constexpr uint32_t kIndexMask = 0x3fffffffu;  // indices are below 2^30
 
 struct Layout {
   int32_t n = 0;
@@ -33,12 +45,14 @@ struct Layout {
 
   // execution structure
   std::vector<int32_t> phase_leaf_ptr;  // n_phases + 1, into the leaves list
+  std::vector<int32_t> phase_unit_ptr;  // n_phases + 1, into the units (execution order is phase-major)
   std::vector<int32_t> leaf_units;      // 2 per leaf (tree order): first unit, one past the last
   std::vector<int32_t> unit_order_leaves;  // leaves in execution order (phase, then descending work)
   std::vector<int32_t> unit_leaf, unit_lo, unit_hi;
   std::vector<int32_t> unit_halo_ptr;   // n_units + 1
-  std::vector<uint32_t> halo;           // index | kFirstBit when first writer
-  std::vector<uint32_t> row_first_bits; // bit r: the row's own unit writes y[r] first
+  std::vector<uint32_t> halo;           // index | kFirstBit | kSharedBit
+  std::vector<uint32_t> row_flags;      // 2 bits per row (word r / 16, bits 2 (r % 16) + {0 first, 1 shared})
+  std::vector<int32_t> zero_idx;        // ascending: y indices cleared before a product (first touch is shared)
   std::vector<int32_t> unit_chunk_ptr;  // n_units + 1
   std::vector<uint32_t> chunk_off;      // element offset of a slice
   std::vector<int32_t> chunk_len;       // slots per row | (slice width << 16)
@@ -48,17 +62,23 @@ struct Layout {
   std::vector<uint16_t> sell_slot;
   std::vector<int32_t> phase_max_window;  // per phase, largest unit window
   // conflict edges for dataflow execution: unit u waits for dep_idx[dep_ptr[u]
-  // .. dep_ptr[u+1]), the latest earlier units touching each of its indices
+  // .. dep_ptr[u+1]), the earlier units touching one of its indices that it
+  // cannot run beside (every pair except two shared touches)
   std::vector<int32_t> dep_ptr, dep_idx;
 
   int32_t max_window = 0;
-  int64_t halo_total = 0, rows_rmw = 0, halo_rmw = 0;
+  int64_t halo_total = 0, rows_rmw = 0, halo_rmw = 0, shared_touches = 0;
 };
+
+inline uint32_t row_flag(const std::vector<uint32_t>& f, int32_t r) {
+  return (f[static_cast<size_t>(r) >> 4] >> (2 * (r & 15))) & 3u;
+}
 
 // Builds the layout; returns "" or an error message.  *code receives the
 // RACE_E* code for errors (RACE_EUNSUPPORTED when a single row does not fit
-// the window, RACE_EINTERNAL when concurrent units would touch one index).
+// the window or n >= 2^30, RACE_EINTERNAL when units of two leaves of one
+// phase would touch one index).
 std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, const Tree& tree,
-                         int32_t window_max, int32_t value_type, Layout& out, int* code);
+                         int32_t window_max, int32_t value_type, bool shared_atomics, Layout& out, int* code);
 
 }  // namespace race

@@ -79,9 +79,10 @@ __device__ __forceinline__ void apply_batch(const double* v, const int32_t* sl, 
 //        yw[slot_j] += v_j * x[r]  for every j           (the scatter, LDS atomics)
 //        yw[slot_r] += acc
 //   3. flush the window: y[g] = yw[s] when this unit is the first writer of
-//      y[g], else y[g] += yw[s].  Units that may run at the same time never
-//      share an index (distance-2 coloring), so the flush needs no global
-//      atomics.
+//      y[g], else y[g] += yw[s].  Units of different leaves that may run at
+//      the same time never share an index (distance-2 coloring), so this
+//      needs no global atomics; only indices shared with other units of the
+//      unit's own leaf (when the layout marks them) take a global atomic add.
 template <typename ValT, int K>
 __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u, const double* __restrict__ x,
                                              double* xw, double* yw, uint32_t* gw, int32_t tid, int32_t nthr) {
@@ -100,14 +101,16 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u,
   }
   // 1. stage the windows while the first slice is in flight
   for (int32_t base = 0; base < W; base += kStage * nthr) {
-    // window index with the first-writer flag in bit 31, kept in LDS for the flush
+    // window index with the first-writer flag in bit 31 and the shared flag
+    // in bit 30, kept in LDS for the flush
     uint32_t h[kStage];
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
       if (s < R) {
         const uint32_t r = static_cast<uint32_t>(lo + s);
-        h[q] = r | (((a.row_first_bits[r >> 5] >> (r & 31)) & 1u) << 31);
+        const uint32_t f = (a.row_flags[r >> 4] >> (2 * (r & 15))) & 3u;
+        h[q] = r | ((f & 1u) << 31) | ((f & 2u) << 29);
       } else {
         h[q] = s < W ? a.halo[h0 + s - R] : 0u;
       }
@@ -117,7 +120,7 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u,
     for (int q = 0; q < kStage; ++q) {
       const bool in = base + q * nthr + tid < W;
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv[q][k] = in ? x[static_cast<size_t>(h[q] & 0x7fffffffu) * K + k] : 0.0;
+      for (int k = 0; k < K; ++k) xv[q][k] = in ? x[static_cast<size_t>(h[q] & 0x3fffffffu) * K + k] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
@@ -193,8 +196,12 @@ __device__ __forceinline__ void y_store(double* p, double v) {
 }
 
 // Step 3 of a unit: flush the y window.  y[g] = yw[s] when this unit is the
-// first writer of y[g], else y[g] += yw[s].  Units that may run at the same
-// time never share an index (distance-2 coloring), so no global atomics.
+// first writer of y[g], else y[g] += yw[s]; units of different leaves that
+// may run at the same time never share an index (distance-2 coloring), so
+// these need no global atomics.  Indices flagged shared (touched by several
+// units of this unit's own leaf, which run concurrently) are combined with
+// a global atomic add instead; they were cleared before the product when no
+// earlier unit wrote them.
 template <typename ValT, int K, bool kCoherent>
 __device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, double* __restrict__ y,
                                            const double* yw, const uint32_t* gw, int32_t tid, int32_t nthr) {
@@ -212,34 +219,41 @@ __device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, d
     for (int q = 0; q < kStage; ++q)
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        old[q][k] = (h[q] >> 31) ? 0.0 : y_load<kCoherent>(y + static_cast<size_t>(h[q] & 0x7fffffffu) * K + k);
+        old[q][k] = (h[q] >> 30) ? 0.0 : y_load<kCoherent>(y + static_cast<size_t>(h[q] & 0x3fffffffu) * K + k);
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
       if (s < W) {
+        double* p = y + static_cast<size_t>(h[q] & 0x3fffffffu) * K;
+        if (h[q] & 0x40000000u) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-          y_store<kCoherent>(y + static_cast<size_t>(h[q] & 0x7fffffffu) * K + k, old[q][k] + yw[s * K + k]);
+          for (int k = 0; k < K; ++k) unsafeAtomicAdd(p + k, yw[s * K + k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < K; ++k) y_store<kCoherent>(p + k, old[q][k] + yw[s * K + k]);
+        }
       }
     }
   }
 }
 
-// Phase-by-phase execution: one launch per phase, one workgroup per leaf
-// running the leaf's units in order.
 // Device wall clock (constant rate, common to all CUs) for unit traces.
 __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Phase-by-phase execution: one launch per phase; one workgroup per leaf
+// running the leaf's units in order, or (per_unit, when the units of a leaf
+// combine shared indices atomically) one workgroup per unit.
 template <typename ValT, int K>
-__global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32_t leaf_base,
+__global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32_t base, int32_t per_unit,
                                                          const double* __restrict__ x, double* __restrict__ y,
                                                          int32_t wmax, uint64_t* trace) {
   extern __shared__ double smem[];
   double* xw = smem;
   double* yw = smem + static_cast<size_t>(wmax) * K;
   uint32_t* gw = reinterpret_cast<uint32_t*>(smem + 2 * static_cast<size_t>(wmax) * K);
-  const int32_t leaf = leaf_base + static_cast<int32_t>(blockIdx.x);
-  const int32_t u0 = a.leaf_units[2 * leaf], u1 = a.leaf_units[2 * leaf + 1];
+  const int32_t item = base + static_cast<int32_t>(blockIdx.x);
+  const int32_t u0 = per_unit ? item : a.leaf_units[2 * item];
+  const int32_t u1 = per_unit ? item + 1 : a.leaf_units[2 * item + 1];
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
   for (int32_t u = u0; u < u1; ++u) {
     const uint64_t t0 = trace ? wall_clock() : 0;
@@ -348,11 +362,27 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
   }
 }
 
-// Clears a batch's dataflow state (done flags, status, ticket counter) with
-// plain stores, so a captured graph can replay the run.
-__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t* state, int64_t words) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < words) state[i] = 0u;
+// Clears a batch's dataflow state (done flags, status, ticket counter) and
+// the y entries first touched by shared units, with plain stores, so a
+// captured graph can replay the run.
+template <typename ValT>
+__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t* state, int64_t words,
+                                                          const BatchMat<ValT>* __restrict__ mats, int32_t k,
+                                                          const int32_t* __restrict__ zero_mat,
+                                                          const int32_t* __restrict__ zero_idx, int64_t n_zero) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += stride) state[i] = 0u;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_zero; i += stride) {
+    double* y = mats[zero_mat[i]].y + static_cast<size_t>(zero_idx[i]) * k;
+    for (int32_t c = 0; c < k; ++c) y[c] = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) zero_entries_kernel(double* __restrict__ y, int32_t k,
+                                                           const int32_t* __restrict__ idx, int64_t count) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count * k; i += stride)
+    y[static_cast<size_t>(idx[i / k]) * k + i % k] = 0.0;
 }
 
 // Many matrices in one persistent launch: tickets are (matrix, unit) pairs
@@ -462,13 +492,25 @@ static hipError_t set_lds_attr(const void* fn) {
 }
 
 template <typename ValT, int K>
-static hipError_t launch_leaf(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, const double* x, double* y,
-                              int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
+static hipError_t launch_leaf(const UnitArgs<ValT>& a, int32_t base, int32_t count, int32_t per_unit, const double* x,
+                              double* y, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
   const size_t lds = window_lds_bytes(wmax, K);
   hipError_t e = set_lds_attr<ValT, K>(reinterpret_cast<const void*>(&dev::race_leaf_kernel<ValT, K>));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((dev::race_leaf_kernel<ValT, K>), dim3(n_leaves), dim3(threads), lds, st, a, leaf_base, x, y,
+  hipLaunchKernelGGL((dev::race_leaf_kernel<ValT, K>), dim3(count), dim3(threads), lds, st, a, base, per_unit, x, y,
                      wmax, trace);
+  return hipGetLastError();
+}
+
+// Grid of a grid-stride fill over `items` elements: enough workgroups to
+// cover them once, at most 4096.
+static dim3 fill_grid(int64_t items) {
+  return dim3(static_cast<uint32_t>(std::max<int64_t>(1, std::min<int64_t>(4096, (items + 255) / 256))));
+}
+
+hipError_t launch_zero_entries(double* y, int32_t k, const int32_t* idx, int64_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::zero_entries_kernel, fill_grid(count * k), dim3(256), 0, st, y, k, idx, count);
   return hipGetLastError();
 }
 
@@ -522,9 +564,10 @@ static hipError_t flow_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_
   }
 
 template <typename ValT>
-hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t leaf_base, int32_t n_leaves, int32_t k, const double* x,
-                             double* y, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
-#define CALL(KK) launch_leaf<ValT, KK>(a, leaf_base, n_leaves, x, y, wmax, threads, trace, st)
+hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t base, int32_t count, int32_t per_unit, int32_t k,
+                             const double* x, double* y, int32_t wmax, int32_t threads, uint64_t* trace,
+                             hipStream_t st) {
+#define CALL(KK) launch_leaf<ValT, KK>(a, base, count, per_unit, x, y, wmax, threads, trace, st)
   RACE_K_SWITCH(CALL)
 #undef CALL
 }
@@ -545,9 +588,9 @@ hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t
 #undef CALL
 }
 
-template hipError_t launch_race_phase<double>(const UnitArgs<double>&, int32_t, int32_t, int32_t, const double*,
-                                              double*, int32_t, int32_t, uint64_t*, hipStream_t);
-template hipError_t launch_race_phase<float>(const UnitArgs<float>&, int32_t, int32_t, int32_t, const double*,
+template hipError_t launch_race_phase<double>(const UnitArgs<double>&, int32_t, int32_t, int32_t, int32_t,
+                                              const double*, double*, int32_t, int32_t, uint64_t*, hipStream_t);
+template hipError_t launch_race_phase<float>(const UnitArgs<float>&, int32_t, int32_t, int32_t, int32_t, const double*,
                                              double*, int32_t, int32_t, uint64_t*, hipStream_t);
 template hipError_t launch_race_flow<double>(const UnitArgs<double>&, const FlowArgs&, int32_t, const double*, double*,
                                              int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
@@ -566,8 +609,8 @@ static hipError_t launch_batch_k(const BatchMat<ValT>* mats, const BatchArgs& b,
   hipError_t e = set_lds_attr<BatchTag<ValT, K>, K>(reinterpret_cast<const void*>(&dev::race_batch_kernel<ValT, K>));
   if (e != hipSuccess) return e;
   const int64_t words = b.state_words;
-  hipLaunchKernelGGL(dev::batch_reset_kernel, dim3(static_cast<uint32_t>((words + 255) / 256)), dim3(256), 0, st,
-                     b.state, words);
+  hipLaunchKernelGGL(dev::batch_reset_kernel<ValT>, fill_grid(std::max(words, b.n_zero)), dim3(256), 0, st, b.state,
+                     words, mats, K, b.zero_mat, b.zero_idx, b.n_zero);
   hipLaunchKernelGGL((dev::race_batch_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, mats, b, wmax);
   return hipGetLastError();
 }

@@ -88,6 +88,19 @@ SMALL = [
     ("banded_40k_phases", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
      dict(n_workers=256, exec_mode="phases")),
     ("rand_islands_phases", lambda: matgen.random_symmetric(500, 0.003, seed=8), dict(n_workers=16, exec_mode="phases")),
+    # a leaf's units in order instead of concurrently with shared atomics
+    ("3d27pt_24_w128_chain", lambda: matgen.stencil3d_27pt(24, seed=5),
+     dict(n_workers=64, window_max=128, shared_atomics=False)),
+    ("3d27pt_24_w128_phases_chain", lambda: matgen.stencil3d_27pt(24, seed=5),
+     dict(n_workers=64, window_max=128, exec_mode="phases", shared_atomics=False)),
+    ("banded_40k_chain", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
+     dict(n_workers=256, shared_atomics=False)),
+    # many units per leaf: most y entries are shared and combined atomically
+    ("banded_40k_w96", lambda: matgen.banded_irregular(40000, seed=6, band=4000), dict(n_workers=16, window_max=96)),
+    ("banded_40k_w96_phases", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
+     dict(n_workers=16, window_max=96, exec_mode="phases")),
+    ("batch_family_irregular", lambda: matgen.batch_family(2, 102), dict(n_workers=4)),
+    ("batch_family_irregular_b1024", lambda: matgen.batch_family(5, 105), dict(n_workers=30, block_threads=1024)),
 ]
 
 
@@ -231,6 +244,28 @@ def test_race_full_size_3d27pt_128(nt, mode):
     rows = np.random.default_rng(0).choice(m.n, size=200, replace=False)
     exact = _sampled_rows_exact(m, x, rows)
     assert np.all(np.abs(y[rows] - exact) <= 1e-12 * np.max(np.abs(y_ref)))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("value_type", ["f64", "f32"])
+def test_race_full_size_banded_4m(value_type):
+    """Irregular banded N = 4M: FP64 values within the FP64 bound; FP32 values
+    (promoted, FP64 accumulation) against the oracle on the same FP32-rounded
+    values, and their error against the FP64 matrix stated."""
+    m = matgen.config_banded_4m()
+    print(f"case banded_4m {value_type}: n={m.n} nnz={m.nnz}", flush=True)
+    x = matgen.rhs(m.n, 3)
+    vals = m.val if value_type == "f64" else m.val.astype(np.float32).astype(np.float64)
+    y, st = run_race(m, x, n_workers=1024, value_type=value_type)
+    print(f"  units={st['n_units']} leaves={st['n_leaves']} eta={st['eta']:.3f} shared={st['shared_touches']} "
+          f"zeroed={st['n_zeroed']}", flush=True)
+    y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, vals, x)
+    _check(y, y_ref, O.abs_product(m.n, m.row_ptr, m.col, vals, x), _full_row_len(m), f"banded_4m {value_type}")
+    if value_type == "f32":
+        y64 = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
+        rel = np.linalg.norm(y - y64) / np.linalg.norm(y64)
+        print(f"  FP32-value error vs the FP64 matrix: {rel:.3e} (unit roundoff of FP32 {2.0 ** -24:.3e})", flush=True)
+        assert rel < 2.0 ** -20
 
 
 def _batch_mats():

@@ -90,32 +90,52 @@ def test_schedule_bit_exact_3d27pt_128():
     s.close()
 
 
-def first_writers(n, unit_leaf, leaf_phase, lo, hi, halo_ptr, halo):
-    """Independent derivation: walk units in execution order; the first unit
-    touching an index writes it; two leaves of one phase must not share one."""
+def touch_flags(n, unit_leaf, leaf_phase, lo, hi, halo_ptr, halo, shared_atomics):
+    """Independent derivation of the flush flags.  An index is shared when two
+    or more units of one leaf touch it (only with shared_atomics).  Walking
+    units in execution order, the first unit touching an index writes it;
+    when that touch is shared the index is cleared before the product
+    instead.  Two leaves of one phase must never share an index."""
+    n_units = len(lo)
+    touches = [np.concatenate([np.arange(lo[u], hi[u]), halo[halo_ptr[u]:halo_ptr[u + 1]]]) for u in range(n_units)]
+    shared = [np.zeros(t.size, dtype=bool) for t in touches]
+    if shared_atomics:
+        for leaf in np.unique(unit_leaf):
+            us = np.flatnonzero(unit_leaf == leaf)
+            if us.size < 2:
+                continue
+            cnt = np.bincount(np.concatenate([touches[u] for u in us]), minlength=n)
+            for u in us:
+                shared[u] = cnt[touches[u]] > 1
     seen_phase = np.full(n, -1, dtype=np.int64)
     seen_leaf = np.full(n, -1, dtype=np.int64)
-    row_first = np.zeros(n, dtype=np.uint8)
-    halo_first = np.zeros(len(halo), dtype=np.uint8)
-    for u in range(len(lo)):
+    row_flags = np.zeros(n, dtype=np.uint8)
+    halo_flags = np.zeros(len(halo), dtype=np.uint8)
+    zero = []
+    for u in range(n_units):
         leaf = unit_leaf[u]
         ph = leaf_phase[leaf]
-        idx = np.concatenate([np.arange(lo[u], hi[u]), halo[halo_ptr[u]:halo_ptr[u + 1]]])
+        idx = touches[u]
         clash = (seen_phase[idx] == ph) & (seen_leaf[idx] != leaf)
         assert not clash.any()
         fresh = seen_phase[idx] < 0
+        flags = ((fresh & ~shared[u]).astype(np.uint8)) | (shared[u].astype(np.uint8) << 1)
+        zero.append(idx[fresh & shared[u]])
         r = hi[u] - lo[u]
-        row_first[lo[u]:hi[u]] = fresh[:r]
-        halo_first[halo_ptr[u]:halo_ptr[u + 1]] = fresh[r:]
+        row_flags[lo[u]:hi[u]] = flags[:r]
+        halo_flags[halo_ptr[u]:halo_ptr[u + 1]] = flags[r:]
         seen_phase[idx] = ph
         seen_leaf[idx] = leaf
-    return row_first, halo_first
+    zero = np.sort(np.concatenate(zero)) if zero else np.zeros(0, np.int64)
+    return row_flags, halo_flags, zero
 
 
+@pytest.mark.parametrize("shared", [True, False], ids=["shared", "chain"])
 @pytest.mark.parametrize("name,make,nt,kw", CASES[:9], ids=[c[0] for c in CASES[:9]])
-def test_layout_consistent(name, make, nt, kw):
+def test_layout_consistent(name, make, nt, kw, shared):
     m = make()
-    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, n_workers=nt, window_max=256, **kw)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, n_workers=nt, window_max=256, shared_atomics=shared,
+                   **kw)
     try:
         u = s.units()
         node, phase = s.leaves()
@@ -138,9 +158,15 @@ def test_layout_consistent(name, make, nt, kw):
             got = u["halo"][u["halo_ptr"][k]:u["halo_ptr"][k + 1]]
             assert np.array_equal(got, want)
             assert (b - a) + got.size <= 256
-        rf, hf = first_writers(m.n, u["unit_leaf"], phase, u["lo"], u["hi"], u["halo_ptr"], u["halo"])
-        assert np.array_equal(rf, u["row_first"])
-        assert np.array_equal(hf, u["halo_first"])
+        rf, hf, zero = touch_flags(m.n, u["unit_leaf"], phase, u["lo"], u["hi"], u["halo_ptr"], u["halo"], shared)
+        assert np.array_equal(rf, u["row_flags"])
+        assert np.array_equal(hf, u["halo_flags"])
+        assert np.array_equal(zero, s.zero_list())
+        st = s.stats()
+        assert st["n_zeroed"] == zero.size
+        assert st["shared_touches"] == int(((rf >> 1) & 1).sum() + ((hf >> 1) & 1).sum())
+        if not shared:
+            assert zero.size == 0 and st["shared_touches"] == 0
         # the schedule itself passes the brute-force checker
         C.check_schedule(m.n, m.row_ptr, m.col, perm, tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase)
     finally:
@@ -173,6 +199,9 @@ def test_error_codes():
     p = R.make_params(window_max=100000)
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params(block_threads=100)
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params()
+    p.shared_atomics = 2
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     # a row whose window alone exceeds the budget
     n = 40
