@@ -52,15 +52,18 @@ typedef struct {
   int32_t dist_k;        /* distance of the coloring; SymmSpMV needs 2 (the only value accepted) */
   int32_t n_workers;     /* N_t: concurrent workers the tree is built for (>= 1) */
   int32_t max_stages;    /* recursion stages including stage 0 (1..16) */
-  int32_t balance_by;    /* 0: nonzeros of the full row, 1: rows, 2: learned cost model (cost_model) */
+  int32_t balance_by;    /* 0: nonzeros of the full row, 1: rows, 2: learned cost model (cost_model): every stage-0
+                            BFS level is cut into window-sized pieces, each piece's predicted cost is shared among
+                            its rows in proportion to 1 + their stored off-diagonals */
   int32_t global_lb;     /* 1: run Algorithm "Load Balancing" over all children after the pair split */
   int32_t value_type;    /* 0: float64 matrix values, 1: float32 values (promoted; FP64 accumulation) */
   int32_t window_max;    /* max LDS window entries (rows + halo) of one unit, 2..8000; 0 = 3840 (20 B of LDS each per
                             right-hand side pair of x/y plus the index) */
   int32_t block_threads; /* workgroup size of the RACE kernel: 64, 128, 256, 512 or 1024; 0 = 256 */
   double eps[8];         /* eps_s per stage (stages past 7 use eps[7]); each in [0, 1) */
-  const float* cost_model; /* host: weights of the cost-model network (balance_by == 2), else NULL */
-  int32_t cost_model_len;  /* number of floats in cost_model */
+  const float* cost_model; /* host: RACE_MLP_PARAMS weights of the cost-model network (balance_by == 2), else
+                              NULL; read during race_build_schedule only */
+  int32_t cost_model_len;  /* number of floats in cost_model (must be RACE_MLP_PARAMS when used) */
   int32_t exec_mode;       /* 0: one launch per phase; 1: one persistent dataflow launch (units wait only for the
                               earlier units they conflict with) */
   int32_t shared_atomics;  /* a leaf whose rows need several LDS windows is cut into several units.  0: those units
@@ -232,6 +235,63 @@ void race_csr_destroy(race_csr_t h);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* race_last_error(void);
+
+/* ---- Learned cost model (an extension beyond the paper) ----------------
+ * A ReLU network 12 -> 64 -> 64 -> 1 in float32 predicts the natural log of
+ * a unit's cost (compute + flush time in microseconds) from 12 features of
+ * the unit.  It replaces the nonzero count as the load m of Sections 4.3-4.4
+ * (race_params.balance_by = 2) and ranks candidate schedules by predicted
+ * makespan (standing in for the hand-tuned eps_s and depth of Section 5).
+ * Parameters are one flat float32 vector: W1 (64 x 12, row-major, output by
+ * input), b1 (64), W2 (64 x 64, row-major), b2 (64), w3 (64), b3 (1). */
+#define RACE_MLP_INPUTS 12
+#define RACE_MLP_HIDDEN 64
+#define RACE_MLP_PARAMS 5057
+
+/* Features of every unit, n_units x RACE_MLP_INPUTS row-major (host), units in
+ * execution order, for products with k right-hand sides (1..16):
+ *  0 log2(1 + rows)   1 log2(1 + stored entries)   2 mean off-diagonals per row
+ *  3 max off-diagonals per row   4 coefficient of variation of off-diagonals per row
+ *  5 halo entries / rows   6 fraction of off-diagonals whose column lies past the unit's rows
+ *  7 fraction of window entries flushed read-modify-write   8 fraction flushed by shared atomics
+ *  9 log2(1 + units of the unit's phase)   10 phase / n_phases   11 log2(k).
+ * Works on pattern-only schedules (no device needed). */
+int race_schedule_features(race_schedule_t s, int32_t k, float* out);
+
+/* Predicted makespan of a dataflow product: tickets in execution order on
+ * `workers` workgroups, unit u computes for (1 - flush_frac) cost[u], waits
+ * for the earlier units it conflicts with, then flushes for flush_frac
+ * cost[u].  cost: host, n_units values (any time unit; the result is in the
+ * same unit).  flush_frac in [0, 1], workers >= 1. */
+int race_schedule_simulate(race_schedule_t s, const float* cost, double flush_frac, int32_t workers,
+                           double* makespan);
+
+/* Workgroups a dataflow product with k right-hand sides launches on the
+ * current device (occupancy of the kernel times the compute units, at most
+ * the number of units). */
+int race_schedule_flow_grid(race_schedule_t s, int32_t k, int32_t* grid);
+
+/* y[i] = network(X[i]) for n rows of X (n x RACE_MLP_INPUTS, row-major).
+ * _host: host arrays, float32 arithmetic on the CPU (used by balance_by = 2);
+ * otherwise device arrays, enqueued on `stream`. */
+int race_mlp_forward_host(const float* theta, const float* X, int64_t n, float* y);
+int race_mlp_forward(const float* theta, const float* X, int64_t n, float* y, void* stream);
+
+/* Floats of device workspace race_mlp_loss_grad needs for n samples. */
+int race_mlp_workspace(int64_t n, int64_t* floats);
+
+/* Mean squared error L = (1/n) sum_i (network(X[i]) - t[i])^2 and its
+ * gradient: grad (RACE_MLP_PARAMS floats) and loss (1 float, may be NULL)
+ * overwritten.  All pointers device; n >= 1.  Deterministic: per-workgroup
+ * partial sums are added in a fixed order. */
+int race_mlp_loss_grad(const float* theta, const float* X, const float* t, int64_t n, float* workspace, float* grad,
+                       float* loss, void* stream);
+
+/* One Adam step (Kingma and Ba, 2015) on theta with moment buffers m and v
+ * (device, RACE_MLP_PARAMS floats each, zero before step 1); step counts
+ * from 1. */
+int race_mlp_adam(float* theta, const float* grad, float* m, float* v, int32_t step, float lr, float beta1, float beta2,
+                  float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -17,12 +17,14 @@ from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_ch
                    race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
                    race_symm_spmv_atomic)
 
-BALANCE = {"nnz": 0, "rows": 1}
+BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
-                shared_atomics=True):
+                shared_atomics=True, cost_model=None):
+    """race_params from keywords.  balance="model" needs cost_model: the
+    network's MLP_PARAMS float32 weights (kept alive on the returned struct)."""
     p = race_params_default()
     p.n_workers = int(n_workers)
     p.max_stages = int(max_stages)
@@ -33,6 +35,14 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.block_threads = int(block_threads)
     p.exec_mode = {"phases": 0, "flow": 1}[exec_mode]
     p.shared_atomics = int(bool(shared_atomics))
+    if cost_model is not None:
+        import ctypes
+
+        import numpy as np
+        w = np.ascontiguousarray(cost_model, dtype=np.float32)
+        p._cost_model_ref = w
+        p.cost_model = w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        p.cost_model_len = int(w.size)
     eps = list(eps) + [eps[-1]] * (8 - len(eps))
     for i in range(8):
         p.eps[i] = float(eps[i])
@@ -72,6 +82,17 @@ class Schedule:
 
     def zero_list(self):
         return race_schedule_zero_list(self.handle)
+
+    def features(self, k=1):
+        """Cost-model features of every unit (n_units x 12, float32)."""
+        return _lib.race_schedule_features(self.handle, self.stats()["n_units"], k)
+
+    def simulate(self, cost, flush_frac, workers):
+        """Predicted dataflow makespan for per-unit costs."""
+        return _lib.race_schedule_simulate(self.handle, cost, flush_frac, workers)
+
+    def flow_grid(self, k=1):
+        return _lib.race_schedule_flow_grid(self.handle, k)
 
     def spmv(self, x, y, stream=None):
         race_symm_spmv(self.handle, x, y, stream)

@@ -27,8 +27,13 @@ EXPORTS = [
     "race_schedule_units", "race_schedule_zero_list", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
     "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
     "race_batch_create", "race_batch_bind", "race_batch_run", "race_batch_check", "race_batch_info",
-    "race_batch_destroy",
+    "race_batch_destroy", "race_schedule_features", "race_schedule_simulate", "race_schedule_flow_grid",
+    "race_mlp_forward_host", "race_mlp_forward", "race_mlp_workspace", "race_mlp_loss_grad", "race_mlp_adam",
 ]
+
+MLP_INPUTS = 12
+MLP_HIDDEN = 64
+MLP_PARAMS = 5057
 
 
 class RaceError(RuntimeError):
@@ -71,6 +76,7 @@ _I32P = ctypes.POINTER(ctypes.c_int32)
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _U8P = ctypes.POINTER(ctypes.c_uint8)
 _DP = ctypes.POINTER(ctypes.c_double)
+_FP = ctypes.POINTER(ctypes.c_float)
 
 
 def lib():
@@ -110,6 +116,15 @@ def lib():
         "race_batch_check": ([_P], ctypes.c_int),
         "race_batch_info": ([_P, _I32P, _I32P, _I32P], ctypes.c_int),
         "race_batch_destroy": ([_P], None),
+        "race_schedule_features": ([_P, ctypes.c_int32, _FP], ctypes.c_int),
+        "race_schedule_simulate": ([_P, _FP, ctypes.c_double, ctypes.c_int32, _DP], ctypes.c_int),
+        "race_schedule_flow_grid": ([_P, ctypes.c_int32, _I32P], ctypes.c_int),
+        "race_mlp_forward_host": ([_FP, _FP, ctypes.c_int64, _FP], ctypes.c_int),
+        "race_mlp_forward": ([_P, _P, ctypes.c_int64, _P, _P], ctypes.c_int),
+        "race_mlp_workspace": ([ctypes.c_int64, _I64P], ctypes.c_int),
+        "race_mlp_loss_grad": ([_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P], ctypes.c_int),
+        "race_mlp_adam": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -324,3 +339,52 @@ def race_batch_info(b):
 
 def race_batch_destroy(b):
     lib().race_batch_destroy(b)
+
+
+def race_schedule_features(h, n_units, k=1):
+    out = np.empty((n_units, MLP_INPUTS), dtype=np.float32)
+    check(lib().race_schedule_features(h, int(k), _np_ptr(out, ctypes.c_float)))
+    return out
+
+
+def race_schedule_simulate(h, cost, flush_frac, workers):
+    cost = np.ascontiguousarray(cost, dtype=np.float32)
+    out = ctypes.c_double()
+    check(lib().race_schedule_simulate(h, _np_ptr(cost, ctypes.c_float), float(flush_frac), int(workers),
+                                       ctypes.byref(out)))
+    return out.value
+
+
+def race_schedule_flow_grid(h, k=1):
+    g = ctypes.c_int32()
+    check(lib().race_schedule_flow_grid(h, int(k), ctypes.byref(g)))
+    return g.value
+
+
+def race_mlp_forward_host(theta, X):
+    theta = np.ascontiguousarray(theta, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, MLP_INPUTS)
+    y = np.empty(X.shape[0], dtype=np.float32)
+    check(lib().race_mlp_forward_host(_np_ptr(theta, ctypes.c_float), _np_ptr(X, ctypes.c_float), X.shape[0],
+                                      _np_ptr(y, ctypes.c_float)))
+    return y
+
+
+def race_mlp_forward(theta, X, y, stream=None):
+    check(lib().race_mlp_forward(_dev_ptr(theta), _dev_ptr(X), int(X.shape[0]), _dev_ptr(y), _stream_ptr(stream)))
+
+
+def race_mlp_workspace(n):
+    out = ctypes.c_int64()
+    check(lib().race_mlp_workspace(int(n), ctypes.byref(out)))
+    return out.value
+
+
+def race_mlp_loss_grad(theta, X, t, workspace, grad, loss=None, stream=None):
+    check(lib().race_mlp_loss_grad(_dev_ptr(theta), _dev_ptr(X), _dev_ptr(t), int(X.shape[0]), _dev_ptr(workspace),
+                                   _dev_ptr(grad), _dev_ptr(loss) if loss is not None else None, _stream_ptr(stream)))
+
+
+def race_mlp_adam(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(lib().race_mlp_adam(_dev_ptr(theta), _dev_ptr(grad), _dev_ptr(m), _dev_ptr(v), int(step), float(lr),
+                              float(beta1), float(beta2), float(eps), _stream_ptr(stream)))

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -9,6 +10,7 @@
 #include <vector>
 
 #include "../../include/race.h"
+#include "costmodel.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 #include "schedule.hpp"
@@ -166,8 +168,10 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (prm.dist_k != 2) return fail(RACE_EUNSUPPORTED, "only distance-2 coloring (dist_k = 2) is implemented");
   if (prm.n_workers < 1) return fail(RACE_EINVAL, "n_workers must be >= 1");
   if (prm.max_stages < 1 || prm.max_stages > 16) return fail(RACE_EINVAL, "max_stages must be in 1..16");
-  if (prm.balance_by < 0 || prm.balance_by > 1)
-    return fail(RACE_EUNSUPPORTED, "balance_by must be 0 (nonzeros) or 1 (rows)");
+  if (prm.balance_by < 0 || prm.balance_by > 2)
+    return fail(RACE_EINVAL, "balance_by must be 0 (nonzeros), 1 (rows) or 2 (cost model)");
+  if (prm.balance_by == 2 && (!prm.cost_model || prm.cost_model_len != race::kMlpParams))
+    return fail(RACE_EINVAL, "balance_by 2 needs cost_model with RACE_MLP_PARAMS floats");
   if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
   if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
   if (prm.shared_atomics < 0 || prm.shared_atomics > 1) return fail(RACE_EINVAL, "shared_atomics must be 0 or 1");
@@ -188,7 +192,10 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     race::Graph g;
     race::build_graph(n, row_ptr, col, g);
     std::vector<int64_t> m;
-    race::row_loads(n, row_ptr, col, prm.balance_by == 1, m);
+    if (prm.balance_by == 2)
+      race::learned_row_loads(g, n, row_ptr, col, prm.cost_model, prm.window_max, m);
+    else
+      race::row_loads(n, row_ptr, col, prm.balance_by == 1, m);
     race::TreeParams tp;
     tp.n_workers = prm.n_workers;
     tp.max_stages = prm.max_stages;
@@ -208,6 +215,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
       return fail(code, err);
     }
     s->has_values = val != nullptr;
+    s->params.cost_model = nullptr;  // borrowed for the build only
+    s->params.cost_model_len = 0;
     race_stats& st = s->stats;
     const race::Tree& t = s->tree;
     const race::Layout& L = s->L;
@@ -397,6 +406,96 @@ int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx) {
   if (!s || !count) return fail(RACE_EINVAL, "NULL argument");
   *count = static_cast<int64_t>(s->L.zero_idx.size());
   if (idx) std::copy(s->L.zero_idx.begin(), s->L.zero_idx.end(), idx);
+  return RACE_OK;
+}
+
+int race_schedule_features(race_schedule_t s, int32_t k, float* out) {
+  if (!s || !out) return fail(RACE_EINVAL, "NULL argument");
+  if (k < 1 || k > 16) return fail(RACE_EINVAL, "k must be in 1..16");
+  try {
+    std::vector<float> f;
+    race::unit_features(s->L, s->tree, k, f);
+    std::copy(f.begin(), f.end(), out);
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory");
+  }
+  return RACE_OK;
+}
+
+int race_schedule_simulate(race_schedule_t s, const float* cost, double flush_frac, int32_t workers,
+                           double* makespan) {
+  if (!s || !makespan || (!cost && !s->L.unit_lo.empty())) return fail(RACE_EINVAL, "NULL argument");
+  if (!(flush_frac >= 0.0 && flush_frac <= 1.0)) return fail(RACE_EINVAL, "flush_frac must be in [0, 1]");
+  if (workers < 1) return fail(RACE_EINVAL, "workers must be >= 1");
+  try {
+    *makespan = race::simulate(s->L, cost, flush_frac, workers);
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory");
+  }
+  return RACE_OK;
+}
+
+int race_schedule_flow_grid(race_schedule_t s, int32_t k, int32_t* grid) {
+  if (!s || !grid) return fail(RACE_EINVAL, "NULL argument");
+  if (k < 1 || k > 16) return fail(RACE_EINVAL, "k must be in 1..16");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device query");
+  const int32_t wmax = std::max(1, s->L.max_window);
+  int32_t per_cu = 0;
+  e = s->params.value_type == 0 ? race::race_flow_occupancy<double>(k, s->params.block_threads, wmax, &per_cu)
+                                : race::race_flow_occupancy<float>(k, s->params.block_threads, wmax, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  const int32_t n_units = static_cast<int32_t>(s->L.unit_lo.size());
+  *grid = std::max(1, std::min(n_units, per_cu * cus));
+  return RACE_OK;
+}
+
+int race_mlp_forward_host(const float* theta, const float* X, int64_t n, float* y) {
+  if (n < 0) return fail(RACE_EINVAL, "n must be >= 0");
+  if (n > 0 && (!theta || !X || !y)) return fail(RACE_EINVAL, "NULL argument");
+  race::mlp_forward_host(theta, X, n, y);
+  return RACE_OK;
+}
+
+int race_mlp_forward(const float* theta, const float* X, int64_t n, float* y, void* stream) {
+  if (n < 0) return fail(RACE_EINVAL, "n must be >= 0");
+  if (n == 0) return RACE_OK;
+  if (!theta || !X || !y) return fail(RACE_EINVAL, "NULL argument");
+  if (n > (int64_t(1) << 31) * 255) return fail(RACE_EUNSUPPORTED, "too many samples for one launch");
+  hipError_t e = race::launch_mlp_forward(theta, X, n, y, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "network forward launch");
+  return RACE_OK;
+}
+
+int race_mlp_workspace(int64_t n, int64_t* floats) {
+  if (!floats || n < 1) return fail(RACE_EINVAL, "need n >= 1 and an output");
+  *floats = race::mlp_workspace_floats(n);
+  return RACE_OK;
+}
+
+int race_mlp_loss_grad(const float* theta, const float* X, const float* t, int64_t n, float* workspace, float* grad,
+                       float* loss, void* stream) {
+  if (n < 1) return fail(RACE_EINVAL, "n must be >= 1");
+  if (!theta || !X || !t || !workspace || !grad) return fail(RACE_EINVAL, "NULL argument");
+  if (n > (int64_t(1) << 30)) return fail(RACE_EUNSUPPORTED, "at most 2^30 samples per call");
+  hipError_t e = race::launch_mlp_loss_grad(theta, X, t, n, workspace, grad, loss, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "network gradient launch");
+  return RACE_OK;
+}
+
+int race_mlp_adam(float* theta, const float* grad, float* m, float* v, int32_t step, float lr, float beta1, float beta2,
+                  float eps, void* stream) {
+  if (!theta || !grad || !m || !v) return fail(RACE_EINVAL, "NULL argument");
+  if (step < 1) return fail(RACE_EINVAL, "step counts from 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+    return fail(RACE_EINVAL, "need 0 <= beta < 1, eps > 0, lr >= 0");
+  const double c1 = 1.0 / (1.0 - std::pow(static_cast<double>(beta1), step));
+  const double c2 = 1.0 / (1.0 - std::pow(static_cast<double>(beta2), step));
+  hipError_t e = race::launch_mlp_adam(theta, grad, m, v, lr, beta1, beta2, eps, static_cast<float>(c1),
+                                       static_cast<float>(c2), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "Adam launch");
   return RACE_OK;
 }
 

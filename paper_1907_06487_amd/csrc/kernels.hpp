@@ -111,4 +111,13 @@ hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, 
 hipError_t launch_permute(int32_t n, int32_t k, const int32_t* new2old, const double* in, double* out,
                           int32_t to_permuted, hipStream_t st);
 
+// Cost-model network (mlp_kernels.hip).  Workspace of the gradient: one
+// partial gradient (plus loss) per 256 samples.
+int64_t mlp_workspace_floats(int64_t n);
+hipError_t launch_mlp_forward(const float* theta, const float* X, int64_t n, float* y, hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float* theta, const float* X, const float* t, int64_t n, float* workspace,
+                                float* grad, float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* theta, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, hipStream_t st);
+
 }  // namespace race
