@@ -165,6 +165,81 @@ def run_batch(args, k, torch):
         s.close()
 
 
+def run_learned_ab(args, torch):
+    """Held-out A/B of the learned cost model on the 3D 27-point 160^3
+    stencil: the schedule the nonzero heuristic picks against the one the
+    network picks (same candidate grid, same makespan simulation, different
+    unit costs), plus the default parameters; each timed over several rounds
+    of ring-buffered products."""
+    import numpy as np
+
+    import matgen
+    import paper_1907_06487_amd as R
+    from paper_1907_06487_amd import costmodel as CM
+    from oracle import symmspmv as O
+
+    mdir = args.model_dir or os.path.dirname(CM.MODEL_PATH)
+    theta, meta = CM.load(os.path.join(mdir, "cost_model.npy"), os.path.join(mdir, "cost_model.json"))
+    t0 = time.perf_counter()
+    m = matgen.config_3d_160()
+    log(f"learned A/B: 3d27pt_160 n={m.n} nnz_upper={m.nnz} generated in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    res = CM.choose(m, theta, meta, log=log)
+    t_choose = time.perf_counter() - t0
+    log(f"scored {len(res['candidates'])} candidate schedules in {t_choose:.1f}s")
+    dev = "cuda:0"
+    nring = max(2, -(-RING_BYTES // (8 * m.n)))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4242)
+    xs = [torch.rand(m.n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1 for _ in range(nring)]
+    ys = [torch.empty(m.n, dtype=torch.float64, device=dev) for _ in range(nring)]
+    x0 = xs[0].cpu().numpy()
+    arms = {"heuristic": res["heuristic"], "learned": res["learned"],
+            "default": {"params": dict(n_workers=args.n_workers, block_threads=args.block, window_max=args.window,
+                                       balance="nnz"), "pred_us": None, "pred_nnz": None}}
+    out_arms = {}
+    for name, arm in arms.items():
+        kw = dict(arm["params"])
+        if kw.get("balance") == "model":
+            kw["cost_model"] = theta
+        t0 = time.perf_counter()
+        s = R.Schedule(m.n, m.row_ptr, m.col, m.val, **kw)
+        t_build = time.perf_counter() - t0
+        st = s.stats()
+        if arm["pred_us"] is None:
+            arm["pred_us"] = s.simulate(CM.predict_costs(theta, s.features(1)), meta["flush_frac"], s.flow_grid(1))
+        rounds = [time_ring(lambda x, y: s.spmv(x, y), xs, ys, args.steps, args.warmup, torch) * 1e3
+                  for _ in range(args.rounds)]
+        s.check()
+        perm = s.perm()
+        xo = np.empty(m.n)
+        xo[perm] = x0
+        s.spmv(xs[0], ys[0])
+        torch.cuda.synchronize()
+        err = O.errors(ys[0].cpu().numpy(), O.symm_spmv(m.n, m.row_ptr, m.col, m.val, xo)[perm])[0]
+        out_arms[name] = {"params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in arm["params"].items()},
+                          "us_median": float(np.median(rounds)), "us_min": float(min(rounds)),
+                          "us_max": float(max(rounds)), "pred_us": arm["pred_us"], "units": st["n_units"],
+                          "eta": st["eta"], "build_s": t_build, "err_norm": err,
+                          "gbs": st["bytes_min"] / (np.median(rounds) * 1e-6) / 1e9}
+        log(f"{name}: {out_arms[name]['us_median']:.2f} us (min {min(rounds):.2f}, max {max(rounds):.2f}), "
+            f"predicted {arm['pred_us']:.2f} us, params {arm['params']}, err {err:.2e}")
+        s.close()
+    h, l = out_arms["heuristic"], out_arms["learned"]
+    flops = 2 * (2 * m.nnz - m.n)
+    out = {
+        "metric": "learned cost model: time per SymmSpMV product, learned vs nonzero-heuristic schedule choice",
+        "value": round(h["us_median"] / l["us_median"], 4), "unit": "speedup (heuristic time / learned time)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": l["us_median"] * 1e-3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3d27pt_160 (held out)", "n": m.n, "nnz_upper": m.nnz, "rounds": args.rounds,
+                   "candidates": len(res["candidates"])},
+        "arms": out_arms, "gflops_learned": flops / (l["us_median"] * 1e-6) / 1e9,
+        "candidates": res["candidates"], "model": meta, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +258,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--k", default="1", help="batch64 workload: right-hand sides, e.g. 1,4,16")
+    ap.add_argument("--model-dir", default=None, help="learned_ab workload: directory of cost_model.npy/.json")
+    ap.add_argument("--rounds", type=int, default=5, help="learned_ab workload: timing rounds per arm")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a device copy of this many MiB (reference for the traffic counters)")
     ap.add_argument("--sweep", default="",
@@ -204,6 +281,9 @@ def main():
     if args.workload == "batch64":
         for k in (int(v) for v in args.k.split(",")):
             run_batch(args, k, torch)
+        return
+    if args.workload == "learned_ab":
+        run_learned_ab(args, torch)
         return
     m, desc = workload(args.workload)
     log(f"workload {args.workload}: n={m.n} nnz_upper={m.nnz}")

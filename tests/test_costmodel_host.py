@@ -179,3 +179,24 @@ def test_simulate_errors():
         with pytest.raises(_lib.RaceError):
             s.simulate(cost, frac, w)
     s.close()
+
+
+def test_fold_normalisation_is_exact_reparametrisation():
+    """The network trained on standardised inputs and the folded network on
+    raw inputs give the same outputs (up to float32 rounding)."""
+    torch = pytest.importorskip("torch")  # costmodel imports torch for device buffers
+    from paper_1907_06487_amd import costmodel as CM
+    rng = np.random.default_rng(40)
+    X = rng.normal(3.0, 5.0, size=(300, 12)).astype(np.float64)
+    mu, sd = X.mean(axis=0), X.std(axis=0)
+    theta = _theta(41, 0.1)
+    y_std = M.forward(theta.astype(np.float64), (X - mu) / sd)
+    y_raw = M.forward(CM.fold_normalisation(theta, mu, sd).astype(np.float64), X)
+    assert np.allclose(y_raw, y_std, rtol=1e-4, atol=1e-4 * np.abs(y_std).max())
+
+
+def test_init_params_shape():
+    pytest.importorskip("torch")
+    from paper_1907_06487_amd import costmodel as CM
+    th = CM.init_params(0)
+    assert th.dtype == np.float32 and th.size == M.N_PARAMS and th[-1] == 0.0
