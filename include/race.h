@@ -96,7 +96,9 @@ typedef struct {
   int64_t bytes_min;         /* 12 nnz_u + 20 N + 4: minimum bytes of one product in upper CRS with FP64 values */
   int64_t bytes_kernel;      /* bytes one product of the RACE kernel moves by its own format, counted once each */
   int64_t device_bytes;      /* device memory held by the schedule */
-  int64_t n_deps;            /* conflict edges between units (dataflow mode) */
+  int64_t n_deps;            /* conflict edges of the dataflow mode: between units, plus one from each unit to
+                                each clearing task (a chunk of 4096 entries of the zero list) whose entries it
+                                touches shared */
   int32_t flow_grid;         /* workgroups of the dataflow launch (0 before the first dataflow product) */
   int32_t exec_mode;
   int64_t wall_clock_hz;     /* rate of the device clock used by traced products (set by race_schedule_upload) */
@@ -156,7 +158,9 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
                         int32_t* row_hi, int64_t* halo_ptr, int32_t* halo, uint8_t* halo_flags, uint8_t* row_flags);
 
 /* The y entries cleared before every product (ascending, permuted order):
- * those whose first toucher is a shared touch.  idx NULL: only *count. */
+ * those whose first toucher is a shared touch.  The dataflow mode clears
+ * them in its first tickets (one task per 4096 entries), the phase mode with
+ * a separate launch before the first phase.  idx NULL: only *count. */
 int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx);
 
 /* y = A x (Algorithm "SymmSpMV"): x, y device float64 arrays of n in
@@ -261,7 +265,7 @@ int race_schedule_features(race_schedule_t s, int32_t k, float* out);
 /* Predicted makespan of a dataflow product: tickets in execution order on
  * `workers` workgroups, unit u computes for (1 - flush_frac) cost[u], waits
  * for the earlier units it conflicts with, then flushes for flush_frac
- * cost[u].  cost: host, n_units values (any time unit; the result is in the
+ * cost[u] (clearing tasks are not modelled).  cost: host, n_units values (any time unit; the result is in the
  * same unit).  flush_frac in [0, 1], workers >= 1. */
 int race_schedule_simulate(race_schedule_t s, const float* cost, double flush_frac, int32_t workers,
                            double* makespan);

@@ -85,7 +85,7 @@ struct race_schedule {
   bool uploaded = false;
   int device = -1;
   DevBuf<int32_t> leaf_units, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old, dep_ptr, dep_idx;
-  DevBuf<uint32_t> flow_state;  // done[n_units], status, padding, counter (64-bit, 8-byte aligned)
+  DevBuf<uint32_t> flow_state;  // done[n_units + n_zero_tasks], status, padding, counter (64-bit, 8-byte aligned)
   uint32_t epoch = 0;
   uint64_t ticket_next = 0;
   int32_t n_cus = 0;
@@ -125,7 +125,7 @@ struct race_batch {
   int device = -1;
   std::vector<race_schedule_t> mats;
   std::vector<int64_t> unit_base;  // offset of each matrix's done flags in the state
-  DevBuf<int32_t> ticket_mat, ticket_unit, zero_mat, zero_idx;
+  DevBuf<int32_t> ticket_mat, ticket_unit;
   DevBuf<uint32_t> state;
   void* d_mats = nullptr;          // BatchMat<ValT>[count]
   bool bound = false;
@@ -302,8 +302,8 @@ int race_schedule_upload(race_schedule_t s) {
   UP(dep_ptr, L.dep_ptr)
   UP(dep_idx, L.dep_idx)
   {
-    // done[] per unit, then status, then an aligned 64-bit counter
-    const size_t words = (L.unit_lo.size() + 2 + 1) / 2 * 2 + 2;
+    // done[] per unit and clearing task, then status, then an aligned 64-bit counter
+    const size_t words = (L.unit_lo.size() + static_cast<size_t>(L.n_zero_tasks) + 2 + 1) / 2 * 2 + 2;
     std::vector<uint32_t> zeros(words, 0u);
     UP(flow_state, zeros)
   }
@@ -520,15 +520,18 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   hipError_t e = race::race_flow_occupancy<ValT>(k, s->params.block_threads, wmax, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(RACE_EUNSUPPORTED, "dataflow kernel does not fit a CU with this window and block size");
-  const int32_t n_tickets = n_units;
+  // the first tickets clear the y entries whose first touch is a shared atomic add
+  const int32_t n_flags = n_units + L.n_zero_tasks;
+  const int32_t n_tickets = n_flags;
   const int32_t grid = std::max(1, std::min(n_tickets, per_cu * s->n_cus));
   uint32_t* base = s->flow_state.p;
   const size_t counter_word = s->flow_state.count - 2;
   race::FlowArgs f{s->dep_ptr.p, s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word),
-                   base + n_units, trace, n_tickets};
+                   base + n_flags, trace, n_tickets, n_units, L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p,
+                   static_cast<int64_t>(L.zero_idx.size())};
   s->epoch += 1;
   if (s->epoch == 0) {  // wrapped: every done flag must differ from the new epoch
-    e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_units, st);
+    e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_flags, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
     s->epoch = 1;
   }
@@ -571,8 +574,10 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
     return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
                                        " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t ze = race::launch_zero_entries(y, k, s->zero_idx.p, static_cast<int64_t>(s->L.zero_idx.size()), st);
-  if (ze != hipSuccess) return hip_fail(ze, "clearing shared entries");
+  if (s->params.exec_mode == 0) {  // (the dataflow launch clears them itself, in its first tickets)
+    hipError_t ze = race::launch_zero_entries(y, k, s->zero_idx.p, static_cast<int64_t>(s->L.zero_idx.size()), st);
+    if (ze != hipSuccess) return hip_fail(ze, "clearing shared entries");
+  }
   if (s->params.value_type == 0) {
     const auto a = unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p);
     return s->params.exec_mode == 1 ? run_flow<double>(s, a, k, x, y, trace, st)
@@ -590,13 +595,13 @@ int race_schedule_check(race_schedule_t s) {
   if (!s->uploaded) return RACE_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-  const int32_t n_units = static_cast<int32_t>(s->L.unit_lo.size());
+  const int32_t n_flags = static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
   uint32_t status = 0;
-  e = hipMemcpy(&status, s->flow_state.p + n_units, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  e = hipMemcpy(&status, s->flow_state.p + n_flags, sizeof(uint32_t), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   if (status) {
     const uint32_t zero = 0;
-    e = hipMemcpy(s->flow_state.p + n_units, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(s->flow_state.p + n_flags, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     return fail(RACE_EINTERNAL, "a dataflow wait gave up (bounded spin exceeded)");
   }
@@ -632,7 +637,17 @@ int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, in
 template <typename ValT>
 static race::BatchMat<ValT> batch_mat(race_schedule_t s, const ValT* diag, const ValT* vals, uint32_t* done,
                                       const double* x, double* y) {
-  return race::BatchMat<ValT>{unit_args<ValT>(s, diag, vals), s->dep_ptr.p, s->dep_idx.p, done, x, y};
+  return race::BatchMat<ValT>{unit_args<ValT>(s, diag, vals),
+                              s->dep_ptr.p,
+                              s->dep_idx.p,
+                              done,
+                              x,
+                              y,
+                              s->zero_idx.p,
+                              static_cast<int64_t>(s->L.zero_idx.size()),
+                              static_cast<int32_t>(s->L.unit_lo.size()),
+                              s->L.n_zero_tasks,
+                              race::kZeroChunk};
 }
 
 static void batch_release(race_batch_t b) {
@@ -646,14 +661,11 @@ static void batch_release(race_batch_t b) {
   b->d_mats = nullptr;
   release(b->ticket_mat);
   release(b->ticket_unit);
-  release(b->zero_mat);
-  release(b->zero_idx);
   release(b->state);
 }
 
 static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
-  race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count), b->n_tickets,
-                    b->zero_mat.p, b->zero_idx.p, static_cast<int64_t>(b->zero_idx.count)};
+  race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count), b->n_tickets};
   if (b->value_type == 0)
     return race::launch_race_batch<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), a, b->k, b->wmax,
                                            b->threads, b->grid, st);
@@ -697,8 +709,10 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   b->wmax = wmax;
   b->device = dev;
   b->mats.assign(s, s + count);
-  // tickets: (phase as a fraction of the matrix's phases, matrix, unit); every
-  // matrix keeps its own unit order, so all conflict edges point backwards
+  // tickets: (key, matrix, ticket of the matrix): every matrix's clearing
+  // tasks first (key -1), then its units keyed by their phase as a fraction
+  // of the matrix's phases; every matrix keeps its own order, so all
+  // conflict edges point backwards
   struct Tk {
     double key;
     int32_t m, u;
@@ -711,9 +725,11 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     const race::Tree& t = s[m]->tree;
     b->unit_base[m] = total_units;
     const int32_t nu = static_cast<int32_t>(L.unit_lo.size());
+    for (int32_t z = 0; z < L.n_zero_tasks; ++z) tk.push_back({-1.0, m, z});
     for (int32_t u = 0; u < nu; ++u)
-      tk.push_back({static_cast<double>(t.leaf_phase[L.unit_leaf[u]]) / static_cast<double>(t.n_phases), m, u});
-    total_units += nu;
+      tk.push_back({static_cast<double>(t.leaf_phase[L.unit_leaf[u]]) / static_cast<double>(t.n_phases), m,
+                    L.n_zero_tasks + u});
+    total_units += nu + L.n_zero_tasks;
   }
   std::stable_sort(tk.begin(), tk.end(), [](const Tk& a, const Tk& c) {
     if (a.key != c.key) return a.key < c.key;
@@ -724,13 +740,6 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     tm[i] = tk[i].m;
     tu[i] = tk[i].u;
   }
-  // y entries to clear at the start of a run, of every matrix
-  std::vector<int32_t> zm, zi;
-  for (int32_t m = 0; m < count; ++m)
-    for (int32_t g : s[m]->L.zero_idx) {
-      zm.push_back(m);
-      zi.push_back(g);
-    }
   b->n_tickets = static_cast<int32_t>(tk.size());
   int64_t total = 0;
   const size_t words = static_cast<size_t>((total_units + 4 + 1) / 2 * 2);
@@ -738,8 +747,6 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   e = upload(b->ticket_mat, tm.data(), tm.size(), &total);
   if (e == hipSuccess) e = upload(b->ticket_unit, tu.data(), tu.size(), &total);
   if (e == hipSuccess) e = upload(b->state, zeros.data(), zeros.size(), &total);
-  if (e == hipSuccess) e = upload(b->zero_mat, zm.data(), zm.size(), &total);
-  if (e == hipSuccess) e = upload(b->zero_idx, zi.data(), zi.size(), &total);
   int32_t per_cu = 0;
   if (e == hipSuccess)
     e = vt == 0 ? race::race_flow_occupancy<double>(k, threads, wmax, &per_cu)

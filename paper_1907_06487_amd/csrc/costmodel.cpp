@@ -110,7 +110,10 @@ double simulate(const Layout& L, const float* cost, double flush_frac, int32_t w
     const double start = free_at.top();
     free_at.pop();
     double ready = start + (1.0 - flush_frac) * cost[u];
-    for (int32_t i = L.dep_ptr[u]; i < L.dep_ptr[u + 1]; ++i) ready = std::max(ready, finish[L.dep_idx[i]]);
+    // edges to clearing tasks (index >= n_units) count as met at the start:
+    // the tasks hold the first tickets and clear a few KB each
+    for (int32_t i = L.dep_ptr[u]; i < L.dep_ptr[u + 1]; ++i)
+      if (L.dep_idx[i] < n_units) ready = std::max(ready, finish[L.dep_idx[i]]);
     finish[u] = ready + flush_frac * cost[u];
     free_at.push(finish[u]);
     end = std::max(end, finish[u]);

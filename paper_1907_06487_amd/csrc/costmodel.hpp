@@ -33,7 +33,8 @@ void unit_features(const Layout& L, const Tree& t, int32_t k, std::vector<float>
 
 // Predicted makespan of a dataflow product: tickets in execution order on
 // `workers` workgroups; unit u computes for (1 - flush_frac) cost[u], waits
-// for its conflict edges, then flushes for flush_frac cost[u].
+// for its conflict edges, then flushes for flush_frac cost[u].  The clearing
+// tasks are not modelled (their edges count as met).
 double simulate(const Layout& L, const float* cost, double flush_frac, int32_t workers);
 
 // Row loads from the network (see above); loads are in nanoseconds, >= 1.

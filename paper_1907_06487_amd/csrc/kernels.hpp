@@ -29,14 +29,24 @@ struct UnitArgs {
 // conflict edges between units (CSR over units, every edge pointing to a
 // smaller unit), per-unit completion epochs, the ticket counter and a status
 // word (bit 0: a bounded wait gave up).
+//
+// Clearing tasks: the first n_zero_tasks tickets each clear zero_chunk
+// entries of zero_idx (y entries whose first touch is a shared atomic add);
+// ticket n_zero_tasks + u is unit u.  A task's completion flag is
+// done[n_units + task].
 struct FlowArgs {
   const int32_t* dep_ptr;
   const int32_t* dep_idx;
-  uint32_t* done;
+  uint32_t* done;       // n_units + n_zero_tasks completion flags
   uint64_t* counter;
   uint32_t* status;
   uint64_t* trace;  // NULL, or 4 stamps per unit: taken, computed, dependencies met, flushed
-  int32_t n_tickets;  // units, in execution order
+  int32_t n_tickets;  // n_zero_tasks + n_units
+  int32_t n_units;
+  int32_t n_zero_tasks;
+  int32_t zero_chunk;
+  const int32_t* zero_idx;
+  int64_t n_zero;
 };
 
 // One matrix of a batch: its layout, conflict edges, completion flags (a
@@ -46,24 +56,26 @@ struct BatchMat {
   UnitArgs<ValT> a;
   const int32_t* dep_ptr;
   const int32_t* dep_idx;
-  uint32_t* done;
+  uint32_t* done;       // n_units + n_zero_tasks flags (a slice of the batch state)
   const double* x;
   double* y;
+  const int32_t* zero_idx;
+  int64_t n_zero;
+  int32_t n_units;
+  int32_t n_zero_tasks;
+  int32_t zero_chunk;
 };
 
-// Tickets of a batch: (matrix, unit) pairs, merged so every matrix keeps its
-// own execution order; the counter, status word and all done flags are
-// cleared by a reset kernel at the start of every run, and the y entries the
-// matrices' shared units touch first are cleared with them.
+// Tickets of a batch: (matrix, ticket of that matrix) pairs, merged so every
+// matrix keeps its own order (clearing tasks first, then units in execution
+// order); the counter, status word and all done flags are cleared by a reset
+// kernel at the start of every run.
 struct BatchArgs {
   const int32_t* ticket_mat;
   const int32_t* ticket_unit;
   uint32_t* state;       // all done flags, then status, then the 64-bit counter
   int64_t state_words;   // length of `state` in 32-bit words (even)
   int32_t n_tickets;
-  const int32_t* zero_mat;  // per cleared entry: matrix
-  const int32_t* zero_idx;  // and y index
-  int64_t n_zero;
 };
 
 // LDS bytes of a unit window of wmax entries with k right-hand sides: the

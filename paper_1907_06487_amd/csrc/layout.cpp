@@ -271,6 +271,9 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
     }
   }
   std::sort(L.zero_idx.begin(), L.zero_idx.end());
+  L.n_zero_tasks = static_cast<int32_t>((L.zero_idx.size() + kZeroChunk - 1) / kZeroChunk);
+  std::vector<int32_t> zero_task(static_cast<size_t>(n), -1);
+  for (size_t i = 0; i < L.zero_idx.size(); ++i) zero_task[L.zero_idx[i]] = static_cast<int32_t>(i / kZeroChunk);
   // conflict edges: a plain touch of y[g] waits for the last plain toucher and
   // every shared toucher since; a shared touch waits for the last plain
   // toucher only (atomic adds of shared touches commute)
@@ -282,6 +285,7 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
       deps.clear();
       auto touch = [&](int32_t g, bool shared) {
         if (last_plain[g] >= 0) deps.push_back(last_plain[g]);
+        if (shared && zero_task[g] >= 0) deps.push_back(n_units + zero_task[g]);
         if (shared) {
           pool_unit.push_back(u);
           pool_next.push_back(shared_head[g]);
@@ -298,7 +302,7 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
       std::sort(deps.begin(), deps.end());
       deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
       for (int32_t v : deps) {
-        if (v >= u) {
+        if (v >= u && v < n_units) {
           *code = RACE_EINTERNAL;
           return "conflict edge does not point to an earlier unit";
         }

@@ -34,6 +34,7 @@ constexpr uint16_t kNoRow = 0xFFFF;      // padding lane
 constexpr uint32_t kFirstBit = 0x80000000u;
 constexpr uint32_t kSharedBit = 0x40000000u;
 constexpr uint32_t kIndexMask = 0x3fffffffu;  // indices are below 2^30
+constexpr int32_t kZeroChunk = 4096;          // y entries one clearing task clears
 
 struct Layout {
   int32_t n = 0;
@@ -53,6 +54,7 @@ struct Layout {
   std::vector<uint32_t> halo;           // index | kFirstBit | kSharedBit
   std::vector<uint32_t> row_flags;      // 2 bits per row (word r / 16, bits 2 (r % 16) + {0 first, 1 shared})
   std::vector<int32_t> zero_idx;        // ascending: y indices cleared before a product (first touch is shared)
+  int32_t n_zero_tasks = 0;             // ceil(zero_idx / kZeroChunk): clearing tasks of a dataflow product
   std::vector<int32_t> unit_chunk_ptr;  // n_units + 1
   std::vector<uint32_t> chunk_off;      // element offset of a slice
   std::vector<int32_t> chunk_len;       // slots per row | (slice width << 16)
@@ -63,7 +65,9 @@ struct Layout {
   std::vector<int32_t> phase_max_window;  // per phase, largest unit window
   // conflict edges for dataflow execution: unit u waits for dep_idx[dep_ptr[u]
   // .. dep_ptr[u+1]), the earlier units touching one of its indices that it
-  // cannot run beside (every pair except two shared touches)
+  // cannot run beside (every pair except two shared touches), and for a
+  // shared touch of a cleared entry, the clearing task of that entry's chunk
+  // (encoded as n_units + task; the tasks are the first tickets of a product)
   std::vector<int32_t> dep_ptr, dep_idx;
 
   int32_t max_window = 0;

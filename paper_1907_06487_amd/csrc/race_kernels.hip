@@ -319,6 +319,27 @@ __device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, co
   }
 }
 
+// A clearing task: y entries zero_idx[i0 .. i1) set to zero with coherent
+// stores (later shared units add to them atomically), then published like a
+// unit.
+template <int K>
+__device__ __forceinline__ void clear_task(const int32_t* __restrict__ zero_idx, int64_t i0, int64_t i1,
+                                           double* __restrict__ y, uint32_t* done_slot, uint32_t epoch, int32_t tid,
+                                           int32_t nthr, bool wave0) {
+  for (int64_t i = i0 + tid; i < i1; i += nthr) {
+    double* p = y + static_cast<size_t>(zero_idx[i]) * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) y_store<true>(p + k, 0.0);
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (wave0) {
+    if (tid == 0) __hip_atomic_store(done_slot, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // Dataflow execution in one persistent launch.  Units are taken in the
 // execution order (phase, then heaviest leaf first, a leaf's units in row
 // order) from a ticket counter; a unit computes right away and, before its
@@ -355,27 +376,24 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
     // the same value in every lane; read into a scalar register so the loop's
     // exit and the barriers below stay in uniform control flow (a ticket taken
     // only when the workgroup is free keeps the end of the run balanced)
-    const int32_t u = __builtin_amdgcn_readfirstlane(s_unit[0]);
-    if (u < 0) break;
-    flow_unit<ValT, K>(a, u, f.dep_ptr, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, xw, yw, gw, tid, nthr,
-                       wave0);
+    const int32_t t = __builtin_amdgcn_readfirstlane(s_unit[0]);
+    if (t < 0) break;
+    if (t < f.n_zero_tasks) {
+      const int64_t i0 = static_cast<int64_t>(t) * f.zero_chunk;
+      clear_task<K>(f.zero_idx, i0, i0 + f.zero_chunk < f.n_zero ? i0 + f.zero_chunk : f.n_zero, y,
+                    f.done + f.n_units + t, epoch, tid, nthr, wave0);
+      continue;
+    }
+    flow_unit<ValT, K>(a, t - f.n_zero_tasks, f.dep_ptr, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, xw, yw,
+                       gw, tid, nthr, wave0);
   }
 }
 
-// Clears a batch's dataflow state (done flags, status, ticket counter) and
-// the y entries first touched by shared units, with plain stores, so a
-// captured graph can replay the run.
-template <typename ValT>
-__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t* state, int64_t words,
-                                                          const BatchMat<ValT>* __restrict__ mats, int32_t k,
-                                                          const int32_t* __restrict__ zero_mat,
-                                                          const int32_t* __restrict__ zero_idx, int64_t n_zero) {
+// Clears a batch's dataflow state (done flags, status, ticket counter) with
+// plain stores, so a captured graph can replay the run.
+__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t* state, int64_t words) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += stride) state[i] = 0u;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_zero; i += stride) {
-    double* y = mats[zero_mat[i]].y + static_cast<size_t>(zero_idx[i]) * k;
-    for (int32_t c = 0; c < k; ++c) y[c] = 0.0;
-  }
 }
 
 __global__ void __launch_bounds__(256) zero_entries_kernel(double* __restrict__ y, int32_t k,
@@ -412,10 +430,16 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
     const int32_t t = __builtin_amdgcn_readfirstlane(s_ticket[0]);
     if (t < 0) break;
     const int32_t m = __builtin_amdgcn_readfirstlane(b.ticket_mat[t]);
-    const int32_t u = __builtin_amdgcn_readfirstlane(b.ticket_unit[t]);
+    const int32_t lt = __builtin_amdgcn_readfirstlane(b.ticket_unit[t]);
     const BatchMat<ValT> mm = mats[m];
-    flow_unit<ValT, K>(mm.a, u, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u, mm.x, mm.y, xw, yw, gw, tid,
-                       nthr, wave0);
+    if (lt < mm.n_zero_tasks) {
+      const int64_t i0 = static_cast<int64_t>(lt) * mm.zero_chunk;
+      clear_task<K>(mm.zero_idx, i0, i0 + mm.zero_chunk < mm.n_zero ? i0 + mm.zero_chunk : mm.n_zero, mm.y,
+                    mm.done + mm.n_units + lt, 1u, tid, nthr, wave0);
+      continue;
+    }
+    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u, mm.x, mm.y,
+                       xw, yw, gw, tid, nthr, wave0);
   }
 }
 
@@ -609,8 +633,7 @@ static hipError_t launch_batch_k(const BatchMat<ValT>* mats, const BatchArgs& b,
   hipError_t e = set_lds_attr<BatchTag<ValT, K>, K>(reinterpret_cast<const void*>(&dev::race_batch_kernel<ValT, K>));
   if (e != hipSuccess) return e;
   const int64_t words = b.state_words;
-  hipLaunchKernelGGL(dev::batch_reset_kernel<ValT>, fill_grid(std::max(words, b.n_zero)), dim3(256), 0, st, b.state,
-                     words, mats, K, b.zero_mat, b.zero_idx, b.n_zero);
+  hipLaunchKernelGGL(dev::batch_reset_kernel, fill_grid(words), dim3(256), 0, st, b.state, words);
   hipLaunchKernelGGL((dev::race_batch_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, mats, b, wmax);
   return hipGetLastError();
 }

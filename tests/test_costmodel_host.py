@@ -98,25 +98,36 @@ def test_unit_features_independent(name, make, kw, k):
         s.close()
 
 
-def independent_deps(u):
+ZERO_CHUNK = 4096  # entries of the zero list one clearing task clears
+
+
+def independent_deps(u, zero=None):
     """Conflict edges from the flags alone: a plain touch of index g waits
     for the last plain toucher of g and every shared toucher since; a shared
-    touch waits for the last plain toucher only."""
+    touch waits for the last plain toucher only.  With the zero list given,
+    a shared touch of a cleared entry also waits for the clearing task of
+    that entry's chunk (returned separately as task numbers)."""
+    chunk = {}
+    if zero is not None:
+        chunk = {int(g): i // ZERO_CHUNK for i, g in enumerate(zero)}
     last_plain = {}
     shared_since = {}
-    deps = []
+    deps, tasks = [], []
     for i, (idx, fl) in enumerate(_units_touches(u)):
-        d = set()
+        d, tk = set(), set()
         for g, f in zip(idx.tolist(), fl.tolist()):
             if g in last_plain:
                 d.add(last_plain[g])
             if f & 2:
+                if g in chunk:
+                    tk.add(chunk[g])
                 shared_since.setdefault(g, set()).add(i)
             else:
                 d |= shared_since.pop(g, set())
                 last_plain[g] = i
         deps.append(sorted(d))
-    return deps
+        tasks.append(sorted(tk))
+    return (deps, tasks) if zero is not None else deps
 
 
 @pytest.mark.parametrize("workers", [1, 7, 64])
@@ -133,7 +144,8 @@ def test_simulate_matches_oracle(name, make, kw, workers):
         c64 = cost.astype(np.float64)
         want, _ = D.makespan(list((1 - frac) * c64), list(frac * c64), independent_deps(u), workers)
         assert got == pytest.approx(want, rel=1e-12)
-        assert s.stats()["n_deps"] == sum(len(d) for d in independent_deps(u))
+        deps, tasks = independent_deps(u, s.zero_list())
+        assert s.stats()["n_deps"] == sum(len(d) for d in deps) + sum(len(t) for t in tasks)
     finally:
         s.close()
 
