@@ -165,6 +165,63 @@ def run_batch(args, k, torch):
         s.close()
 
 
+def run_spmm(args, k, torch, m=None, one_pass=False):
+    """SymmSpMM Y = A X with k right-hand sides (row-major n x k) on the
+    workload's matrix: one JSON line per k.  Default: the bench window, in
+    passes of the widest column tile that fits; one_pass: a window small
+    enough for all k columns at once."""
+    import numpy as np
+
+    import paper_1907_06487_amd as R
+    from paper_1907_06487_amd import autotune
+    from oracle import symmspmv as O
+
+    if m is None:
+        m, desc = workload(args.workload)
+    win = min(args.window, autotune.max_window(k)) if one_pass else args.window
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
+                   block_threads=args.block, window_max=win, value_type=args.value_type, exec_mode=args.exec_mode,
+                   shared_atomics=bool(args.shared_atomics))
+    st = s.stats()
+    dev = "cuda:0"
+    nring = max(2, -(-RING_BYTES // (8 * m.n * k)))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(54321 + k)
+    xs = [torch.rand((m.n, k), dtype=torch.float64, device=dev, generator=gen) * 2 - 1 for _ in range(nring)]
+    ys = [torch.empty((m.n, k), dtype=torch.float64, device=dev) for _ in range(nring)]
+    perm = s.perm()
+    X0 = np.empty((m.n, k))
+    X0[perm] = xs[0].cpu().numpy()
+    s.spmm(xs[0], ys[0])
+    torch.cuda.synchronize()
+    Y = ys[0].cpu().numpy()
+    Y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, X0)[perm]
+    absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(X0))[perm]
+    err = max(O.errors(Y[:, j], Y_ref[:, j], absax[:, j])[0] for j in range(k))
+    ms = time_ring(lambda x, y: s.spmm(x, y), xs, ys, args.steps, args.warmup, torch)
+    s.check()
+    flops = 2 * st["nnz_full"] * k
+    bytes_min = 12 * st["nnz_upper"] + 16 * k * m.n + 4 * (m.n + 1)
+    achieved = bytes_min / (ms * 1e-3) / 1e9
+    tile = k
+    while tile > 1 and st["max_window"] * (16 * tile + 4) > 159 * 1024:
+        tile -= 1
+    log(f"SpMM k={k}: {ms * 1e3:.2f} us/product, {flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, {achieved:.1f} GB/s "
+        f"algorithmic, window {win}, passes of {tile} columns, worst column error {err:.2e}")
+    out = {
+        "metric": f"SymmSpMM GFLOP/s, {k} right-hand sides", "value": round(flops / (ms * 1e-3) / 1e9, 3),
+        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "k": k, "n_workers": args.n_workers, "block_threads": args.block,
+                   "window_max": win, "rhs_tile": tile, "units": st["n_units"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_min},
+        "error": {"norm_worst_column": err}, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def run_learned_ab(args, torch):
     """Held-out A/B of the learned cost model on the 3D 27-point 160^3
     stencil: the schedule the nonzero heuristic picks against the one the
@@ -260,6 +317,7 @@ def main():
     ap.add_argument("--k", default="1", help="batch64 workload: right-hand sides, e.g. 1,4,16")
     ap.add_argument("--model-dir", default=None, help="learned_ab workload: directory of cost_model.npy/.json")
     ap.add_argument("--rounds", type=int, default=5, help="learned_ab workload: timing rounds per arm")
+    ap.add_argument("--spmm-k", default="", help="SymmSpMM on the workload's matrix instead, e.g. 4,16 (one line each)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a device copy of this many MiB (reference for the traffic counters)")
     ap.add_argument("--sweep", default="",
@@ -284,6 +342,13 @@ def main():
         return
     if args.workload == "learned_ab":
         run_learned_ab(args, torch)
+        return
+    if args.spmm_k:
+        m, _ = workload(args.workload)
+        for k in (int(v) for v in args.spmm_k.split(",")):
+            run_spmm(args, k, torch, m)
+            if k > 2:
+                run_spmm(args, k, torch, m, one_pass=True)
         return
     m, desc = workload(args.workload)
     log(f"workload {args.workload}: n={m.n} nnz_upper={m.nnz}")

@@ -69,6 +69,9 @@ typedef struct {
   int32_t shared_atomics;  /* a leaf whose rows need several LDS windows is cut into several units.  0: those units
                               run one after another; 1: they run concurrently and combine the y entries they share
                               with global float64 atomic adds (other entries stay atomic-free) */
+  int32_t rhs_tile;        /* right-hand sides per pass of race_symm_spmm (0: all k when the unit windows of k
+                              columns fit the LDS, else the widest tile that fits; t > 0: at most t).  Each pass
+                              re-reads the matrix; narrower passes keep the windows, and so the reuse, large */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */
@@ -173,11 +176,13 @@ int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx);
 int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream);
 
 /* Y = A X for k right-hand sides, X and Y device float64 row-major n x k
- * (k in 1..16), permuted order, Y overwritten. */
+ * (k in 1..16), permuted order, Y overwritten.  Runs in passes of
+ * race_params.rhs_tile columns (see there). */
 int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream);
 
 /* As race_symm_spmm, and record per unit four device wall-clock stamps into
- * trace (device uint64 array of 4 * n_units, units in execution order):
+ * trace (device uint64 array of 4 * n_units, units in execution order; with
+ * several passes, those of the last pass):
  * [0] work taken, [1] arithmetic done, [2] earlier conflicting units done,
  * [3] y flushed.  Ticks at race_stats.wall_clock_hz.  These per-unit times
  * are the measurements the cost model learns from. */
@@ -196,11 +201,13 @@ int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, in
 /* ---- batches: many schedules in one persistent launch ---- */
 
 /* Group `count` uploaded schedules (same device and value type) for k
- * right-hand sides each.  Their units are merged into one ticket sequence
- * (by phase, keeping every matrix's own order) for a single persistent
- * dataflow launch of `threads` threads per workgroup (0: the largest
- * block_threads of the schedules).  The schedules are borrowed and must
- * outlive the batch. */
+ * right-hand sides each.  Their clearing tasks and units are merged into one
+ * ticket sequence (clearing first, then by phase, keeping every matrix's own
+ * order) for a single persistent dataflow launch of `threads` threads per
+ * workgroup (0: the largest block_threads of the schedules); when the
+ * largest unit window cannot hold k columns, the run takes passes of the
+ * widest tile that fits, one launch each.  The schedules are borrowed and
+ * must outlive the batch. */
 int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_t threads, race_batch_t* out);
 
 /* Set the device arrays of every matrix (host arrays of `count` device

@@ -22,7 +22,7 @@ BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
-                shared_atomics=True, cost_model=None):
+                shared_atomics=True, cost_model=None, rhs_tile=0):
     """race_params from keywords.  balance="model" needs cost_model: the
     network's MLP_PARAMS float32 weights (kept alive on the returned struct)."""
     p = race_params_default()
@@ -35,6 +35,7 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.block_threads = int(block_threads)
     p.exec_mode = {"phases": 0, "flow": 1}[exec_mode]
     p.shared_atomics = int(bool(shared_atomics))
+    p.rhs_tile = int(rhs_tile)
     if cost_model is not None:
         import ctypes
 

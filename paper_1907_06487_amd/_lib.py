@@ -48,7 +48,7 @@ class race_params(ctypes.Structure):
         ("balance_by", ctypes.c_int32), ("global_lb", ctypes.c_int32), ("value_type", ctypes.c_int32),
         ("window_max", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("eps", ctypes.c_double * 8),
         ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
-        ("exec_mode", ctypes.c_int32), ("shared_atomics", ctypes.c_int32),
+        ("exec_mode", ctypes.c_int32), ("shared_atomics", ctypes.c_int32), ("rhs_tile", ctypes.c_int32),
     ]
 
 

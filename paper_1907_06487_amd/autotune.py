@@ -3,8 +3,11 @@
 Picks, per matrix and number of right-hand sides k, the RACE worker count
 (N_t, Section 5), the unit window and the workgroup size by timing candidate
 schedules on the device (HIP events around the library's own product
-calls).  A batch needs one workgroup size for all matrices; `tune_batch`
-chooses it by timing the whole batch.
+calls).  For k > 2 it also weighs the right-hand-side tile: windows that
+hold all k columns in one pass (small, so little reuse) against the largest
+window taken in passes of the widest tile that fits (the matrix re-read
+per pass).  A batch needs one workgroup size for all matrices; `tune_batch`
+chooses it, and the window mode, by timing the whole batch.
 """
 from __future__ import annotations
 
@@ -19,10 +22,10 @@ def max_window(k: int) -> int:
     return min(3840, (159 * 1024) // (16 * k + 4) - 16)
 
 
-def candidates(n: int, k: int, block: int):
-    """Worker counts of 8000, 4000 and 2000 rows per worker at the largest
-    window that fits for k."""
-    wm = max_window(k)
+def candidates(n: int, k: int, block: int, window: int = 0):
+    """Worker counts of 8000, 4000 and 2000 rows per worker at the given
+    window (0: the largest that holds all k columns)."""
+    wm = window or max_window(k)
     nts = sorted({int(min(4096, max(4, n // r))) for r in (8000, 4000, 2000)})
     return [dict(n_workers=nt, window_max=wm, block_threads=block) for nt in nts]
 
@@ -41,13 +44,13 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0"):
+def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0", window: int = 0):
     """Best shape for one matrix: returns (params, ms, all results)."""
     shape = (m.n, k) if k > 1 else (m.n,)
     x = torch.rand(shape, dtype=torch.float64, device=device)
     y = torch.empty_like(x)
     results = []
-    for c in candidates(m.n, k, block):
+    for c in candidates(m.n, k, block, window):
         s = Schedule(m.n, m.row_ptr, m.col, m.val, **c)
         ms = _time(lambda: s.spmm(x, y) if k > 1 else s.spmv(x, y), reps)
         s.close()
@@ -57,26 +60,35 @@ def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0"):
 
 
 def tune_batch(mats, k: int, blocks=(256, 512, 1024), reps: int = 5, device: str = "cuda:0", log=None):
-    """Per-matrix shapes (timed at 512 threads), then the workgroup size
-    whose whole batch replay runs fastest.  Returns (schedules, batch, chosen)."""
-    params = []
-    for i, m in enumerate(mats):
-        params.append(tune_matrix(m, k, 512, reps=3, device=device)[0])
-        if log and i % 16 == 15:
-            log(f"autotune k={k}: {i + 1}/{len(mats)} matrices")
-    scheds = [Schedule(m.n, m.row_ptr, m.col, m.val, **p) for m, p in zip(mats, params)]
+    """Per-matrix shapes (timed at 512 threads) for each window mode, then the
+    mode and workgroup size whose whole batch replay runs fastest.  Returns
+    (schedules, batch, chosen)."""
+    modes = [0] if max_window(k) >= 3840 else [0, 3840]  # one pass of k columns; or the largest window, tiled
     xs = [torch.rand((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=device) for m in mats]
     ys = [torch.empty_like(x) for x in xs]
     best = None
-    for blk in blocks:
-        batch = Batch(scheds, k, threads=blk)
-        batch.bind(xs, ys)
-        ms = _time(lambda: batch.run(use_graph=True), reps)
-        if best is None or ms < best[0]:
-            if best is not None:
-                best[1].close()
-            best = (ms, batch, blk)
-        else:
-            batch.close()
-    ms, batch, blk = best
+    for window in modes:
+        params = []
+        for i, m in enumerate(mats):
+            params.append(tune_matrix(m, k, 512, reps=3, device=device, window=window)[0])
+            if log and i % 16 == 15:
+                log(f"autotune k={k} window {window or max_window(k)}: {i + 1}/{len(mats)} matrices")
+        scheds = [Schedule(m.n, m.row_ptr, m.col, m.val, **p) for m, p in zip(mats, params)]
+        for blk in blocks:
+            batch = Batch(scheds, k, threads=blk)
+            batch.bind(xs, ys)
+            ms = _time(lambda: batch.run(use_graph=True), reps)
+            if best is None or ms < best[0]:
+                if best is not None:
+                    best[1].close()
+                    if best[2] is not scheds:
+                        for sc in best[2]:
+                            sc.close()
+                best = (ms, batch, scheds, params, blk)
+            else:
+                batch.close()
+        if best[2] is not scheds:
+            for sc in scheds:
+                sc.close()
+    ms, batch, scheds, params, blk = best
     return scheds, batch, {"block_threads": blk, "params": params, "ms": ms}

@@ -94,13 +94,14 @@ struct race_schedule {
   DevBuf<uint16_t> lane_slot, sell_slot;
   DevBuf<double> lane_diag64, sell_val64;
   DevBuf<float> lane_diag32, sell_val32;
+  DevBuf<double> tiles_x, tiles_y;  // column tiles of X and Y for products with many passes (grown on demand)
 
   void free_device() {
     release(leaf_units); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
-    release(sell_val32); release(dep_ptr); release(dep_idx); release(flow_state);
+    release(sell_val32); release(dep_ptr); release(dep_idx); release(flow_state); release(tiles_x); release(tiles_y);
     uploaded = false;
   }
 };
@@ -117,6 +118,7 @@ struct race_csr {
 struct race_batch {
   int32_t count = 0;
   int32_t k = 1;
+  int32_t kt = 1;  // right-hand sides per pass
   int32_t value_type = 0;
   int32_t threads = 256;
   int32_t grid = 0;
@@ -155,6 +157,7 @@ int race_params_default(race_params* p) {
   p->cost_model_len = 0;
   p->exec_mode = 1;
   p->shared_atomics = 1;
+  p->rhs_tile = 0;
   return RACE_OK;
 }
 
@@ -175,6 +178,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
   if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
   if (prm.shared_atomics < 0 || prm.shared_atomics > 1) return fail(RACE_EINVAL, "shared_atomics must be 0 or 1");
+  if (prm.rhs_tile < 0 || prm.rhs_tile > 16) return fail(RACE_EINVAL, "rhs_tile must be in 0..16");
   if (prm.window_max == 0) prm.window_max = 3840;
   if (prm.window_max < 2 || prm.window_max > 8000) return fail(RACE_EINVAL, "window_max must be in 2..8000");
   if (prm.block_threads == 0) prm.block_threads = 256;
@@ -511,7 +515,7 @@ static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const
 
 template <typename ValT>
 static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
-                    uint64_t* trace, hipStream_t st) {
+                    int32_t ld, uint64_t* trace, hipStream_t st) {
   const race::Layout& L = s->L;
   const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
   if (n_units == 0) return RACE_OK;
@@ -538,14 +542,14 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   const uint64_t ticket_base = s->ticket_next;
   s->ticket_next += static_cast<uint64_t>(n_tickets) + static_cast<uint64_t>(grid);
   s->stats.flow_grid = grid;
-  e = race::launch_race_flow<ValT>(a, f, k, x, y, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
+  e = race::launch_race_flow<ValT>(a, f, k, x, y, ld, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
   if (e != hipSuccess) return hip_fail(e, "RACE dataflow launch");
   return RACE_OK;
 }
 
 template <typename ValT>
 static int run_phases(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
-                      uint64_t* trace, hipStream_t st) {
+                      int32_t ld, uint64_t* trace, hipStream_t st) {
   const race::Layout& L = s->L;
   // a leaf's units run on one workgroup in order, or each on its own
   // workgroup when they combine their shared entries atomically
@@ -556,10 +560,20 @@ static int run_phases(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t 
     if (i1 == i0) continue;
     const int32_t wmax = std::max(1, L.phase_max_window[ph]);
     hipError_t e =
-        race::launch_race_phase<ValT>(a, i0, i1 - i0, per_unit, k, x, y, wmax, s->params.block_threads, trace, st);
+        race::launch_race_phase<ValT>(a, i0, i1 - i0, per_unit, k, x, y, ld, wmax, s->params.block_threads, trace, st);
     if (e != hipSuccess) return hip_fail(e, "RACE phase launch");
   }
   return RACE_OK;
+}
+
+// Right-hand sides per pass: all k when the unit windows of that many fit
+// the LDS (or rhs_tile asks for fewer), else the widest tile that fits.
+static int32_t rhs_tile(race_schedule_t s, int32_t k) {
+  const size_t lds_limit = 159 * 1024;  // dynamic windows plus the kernels' own few bytes
+  const int32_t wmax = std::max(1, s->L.max_window);
+  int32_t kt = s->params.rhs_tile > 0 ? std::min(k, s->params.rhs_tile) : k;
+  while (kt > 1 && race::window_lds_bytes(wmax, kt) > lds_limit) --kt;
+  return race::window_lds_bytes(wmax, kt) > lds_limit ? 0 : kt;
 }
 
 static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, uint64_t* trace, void* stream) {
@@ -568,24 +582,60 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
   if (s->tree.n == 0) return RACE_OK;
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
-  const size_t lds_limit = 159 * 1024;  // dynamic windows plus the kernels' own few bytes
-  const int32_t wmax = std::max(1, s->L.max_window);
-  if (race::window_lds_bytes(wmax, k) > lds_limit)
-    return fail(RACE_EUNSUPPORTED, "window of " + std::to_string(wmax) + " entries x " + std::to_string(k) +
-                                       " right-hand sides exceeds the LDS; rebuild with a smaller window_max");
+  const int32_t kt = rhs_tile(s, k);
+  if (kt < 1) return fail(RACE_EUNSUPPORTED, "a unit window does not fit the LDS; rebuild with a smaller window_max");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (s->params.exec_mode == 0) {  // (the dataflow launch clears them itself, in its first tickets)
-    hipError_t ze = race::launch_zero_entries(y, k, s->zero_idx.p, static_cast<int64_t>(s->L.zero_idx.size()), st);
-    if (ze != hipSuccess) return hip_fail(ze, "clearing shared entries");
+  const int32_t n = s->tree.n;
+  // with four or more passes, strided columns would waste most of every
+  // cache line: copy X into contiguous column tiles, run the passes on
+  // them, and copy Y back
+  const int32_t passes = (k + kt - 1) / kt;
+  const bool tiled = passes >= 4;
+  const double* xp = x;
+  double* yp = y;
+  if (tiled) {
+    const size_t need = static_cast<size_t>(n) * k;
+    for (DevBuf<double>* b : {&s->tiles_x, &s->tiles_y}) {
+      if (b->count < need) {
+        release(*b);
+        hipError_t e = hipMalloc(&b->p, need * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc of the column tiles");
+        b->count = need;
+      }
+    }
+    hipError_t e = race::launch_tile(n, k, kt, const_cast<double*>(x), s->tiles_x.p, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "tiling X");
+    xp = s->tiles_x.p;
+    yp = s->tiles_y.p;
   }
-  if (s->params.value_type == 0) {
-    const auto a = unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p);
-    return s->params.exec_mode == 1 ? run_flow<double>(s, a, k, x, y, trace, st)
-                                    : run_phases<double>(s, a, k, x, y, trace, st);
+  // one pass per tile of right-hand sides: columns c0 .. c0 + kc, either in
+  // place (rows k doubles apart) or in their contiguous tile (rows kc apart)
+  for (int32_t c0 = 0; c0 < k; c0 += kt) {
+    const int32_t kc = std::min(kt, k - c0);
+    const size_t off = tiled ? static_cast<size_t>(n) * c0 : static_cast<size_t>(c0);
+    const int32_t ld = tiled ? kc : k;
+    int rc = RACE_OK;
+    if (s->params.exec_mode == 0) {  // (the dataflow launch clears them itself, in its first tickets)
+      hipError_t ze = race::launch_zero_entries(yp + off, ld, kc, s->zero_idx.p,
+                                                static_cast<int64_t>(s->L.zero_idx.size()), st);
+      if (ze != hipSuccess) return hip_fail(ze, "clearing shared entries");
+    }
+    if (s->params.value_type == 0) {
+      const auto a = unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p);
+      rc = s->params.exec_mode == 1 ? run_flow<double>(s, a, kc, xp + off, yp + off, ld, trace, st)
+                                    : run_phases<double>(s, a, kc, xp + off, yp + off, ld, trace, st);
+    } else {
+      const auto a = unit_args<float>(s, s->lane_diag32.p, s->sell_val32.p);
+      rc = s->params.exec_mode == 1 ? run_flow<float>(s, a, kc, xp + off, yp + off, ld, trace, st)
+                                    : run_phases<float>(s, a, kc, xp + off, yp + off, ld, trace, st);
+    }
+    if (rc != RACE_OK) return rc;
   }
-  const auto a = unit_args<float>(s, s->lane_diag32.p, s->sell_val32.p);
-  return s->params.exec_mode == 1 ? run_flow<float>(s, a, k, x, y, trace, st)
-                                  : run_phases<float>(s, a, k, x, y, trace, st);
+  if (tiled) {
+    hipError_t e = race::launch_tile(n, k, kt, y, s->tiles_y.p, 0, st);
+    if (e != hipSuccess) return hip_fail(e, "untiling Y");
+  }
+  return RACE_OK;
 }
 
 extern "C" {
@@ -664,13 +714,22 @@ static void batch_release(race_batch_t b) {
   release(b->state);
 }
 
+// One pass per tile of right-hand sides, each a state reset and one
+// persistent launch over all tickets.
 static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
-  race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count), b->n_tickets};
-  if (b->value_type == 0)
-    return race::launch_race_batch<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), a, b->k, b->wmax,
-                                           b->threads, b->grid, st);
-  return race::launch_race_batch<float>(static_cast<const race::BatchMat<float>*>(b->d_mats), a, b->k, b->wmax,
-                                        b->threads, b->grid, st);
+  for (int32_t c0 = 0; c0 < b->k; c0 += b->kt) {
+    const int32_t kc = std::min(b->kt, b->k - c0);
+    race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count),
+                      b->n_tickets, c0, b->k};
+    hipError_t e =
+        b->value_type == 0
+            ? race::launch_race_batch<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), a, kc, b->wmax,
+                                              b->threads, b->grid, st)
+            : race::launch_race_batch<float>(static_cast<const race::BatchMat<float>*>(b->d_mats), a, kc, b->wmax,
+                                             b->threads, b->grid, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 extern "C" {
@@ -692,8 +751,11 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     threads = std::max(threads, s[m]->params.block_threads);
     wmax = std::max(wmax, s[m]->L.max_window);
   }
-  if (race::window_lds_bytes(wmax, k) > 159 * 1024)
-    return fail(RACE_EUNSUPPORTED, "largest window x k exceeds the LDS; rebuild with a smaller window_max");
+  // right-hand sides per pass: all k if the largest window allows, else the widest tile that fits
+  int32_t kt = k;
+  while (kt > 1 && race::window_lds_bytes(wmax, kt) > 159 * 1024) --kt;
+  if (race::window_lds_bytes(wmax, kt) > 159 * 1024)
+    return fail(RACE_EUNSUPPORTED, "largest window exceeds the LDS; rebuild with a smaller window_max");
   if (threads_override != 0) {
     if (threads_override != 64 && threads_override != 128 && threads_override != 256 && threads_override != 512 &&
         threads_override != 1024)
@@ -704,6 +766,7 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   if (!b) return fail(RACE_ENOMEM, "out of host memory");
   b->count = count;
   b->k = k;
+  b->kt = kt;
   b->value_type = vt;
   b->threads = threads;
   b->wmax = wmax;
@@ -749,8 +812,8 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   if (e == hipSuccess) e = upload(b->state, zeros.data(), zeros.size(), &total);
   int32_t per_cu = 0;
   if (e == hipSuccess)
-    e = vt == 0 ? race::race_flow_occupancy<double>(k, threads, wmax, &per_cu)
-                : race::race_flow_occupancy<float>(k, threads, wmax, &per_cu);
+    e = vt == 0 ? race::race_flow_occupancy<double>(kt, threads, wmax, &per_cu)
+                : race::race_flow_occupancy<float>(kt, threads, wmax, &per_cu);
   if (e != hipSuccess) {
     batch_release(b);
     delete b;
@@ -795,7 +858,12 @@ int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y) {
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   }
-  e = b->value_type == 0 ? race::prepare_race_batch<double>(b->k) : race::prepare_race_batch<float>(b->k);
+  // kernel attributes of every width a pass uses (the tile, and a narrower last tile)
+  for (const int32_t kc : {b->kt, b->k % b->kt}) {
+    if (kc == 0) continue;
+    e = b->value_type == 0 ? race::prepare_race_batch<double>(kc) : race::prepare_race_batch<float>(kc);
+    if (e != hipSuccess) break;
+  }
   if (e != hipSuccess) return hip_fail(e, "batch kernel attributes");
   e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");

@@ -76,6 +76,8 @@ struct BatchArgs {
   uint32_t* state;       // all done flags, then status, then the 64-bit counter
   int64_t state_words;   // length of `state` in 32-bit words (even)
   int32_t n_tickets;
+  int32_t col0;          // first right-hand side of this pass
+  int32_t ld;            // row stride of every x and y (the batch's k)
 };
 
 // LDS bytes of a unit window of wmax entries with k right-hand sides: the
@@ -87,22 +89,23 @@ inline size_t window_lds_bytes(int32_t wmax, int32_t k) {
 // One phase: `count` workgroups starting at `base`, each running one leaf's
 // units in order (per_unit 0; base and count index the leaves list) or one
 // unit (per_unit 1; base and count index the units); k right-hand sides
-// (1..16) in row-major x/y; wmax = largest unit window of the phase.
+// (1..16): columns 0..k-1 of x and y, whose rows are ld doubles apart;
+// wmax = largest unit window of the phase.
 template <typename ValT>
 hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t base, int32_t count, int32_t per_unit, int32_t k,
-                             const double* x, double* y, int32_t wmax, int32_t threads, uint64_t* trace,
+                             const double* x, double* y, int32_t ld, int32_t wmax, int32_t threads, uint64_t* trace,
                              hipStream_t st);
 
-// y[idx[i] * k + c] = 0 for i < count, c < k (entries whose first toucher
+// y[idx[i] * ld + c] = 0 for i < count, c < k (entries whose first toucher
 // is a shared unit).
-hipError_t launch_zero_entries(double* y, int32_t k, const int32_t* idx, int64_t count, hipStream_t st);
+hipError_t launch_zero_entries(double* y, int32_t ld, int32_t k, const int32_t* idx, int64_t count, hipStream_t st);
 
 // Whole product in one persistent launch of `grid` workgroups; epoch and
 // ticket_base identify the call (see race_flow_kernel).
 template <typename ValT>
 hipError_t launch_race_flow(const UnitArgs<ValT>& a, const FlowArgs& f, int32_t k, const double* x, double* y,
-                            int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
-                            hipStream_t st);
+                            int32_t ld, int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch,
+                            uint64_t ticket_base, hipStream_t st);
 
 template <typename ValT>
 hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu);
@@ -122,6 +125,10 @@ hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, 
                               double* y, int32_t lanes_per_row, hipStream_t st);
 hipError_t launch_permute(int32_t n, int32_t k, const int32_t* new2old, const double* in, double* out,
                           int32_t to_permuted, hipStream_t st);
+// Row-major n x k arrays to column tiles of kt columns (each a contiguous
+// n x kc block, kc = kt but for a narrower last tile) and back.
+hipError_t launch_tile(int32_t n, int32_t k, int32_t kt, double* full, double* tiles, int32_t to_tiles,
+                       hipStream_t st);
 
 // Cost-model network (mlp_kernels.hip).  Workspace of the gradient: one
 // partial gradient (plus loss) per 256 samples.

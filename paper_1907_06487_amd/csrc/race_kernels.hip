@@ -85,7 +85,8 @@ __device__ __forceinline__ void apply_batch(const double* v, const int32_t* sl, 
 //      unit's own leaf (when the layout marks them) take a global atomic add.
 template <typename ValT, int K>
 __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u, const double* __restrict__ x,
-                                             double* xw, double* yw, uint32_t* gw, int32_t tid, int32_t nthr) {
+                                             int32_t ld, double* xw, double* yw, uint32_t* gw, int32_t tid,
+                                             int32_t nthr) {
   constexpr int kStage = K >= 4 ? 1 : 4;  // window entries per thread per staging round
   const int32_t lane = tid & (kSlice - 1), wave = tid / kSlice, nwaves = nthr / kSlice;
   const int32_t lo = a.unit_lo[u];
@@ -120,7 +121,7 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u,
     for (int q = 0; q < kStage; ++q) {
       const bool in = base + q * nthr + tid < W;
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv[q][k] = in ? x[static_cast<size_t>(h[q] & 0x3fffffffu) * K + k] : 0.0;
+      for (int k = 0; k < K; ++k) xv[q][k] = in ? x[static_cast<size_t>(h[q] & 0x3fffffffu) * ld + k] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
@@ -203,7 +204,7 @@ __device__ __forceinline__ void y_store(double* p, double v) {
 // a global atomic add instead; they were cleared before the product when no
 // earlier unit wrote them.
 template <typename ValT, int K, bool kCoherent>
-__device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, double* __restrict__ y,
+__device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, double* __restrict__ y, int32_t ld,
                                            const double* yw, const uint32_t* gw, int32_t tid, int32_t nthr) {
   constexpr int kStage = K >= 4 ? 2 : 8;
   const int32_t W = (a.unit_hi[u] - a.unit_lo[u]) + (a.unit_halo_ptr[u + 1] - a.unit_halo_ptr[u]);
@@ -219,12 +220,12 @@ __device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, d
     for (int q = 0; q < kStage; ++q)
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        old[q][k] = (h[q] >> 30) ? 0.0 : y_load<kCoherent>(y + static_cast<size_t>(h[q] & 0x3fffffffu) * K + k);
+        old[q][k] = (h[q] >> 30) ? 0.0 : y_load<kCoherent>(y + static_cast<size_t>(h[q] & 0x3fffffffu) * ld + k);
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
       if (s < W) {
-        double* p = y + static_cast<size_t>(h[q] & 0x3fffffffu) * K;
+        double* p = y + static_cast<size_t>(h[q] & 0x3fffffffu) * ld;
         if (h[q] & 0x40000000u) {
 #pragma unroll
           for (int k = 0; k < K; ++k) unsafeAtomicAdd(p + k, yw[s * K + k]);
@@ -246,7 +247,7 @@ __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_mem
 template <typename ValT, int K>
 __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32_t base, int32_t per_unit,
                                                          const double* __restrict__ x, double* __restrict__ y,
-                                                         int32_t wmax, uint64_t* trace) {
+                                                         int32_t ld, int32_t wmax, uint64_t* trace) {
   extern __shared__ double smem[];
   double* xw = smem;
   double* yw = smem + static_cast<size_t>(wmax) * K;
@@ -257,9 +258,9 @@ __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
   for (int32_t u = u0; u < u1; ++u) {
     const uint64_t t0 = trace ? wall_clock() : 0;
-    compute_unit<ValT, K>(a, u, x, xw, yw, gw, tid, nthr);
+    compute_unit<ValT, K>(a, u, x, ld, xw, yw, gw, tid, nthr);
     const uint64_t t1 = trace ? wall_clock() : 0;
-    flush_unit<ValT, K, false>(a, u, y, yw, gw, tid, nthr);
+    flush_unit<ValT, K, false>(a, u, y, ld, yw, gw, tid, nthr);
     __syncthreads();
     if (trace && tid == 0) {
       const uint64_t t2 = wall_clock();
@@ -277,12 +278,12 @@ template <typename ValT, int K>
 __device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, const int32_t* dep_ptr,
                                           const int32_t* dep_idx, uint32_t* done, uint32_t* status, uint64_t* trace,
                                           uint32_t epoch, const double* __restrict__ x, double* __restrict__ y,
-                                          double* xw, double* yw, uint32_t* gw, int32_t tid, int32_t nthr,
-                                          bool wave0) {
+                                          int32_t ld, double* xw, double* yw, uint32_t* gw, int32_t tid,
+                                          int32_t nthr, bool wave0) {
   const uint64_t t0 = trace ? wall_clock() : 0;
   // the unit's arithmetic needs nothing from other units; only its flush
   // must follow the earlier units it conflicts with
-  compute_unit<ValT, K>(a, u, x, xw, yw, gw, tid, nthr);
+  compute_unit<ValT, K>(a, u, x, ld, xw, yw, gw, tid, nthr);
   const uint64_t t1 = trace ? wall_clock() : 0;
   const int32_t d0 = dep_ptr[u], d1 = dep_ptr[u + 1];
   for (int32_t i = d0 + tid; i < d1; i += nthr) {
@@ -298,7 +299,7 @@ __device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, co
   }
   __syncthreads();
   const uint64_t t2 = trace ? wall_clock() : 0;
-  flush_unit<ValT, K, true>(a, u, y, yw, gw, tid, nthr);
+  flush_unit<ValT, K, true>(a, u, y, ld, yw, gw, tid, nthr);
   // every thread's coherent y stores complete before the barrier, so the
   // completion flag written after it is only seen once they are visible
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -324,10 +325,10 @@ __device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, co
 // unit.
 template <int K>
 __device__ __forceinline__ void clear_task(const int32_t* __restrict__ zero_idx, int64_t i0, int64_t i1,
-                                           double* __restrict__ y, uint32_t* done_slot, uint32_t epoch, int32_t tid,
-                                           int32_t nthr, bool wave0) {
+                                           double* __restrict__ y, int32_t ld, uint32_t* done_slot, uint32_t epoch,
+                                           int32_t tid, int32_t nthr, bool wave0) {
   for (int64_t i = i0 + tid; i < i1; i += nthr) {
-    double* p = y + static_cast<size_t>(zero_idx[i]) * K;
+    double* p = y + static_cast<size_t>(zero_idx[i]) * ld;
 #pragma unroll
     for (int k = 0; k < K; ++k) y_store<true>(p + k, 0.0);
   }
@@ -352,8 +353,8 @@ __device__ __forceinline__ void clear_task(const int32_t* __restrict__ zero_idx,
 // up, so the grid always drains.
 template <typename ValT, int K>
 __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowArgs f, const double* __restrict__ x,
-                                                         double* __restrict__ y, int32_t wmax, uint32_t epoch,
-                                                         uint64_t ticket_base) {
+                                                         double* __restrict__ y, int32_t ld, int32_t wmax,
+                                                         uint32_t epoch, uint64_t ticket_base) {
   extern __shared__ double smem[];
   double* xw = smem;
   double* yw = smem + static_cast<size_t>(wmax) * K;
@@ -380,12 +381,12 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
     if (t < 0) break;
     if (t < f.n_zero_tasks) {
       const int64_t i0 = static_cast<int64_t>(t) * f.zero_chunk;
-      clear_task<K>(f.zero_idx, i0, i0 + f.zero_chunk < f.n_zero ? i0 + f.zero_chunk : f.n_zero, y,
+      clear_task<K>(f.zero_idx, i0, i0 + f.zero_chunk < f.n_zero ? i0 + f.zero_chunk : f.n_zero, y, ld,
                     f.done + f.n_units + t, epoch, tid, nthr, wave0);
       continue;
     }
-    flow_unit<ValT, K>(a, t - f.n_zero_tasks, f.dep_ptr, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, xw, yw,
-                       gw, tid, nthr, wave0);
+    flow_unit<ValT, K>(a, t - f.n_zero_tasks, f.dep_ptr, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, ld, xw,
+                       yw, gw, tid, nthr, wave0);
   }
 }
 
@@ -396,11 +397,11 @@ __global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t* state, int64
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += stride) state[i] = 0u;
 }
 
-__global__ void __launch_bounds__(256) zero_entries_kernel(double* __restrict__ y, int32_t k,
+__global__ void __launch_bounds__(256) zero_entries_kernel(double* __restrict__ y, int32_t ld, int32_t k,
                                                            const int32_t* __restrict__ idx, int64_t count) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count * k; i += stride)
-    y[static_cast<size_t>(idx[i / k]) * k + i % k] = 0.0;
+    y[static_cast<size_t>(idx[i / k]) * ld + i % k] = 0.0;
 }
 
 // Many matrices in one persistent launch: tickets are (matrix, unit) pairs
@@ -434,12 +435,12 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
     const BatchMat<ValT> mm = mats[m];
     if (lt < mm.n_zero_tasks) {
       const int64_t i0 = static_cast<int64_t>(lt) * mm.zero_chunk;
-      clear_task<K>(mm.zero_idx, i0, i0 + mm.zero_chunk < mm.n_zero ? i0 + mm.zero_chunk : mm.n_zero, mm.y,
-                    mm.done + mm.n_units + lt, 1u, tid, nthr, wave0);
+      clear_task<K>(mm.zero_idx, i0, i0 + mm.zero_chunk < mm.n_zero ? i0 + mm.zero_chunk : mm.n_zero, mm.y + b.col0,
+                    b.ld, mm.done + mm.n_units + lt, 1u, tid, nthr, wave0);
       continue;
     }
-    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u, mm.x, mm.y,
-                       xw, yw, gw, tid, nthr, wave0);
+    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u,
+                       mm.x + b.col0, mm.y + b.col0, b.ld, xw, yw, gw, tid, nthr, wave0);
   }
 }
 
@@ -489,6 +490,24 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double* __restrict__ y, 
   if (i < n) y[i] = 0.0;
 }
 
+// Row-major n x k <-> column tiles: tile t holds columns [t kt, t kt + kc)
+// as a contiguous row-major n x kc block at offset n kt t (kc = kt but for
+// a narrower last tile).  to_tiles: tiles[...] = full[...]; else back.
+__global__ void __launch_bounds__(256) tile_kernel(int32_t n, int32_t k, int32_t kt, double* __restrict__ full,
+                                                   double* __restrict__ tiles, int32_t to_tiles) {
+  const int64_t total = static_cast<int64_t>(n) * k;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / k;
+    const int32_t c = static_cast<int32_t>(e % k);
+    const int32_t t = c / kt, c0 = t * kt;
+    const int32_t kc = k - c0 < kt ? k - c0 : kt;
+    const int64_t at = static_cast<int64_t>(n) * kt * t + i * kc + (c - c0);
+    if (to_tiles) tiles[at] = full[e];
+    else full[e] = tiles[at];
+  }
+}
+
 __global__ void __launch_bounds__(256) permute_kernel(int32_t n, int32_t k, const int32_t* __restrict__ new2old,
                                                       const double* __restrict__ in, double* __restrict__ out,
                                                       int32_t to_permuted) {
@@ -517,12 +536,12 @@ static hipError_t set_lds_attr(const void* fn) {
 
 template <typename ValT, int K>
 static hipError_t launch_leaf(const UnitArgs<ValT>& a, int32_t base, int32_t count, int32_t per_unit, const double* x,
-                              double* y, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
+                              double* y, int32_t ld, int32_t wmax, int32_t threads, uint64_t* trace, hipStream_t st) {
   const size_t lds = window_lds_bytes(wmax, K);
   hipError_t e = set_lds_attr<ValT, K>(reinterpret_cast<const void*>(&dev::race_leaf_kernel<ValT, K>));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((dev::race_leaf_kernel<ValT, K>), dim3(count), dim3(threads), lds, st, a, base, per_unit, x, y,
-                     wmax, trace);
+                     ld, wmax, trace);
   return hipGetLastError();
 }
 
@@ -532,9 +551,9 @@ static dim3 fill_grid(int64_t items) {
   return dim3(static_cast<uint32_t>(std::max<int64_t>(1, std::min<int64_t>(4096, (items + 255) / 256))));
 }
 
-hipError_t launch_zero_entries(double* y, int32_t k, const int32_t* idx, int64_t count, hipStream_t st) {
+hipError_t launch_zero_entries(double* y, int32_t ld, int32_t k, const int32_t* idx, int64_t count, hipStream_t st) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::zero_entries_kernel, fill_grid(count * k), dim3(256), 0, st, y, k, idx, count);
+  hipLaunchKernelGGL(dev::zero_entries_kernel, fill_grid(count * k), dim3(256), 0, st, y, ld, k, idx, count);
   return hipGetLastError();
 }
 
@@ -542,13 +561,14 @@ template <typename ValT, int K>
 struct FlowTag {};
 
 template <typename ValT, int K>
-static hipError_t launch_flow(const UnitArgs<ValT>& a, const FlowArgs& f, const double* x, double* y, int32_t wmax,
-                              int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base, hipStream_t st) {
+static hipError_t launch_flow(const UnitArgs<ValT>& a, const FlowArgs& f, const double* x, double* y, int32_t ld,
+                              int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
+                              hipStream_t st) {
   const size_t lds = window_lds_bytes(wmax, K);
   hipError_t e = set_lds_attr<FlowTag<ValT, K>, K>(reinterpret_cast<const void*>(&dev::race_flow_kernel<ValT, K>));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((dev::race_flow_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, a, f, x, y, wmax, epoch,
-                     ticket_base);
+  hipLaunchKernelGGL((dev::race_flow_kernel<ValT, K>), dim3(grid), dim3(threads), lds, st, a, f, x, y, ld, wmax,
+                     epoch, ticket_base);
   return hipGetLastError();
 }
 
@@ -589,18 +609,18 @@ static hipError_t flow_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_
 
 template <typename ValT>
 hipError_t launch_race_phase(const UnitArgs<ValT>& a, int32_t base, int32_t count, int32_t per_unit, int32_t k,
-                             const double* x, double* y, int32_t wmax, int32_t threads, uint64_t* trace,
+                             const double* x, double* y, int32_t ld, int32_t wmax, int32_t threads, uint64_t* trace,
                              hipStream_t st) {
-#define CALL(KK) launch_leaf<ValT, KK>(a, base, count, per_unit, x, y, wmax, threads, trace, st)
+#define CALL(KK) launch_leaf<ValT, KK>(a, base, count, per_unit, x, y, ld, wmax, threads, trace, st)
   RACE_K_SWITCH(CALL)
 #undef CALL
 }
 
 template <typename ValT>
 hipError_t launch_race_flow(const UnitArgs<ValT>& a, const FlowArgs& f, int32_t k, const double* x, double* y,
-                            int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
-                            hipStream_t st) {
-#define CALL(KK) launch_flow<ValT, KK>(a, f, x, y, wmax, threads, grid, epoch, ticket_base, st)
+                            int32_t ld, int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch,
+                            uint64_t ticket_base, hipStream_t st) {
+#define CALL(KK) launch_flow<ValT, KK>(a, f, x, y, ld, wmax, threads, grid, epoch, ticket_base, st)
   RACE_K_SWITCH(CALL)
 #undef CALL
 }
@@ -613,13 +633,14 @@ hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t
 }
 
 template hipError_t launch_race_phase<double>(const UnitArgs<double>&, int32_t, int32_t, int32_t, int32_t,
-                                              const double*, double*, int32_t, int32_t, uint64_t*, hipStream_t);
+                                              const double*, double*, int32_t, int32_t, int32_t, uint64_t*,
+                                              hipStream_t);
 template hipError_t launch_race_phase<float>(const UnitArgs<float>&, int32_t, int32_t, int32_t, int32_t, const double*,
-                                             double*, int32_t, int32_t, uint64_t*, hipStream_t);
+                                             double*, int32_t, int32_t, int32_t, uint64_t*, hipStream_t);
 template hipError_t launch_race_flow<double>(const UnitArgs<double>&, const FlowArgs&, int32_t, const double*, double*,
-                                             int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
+                                             int32_t, int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
 template hipError_t launch_race_flow<float>(const UnitArgs<float>&, const FlowArgs&, int32_t, const double*, double*,
-                                            int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
+                                            int32_t, int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
 template hipError_t race_flow_occupancy<double>(int32_t, int32_t, int32_t, int32_t*);
 template hipError_t race_flow_occupancy<float>(int32_t, int32_t, int32_t, int32_t*);
 
@@ -695,6 +716,14 @@ hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, 
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile(int32_t n, int32_t k, int32_t kt, double* full, double* tiles, int32_t to_tiles,
+                       hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(n) * k;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::tile_kernel, fill_grid(total), dim3(256), 0, st, n, k, kt, full, tiles, to_tiles);
   return hipGetLastError();
 }
 

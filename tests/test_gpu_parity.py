@@ -140,6 +140,23 @@ def test_race_symm_spmm(k):
         _check(yj, rj, aj, _full_row_len(m), f"spmm k={k} col={j}")
 
 
+@pytest.mark.parametrize("k,tile,window,mode", [(3, 0, 3840, "flow"), (5, 0, 3840, "flow"), (16, 0, 3840, "flow"),
+                                               (7, 1, 3840, "flow"), (9, 4, 2000, "flow"), (5, 0, 3840, "phases"),
+                                               (9, 2, 3840, "phases")])
+def test_race_symm_spmm_tiled(k, tile, window, mode):
+    """More right-hand sides than one pass can hold: passes of `tile` columns
+    (0: the widest that fits the window) over row-major n x k arrays; with
+    four or more passes through contiguous column tiles."""
+    m = matgen.stencil3d_27pt(18, seed=8)
+    print(f"case spmm tiled k={k} tile={tile} window={window} mode={mode}", flush=True)
+    X = matgen.rhs(m.n, 29, k=k).reshape(m.n, k)
+    Y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, X)
+    Y, st = run_race(m, X, k=k, n_workers=64, window_max=window, rhs_tile=tile, exec_mode=mode)
+    absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(X))
+    for j in range(k):
+        _check(Y[:, j], Y_ref[:, j], absax[:, j], _full_row_len(m), f"spmm tiled k={k} col={j}")
+
+
 def test_race_spmm_column_equals_spmv():
     m = matgen.stencil2d_5pt(60, seed=3)
     X = matgen.rhs(m.n, 31, k=4)
@@ -266,6 +283,41 @@ def test_race_full_size_banded_4m(value_type):
         rel = np.linalg.norm(y - y64) / np.linalg.norm(y64)
         print(f"  FP32-value error vs the FP64 matrix: {rel:.3e} (unit roundoff of FP32 {2.0 ** -24:.3e})", flush=True)
         assert rel < 2.0 ** -20
+
+
+def test_batch_tiled_replays():
+    """A batch whose windows cannot hold all k columns runs in passes; graph
+    replays stay correct."""
+    mats = _batch_mats()
+    k = 5
+    scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500)) for m in mats]
+    batch = R.Batch(scheds, k)
+    xs = [torch.empty((m.n, k), dtype=torch.float64, device=DEV) for m in mats]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    batch.bind(xs, ys)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(77)
+    for rep in range(3):
+        for x in xs:
+            x.uniform_(-1.0, 1.0, generator=gen)
+        for y in ys:
+            y.fill_(float("nan"))
+        batch.run(use_graph=(rep != 1))
+        torch.cuda.synchronize()
+        batch.check()
+        for m, s, x, y in zip(mats, scheds, xs, ys):
+            perm = s.perm()
+            xp = x.cpu().numpy()
+            x_orig = np.empty_like(xp)
+            x_orig[perm] = xp
+            y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x_orig)[perm]
+            absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(x_orig))[perm]
+            yh = y.cpu().numpy()
+            for j in range(k):
+                _check(yh[:, j], y_ref[:, j], absax[:, j], _full_row_len(m), f"batch tiled rep={rep} {m.name} col={j}")
+    batch.close()
+    for s in scheds:
+        s.close()
 
 
 def _batch_mats():
