@@ -119,6 +119,7 @@ struct race_batch {
   int32_t count = 0;
   int32_t k = 1;
   int32_t kt = 1;  // right-hand sides per pass
+  bool tiled = false;  // four or more passes: through contiguous column tiles
   int32_t value_type = 0;
   int32_t threads = 256;
   int32_t grid = 0;
@@ -129,6 +130,8 @@ struct race_batch {
   std::vector<int64_t> unit_base;  // offset of each matrix's done flags in the state
   DevBuf<int32_t> ticket_mat, ticket_unit;
   DevBuf<uint32_t> state;
+  DevBuf<double> tiles_x, tiles_y;  // every matrix's column tiles (tiled runs), matrix m at tile_base[m]
+  std::vector<int64_t> tile_base;
   void* d_mats = nullptr;          // BatchMat<ValT>[count]
   bool bound = false;
   hipStream_t cap = nullptr;
@@ -697,7 +700,10 @@ static race::BatchMat<ValT> batch_mat(race_schedule_t s, const ValT* diag, const
                               static_cast<int64_t>(s->L.zero_idx.size()),
                               static_cast<int32_t>(s->L.unit_lo.size()),
                               s->L.n_zero_tasks,
-                              race::kZeroChunk};
+                              race::kZeroChunk,
+                              s->tree.n,
+                              nullptr,
+                              nullptr};
 }
 
 static void batch_release(race_batch_t b) {
@@ -712,15 +718,25 @@ static void batch_release(race_batch_t b) {
   release(b->ticket_mat);
   release(b->ticket_unit);
   release(b->state);
+  release(b->tiles_x);
+  release(b->tiles_y);
 }
 
 // One pass per tile of right-hand sides, each a state reset and one
 // persistent launch over all tickets.
 static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
+  if (b->tiled) {
+    hipError_t e = b->value_type == 0
+                       ? race::launch_batch_tile<double>(static_cast<const race::BatchMat<double>*>(b->d_mats),
+                                                         b->count, b->k, b->kt, 1, st)
+                       : race::launch_batch_tile<float>(static_cast<const race::BatchMat<float>*>(b->d_mats),
+                                                        b->count, b->k, b->kt, 1, st);
+    if (e != hipSuccess) return e;
+  }
   for (int32_t c0 = 0; c0 < b->k; c0 += b->kt) {
     const int32_t kc = std::min(b->kt, b->k - c0);
     race::BatchArgs a{b->ticket_mat.p, b->ticket_unit.p, b->state.p, static_cast<int64_t>(b->state.count),
-                      b->n_tickets, c0, b->k};
+                      b->n_tickets, c0, b->tiled ? kc : b->k, b->tiled ? 1 : 0};
     hipError_t e =
         b->value_type == 0
             ? race::launch_race_batch<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), a, kc, b->wmax,
@@ -729,6 +745,12 @@ static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
                                              b->threads, b->grid, st);
     if (e != hipSuccess) return e;
   }
+  if (b->tiled)
+    return b->value_type == 0
+               ? race::launch_batch_tile<double>(static_cast<const race::BatchMat<double>*>(b->d_mats), b->count,
+                                                 b->k, b->kt, 0, st)
+               : race::launch_batch_tile<float>(static_cast<const race::BatchMat<float>*>(b->d_mats), b->count, b->k,
+                                                b->kt, 0, st);
   return hipSuccess;
 }
 
@@ -767,6 +789,7 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   b->count = count;
   b->k = k;
   b->kt = kt;
+  b->tiled = (k + kt - 1) / kt >= 4;
   b->value_type = vt;
   b->threads = threads;
   b->wmax = wmax;
@@ -835,17 +858,39 @@ int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y) {
     e = hipMalloc(&b->d_mats, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
   }
+  if (b->tiled && !b->tiles_x.p) {
+    int64_t total = 0;
+    b->tile_base.resize(b->count);
+    for (int32_t m = 0; m < b->count; ++m) {
+      b->tile_base[m] = total;
+      total += static_cast<int64_t>(b->mats[m]->tree.n) * b->k;
+    }
+    for (DevBuf<double>* t : {&b->tiles_x, &b->tiles_y}) {
+      e = hipMalloc(&t->p, std::max<int64_t>(1, total) * sizeof(double));
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc of the column tiles");
+      t->count = static_cast<size_t>(total);
+    }
+  }
+  auto tiles = [&](auto& bm, int32_t m) {
+    bm.n = b->mats[m]->tree.n;
+    bm.xt = b->tiled ? b->tiles_x.p + b->tile_base[m] : nullptr;
+    bm.yt = b->tiled ? b->tiles_y.p + b->tile_base[m] : nullptr;
+  };
   if (b->value_type == 0) {
     std::vector<race::BatchMat<double>> h(b->count);
-    for (int32_t m = 0; m < b->count; ++m)
+    for (int32_t m = 0; m < b->count; ++m) {
       h[m] = batch_mat<double>(b->mats[m], b->mats[m]->lane_diag64.p, b->mats[m]->sell_val64.p,
                                b->state.p + b->unit_base[m], X[m], Y[m]);
+      tiles(h[m], m);
+    }
     e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
   } else {
     std::vector<race::BatchMat<float>> h(b->count);
-    for (int32_t m = 0; m < b->count; ++m)
+    for (int32_t m = 0; m < b->count; ++m) {
       h[m] = batch_mat<float>(b->mats[m], b->mats[m]->lane_diag32.p, b->mats[m]->sell_val32.p,
                               b->state.p + b->unit_base[m], X[m], Y[m]);
+      tiles(h[m], m);
+    }
     e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");

@@ -64,6 +64,9 @@ struct BatchMat {
   int32_t n_units;
   int32_t n_zero_tasks;
   int32_t zero_chunk;
+  int32_t n;            // rows
+  double* xt;           // column tiles of x and y (runs with four or more passes), else NULL
+  double* yt;
 };
 
 // Tickets of a batch: (matrix, ticket of that matrix) pairs, merged so every
@@ -77,7 +80,8 @@ struct BatchArgs {
   int64_t state_words;   // length of `state` in 32-bit words (even)
   int32_t n_tickets;
   int32_t col0;          // first right-hand side of this pass
-  int32_t ld;            // row stride of every x and y (the batch's k)
+  int32_t ld;            // row stride of the pass's x and y: the batch's k, or the tile width when tiled
+  int32_t tiled;         // the pass reads and writes the contiguous column tiles xt / yt
 };
 
 // LDS bytes of a unit window of wmax entries with k right-hand sides: the
@@ -113,6 +117,12 @@ hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t
 // Kernel attributes of the batch kernel (call once before stream capture).
 template <typename ValT>
 hipError_t prepare_race_batch(int32_t k);
+
+// Every matrix's x (row-major n x k) into its column tiles (to_tiles), or
+// its y tiles back into y.
+template <typename ValT>
+hipError_t launch_batch_tile(const BatchMat<ValT>* mats, int32_t count, int32_t k, int32_t kt, int32_t to_tiles,
+                             hipStream_t st);
 
 // A batch run: the reset kernel, then one persistent launch over all tickets.
 template <typename ValT>

@@ -435,12 +435,15 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
     const BatchMat<ValT> mm = mats[m];
     if (lt < mm.n_zero_tasks) {
       const int64_t i0 = static_cast<int64_t>(lt) * mm.zero_chunk;
-      clear_task<K>(mm.zero_idx, i0, i0 + mm.zero_chunk < mm.n_zero ? i0 + mm.zero_chunk : mm.n_zero, mm.y + b.col0,
-                    b.ld, mm.done + mm.n_units + lt, 1u, tid, nthr, wave0);
+      double* yp = b.tiled ? mm.yt + static_cast<size_t>(mm.n) * b.col0 : mm.y + b.col0;
+      clear_task<K>(mm.zero_idx, i0, i0 + mm.zero_chunk < mm.n_zero ? i0 + mm.zero_chunk : mm.n_zero, yp, b.ld,
+                    mm.done + mm.n_units + lt, 1u, tid, nthr, wave0);
       continue;
     }
-    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u,
-                       mm.x + b.col0, mm.y + b.col0, b.ld, xw, yw, gw, tid, nthr, wave0);
+    const double* xp = b.tiled ? mm.xt + static_cast<size_t>(mm.n) * b.col0 : mm.x + b.col0;
+    double* yp = b.tiled ? mm.yt + static_cast<size_t>(mm.n) * b.col0 : mm.y + b.col0;
+    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u, xp, yp, b.ld,
+                       xw, yw, gw, tid, nthr, wave0);
   }
 }
 
@@ -505,6 +508,24 @@ __global__ void __launch_bounds__(256) tile_kernel(int32_t n, int32_t k, int32_t
     const int64_t at = static_cast<int64_t>(n) * kt * t + i * kc + (c - c0);
     if (to_tiles) tiles[at] = full[e];
     else full[e] = tiles[at];
+  }
+}
+
+// tile_kernel for every matrix of a batch: blockIdx.y selects the matrix.
+template <typename ValT>
+__global__ void __launch_bounds__(256) batch_tile_kernel(const BatchMat<ValT>* __restrict__ mats, int32_t k, int32_t kt,
+                                                         int32_t to_tiles) {
+  const BatchMat<ValT>& mm = mats[blockIdx.y];
+  const int64_t total = static_cast<int64_t>(mm.n) * k;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / k;
+    const int32_t c = static_cast<int32_t>(e % k);
+    const int32_t t = c / kt, c0 = t * kt;
+    const int32_t kc = k - c0 < kt ? k - c0 : kt;
+    const int64_t at = static_cast<int64_t>(mm.n) * kt * t + i * kc + (c - c0);
+    if (to_tiles) mm.xt[at] = mm.x[e];
+    else mm.y[e] = mm.yt[at];
   }
 }
 
@@ -674,6 +695,17 @@ hipError_t prepare_race_batch(int32_t k) {
 #undef CALL
 }
 
+template <typename ValT>
+hipError_t launch_batch_tile(const BatchMat<ValT>* mats, int32_t count, int32_t k, int32_t kt, int32_t to_tiles,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(dev::batch_tile_kernel<ValT>, dim3(256, static_cast<uint32_t>(count)), dim3(256), 0, st, mats, k,
+                     kt, to_tiles);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_tile<double>(const BatchMat<double>*, int32_t, int32_t, int32_t, int32_t,
+                                              hipStream_t);
+template hipError_t launch_batch_tile<float>(const BatchMat<float>*, int32_t, int32_t, int32_t, int32_t, hipStream_t);
 template hipError_t prepare_race_batch<double>(int32_t);
 template hipError_t prepare_race_batch<float>(int32_t);
 template hipError_t launch_race_batch<double>(const BatchMat<double>*, const BatchArgs&, int32_t, int32_t, int32_t,

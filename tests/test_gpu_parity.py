@@ -285,11 +285,12 @@ def test_race_full_size_banded_4m(value_type):
         assert rel < 2.0 ** -20
 
 
-def test_batch_tiled_replays():
-    """A batch whose windows cannot hold all k columns runs in passes; graph
-    replays stay correct."""
+@pytest.mark.parametrize("k", [5, 9])
+def test_batch_tiled_replays(k):
+    """A batch whose windows cannot hold all k columns runs in passes (k = 9:
+    five passes, through contiguous column tiles); graph replays stay
+    correct."""
     mats = _batch_mats()
-    k = 5
     scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500)) for m in mats]
     batch = R.Batch(scheds, k)
     xs = [torch.empty((m.n, k), dtype=torch.float64, device=DEV) for m in mats]
