@@ -203,6 +203,9 @@ def test_error_codes():
     p = R.make_params()
     p.shared_atomics = 2
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    for bad in (-1, 17):
+        p = R.make_params(rhs_tile=bad)
+        _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     # a row whose window alone exceeds the budget
     n = 40
     rp = np.array([0, n] + [n + i for i in range(1, n)], np.int32)
