@@ -385,3 +385,37 @@ def test_traced_product_stamps():
     y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
     _check(y.cpu().numpy(), y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), "traced")
     s.close()
+
+
+def test_product_fuzz():
+    """Seeded random matrices and parameters (window, workgroup size,
+    execution mode, shared atomics, value type, right-hand sides) against the
+    oracle, one case after another in this process."""
+    for seed in range(40):
+        rng = np.random.default_rng(500 + seed)
+        kind = int(rng.integers(4))
+        if kind == 0:
+            m = matgen.random_symmetric(int(rng.integers(50, 1500)), float(rng.uniform(0.001, 0.01)), seed=seed,
+                                        with_diag=bool(rng.integers(2)))
+        elif kind == 1:
+            m = matgen.stencil2d_5pt(int(rng.integers(8, 70)), seed=seed)
+        elif kind == 2:
+            m = matgen.stencil3d_27pt(int(rng.integers(4, 18)), seed=seed)
+        else:
+            n = int(rng.integers(500, 8000))
+            m = matgen.banded_irregular(n, seed=seed, band=int(rng.integers(2, max(3, n // 8))))
+        k = int(rng.choice([1, 1, 2, 3, 5]))
+        vt = str(rng.choice(["f64", "f64", "f32"]))
+        params = dict(n_workers=int(rng.choice([2, 8, 32, 128, 512])), window_max=int(rng.choice([96, 256, 1000, 3840])),
+                      block_threads=int(rng.choice([64, 128, 256, 512, 1024])),
+                      exec_mode=str(rng.choice(["flow", "flow", "phases"])), shared_atomics=bool(rng.integers(2)),
+                      max_stages=int(rng.integers(1, 5)), value_type=vt)
+        print(f"case fuzz seed={seed}: n={m.n} nnz={m.nnz} k={k} {params}", flush=True)
+        vals = m.val if vt == "f64" else m.val.astype(np.float32).astype(np.float64)
+        X = matgen.rhs(m.n, 900 + seed, k=k).reshape(m.n, k) if k > 1 else matgen.rhs(m.n, 900 + seed)
+        Y, st = run_race(m, X, k=k, **params)
+        Y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, vals, X)
+        absax = O.abs_product(m.n, m.row_ptr, m.col, vals, np.abs(X))
+        for j in range(k):
+            sl = (slice(None), j) if k > 1 else slice(None)
+            _check(Y[sl], Y_ref[sl], absax[sl], _full_row_len(m), f"fuzz seed={seed} col={j}")

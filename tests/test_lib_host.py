@@ -215,3 +215,40 @@ def test_error_codes():
     h = R.race_build_schedule(2, ok_rp, ok_col, None)
     _expect(-5, lambda: R.race_schedule_upload(h))
     R.race_schedule_destroy(h)
+
+
+def _fuzz_case(seed):
+    """A seeded random matrix and schedule parameters: structure, size,
+    density, N_t, eps, depth, load metric and the global pass all drawn."""
+    rng = np.random.default_rng(seed)
+    kind = int(rng.integers(5))
+    if kind == 0:
+        m = matgen.random_symmetric(int(rng.integers(50, 1500)), float(rng.uniform(0.001, 0.01)), seed=seed,
+                                    with_diag=bool(rng.integers(2)))
+    elif kind == 1:
+        m = matgen.stencil2d_5pt(int(rng.integers(8, 70)), seed=seed)
+    elif kind == 2:
+        m = matgen.stencil3d_27pt(int(rng.integers(4, 18)), seed=seed)
+    elif kind == 3:
+        n = int(rng.integers(500, 8000))
+        m = matgen.banded_irregular(n, seed=seed, band=int(rng.integers(2, max(3, n // 8))))
+    else:
+        m = matgen.stencil2d_7pt(int(rng.integers(8, 50)))
+    eps0 = float(rng.choice([0.5, 0.6, 0.7, 0.8, 0.9]))
+    kw = dict(eps=(eps0, float(rng.choice([0.5, 0.8])), 0.5), balance=str(rng.choice(["nnz", "rows"])),
+              max_stages=int(rng.integers(1, 6)), global_lb=bool(rng.integers(2)))
+    return m, int(rng.choice([2, 5, 8, 16, 32, 64, 128, 256])), kw
+
+
+@pytest.mark.parametrize("seed", range(150))
+def test_schedule_fuzz_bit_exact_and_valid(seed):
+    """Random matrices and parameters: the native builder equals the oracle
+    bit for bit, and the schedule passes the brute-force conflict checker."""
+    m, nt, kw = _fuzz_case(seed)
+    s, ref = _compare(m, nt, **kw)
+    try:
+        tr = s.tree()
+        node, phase = s.leaves()
+        C.check_schedule(m.n, m.row_ptr, m.col, s.perm(), tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase)
+    finally:
+        s.close()
