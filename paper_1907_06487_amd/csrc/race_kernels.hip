@@ -12,17 +12,23 @@ namespace dev {
 
 constexpr int kSlice = 64;
 constexpr uint16_t kNoRow = 0xFFFF;
-constexpr int kBatch = 16;               // slots per lane loaded before any arithmetic
+// slots per lane loaded before any arithmetic: FP32 values take one register
+// each, so a batch of 24 costs what 16 FP64 values do
+template <typename ValT>
+struct BatchSize {
+  static constexpr int value = sizeof(ValT) == 4 ? 24 : 16;
+};
 constexpr uint32_t kSpinLimit = 1u << 16;  // bounded wait (milliseconds), then report and go on
 
 // One slice descriptor as held in registers by a wavefront.
 template <typename ValT>
 struct SliceRegs {
+  static constexpr int kBatch = BatchSize<ValT>::value;
   int32_t len = 0, width = 0;
   uint32_t off = 0;
   uint16_t rs = kNoRow;
   double d = 0.0;
-  double v[kBatch];
+  ValT v[kBatch];
   int32_t sl[kBatch];
 };
 
@@ -42,28 +48,29 @@ __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane
   const ValT* vp = a.sell_val + r.off + lane;
   const uint16_t* sp = a.sell_slot + r.off + lane;
 #pragma unroll
-  for (int b = 0; b < kBatch; ++b) {
+  for (int b = 0; b < SliceRegs<ValT>::kBatch; ++b) {
     const int32_t j = j0 + b;
     if (active && j < r.len) {
-      r.v[b] = static_cast<double>(vp[j * r.width]);
+      r.v[b] = vp[j * r.width];
       r.sl[b] = sp[j * r.width];
     } else {
-      r.v[b] = 0.0;
+      r.v[b] = ValT(0);
       r.sl[b] = 0;
     }
   }
 }
 
-template <int K>
-__device__ __forceinline__ void apply_batch(const double* v, const int32_t* sl, const double* xw, double* yw,
+template <int K, int B, typename ValT>
+__device__ __forceinline__ void apply_batch(const ValT* v, const int32_t* sl, const double* xw, double* yw,
                                             const double (&xr)[K], double (&acc)[K]) {
 #pragma unroll
-  for (int b = 0; b < kBatch; ++b) {
-    if (v[b] != 0.0) {
+  for (int b = 0; b < B; ++b) {
+    if (v[b] != ValT(0)) {
+      const double vb = static_cast<double>(v[b]);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        acc[k] += v[b] * xw[sl[b] * K + k];
-        atomicAdd(&yw[sl[b] * K + k], v[b] * xr[k]);
+        acc[k] += vb * xw[sl[b] * K + k];
+        atomicAdd(&yw[sl[b] * K + k], vb * xr[k]);
       }
     }
   }
@@ -158,10 +165,11 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u,
         xr[k] = xw[cur.rs * K + k];
         acc[k] = cur.d * xr[k];
       }
-      apply_batch<K>(cur.v, cur.sl, xw, yw, xr, acc);
-      for (int32_t j0 = kBatch; j0 < cur.len; j0 += kBatch) {
+      constexpr int B = SliceRegs<ValT>::kBatch;
+      apply_batch<K, B>(cur.v, cur.sl, xw, yw, xr, acc);
+      for (int32_t j0 = B; j0 < cur.len; j0 += B) {
         load_batch(a, lane, j0, cur);
-        apply_batch<K>(cur.v, cur.sl, xw, yw, xr, acc);
+        apply_batch<K, B>(cur.v, cur.sl, xw, yw, xr, acc);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) atomicAdd(&yw[cur.rs * K + k], acc[k]);
