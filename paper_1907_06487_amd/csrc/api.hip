@@ -84,7 +84,8 @@ struct race_schedule {
   bool has_values = false;
   bool uploaded = false;
   int device = -1;
-  DevBuf<int32_t> leaf_units, unit_lo, unit_hi, unit_halo_ptr, unit_chunk_ptr, chunk_len, new2old, dep_ptr, dep_idx;
+  DevBuf<int32_t> leaf_units, chunk_len, new2old, dep_idx;
+  DevBuf<race::UnitDesc> unit_desc;
   DevBuf<uint32_t> flow_state;  // done[n_units + n_zero_tasks], status, padding, counter (64-bit, 8-byte aligned)
   uint32_t epoch = 0;
   uint64_t ticket_next = 0;
@@ -97,11 +98,11 @@ struct race_schedule {
   DevBuf<double> tiles_x, tiles_y;  // column tiles of X and Y for products with many passes (grown on demand)
 
   void free_device() {
-    release(leaf_units); release(unit_lo); release(unit_hi); release(unit_halo_ptr); release(unit_chunk_ptr);
+    release(leaf_units); release(unit_desc);
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
-    release(sell_val32); release(dep_ptr); release(dep_idx); release(flow_state); release(tiles_x); release(tiles_y);
+    release(sell_val32); release(dep_idx); release(flow_state); release(tiles_x); release(tiles_y);
     uploaded = false;
   }
 };
@@ -294,10 +295,13 @@ int race_schedule_upload(race_schedule_t s) {
     return hip_fail(e, "upload of " #buf);                         \
   }
   UP(leaf_units, L.leaf_units)
-  UP(unit_lo, L.unit_lo)
-  UP(unit_hi, L.unit_hi)
-  UP(unit_halo_ptr, L.unit_halo_ptr)
-  UP(unit_chunk_ptr, L.unit_chunk_ptr)
+  {
+    std::vector<race::UnitDesc> desc(L.unit_lo.size());
+    for (size_t u = 0; u < desc.size(); ++u)
+      desc[u] = race::UnitDesc{L.unit_lo[u],         L.unit_hi[u],         L.unit_halo_ptr[u], L.unit_halo_ptr[u + 1],
+                               L.unit_chunk_ptr[u], L.unit_chunk_ptr[u + 1], L.dep_ptr[u],       L.dep_ptr[u + 1]};
+    UP(unit_desc, desc)
+  }
   UP(chunk_len, L.chunk_len)
   UP(new2old, s->tree.perm)
   UP(halo, L.halo)
@@ -306,7 +310,6 @@ int race_schedule_upload(race_schedule_t s) {
   UP(chunk_off, L.chunk_off)
   UP(lane_slot, L.lane_slot)
   UP(sell_slot, L.sell_slot)
-  UP(dep_ptr, L.dep_ptr)
   UP(dep_idx, L.dep_idx)
   {
     // done[] per unit and clearing task, then status, then an aligned 64-bit counter
@@ -510,10 +513,8 @@ int race_mlp_adam(float* theta, const float* grad, float* m, float* v, int32_t s
 
 template <typename ValT>
 static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const ValT* vals) {
-  return race::UnitArgs<ValT>{s->leaf_units.p, s->unit_lo.p,    s->unit_hi.p,        s->unit_halo_ptr.p,
-                              s->halo.p,          s->row_flags.p,    s->unit_chunk_ptr.p, s->chunk_off.p,
-                              s->chunk_len.p,     s->lane_slot.p,  diag,                vals,
-                              s->sell_slot.p};
+  return race::UnitArgs<ValT>{s->leaf_units.p, s->unit_desc.p, s->halo.p, s->row_flags.p, s->chunk_off.p,
+                              s->chunk_len.p,  s->lane_slot.p, diag,      vals,          s->sell_slot.p};
 }
 
 template <typename ValT>
@@ -533,7 +534,7 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   const int32_t grid = std::max(1, std::min(n_tickets, per_cu * s->n_cus));
   uint32_t* base = s->flow_state.p;
   const size_t counter_word = s->flow_state.count - 2;
-  race::FlowArgs f{s->dep_ptr.p, s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word),
+  race::FlowArgs f{s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word),
                    base + n_flags, trace, n_tickets, n_units, L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p,
                    static_cast<int64_t>(L.zero_idx.size())};
   s->epoch += 1;
@@ -691,7 +692,6 @@ template <typename ValT>
 static race::BatchMat<ValT> batch_mat(race_schedule_t s, const ValT* diag, const ValT* vals, uint32_t* done,
                                       const double* x, double* y) {
   return race::BatchMat<ValT>{unit_args<ValT>(s, diag, vals),
-                              s->dep_ptr.p,
                               s->dep_idx.p,
                               done,
                               x,

@@ -7,16 +7,20 @@
 
 namespace race {
 
+// One unit's index ranges, read by a workgroup with a single scalar load:
+// own rows [lo, hi), halo list [h0, h1), slices [c0, c1) and conflict edges
+// [d0, d1) (indices into the dataflow edge list).
+struct alignas(32) UnitDesc {
+  int32_t lo, hi, h0, h1, c0, c1, d0, d1;
+};
+
 // Device pointers of one schedule's layout (see layout.hpp for the meaning).
 template <typename ValT>
 struct UnitArgs {
   const int32_t* leaf_units;  // 2 per leaf: first unit, one past the last
-  const int32_t* unit_lo;
-  const int32_t* unit_hi;
-  const int32_t* unit_halo_ptr;
+  const UnitDesc* unit_desc;  // per unit
   const uint32_t* halo;
   const uint32_t* row_flags;  // 2 bits per row: first writer, shared
-  const int32_t* unit_chunk_ptr;
   const uint32_t* chunk_off;
   const int32_t* chunk_len;
   const uint16_t* lane_slot;
@@ -35,7 +39,6 @@ struct UnitArgs {
 // ticket n_zero_tasks + u is unit u.  A task's completion flag is
 // done[n_units + task].
 struct FlowArgs {
-  const int32_t* dep_ptr;
   const int32_t* dep_idx;
   uint32_t* done;       // n_units + n_zero_tasks completion flags
   uint64_t* counter;
@@ -54,7 +57,6 @@ struct FlowArgs {
 template <typename ValT>
 struct BatchMat {
   UnitArgs<ValT> a;
-  const int32_t* dep_ptr;
   const int32_t* dep_idx;
   uint32_t* done;       // n_units + n_zero_tasks flags (a slice of the batch state)
   const double* x;

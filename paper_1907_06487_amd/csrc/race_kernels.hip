@@ -20,6 +20,22 @@ struct BatchSize {
 };
 constexpr uint32_t kSpinLimit = 1u << 16;  // bounded wait (milliseconds), then report and go on
 
+// Load of a layout word that no kernel writes, at an index that is the same
+// in every lane: through the constant address space the compiler issues a
+// scalar load, which needs no vector-memory wait and no readfirstlane.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p, int64_t i) {
+  using ConstT = const __attribute__((address_space(4))) T;
+  return ((ConstT*)p)[i];
+}
+
+__device__ __forceinline__ UnitDesc uniform_load(const UnitDesc* p, int64_t i) {
+  using I8 = int32_t __attribute__((ext_vector_type(8)));
+  using ConstI8 = const __attribute__((address_space(4))) I8;
+  const I8 w = ((ConstI8*)p)[i];
+  return UnitDesc{w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]};
+}
+
 // One slice descriptor as held in registers by a wavefront.
 template <typename ValT>
 struct SliceRegs {
@@ -34,43 +50,75 @@ struct SliceRegs {
 
 template <typename ValT>
 __device__ __forceinline__ void load_slice_head(const UnitArgs<ValT>& a, int32_t c, int32_t lane, SliceRegs<ValT>& r) {
-  const int32_t meta = a.chunk_len[c];
+  // c is the same in every lane: the descriptor lives in scalar registers
+  const int32_t meta = uniform_load(a.chunk_len, c);
   r.len = meta & 0xFFFF;
   r.width = meta >> 16;
-  r.off = a.chunk_off[c];
+  r.off = uniform_load(a.chunk_off, c);
   r.rs = a.lane_slot[static_cast<size_t>(c) * kSlice + lane];
   r.d = static_cast<double>(a.lane_diag[static_cast<size_t>(c) * kSlice + lane]);
 }
 
+// Loads entries j0 .. j0 + kBatch - 1 of every lane's row.  The bound on j
+// is the same for the whole wavefront, and lanes past the slice's rows read
+// the last row's entries (in bounds, never applied), so the loads of a batch
+// are issued back to back with no per-lane branches between them.
 template <typename ValT>
 __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane, int32_t j0, SliceRegs<ValT>& r) {
-  const bool active = r.rs != kNoRow;
-  const ValT* vp = a.sell_val + r.off + lane;
-  const uint16_t* sp = a.sell_slot + r.off + lane;
+  const int32_t l = lane < r.width ? lane : r.width - 1;
+  const ValT* vp = a.sell_val + r.off + l;
+  const uint16_t* sp = a.sell_slot + r.off + l;
 #pragma unroll
   for (int b = 0; b < SliceRegs<ValT>::kBatch; ++b) {
     const int32_t j = j0 + b;
-    if (active && j < r.len) {
+    if (j < r.len) {
       r.v[b] = vp[j * r.width];
       r.sl[b] = sp[j * r.width];
     } else {
       r.v[b] = ValT(0);
-      r.sl[b] = 0;
+      r.sl[b] = r.rs;
     }
   }
 }
 
+// Applies a loaded batch.  With one or two right-hand sides the gathers of
+// a group of kGather entries are all issued before the first is used; with
+// more, acc and x_r already fill the registers and entries go one at a time.
+// A zero value (row padding) adds +0 to its own row's slot and nothing to
+// acc.
 template <int K, int B, typename ValT>
 __device__ __forceinline__ void apply_batch(const ValT* v, const int32_t* sl, const double* xw, double* yw,
                                             const double (&xr)[K], double (&acc)[K]) {
+  if constexpr (K > 2) {
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    if (v[b] != ValT(0)) {
-      const double vb = static_cast<double>(v[b]);
+    for (int b = 0; b < B; ++b) {
+      if (v[b] != ValT(0)) {
+        const double vb = static_cast<double>(v[b]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          acc[k] += vb * xw[sl[b] * K + k];
+          atomicAdd(&yw[sl[b] * K + k], vb * xr[k]);
+        }
+      }
+    }
+    return;
+  }
+  constexpr int kGather = K == 1 ? 8 : 4;
+#pragma unroll
+  for (int g = 0; g < B; g += kGather) {
+    double xg[kGather][K];
+#pragma unroll
+    for (int b = 0; b < kGather; ++b)
+#pragma unroll
+      for (int k = 0; k < K; ++k) xg[b][k] = g + b < B ? xw[sl[g + b] * K + k] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kGather && g + b < B; ++b) {
+      const bool nz = v[g + b] != ValT(0);
+      const double vb = static_cast<double>(v[g + b]);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        acc[k] += vb * xw[sl[b] * K + k];
-        atomicAdd(&yw[sl[b] * K + k], vb * xr[k]);
+        acc[k] += vb * (nz ? xg[b][k] : 0.0);
+        atomicAdd(&yw[sl[g + b] * K + k], nz ? vb * xr[k] : 0.0);
       }
     }
   }
@@ -91,58 +139,85 @@ __device__ __forceinline__ void apply_batch(const ValT* v, const int32_t* sl, co
 //      needs no global atomics; only indices shared with other units of the
 //      unit's own leaf (when the layout marks them) take a global atomic add.
 template <typename ValT, int K>
-__device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u, const double* __restrict__ x,
-                                             int32_t ld, double* xw, double* yw, uint32_t* gw, int32_t tid,
-                                             int32_t nthr) {
-  constexpr int kStage = K >= 4 ? 1 : 4;  // window entries per thread per staging round
-  const int32_t lane = tid & (kSlice - 1), wave = tid / kSlice, nwaves = nthr / kSlice;
-  const int32_t lo = a.unit_lo[u];
-  const int32_t R = a.unit_hi[u] - lo;
-  const int32_t h0 = a.unit_halo_ptr[u];
-  const int32_t W = R + (a.unit_halo_ptr[u + 1] - h0);
-  const int32_t c1 = a.unit_chunk_ptr[u + 1];
-  int32_t c = a.unit_chunk_ptr[u] + wave;
+__device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const UnitDesc& ud,
+                                             const double* __restrict__ x, int32_t ld, double* xw, double* yw,
+                                             uint32_t* gw, int32_t tid, int32_t nthr) {
+  // window entries per thread per staging round, own rows and halo each
+  constexpr int kStage = K == 1 ? 4 : (K <= 3 ? 2 : 1);
+  const int32_t lane = tid & (kSlice - 1), nwaves = nthr / kSlice;
+  const int32_t wave = __builtin_amdgcn_readfirstlane(tid / kSlice);
+  const int32_t lo = ud.lo;
+  const int32_t R = ud.hi - lo;
+  const int32_t h0 = ud.h0;
+  const int32_t H = ud.h1 - h0;
+  const int32_t c1 = ud.c1;
+  int32_t c = ud.c0 + wave;
   SliceRegs<ValT> cur;
-  if (c < c1) {
-    load_slice_head(a, c, lane, cur);
-    load_batch(a, lane, 0, cur);
-  }
-  // 1. stage the windows while the first slice is in flight
-  for (int32_t base = 0; base < W; base += kStage * nthr) {
+  // 1. stage the windows.  Own rows [0, R) need no index (x is contiguous
+  // there); halo slots R + [0, H) gather x through the halo list.  All loads
+  // of a round are issued before the first wait, the wavefront's first slice
+  // descriptor rides along with the first round and its first batch is
+  // requested before the barrier; lanes past an end read a clamped, valid
+  // address and drop the value.  A unit has at least one own row.
+  const uint32_t* hal = a.halo + h0;
+  const int32_t rounds_end = R > H ? R : H;
+  for (int32_t base = 0; base < rounds_end; base += kStage * nthr) {
+    uint32_t hw[kStage], fw[kStage];
+    double xo[kStage][K], xh[kStage][K];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int32_t s = base + q * nthr + tid;
+      hw[q] = H > 0 ? hal[s < H ? s : H - 1] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int32_t s = base + q * nthr + tid;
+      const uint32_t r = static_cast<uint32_t>(lo + (s < R ? s : R - 1));
+      fw[q] = a.row_flags[r >> 4];
+#pragma unroll
+      for (int k = 0; k < K; ++k) xo[q][k] = x[static_cast<size_t>(r) * ld + k];
+    }
+    if (base == 0 && c < c1) load_slice_head(a, c, lane, cur);
     // window index with the first-writer flag in bit 31 and the shared flag
     // in bit 30, kept in LDS for the flush
-    uint32_t h[kStage];
+    auto put_own = [&]() {
 #pragma unroll
-    for (int q = 0; q < kStage; ++q) {
-      const int32_t s = base + q * nthr + tid;
-      if (s < R) {
-        const uint32_t r = static_cast<uint32_t>(lo + s);
-        const uint32_t f = (a.row_flags[r >> 4] >> (2 * (r & 15))) & 3u;
-        h[q] = r | ((f & 1u) << 31) | ((f & 2u) << 29);
-      } else {
-        h[q] = s < W ? a.halo[h0 + s - R] : 0u;
+      for (int q = 0; q < kStage; ++q) {
+        const int32_t s = base + q * nthr + tid;
+        if (s < R) {
+          const uint32_t r = static_cast<uint32_t>(lo + s);
+          const uint32_t f = (fw[q] >> (2 * (r & 15))) & 3u;
+          gw[s] = r | ((f & 1u) << 31) | ((f & 2u) << 29);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            xw[s * K + k] = xo[q][k];
+            yw[s * K + k] = 0.0;
+          }
+        }
       }
-    }
-    double xv[kStage][K];
+    };
+    // with several right-hand sides the own rows go to LDS before the halo
+    // values are requested, so both never occupy registers at once
+    if constexpr (K > 2) put_own();
 #pragma unroll
-    for (int q = 0; q < kStage; ++q) {
-      const bool in = base + q * nthr + tid < W;
+    for (int q = 0; q < kStage; ++q)
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv[q][k] = in ? x[static_cast<size_t>(h[q] & 0x3fffffffu) * ld + k] : 0.0;
-    }
+      for (int k = 0; k < K; ++k) xh[q][k] = H > 0 ? x[static_cast<size_t>(hw[q] & 0x3fffffffu) * ld + k] : 0.0;
+    if constexpr (K <= 2) put_own();
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
-      if (s < W) {
-        gw[s] = h[q];
+      if (s < H) {
+        gw[R + s] = hw[q];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          xw[s * K + k] = xv[q][k];
-          yw[s * K + k] = 0.0;
+          xw[(R + s) * K + k] = xh[q][k];
+          yw[(R + s) * K + k] = 0.0;
         }
       }
     }
   }
+  if (c < c1) load_batch(a, lane, 0, cur);
   __syncthreads();
   // 2. slices: the next slice's descriptor is in flight during this slice's
   // arithmetic, its elements are requested right after
@@ -153,8 +228,8 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, int32_t u,
     uint16_t rs_n = kNoRow;
     ValT d_n = ValT(0);
     if (cn < c1) {
-      meta_n = a.chunk_len[cn];
-      off_n = a.chunk_off[cn];
+      meta_n = uniform_load(a.chunk_len, cn);
+      off_n = uniform_load(a.chunk_off, cn);
       rs_n = a.lane_slot[static_cast<size_t>(cn) * kSlice + lane];
       d_n = a.lane_diag[static_cast<size_t>(cn) * kSlice + lane];
     }
@@ -211,17 +286,22 @@ __device__ __forceinline__ void y_store(double* p, double v) {
 // units of this unit's own leaf, which run concurrently) are combined with
 // a global atomic add instead; they were cleared before the product when no
 // earlier unit wrote them.
-template <typename ValT, int K, bool kCoherent>
-__device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, double* __restrict__ y, int32_t ld,
-                                           const double* yw, const uint32_t* gw, int32_t tid, int32_t nthr) {
-  constexpr int kStage = K >= 4 ? 2 : 8;
-  const int32_t W = (a.unit_hi[u] - a.unit_lo[u]) + (a.unit_halo_ptr[u + 1] - a.unit_halo_ptr[u]);
+template <int K, bool kCoherent>
+__device__ __forceinline__ void flush_unit(const UnitDesc& ud, double* __restrict__ y, int32_t ld, const double* yw,
+                                           const uint32_t* gw, int32_t tid, int32_t nthr) {
+  constexpr int kStage = K >= 8 ? 1 : (K >= 4 ? 2 : 8);
+  const int32_t W = (ud.hi - ud.lo) + (ud.h1 - ud.h0);
   for (int32_t base = 0; base < W; base += kStage * nthr) {
+    // the window's indices and values come out of LDS before the first y
+    // load is issued
     uint32_t h[kStage];
+    double w[kStage][K];
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
       const int32_t s = base + q * nthr + tid;
       h[q] = s < W ? gw[s] : 0x80000000u;
+#pragma unroll
+      for (int k = 0; k < K; ++k) w[q][k] = s < W ? yw[s * K + k] : 0.0;
     }
     double old[kStage][K];
 #pragma unroll
@@ -236,10 +316,10 @@ __device__ __forceinline__ void flush_unit(const UnitArgs<ValT>& a, int32_t u, d
         double* p = y + static_cast<size_t>(h[q] & 0x3fffffffu) * ld;
         if (h[q] & 0x40000000u) {
 #pragma unroll
-          for (int k = 0; k < K; ++k) unsafeAtomicAdd(p + k, yw[s * K + k]);
+          for (int k = 0; k < K; ++k) unsafeAtomicAdd(p + k, w[q][k]);
         } else {
 #pragma unroll
-          for (int k = 0; k < K; ++k) y_store<kCoherent>(p + k, old[q][k] + yw[s * K + k]);
+          for (int k = 0; k < K; ++k) y_store<kCoherent>(p + k, old[q][k] + w[q][k]);
         }
       }
     }
@@ -266,9 +346,10 @@ __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
   for (int32_t u = u0; u < u1; ++u) {
     const uint64_t t0 = trace ? wall_clock() : 0;
-    compute_unit<ValT, K>(a, u, x, ld, xw, yw, gw, tid, nthr);
+    const UnitDesc ud = uniform_load(a.unit_desc, u);
+    compute_unit<ValT, K>(a, ud, x, ld, xw, yw, gw, tid, nthr);
     const uint64_t t1 = trace ? wall_clock() : 0;
-    flush_unit<ValT, K, false>(a, u, y, ld, yw, gw, tid, nthr);
+    flush_unit<K, false>(ud, y, ld, yw, gw, tid, nthr);
     __syncthreads();
     if (trace && tid == 0) {
       const uint64_t t2 = wall_clock();
@@ -283,7 +364,7 @@ __global__ void __launch_bounds__(1024) race_leaf_kernel(UnitArgs<ValT> a, int32
 // One unit in dataflow order: compute, wait for the earlier units its touch
 // set meets, flush with coherent y accesses, publish completion.
 template <typename ValT, int K>
-__device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, const int32_t* dep_ptr,
+__device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u,
                                           const int32_t* dep_idx, uint32_t* done, uint32_t* status, uint64_t* trace,
                                           uint32_t epoch, const double* __restrict__ x, double* __restrict__ y,
                                           int32_t ld, double* xw, double* yw, uint32_t* gw, int32_t tid,
@@ -291,9 +372,10 @@ __device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, co
   const uint64_t t0 = trace ? wall_clock() : 0;
   // the unit's arithmetic needs nothing from other units; only its flush
   // must follow the earlier units it conflicts with
-  compute_unit<ValT, K>(a, u, x, ld, xw, yw, gw, tid, nthr);
+  const UnitDesc ud = uniform_load(a.unit_desc, u);
+  compute_unit<ValT, K>(a, ud, x, ld, xw, yw, gw, tid, nthr);
   const uint64_t t1 = trace ? wall_clock() : 0;
-  const int32_t d0 = dep_ptr[u], d1 = dep_ptr[u + 1];
+  const int32_t d0 = ud.d0, d1 = ud.d1;
   for (int32_t i = d0 + tid; i < d1; i += nthr) {
     const int32_t v = dep_idx[i];
     uint32_t spins = 0;
@@ -307,7 +389,7 @@ __device__ __forceinline__ void flow_unit(const UnitArgs<ValT>& a, int32_t u, co
   }
   __syncthreads();
   const uint64_t t2 = trace ? wall_clock() : 0;
-  flush_unit<ValT, K, true>(a, u, y, ld, yw, gw, tid, nthr);
+  flush_unit<K, true>(ud, y, ld, yw, gw, tid, nthr);
   // every thread's coherent y stores complete before the barrier, so the
   // completion flag written after it is only seen once they are visible
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -393,7 +475,7 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
                     f.done + f.n_units + t, epoch, tid, nthr, wave0);
       continue;
     }
-    flow_unit<ValT, K>(a, t - f.n_zero_tasks, f.dep_ptr, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, ld, xw,
+    flow_unit<ValT, K>(a, t - f.n_zero_tasks, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, ld, xw,
                        yw, gw, tid, nthr, wave0);
   }
 }
@@ -438,8 +520,8 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
     __syncthreads();
     const int32_t t = __builtin_amdgcn_readfirstlane(s_ticket[0]);
     if (t < 0) break;
-    const int32_t m = __builtin_amdgcn_readfirstlane(b.ticket_mat[t]);
-    const int32_t lt = __builtin_amdgcn_readfirstlane(b.ticket_unit[t]);
+    const int32_t m = uniform_load(b.ticket_mat, t);
+    const int32_t lt = uniform_load(b.ticket_unit, t);
     const BatchMat<ValT> mm = mats[m];
     if (lt < mm.n_zero_tasks) {
       const int64_t i0 = static_cast<int64_t>(lt) * mm.zero_chunk;
@@ -450,7 +532,7 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
     }
     const double* xp = b.tiled ? mm.xt + static_cast<size_t>(mm.n) * b.col0 : mm.x + b.col0;
     double* yp = b.tiled ? mm.yt + static_cast<size_t>(mm.n) * b.col0 : mm.y + b.col0;
-    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_ptr, mm.dep_idx, mm.done, status, nullptr, 1u, xp, yp, b.ld,
+    flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_idx, mm.done, status, nullptr, 1u, xp, yp, b.ld,
                        xw, yw, gw, tid, nthr, wave0);
   }
 }
