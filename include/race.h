@@ -193,6 +193,19 @@ int race_symm_spmm_traced(race_schedule_t s, int32_t k, const double* X, double*
  * product's result is then not reliable); clears the status. */
 int race_schedule_check(race_schedule_t s);
 
+/* Synchronise the device and return in *count how many static tickets of
+ * this schedule's dataflow products ran on a workgroup other than their own
+ * (cumulative).  A dataflow launch starts workgroup b on ticket b; when that
+ * workgroup is not running yet (the device is shared), a running workgroup
+ * that needs the ticket claims and runs it.  Informational: zero on an
+ * otherwise idle device. */
+int race_schedule_flow_takeovers(race_schedule_t s, int64_t* count);
+
+/* Tests only: with stride > 0 every stride-th workgroup of later dataflow
+ * launches joins about 0.2 ms late without claiming its own ticket, so
+ * running workgroups take its ticket over; 0 turns this off. */
+int race_schedule_flow_test_late(race_schedule_t s, int32_t stride);
+
 /* Reorder device float64 row-major n x k arrays between input order and the
  * permuted order: to_permuted != 0: out[i] = in[new2old[i]]; else
  * out[new2old[i]] = in[i]. */

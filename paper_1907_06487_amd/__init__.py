@@ -13,6 +13,7 @@ from . import _lib
 from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_check, race_batch_create,
                    race_batch_destroy, race_batch_info, race_batch_run, race_build_schedule, race_csr_create, race_csr_destroy,
                    race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
+                   race_schedule_flow_takeovers, race_schedule_flow_test_late,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
                    race_symm_spmv_atomic)
@@ -65,6 +66,14 @@ class Schedule:
 
     def check(self):
         race_schedule_check(self.handle)
+
+    def takeovers(self):
+        """Static dataflow tickets run by a workgroup other than their own (cumulative)."""
+        return race_schedule_flow_takeovers(self.handle)
+
+    def test_late(self, stride):
+        """Tests only: every stride-th workgroup of later dataflow launches joins late."""
+        race_schedule_flow_test_late(self.handle, stride)
 
     def stats(self):
         return race_schedule_stats(self.handle)

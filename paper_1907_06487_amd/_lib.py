@@ -24,7 +24,7 @@ ERRORS = {-1: "RACE_EINVAL", -2: "RACE_ENOMEM", -3: "RACE_EHIP", -4: "RACE_EUNSU
 EXPORTS = [
     "race_params_default", "race_build_schedule", "race_schedule_upload", "race_schedule_destroy",
     "race_schedule_stats", "race_schedule_perm", "race_schedule_tree", "race_schedule_leaves",
-    "race_schedule_units", "race_schedule_zero_list", "race_schedule_check", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
+    "race_schedule_units", "race_schedule_zero_list", "race_schedule_check", "race_schedule_flow_takeovers", "race_schedule_flow_test_late", "race_symm_spmv", "race_symm_spmm", "race_symm_spmm_traced", "race_permute", "race_csr_create",
     "race_csr_spmv", "race_atomic_create", "race_symm_spmv_atomic", "race_csr_destroy", "race_last_error",
     "race_batch_create", "race_batch_bind", "race_batch_run", "race_batch_check", "race_batch_info",
     "race_batch_destroy", "race_schedule_features", "race_schedule_simulate", "race_schedule_flow_grid",
@@ -99,6 +99,8 @@ def lib():
         "race_schedule_units": ([_P, _I32P, _I64P, _I32P, _I32P, _I32P, _I64P, _I32P, _U8P, _U8P], ctypes.c_int),
         "race_schedule_zero_list": ([_P, _I64P, _I32P], ctypes.c_int),
         "race_schedule_check": ([_P], ctypes.c_int),
+        "race_schedule_flow_takeovers": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "race_schedule_flow_test_late": ([_P, ctypes.c_int32], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
@@ -257,6 +259,16 @@ def race_schedule_zero_list(h):
 
 def race_schedule_check(h):
     check(lib().race_schedule_check(h))
+
+
+def race_schedule_flow_takeovers(h):
+    v = ctypes.c_int64(0)
+    check(lib().race_schedule_flow_takeovers(h, ctypes.byref(v)))
+    return int(v.value)
+
+
+def race_schedule_flow_test_late(h, stride):
+    check(lib().race_schedule_flow_test_late(h, int(stride)))
 
 
 def race_symm_spmv(h, x, y, stream=None):

@@ -76,6 +76,10 @@ void release(DevBuf<T>& b) {
 
 }  // namespace
 
+// Claim words per CU for the dataflow launch's static tickets: at least the
+// workgroups one CU can hold (32 wavefronts).
+constexpr int32_t kClaimsPerCu = 32;
+
 struct race_schedule {
   race_params params{};
   race::Tree tree;
@@ -87,6 +91,8 @@ struct race_schedule {
   DevBuf<int32_t> leaf_units, chunk_len, new2old, dep_idx;
   DevBuf<race::UnitDesc> unit_desc;
   DevBuf<uint32_t> flow_state;  // done[n_units + n_zero_tasks], status, padding, counter (64-bit, 8-byte aligned)
+  DevBuf<uint32_t> claims;      // claim words of static tickets (32 per CU), then the takeover count
+  int32_t late_stride = 0;      // tests only (race_schedule_flow_test_late)
   uint32_t epoch = 0;
   uint64_t ticket_next = 0;
   int32_t n_cus = 0;
@@ -102,7 +108,7 @@ struct race_schedule {
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
-    release(sell_val32); release(dep_idx); release(flow_state); release(tiles_x); release(tiles_y);
+    release(sell_val32); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
     uploaded = false;
   }
 };
@@ -325,6 +331,10 @@ int race_schedule_upload(race_schedule_t s) {
     return hip_fail(e, "hipDeviceGetAttribute");
   }
   s->stats.wall_clock_hz = static_cast<int64_t>(clock_khz) * 1000;
+  {
+    std::vector<uint32_t> zeros(static_cast<size_t>(kClaimsPerCu) * s->n_cus + 1, 0u);
+    UP(claims, zeros)
+  }
   if (s->params.value_type == 0) {
     UP(lane_diag64, L.lane_diag)
     UP(sell_val64, L.sell_val)
@@ -534,17 +544,24 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   const int32_t grid = std::max(1, std::min(n_tickets, per_cu * s->n_cus));
   uint32_t* base = s->flow_state.p;
   const size_t counter_word = s->flow_state.count - 2;
-  race::FlowArgs f{s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word),
-                   base + n_flags, trace, n_tickets, n_units, L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p,
-                   static_cast<int64_t>(L.zero_idx.size())};
+  // static tickets: workgroup b starts on ticket b; the counter serves the rest
+  const int32_t n_static = std::min(grid, n_tickets);
+  const size_t claim_cap = s->claims.count - 1;
+  if (static_cast<size_t>(n_static) > claim_cap) return fail(RACE_EINTERNAL, "more workgroups than claim words");
+  race::FlowArgs f{s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word), base + n_flags,
+                   s->claims.p, s->claims.p + claim_cap, n_static, s->late_stride, trace, n_tickets, n_units,
+                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size())};
   s->epoch += 1;
-  if (s->epoch == 0) {  // wrapped: every done flag must differ from the new epoch
+  if (s->epoch == 0) {  // wrapped: every done flag and claim must differ from the new epoch
     e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_flags, st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->claims.p, 0, sizeof(uint32_t) * claim_cap, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
     s->epoch = 1;
   }
+  // the counter moves once per counter ticket and once more per workgroup
+  // (its last, empty request)
   const uint64_t ticket_base = s->ticket_next;
-  s->ticket_next += static_cast<uint64_t>(n_tickets) + static_cast<uint64_t>(grid);
+  s->ticket_next += static_cast<uint64_t>(n_tickets - n_static) + static_cast<uint64_t>(grid);
   s->stats.flow_grid = grid;
   e = race::launch_race_flow<ValT>(a, f, k, x, y, ld, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
   if (e != hipSuccess) return hip_fail(e, "RACE dataflow launch");
@@ -659,6 +676,26 @@ int race_schedule_check(race_schedule_t s) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     return fail(RACE_EINTERNAL, "a dataflow wait gave up (bounded spin exceeded)");
   }
+  return RACE_OK;
+}
+
+int race_schedule_flow_takeovers(race_schedule_t s, int64_t* count) {
+  if (!s || !count) return fail(RACE_EINVAL, "NULL argument");
+  *count = 0;
+  if (!s->uploaded) return RACE_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  uint32_t v = 0;
+  e = hipMemcpy(&v, s->claims.p + (s->claims.count - 1), sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  *count = v;
+  return RACE_OK;
+}
+
+int race_schedule_flow_test_late(race_schedule_t s, int32_t stride) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (stride < 0) return fail(RACE_EINVAL, "stride must be >= 0");
+  s->late_stride = stride;
   return RACE_OK;
 }
 

@@ -38,11 +38,21 @@ struct UnitArgs {
 // entries of zero_idx (y entries whose first touch is a shared atomic add);
 // ticket n_zero_tasks + u is unit u.  A task's completion flag is
 // done[n_units + task].
+//
+// Static tickets: workgroup b starts on ticket b (b < n_static) after
+// claiming it, so the launch does not queue every workgroup on the counter
+// at once; the counter hands out the later tickets once all static ones are
+// claimed.  A static ticket whose workgroup is not running yet is claimed
+// and run by a running one that needs it.
 struct FlowArgs {
   const int32_t* dep_idx;
   uint32_t* done;       // n_units + n_zero_tasks completion flags
-  uint64_t* counter;
+  uint64_t* counter;    // tickets n_static and up
   uint32_t* status;
+  uint32_t* claim;      // n_static claim words: the launch's epoch once a running workgroup owns that ticket
+  uint32_t* takeovers;  // count of static tickets run by a workgroup other than their own (informational)
+  int32_t n_static;     // tickets 0 .. n_static-1 start on the workgroup of the same index
+  int32_t late_stride;  // tests only: 0, or every late_stride-th workgroup joins late and claims nothing first
   uint64_t* trace;  // NULL, or 4 stamps per unit: taken, computed, dependencies met, flushed
   int32_t n_tickets;  // n_zero_tasks + n_units
   int32_t n_units;

@@ -223,16 +223,13 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const Unit
   // arithmetic, its elements are requested right after
   while (c < c1) {
     const int32_t cn = c + nwaves;
-    int32_t meta_n = 0;
-    uint32_t off_n = 0;
-    uint16_t rs_n = kNoRow;
-    ValT d_n = ValT(0);
-    if (cn < c1) {
-      meta_n = uniform_load(a.chunk_len, cn);
-      off_n = uniform_load(a.chunk_off, cn);
-      rs_n = a.lane_slot[static_cast<size_t>(cn) * kSlice + lane];
-      d_n = a.lane_diag[static_cast<size_t>(cn) * kSlice + lane];
-    }
+    // the last wavefront's slice re-reads its own descriptor instead of
+    // branching around the loads
+    const int32_t cq = cn < c1 ? cn : c;
+    const int32_t meta_n = uniform_load(a.chunk_len, cq);
+    const uint32_t off_n = uniform_load(a.chunk_off, cq);
+    const uint16_t rs_n = a.lane_slot[static_cast<size_t>(cq) * kSlice + lane];
+    const ValT d_n = a.lane_diag[static_cast<size_t>(cq) * kSlice + lane];
     if (cur.rs != kNoRow) {
       double xr[K], acc[K];
 #pragma unroll
@@ -431,16 +428,131 @@ __device__ __forceinline__ void clear_task(const int32_t* __restrict__ zero_idx,
   }
 }
 
-// Dataflow execution in one persistent launch.  Units are taken in the
-// execution order (phase, then heaviest leaf first, a leaf's units in row
-// order) from a ticket counter; a unit computes right away and, before its
-// flush, waits until every earlier unit whose touch set meets its own has
-// published completion (the conflict edges of the tree's coloring).  Only y crosses units, and it does so through
-// coherent (agent-scope atomic) accesses whose completion each thread
-// awaits before the publishing barrier; x and the matrix are read-only.  Waits only point to smaller tickets, which were
-// handed to running workgroups, so the lowest unfinished ticket can always
-// proceed; every wait is bounded and reports through `status` if it gives
-// up, so the grid always drains.
+constexpr int kSetAside = 8;          // tickets a workgroup can set aside to run an ownerless one first
+constexpr uint32_t kOwnerCheck = 64;  // polls of a flag between checks that its ticket has an owner
+
+// Ticket of completion flag v (units follow the clearing tasks) and back.
+__device__ __forceinline__ int32_t ticket_of_flag(const FlowArgs& f, int32_t v) {
+  return v < f.n_units ? v + f.n_zero_tasks : v - f.n_units;
+}
+__device__ __forceinline__ int32_t flag_of_ticket(const FlowArgs& f, int32_t t) {
+  return t < f.n_zero_tasks ? f.n_units + t : t - f.n_zero_tasks;
+}
+
+// Claims static ticket t for this launch: true when no workgroup had it yet.
+__device__ __forceinline__ bool claim_ticket(uint32_t* claim, int32_t t, uint32_t epoch) {
+  return atomicMax(claim + t, epoch) != epoch;
+}
+
+__device__ __forceinline__ uint32_t coherent_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until the conflict edges [d0, d1) have published.  A flag still
+// unset whose ticket is static and unclaimed belongs to a workgroup that is
+// not running: when `may_take`, the workgroup claims the lowest such ticket
+// it met and returns it (the caller runs that ticket first), else it keeps
+// waiting.  Returns -1 once every edge has published or a bounded wait gave
+// up (status bit 0).  s_red[0] is INT32_MAX on entry and on return.
+__device__ __forceinline__ int32_t wait_edges(const FlowArgs& f, int32_t d0, int32_t d1, uint32_t epoch,
+                                              bool may_take, int32_t* s_red, int32_t tid, int32_t nthr,
+                                              bool wave0) {
+  for (;;) {
+    for (int32_t i = d0 + tid; i < d1; i += nthr) {
+      const int32_t v = f.dep_idx[i];
+      const int32_t tv = ticket_of_flag(f, v);
+      uint32_t spins = 0;
+      while (coherent_load(f.done + v) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(f.status, 1u);
+          break;
+        }
+        if (may_take && tv < f.n_static && spins % kOwnerCheck == 0 && coherent_load(f.claim + tv) != epoch) {
+          atomicMin(s_red, tv);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    const int32_t c = __builtin_amdgcn_readfirstlane(s_red[0]);
+    if (c == INT32_MAX) return -1;
+    __syncthreads();
+    if (wave0) {
+      if (tid == 0) {
+        s_red[0] = INT32_MAX;
+        s_red[1] = claim_ticket(f.claim, c, epoch) ? c : -1;
+      }
+    }
+    __syncthreads();
+    const int32_t got = __builtin_amdgcn_readfirstlane(s_red[1]);
+    if (got >= 0) return got;
+    // another running workgroup claimed it meanwhile: wait again
+  }
+}
+
+// Next ticket of a free workgroup: while static tickets may be unclaimed,
+// the lowest unclaimed one; once all are claimed, the counter's next ticket
+// (-1 when none is left).  Claims never revert within a launch, so a
+// workgroup that saw them all claimed goes straight to the counter.
+__device__ __forceinline__ int32_t next_ticket(const FlowArgs& f, uint32_t epoch, uint64_t ticket_base,
+                                               bool& all_claimed, int32_t* s_red, int32_t bid, int32_t tid,
+                                               int32_t nthr, bool wave0) {
+  while (!all_claimed) {
+    for (int32_t i = tid; i < f.n_static; i += nthr)
+      if (coherent_load(f.claim + i) != epoch) {
+        atomicMin(s_red, i);
+        break;
+      }
+    __syncthreads();
+    const int32_t c = __builtin_amdgcn_readfirstlane(s_red[0]);
+    __syncthreads();
+    if (c == INT32_MAX) {
+      all_claimed = true;
+      break;
+    }
+    if (wave0) {
+      if (tid == 0) {
+        s_red[0] = INT32_MAX;
+        const bool mine = claim_ticket(f.claim, c, epoch);
+        s_red[1] = mine ? c : -1;
+        if (mine && c != bid) atomicAdd(f.takeovers, 1u);
+      }
+    }
+    __syncthreads();
+    const int32_t got = __builtin_amdgcn_readfirstlane(s_red[1]);
+    if (got >= 0) return got;
+  }
+  __syncthreads();
+  if (wave0) {
+    if (tid == 0) {
+      const uint64_t t = atomicAdd(reinterpret_cast<unsigned long long*>(f.counter), 1ull) - ticket_base;
+      s_red[1] = t < static_cast<uint64_t>(f.n_tickets - f.n_static) ? f.n_static + static_cast<int32_t>(t) : -1;
+    }
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s_red[1]);
+}
+
+// Dataflow execution in one persistent launch.  Tickets are the clearing
+// tasks and the units in execution order (phase, then heaviest leaf first,
+// a leaf's units in row order).  Workgroup b starts on static ticket b,
+// later tickets come from a counter once every static ticket is claimed.  A
+// unit computes right away and, before its flush, waits until every earlier
+// unit whose touch set meets its own has published completion (the conflict
+// edges of the tree's coloring).  Only y crosses units, and it does so
+// through coherent (agent-scope atomic) accesses whose completion each
+// thread awaits before the publishing barrier; x and the matrix are
+// read-only.
+//
+// Progress needs no co-residency: waits point only to smaller tickets; a
+// counter ticket is handed out only after every static ticket has a running
+// owner, and a static ticket whose own workgroup is not running is claimed
+// by a running workgroup that waits for it (which sets its computed unit
+// aside, runs that ticket and computes its unit again) or by a free one.
+// So the lowest unfinished ticket is always owned by a running workgroup or
+// claimable by one.  Every wait is bounded and reports through `status` if
+// it gives up, so the grid always drains.
 template <typename ValT, int K>
 __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowArgs f, const double* __restrict__ x,
                                                          double* __restrict__ y, int32_t ld, int32_t wmax,
@@ -449,34 +561,89 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
   double* xw = smem;
   double* yw = smem + static_cast<size_t>(wmax) * K;
   uint32_t* gw = reinterpret_cast<uint32_t*>(smem + 2 * static_cast<size_t>(wmax) * K);
-  __shared__ int32_t s_unit[1];
+  __shared__ int32_t s_red[2];
+  __shared__ int32_t s_aside[kSetAside];
   const int32_t tid = static_cast<int32_t>(threadIdx.x), nthr = static_cast<int32_t>(blockDim.x);
+  const int32_t bid = static_cast<int32_t>(blockIdx.x);
   // wave 0 as a scalar condition: the lane-0 work below sits in small
   // diamonds inside a wave-uniform branch, and barriers close them on both
   // sides, so no lane can run ahead into the next unit's barriers
   const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < kSlice;
+  const bool late = f.late_stride > 0 && bid % f.late_stride == f.late_stride - 1;
+  if (late) {
+    // tests only: join about 0.2 ms late without claiming the own ticket
+    for (int i = 0; i < 64; ++i) __builtin_amdgcn_s_sleep(127);
+  }
+  if (wave0) {
+    if (tid == 0) {
+      s_red[0] = INT32_MAX;
+      s_red[1] = (!late && bid < f.n_static && claim_ticket(f.claim, bid, epoch)) ? bid : -1;
+    }
+  }
+  __syncthreads();
+  // tickets and counts live in scalar registers, so the loop's exits and
+  // the barriers inside stay in uniform control flow
+  int32_t t = __builtin_amdgcn_readfirstlane(s_red[1]);
+  int32_t aside = 0;
+  bool all_claimed = false;
   for (;;) {
-    __syncthreads();
-    if (wave0) {
-      if (tid == 0) {
-        const uint64_t t = atomicAdd(reinterpret_cast<unsigned long long*>(f.counter), 1ull) - ticket_base;
-        s_unit[0] = t < static_cast<uint64_t>(f.n_tickets) ? static_cast<int32_t>(t) : -1;
+    if (t < 0) {
+      if (aside > 0) {
+        --aside;
+        t = __builtin_amdgcn_readfirstlane(s_aside[aside]);
+      } else {
+        t = next_ticket(f, epoch, ticket_base, all_claimed, s_red, bid, tid, nthr, wave0);
+        if (t < 0) break;
       }
     }
-    __syncthreads();
-    // the same value in every lane; read into a scalar register so the loop's
-    // exit and the barriers below stay in uniform control flow (a ticket taken
-    // only when the workgroup is free keeps the end of the run balanced)
-    const int32_t t = __builtin_amdgcn_readfirstlane(s_unit[0]);
-    if (t < 0) break;
     if (t < f.n_zero_tasks) {
       const int64_t i0 = static_cast<int64_t>(t) * f.zero_chunk;
       clear_task<K>(f.zero_idx, i0, i0 + f.zero_chunk < f.n_zero ? i0 + f.zero_chunk : f.n_zero, y, ld,
                     f.done + f.n_units + t, epoch, tid, nthr, wave0);
+      t = -1;
       continue;
     }
-    flow_unit<ValT, K>(a, t - f.n_zero_tasks, f.dep_idx, f.done, f.status, f.trace, epoch, x, y, ld, xw,
-                       yw, gw, tid, nthr, wave0);
+    const int32_t u = t - f.n_zero_tasks;
+    const uint64_t t0 = f.trace ? wall_clock() : 0;
+    // the unit's arithmetic needs nothing from other units; only its flush
+    // must follow the earlier units it conflicts with
+    const UnitDesc ud = uniform_load(a.unit_desc, u);
+    compute_unit<ValT, K>(a, ud, x, ld, xw, yw, gw, tid, nthr);
+    const uint64_t t1 = f.trace ? wall_clock() : 0;
+    const int32_t r = wait_edges(f, ud.d0, ud.d1, epoch, aside < kSetAside, s_red, tid, nthr, wave0);
+    if (r >= 0) {
+      // run the ownerless ticket first; this unit is computed again later
+      if (wave0) {
+        if (tid == 0) {
+          s_aside[aside] = t;
+          atomicAdd(f.takeovers, 1u);
+        }
+      }
+      ++aside;
+      t = r;
+      continue;
+    }
+    const uint64_t t2 = f.trace ? wall_clock() : 0;
+    flush_unit<K, true>(ud, y, ld, yw, gw, tid, nthr);
+    // every thread's coherent y stores complete before the barrier, so the
+    // completion flag written after it is only seen once they are visible
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (wave0) {
+      if (tid == 0) {
+        if (f.trace) {
+          const uint64_t t3 = wall_clock();
+          f.trace[4 * static_cast<size_t>(u) + 0] = t0;
+          f.trace[4 * static_cast<size_t>(u) + 1] = t1;
+          f.trace[4 * static_cast<size_t>(u) + 2] = t2;
+          f.trace[4 * static_cast<size_t>(u) + 3] = t3;
+        }
+        __hip_atomic_store(f.done + u, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    t = -1;
   }
 }
 

@@ -387,6 +387,41 @@ def test_traced_product_stamps():
     s.close()
 
 
+@pytest.mark.parametrize("stride,shared", [(2, True), (5, False)])
+def test_flow_late_workgroups_taken_over(stride, shared):
+    """Workgroups forced from the host to join about 0.2 ms late claim
+    nothing at start: running workgroups that wait for their static tickets,
+    or that are free, claim and run them.  The product is the same and the
+    takeovers are counted; with the forcing off again the next product is
+    correct too."""
+    m = matgen.stencil3d_27pt(40, seed=71)
+    x = matgen.rhs(m.n, 71)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=64, window_max=512, shared_atomics=shared)
+    try:
+        y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
+        absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, x)
+        xd = torch.as_tensor(x, device=DEV)
+        xp = torch.empty_like(xd)
+        s.permute(xd, xp, True)
+        before = s.takeovers()
+        for late in (stride, 0):
+            print(f"case late stride={late} shared={shared}: n={m.n} units={s.stats()['n_units']}", flush=True)
+            s.test_late(late)
+            yp = torch.full_like(xd, float("nan"))
+            s.spmv(xp, yp)
+            y = torch.empty_like(xd)
+            s.permute(yp, y, False)
+            torch.cuda.synchronize()
+            s.check()
+            _check(y.cpu().numpy(), y_ref, absax, _full_row_len(m), f"late{late}")
+            if late:
+                taken = s.takeovers() - before
+                print(f"  takeovers {taken}", flush=True)
+                assert taken > 0
+    finally:
+        s.close()
+
+
 def test_product_fuzz():
     """Seeded random matrices and parameters (window, workgroup size,
     execution mode, shared atomics, value type, right-hand sides) against the
