@@ -66,14 +66,17 @@ __device__ __forceinline__ void load_slice_head(const UnitArgs<ValT>& a, int32_t
 template <typename ValT>
 __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane, int32_t j0, SliceRegs<ValT>& r) {
   const int32_t l = lane < r.width ? lane : r.width - 1;
-  const ValT* vp = a.sell_val + r.off + l;
-  const uint16_t* sp = a.sell_slot + r.off + l;
+  // a wave-uniform base and a 32-bit per-lane byte offset (a slice spans
+  // at most 2^22 entries): one offset register per load
+  const char* vp = reinterpret_cast<const char*>(a.sell_val + r.off);
+  const char* sp = reinterpret_cast<const char*>(a.sell_slot + r.off);
 #pragma unroll
   for (int b = 0; b < SliceRegs<ValT>::kBatch; ++b) {
     const int32_t j = j0 + b;
     if (j < r.len) {
-      r.v[b] = vp[j * r.width];
-      r.sl[b] = sp[j * r.width];
+      const uint32_t e = static_cast<uint32_t>(l + j * r.width);
+      r.v[b] = *reinterpret_cast<const ValT*>(vp + e * static_cast<uint32_t>(sizeof(ValT)));
+      r.sl[b] = *reinterpret_cast<const uint16_t*>(sp + e * 2u);
     } else {
       r.v[b] = ValT(0);
       r.sl[b] = r.rs;
