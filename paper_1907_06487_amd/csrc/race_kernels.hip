@@ -84,15 +84,15 @@ __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane
   }
 }
 
-// Applies a loaded batch.  With one or two right-hand sides the gathers of
-// a group of kGather entries are all issued before the first is used; with
-// more, acc and x_r already fill the registers and entries go one at a time.
-// A zero value (row padding) adds +0 to its own row's slot and nothing to
-// acc.
+// Applies a loaded batch.  With one right-hand side the gathers of a group
+// of kGather entries are all issued before the first is used; with more,
+// each entry's K gathers already overlap and entries go one at a time
+// (measured faster from K = 2 on).  A zero value (row padding) adds +0 to
+// its own row's slot and nothing to acc.
 template <int K, int B, typename ValT>
 __device__ __forceinline__ void apply_batch(const ValT* v, const int32_t* sl, const double* xw, double* yw,
                                             const double (&xr)[K], double (&acc)[K]) {
-  if constexpr (K > 2) {
+  if constexpr (K > 1) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       if (v[b] != ValT(0)) {
@@ -106,7 +106,7 @@ __device__ __forceinline__ void apply_batch(const ValT* v, const int32_t* sl, co
     }
     return;
   }
-  constexpr int kGather = K == 1 ? 8 : 4;
+  constexpr int kGather = 8;
 #pragma unroll
   for (int g = 0; g < B; g += kGather) {
     double xg[kGather][K];
