@@ -40,6 +40,8 @@ def workload(name):
         return matgen.config_banded_4m(), "irregular banded 2^22 rows, bandwidth 2^16, FP64, seed 3"
     if name == "3d27pt_160":
         return matgen.config_3d_160(), "3D 27-point stencil 160^3, FP64, seed 2000"
+    if name == "3d27pt_128_relabel":
+        return matgen.config_3d_128_relabel(), "3D 27-point stencil 128^3 under a random symmetric relabelling (seed 7)"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -311,6 +313,10 @@ def main():
     ap.add_argument("--exec-mode", default="flow", choices=["flow", "phases"])
     ap.add_argument("--shared-atomics", type=int, default=1, choices=[0, 1],
                     help="units of one leaf run concurrently, combining shared y entries atomically (1) or in order (0)")
+    ap.add_argument("--root", default="first", choices=["first", "peripheral"],
+                    help="stage-0 BFS root of every island: its first vertex or a pseudo-peripheral one")
+    ap.add_argument("--level-order", default="input", choices=["input", "cm"],
+                    help="stage-0 order inside a level: input order or Cuthill-McKee numbering")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
@@ -355,7 +361,8 @@ def main():
     t0 = time.perf_counter()
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
                    block_threads=args.block, window_max=args.window, value_type=args.value_type,
-                   exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics))
+                   exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics), root=args.root,
+                   level_order=args.level_order)
     t_build = time.perf_counter() - t0
     st = s.stats()
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
@@ -477,6 +484,7 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_upper": m.nnz,
                    "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
                    "window_max": args.window, "exec_mode": args.exec_mode, "shared_atomics": args.shared_atomics,
+                   "root": args.root, "level_order": args.level_order, "levels0": st["n_levels0"],
                    "phases": st["n_phases_used"], "leaves": st["n_leaves"], "eta": st["eta"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

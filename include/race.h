@@ -72,6 +72,15 @@ typedef struct {
   int32_t rhs_tile;        /* right-hand sides per pass of race_symm_spmm (0: all k when the unit windows of k
                               columns fit the LDS, else the widest tile that fits; t > 0: at most t).  Each pass
                               re-reads the matrix; narrower passes keep the windows, and so the reuse, large */
+  int32_t root_mode;       /* stage-0 BFS root of every island (Section 4.1): 0 = its first vertex in the input
+                              order; 1 = a pseudo-peripheral vertex found from that one (George and Liu's node
+                              finder: repeated level structures from a minimum-degree vertex of the last level
+                              while the eccentricity grows), which gives more levels when the first vertex lies
+                              inside the graph */
+  int32_t level_order;     /* stage-0 order of the vertices inside a level: 0 = input order; 1 = Cuthill-McKee
+                              discovery order (each vertex's new neighbours by increasing degree, ties by index), the
+                              order a bandwidth-reducing level construction gives; it keeps the unit windows local
+                              when the input order is not */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */

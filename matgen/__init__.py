@@ -193,6 +193,25 @@ def config_banded_4m() -> UpperCSR:
     return banded_irregular(2**22, seed=3)
 
 
+def relabel(m: UpperCSR, seed: int) -> UpperCSR:
+    """The same symmetric matrix under a seeded random symmetric permutation
+    (P A P^T): entry (i, j) moves to (p[i], p[j]), stored again as the upper
+    triangle.  The input order then says nothing about the graph, as for a
+    matrix with no bandwidth-reducing preordering."""
+    p = _rng(seed).permutation(m.n).astype(np.int64)
+    rows = np.repeat(np.arange(m.n, dtype=np.int64), np.diff(m.row_ptr))
+    a, b = p[rows], p[m.col.astype(np.int64)]
+    r, c = np.minimum(a, b), np.maximum(a, b)
+    order = np.lexsort((c, r))
+    return _csr_from_sorted(m.n, r[order], c[order], m.val[order], f"{m.name}_relabel{seed}")
+
+
+def config_3d_128_relabel() -> UpperCSR:
+    """The 128^3 27-point stencil (seed 2) under a random symmetric
+    relabelling (seed 7): vertex 0 is an arbitrary grid point."""
+    return relabel(config_3d_128(), 7)
+
+
 def config_3d_160() -> UpperCSR:
     """3D 27-point stencil on a 160^3 grid (N = 4,096,000), seed 2000."""
     return stencil3d_27pt(160, seed=2000)

@@ -25,8 +25,16 @@ Follows Section 4 of the paper in its own order:
 Readings taken where the paper is silent or its text is garbled (the same
 readings bind the GPU library):
 
-* the stage-0 root is vertex 0 of the input order; the BFS runs until the
-  frontier is empty;
+* the stage-0 root is vertex 0 of the input order (``root="first"``); the
+  BFS runs until the frontier is empty.  With ``root="peripheral"`` every
+  stage-0 island starts instead from a pseudo-peripheral vertex found from
+  that first vertex (the bandwidth-reduction root choice the paper's level
+  construction refers to, Section 4.1; see ``pseudo_peripheral``);
+* inside a stage-0 level the input order is kept (``level_order="input"``)
+  or the Cuthill-McKee numbering is used (``level_order="cm"``, Section 4.1
+  names RCM as the alternative level construction; only the numbering
+  inside each level differs, the levels are the BFS levels either way, and
+  the order is not reversed, since the colors need only the levels);
 * disconnected input is handled as islands, exactly like the recursion's
   islands: the next root is the unvisited vertex of the group that comes
   first in the current order, and it gets the largest level assigned so far
@@ -154,13 +162,88 @@ def subgraph_vertices(ptr, idx, members):
     return np.concatenate([members, _neighbors(ptr, idx, members)])
 
 
-def bfs_levels(ptr, idx, members, in_sub, scratch):
+def level_structure(ptr, idx, root, n):
+    """Rooted level structure of the connected component of ``root`` in the
+    full graph: BFS distances (-1 outside the component) and the last
+    level's vertices in ascending order (Section 4.1, Eq. (level))."""
+    dist = np.full(n, -1, dtype=np.int64)
+    dist[root] = 0
+    frontier = np.array([root], dtype=np.int64)
+    last = frontier
+    d = 0
+    while frontier.size:
+        last = frontier
+        nb = _neighbors(ptr, idx, frontier)
+        nb = np.unique(nb[dist[nb] < 0])
+        d += 1
+        dist[nb] = d
+        frontier = nb
+    return dist, np.sort(last)
+
+
+def pseudo_peripheral(ptr, idx, start, n):
+    """Pseudo-peripheral vertex of the component of ``start`` by the node
+    finder of George and Liu (1979): from the current vertex r build the
+    rooted level structure, take a vertex x of minimum degree in its last
+    level (the lowest index among equals), build the structure rooted at x;
+    while x reaches farther than r (larger eccentricity), continue from x.
+    Returns the last x.  Degrees count off-diagonal neighbours."""
+    deg = np.diff(ptr)
+    r = int(start)
+    dist, last = level_structure(ptr, idx, r, n)
+    ecc_r = int(dist.max())
+    while True:
+        x = int(last[np.argmin(deg[last])])   # argmin returns the first (lowest index) minimum
+        dist_x, last_x = level_structure(ptr, idx, x, n)
+        ecc_x = int(dist_x.max())
+        if ecc_x <= ecc_r:
+            return x
+        r, ecc_r, last = x, ecc_x, last_x
+
+
+def cuthill_mckee_levels(ptr, idx, n, root_of=None):
+    """Stage-0 levels with the Cuthill-McKee numbering (Cuthill and McKee,
+    1969): from each island's root, the vertices are numbered level by
+    level, and every numbered vertex numbers its unnumbered neighbours in
+    order of increasing degree (ties: lower index first).  Islands start at
+    their first unnumbered vertex (or ``root_of`` of it), each two levels
+    above the largest so far.  Returns (levels, numbering order).  Plain
+    loops: for test-sized graphs."""
+    deg = np.diff(ptr)
+    lev = np.full(n, -1, dtype=np.int64)
+    order = []
+    cur_max = -1
+    for first in range(n):
+        if lev[first] >= 0:
+            continue
+        root = first if root_of is None else root_of(first)
+        lvl = 0 if cur_max < 0 else cur_max + 2
+        lev[root] = lvl
+        order.append(root)
+        frontier = [root]
+        while frontier:
+            cur_max = max(cur_max, lvl)
+            nxt = []
+            for v in frontier:
+                new = [int(u) for u in idx[ptr[v]:ptr[v + 1]] if lev[u] < 0]
+                for u in new:
+                    lev[u] = lvl + 1
+                new.sort(key=lambda u: (deg[u], u))
+                nxt.extend(new)
+            order.extend(nxt)
+            lvl += 1
+            frontier = nxt
+    return lev, np.array(order, dtype=np.int64)
+
+
+def bfs_levels(ptr, idx, members, in_sub, scratch, root_of=None):
     """Levels (BFS distances) inside the subgraph induced by ``in_sub``.
 
     ``members`` are the group's vertices in current order; roots are taken
-    from them (first unvisited), each new island starting two above the
-    largest level assigned so far.  Returns the levels of ``members``.
-    ``scratch`` is an all -1 array of length n, restored before returning."""
+    from them (first unvisited, or ``root_of`` of it when given), each new
+    island starting two above the largest level assigned so far.  Returns
+    the levels of ``members``.  ``scratch`` is an all -1 array of length n,
+    restored before returning."""
     touched = []
     cur_max = -1
     p = 0
@@ -176,7 +259,7 @@ def bfs_levels(ptr, idx, members, in_sub, scratch):
             p += chunk.shape[0]
         if p >= nm:
             break
-        root = members[p]
+        root = members[p] if root_of is None else root_of(int(members[p]))
         lvl = 0 if cur_max < 0 else cur_max + 2
         scratch[root] = lvl
         frontier = np.array([root], dtype=np.int64)
@@ -373,9 +456,13 @@ def load_balance(t_ptr, worker, m_levels, k):
 # the recursive construction (Section 4.4)
 
 def build_schedule(n, row_ptr, col, n_t, eps=DEFAULT_EPS, k=2, balance="nnz", max_stages=4,
-                   global_lb=False):
+                   global_lb=False, root="first", level_order="input"):
     if k != 2:
         raise ValueError("SymmSpMV needs distance-2 coloring (k = 2)")
+    if root not in ("first", "peripheral"):
+        raise ValueError("root must be 'first' or 'peripheral'")
+    if level_order not in ("input", "cm"):
+        raise ValueError("level_order must be 'input' or 'cm'")
     ptr, idx = full_adjacency(n, row_ptr, col)
     m_row = row_loads(n, row_ptr, col, balance)
     perm = np.arange(n, dtype=np.int64)
@@ -398,7 +485,15 @@ def build_schedule(n, row_ptr, col, n_t, eps=DEFAULT_EPS, k=2, balance="nnz", ma
             in_sub[:] = True
         else:
             in_sub[sub] = True
-        lev = bfs_levels(ptr, idx, members, in_sub, scratch)
+        root_of = None
+        if node.stage < 0 and root == "peripheral":
+            root_of = lambda v: pseudo_peripheral(ptr, idx, v, n)
+        if node.stage < 0 and level_order == "cm":
+            # stage 0 numbered by Cuthill-McKee: the members take that order
+            lev_all, members = cuthill_mckee_levels(ptr, idx, n, root_of)
+            lev = lev_all[members]
+        else:
+            lev = bfs_levels(ptr, idx, members, in_sub, scratch, root_of)
         if sub is None:
             in_sub[:] = False
         else:

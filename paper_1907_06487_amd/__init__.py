@@ -23,9 +23,12 @@ BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
-                shared_atomics=True, cost_model=None, rhs_tile=0):
+                shared_atomics=True, cost_model=None, rhs_tile=0, root="first", level_order="input"):
     """race_params from keywords.  balance="model" needs cost_model: the
-    network's MLP_PARAMS float32 weights (kept alive on the returned struct)."""
+    network's MLP_PARAMS float32 weights (kept alive on the returned struct).
+    root: "first" (stage-0 islands start at their first vertex in the input
+    order) or "peripheral" (at a pseudo-peripheral vertex).  level_order:
+    "input" or "cm" (Cuthill-McKee discovery order inside stage-0 levels)."""
     p = race_params_default()
     p.n_workers = int(n_workers)
     p.max_stages = int(max_stages)
@@ -37,6 +40,8 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.exec_mode = {"phases": 0, "flow": 1}[exec_mode]
     p.shared_atomics = int(bool(shared_atomics))
     p.rhs_tile = int(rhs_tile)
+    p.root_mode = {"first": 0, "peripheral": 1}[root]
+    p.level_order = {"input": 0, "cm": 1}[level_order]
     if cost_model is not None:
         import ctypes
 

@@ -49,6 +49,7 @@ class race_params(ctypes.Structure):
         ("window_max", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("eps", ctypes.c_double * 8),
         ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("shared_atomics", ctypes.c_int32), ("rhs_tile", ctypes.c_int32),
+        ("root_mode", ctypes.c_int32), ("level_order", ctypes.c_int32),
     ]
 
 

@@ -168,6 +168,8 @@ int race_params_default(race_params* p) {
   p->exec_mode = 1;
   p->shared_atomics = 1;
   p->rhs_tile = 0;
+  p->root_mode = 0;
+  p->level_order = 0;
   return RACE_OK;
 }
 
@@ -189,6 +191,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
   if (prm.shared_atomics < 0 || prm.shared_atomics > 1) return fail(RACE_EINVAL, "shared_atomics must be 0 or 1");
   if (prm.rhs_tile < 0 || prm.rhs_tile > 16) return fail(RACE_EINVAL, "rhs_tile must be in 0..16");
+  if (prm.root_mode < 0 || prm.root_mode > 1) return fail(RACE_EINVAL, "root_mode must be 0 or 1");
+  if (prm.level_order < 0 || prm.level_order > 1) return fail(RACE_EINVAL, "level_order must be 0 or 1");
   if (prm.window_max == 0) prm.window_max = 3840;
   if (prm.window_max < 2 || prm.window_max > 8000) return fail(RACE_EINVAL, "window_max must be in 2..8000");
   if (prm.block_threads == 0) prm.block_threads = 256;
@@ -207,7 +211,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     race::build_graph(n, row_ptr, col, g);
     std::vector<int64_t> m;
     if (prm.balance_by == 2)
-      race::learned_row_loads(g, n, row_ptr, col, prm.cost_model, prm.window_max, m);
+      race::learned_row_loads(g, n, row_ptr, col, prm.cost_model, prm.window_max, prm.root_mode, prm.level_order, m);
     else
       race::row_loads(n, row_ptr, col, prm.balance_by == 1, m);
     race::TreeParams tp;
@@ -215,6 +219,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     tp.max_stages = prm.max_stages;
     tp.dist_k = prm.dist_k;
     tp.global_lb = prm.global_lb != 0;
+    tp.root_mode = prm.root_mode;
+    tp.level_order = prm.level_order;
     for (int i = 0; i < 8; ++i) tp.eps[i] = prm.eps[i];
     std::string err = race::build_tree(g, m, tp, s->tree);
     if (!err.empty()) {

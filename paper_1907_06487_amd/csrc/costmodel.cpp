@@ -122,41 +122,17 @@ double simulate(const Layout& L, const float* cost, double flush_frac, int32_t w
 }
 
 void learned_row_loads(const Graph& g, int32_t n, const int32_t* row_ptr, const int32_t* col, const float* theta,
-                       int32_t window_max, std::vector<int64_t>& m) {
+                       int32_t window_max, int32_t root_mode, int32_t level_order, std::vector<int64_t>& m) {
   m.assign(static_cast<size_t>(n), 1);
   if (n == 0) return;
-  // stage-0 BFS levels: roots in index order, each island two levels above
-  // the largest level so far (the tree builder's numbering)
-  std::vector<int32_t> lev(static_cast<size_t>(n), -1), frontier, next;
-  int32_t cur_max = -1;
-  for (int32_t root = 0; root < n; ++root) {
-    if (lev[root] >= 0) continue;
-    int32_t l = cur_max < 0 ? 0 : cur_max + 2;
-    lev[root] = l;
-    frontier.assign(1, root);
-    while (!frontier.empty()) {
-      cur_max = std::max(cur_max, l);
-      next.clear();
-      for (int32_t v : frontier)
-        for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
-          const int32_t u = g.adj[e];
-          if (lev[u] < 0) {
-            lev[u] = l + 1;
-            next.push_back(u);
-          }
-        }
-      ++l;
-      frontier.swap(next);
-    }
-  }
-  const int32_t nl = cur_max + 1;
-  std::vector<int32_t> level_ptr(static_cast<size_t>(nl) + 1, 0), order(static_cast<size_t>(n)), pos(static_cast<size_t>(n));
+  // stage-0 levels and order, as the tree builder finds them
+  std::vector<int32_t> lev, order, pos(static_cast<size_t>(n));
+  stage0_order(g, root_mode, level_order, lev, order);
+  int32_t nl = 0;
+  for (int32_t v = 0; v < n; ++v) nl = std::max(nl, lev[v] + 1);
+  std::vector<int32_t> level_ptr(static_cast<size_t>(nl) + 1, 0);
   for (int32_t v = 0; v < n; ++v) ++level_ptr[lev[v] + 1];
   for (int32_t l = 0; l < nl; ++l) level_ptr[l + 1] += level_ptr[l];
-  {
-    std::vector<int32_t> fill(level_ptr.begin(), level_ptr.end() - 1);
-    for (int32_t v = 0; v < n; ++v) order[fill[lev[v]]++] = v;
-  }
   for (int32_t p = 0; p < n; ++p) pos[order[p]] = p;
   std::vector<uint8_t> has_diag(static_cast<size_t>(n), 0);
   for (int32_t r = 0; r < n; ++r)

@@ -39,6 +39,6 @@ double simulate(const Layout& L, const float* cost, double flush_frac, int32_t w
 
 // Row loads from the network (see above); loads are in nanoseconds, >= 1.
 void learned_row_loads(const Graph& g, int32_t n, const int32_t* row_ptr, const int32_t* col, const float* theta,
-                       int32_t window_max, std::vector<int64_t>& m);
+                       int32_t window_max, int32_t root_mode, int32_t level_order, std::vector<int64_t>& m);
 
 }  // namespace race

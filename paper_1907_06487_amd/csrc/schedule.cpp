@@ -231,6 +231,114 @@ void load_balance(std::vector<int32_t>& t_ptr, const std::vector<int64_t>& worke
 // ---------------------------------------------------------------------------
 // recursion
 
+// Rooted level structure of the component of `root` (Section 4.1): fills
+// dist, records the visited vertices in `seen` and the last level in `last`
+// (ascending); returns the eccentricity of the root.
+static int32_t level_structure(const Graph& g, int32_t root, std::vector<int32_t>& dist, std::vector<int32_t>& seen,
+                               std::vector<int32_t>& last) {
+  std::vector<int32_t> frontier(1, root), next;
+  dist[root] = 0;
+  seen.push_back(root);
+  int32_t d = 0;
+  last = frontier;
+  while (!frontier.empty()) {
+    last = frontier;
+    next.clear();
+    for (int32_t v : frontier)
+      for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
+        const int32_t u = g.adj[e];
+        if (dist[u] < 0) {
+          dist[u] = d + 1;
+          seen.push_back(u);
+          next.push_back(u);
+        }
+      }
+    ++d;
+    frontier.swap(next);
+  }
+  std::sort(last.begin(), last.end());
+  return d - 1;
+}
+
+// George and Liu's pseudo-peripheral node finder: from the current vertex
+// r, take a vertex x of minimum degree in the last level of r's rooted
+// level structure (the lowest index among equals); while x's eccentricity
+// exceeds r's, continue from x.  Returns the last x.
+int32_t pseudo_peripheral(const Graph& g, int32_t start, std::vector<int32_t>& dist) {
+  std::vector<int32_t> seen, last, last_x;
+  auto reset = [&]() {
+    for (int32_t v : seen) dist[v] = -1;
+    seen.clear();
+  };
+  int32_t ecc_r = level_structure(g, start, dist, seen, last);
+  reset();
+  for (;;) {
+    int32_t x = last[0];
+    int64_t best = g.ptr[x + 1] - g.ptr[x];
+    for (int32_t v : last) {
+      const int64_t dv = g.ptr[v + 1] - g.ptr[v];
+      if (dv < best) {
+        best = dv;
+        x = v;
+      }
+    }
+    const int32_t ecc_x = level_structure(g, x, dist, seen, last_x);
+    reset();
+    if (ecc_x <= ecc_r) return x;
+    ecc_r = ecc_x;
+    last.swap(last_x);
+  }
+}
+
+void stage0_order(const Graph& g, int32_t root_mode, int32_t level_order, std::vector<int32_t>& lev,
+                  std::vector<int32_t>& order) {
+  const int32_t n = g.n;
+  lev.assign(static_cast<size_t>(n), -1);
+  order.clear();
+  order.reserve(static_cast<size_t>(n));
+  std::vector<int32_t> pp_dist, frontier, next, grp;
+  if (root_mode == 1) pp_dist.assign(static_cast<size_t>(n), -1);
+  int32_t cur_max = -1;
+  for (int32_t first = 0; first < n; ++first) {
+    if (lev[first] >= 0) continue;
+    const int32_t root = root_mode == 1 ? pseudo_peripheral(g, first, pp_dist) : first;
+    int32_t lvl = cur_max < 0 ? 0 : cur_max + 2;
+    lev[root] = lvl;
+    order.push_back(root);
+    frontier.assign(1, root);
+    while (!frontier.empty()) {
+      cur_max = std::max(cur_max, lvl);
+      next.clear();
+      for (int32_t v : frontier) {
+        grp.clear();
+        for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
+          const int32_t u = g.adj[e];
+          if (lev[u] < 0) {
+            lev[u] = lvl + 1;
+            grp.push_back(u);
+          }
+        }
+        // Cuthill-McKee: a vertex's new neighbours by increasing degree
+        if (level_order == 1)
+          std::stable_sort(grp.begin(), grp.end(), [&](int32_t a, int32_t b) {
+            return g.ptr[a + 1] - g.ptr[a] < g.ptr[b + 1] - g.ptr[b];
+          });
+        next.insert(next.end(), grp.begin(), grp.end());
+      }
+      order.insert(order.end(), next.begin(), next.end());
+      ++lvl;
+      frontier.swap(next);
+    }
+  }
+  if (level_order == 0) {
+    // keep the input order inside every level: stable sort by level
+    std::vector<int32_t> cnt(static_cast<size_t>(cur_max) + 2, 0);
+    for (int32_t v = 0; v < n; ++v) ++cnt[lev[v] + 1];
+    for (size_t l = 1; l < cnt.size(); ++l) cnt[l] += cnt[l - 1];
+    for (int32_t v = 0; v < n; ++v) order[cnt[lev[v]]++] = v;
+  }
+}
+
 namespace {
 
 struct Builder {
@@ -305,9 +413,17 @@ struct Builder {
         }
       }
     }
-    bfs(members.data(), nm, all, lev);
-    if (!all)
+    if (all) {
+      // stage 0: the whole graph, its island roots and in-level order by the
+      // parameters; members follow the level order found
+      std::vector<int32_t> lev_v;
+      stage0_order(g, p.root_mode, p.level_order, lev_v, members);
+      lev.resize(static_cast<size_t>(nm));
+      for (int32_t i = 0; i < nm; ++i) lev[i] = lev_v[members[i]];
+    } else {
+      bfs(members.data(), nm, all, lev);
       for (int32_t v : sub_list) in_sub[v] = 0;
+    }
     int32_t nl = 0;
     for (int32_t l : lev) nl = std::max(nl, l + 1);
     std::vector<int64_t> m_levels(static_cast<size_t>(nl), 0);

@@ -29,6 +29,8 @@ struct TreeParams {
   int32_t max_stages = 4;
   int32_t dist_k = 2;
   bool global_lb = false;
+  int32_t root_mode = 0;    // stage-0 island roots: 0 first vertex in input order, 1 pseudo-peripheral
+  int32_t level_order = 0;  // stage-0 order inside a level: 0 input order, 1 Cuthill-McKee discovery order
   double eps[8] = {0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
 };
 
@@ -54,6 +56,20 @@ void row_loads(int32_t n, const int32_t* row_ptr, const int32_t* col, bool by_ro
 // Builds the tree.  row_load gives m(row) for every row (length n).
 // Returns an empty string on success, else an error message.
 std::string build_tree(const Graph& g, const std::vector<int64_t>& row_load, const TreeParams& p, Tree& out);
+
+// Pseudo-peripheral vertex of the connected component of `start` (George
+// and Liu's node finder, see schedule.cpp).  `dist` is an all -1 scratch
+// array of length g.n, restored before returning.
+int32_t pseudo_peripheral(const Graph& g, int32_t start, std::vector<int32_t>& dist);
+
+// Stage-0 level structure of the whole graph (Section 4.1): islands in the
+// order of their first vertex, each rooted there (root_mode 0) or at the
+// pseudo-peripheral vertex found from it (1), levels two above the largest
+// so far; `order` lists the vertices by level, inside a level in input order
+// (level_order 0) or in Cuthill-McKee discovery order (1: every vertex's new
+// neighbours by increasing degree, ties by index).
+void stage0_order(const Graph& g, int32_t root_mode, int32_t level_order, std::vector<int32_t>& lev,
+                  std::vector<int32_t>& order);
 
 // Exposed for unit tests through the ABI-free C++ layer.
 struct Pair {

@@ -99,6 +99,13 @@ SMALL = [
     ("banded_40k_w96", lambda: matgen.banded_irregular(40000, seed=6, band=4000), dict(n_workers=16, window_max=96)),
     ("banded_40k_w96_phases", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
      dict(n_workers=16, window_max=96, exec_mode="phases")),
+    # stage-0 root and in-level order: a relabelled stencil rebuilt with a
+    # pseudo-peripheral root and the Cuthill-McKee numbering
+    ("3d27pt_24_relabel_pcm", lambda: matgen.relabel(matgen.stencil3d_27pt(24, seed=5), 3),
+     dict(n_workers=256, root="peripheral", level_order="cm")),
+    ("3d27pt_24_relabel", lambda: matgen.relabel(matgen.stencil3d_27pt(24, seed=5), 3), dict(n_workers=256)),
+    ("banded_40k_cm_phases", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
+     dict(n_workers=256, level_order="cm", exec_mode="phases")),
     ("batch_family_irregular", lambda: matgen.batch_family(2, 102), dict(n_workers=4)),
     ("batch_family_irregular_b1024", lambda: matgen.batch_family(5, 105), dict(n_workers=30, block_threads=1024)),
 ]

@@ -36,7 +36,8 @@ def test_exports_every_declared_symbol():
 def _oracle(m, nt, **kw):
     return S.build_schedule(m.n, m.row_ptr, m.col, nt, eps=kw.get("eps", S.DEFAULT_EPS),
                             balance=kw.get("balance", "nnz"), max_stages=kw.get("max_stages", 4),
-                            global_lb=kw.get("global_lb", False))
+                            global_lb=kw.get("global_lb", False), root=kw.get("root", "first"),
+                            level_order=kw.get("level_order", "input"))
 
 
 def _compare(m, nt, **kw):
@@ -73,6 +74,14 @@ CASES = [
     ("rand_nodiag", lambda: matgen.random_symmetric(300, 0.02, seed=9, with_diag=False), 12, {}),
     ("one_row", lambda: matgen.UpperCSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.ones(1)), 4, {}),
     ("empty", lambda: matgen.UpperCSR(0, np.array([0], np.int32), np.array([], np.int32), np.zeros(0)), 4, {}),
+    # stage-0 root and in-level order (pseudo-peripheral root, Cuthill-McKee numbering)
+    ("3d27pt_14_relabel_peripheral_cm", lambda: matgen.relabel(matgen.stencil3d_27pt(14, seed=4), 3), 64,
+     dict(root="peripheral", level_order="cm")),
+    ("3d27pt_14_relabel_peripheral", lambda: matgen.relabel(matgen.stencil3d_27pt(14, seed=4), 3), 64,
+     dict(root="peripheral")),
+    ("banded_30k_cm", lambda: matgen.banded_irregular(30000, seed=6, band=3000), 256, dict(level_order="cm")),
+    ("rand_islands_peripheral_cm", lambda: matgen.random_symmetric(400, 0.003, seed=8), 16,
+     dict(root="peripheral", level_order="cm", global_lb=True)),
 ]
 
 
@@ -198,6 +207,12 @@ def test_error_codes():
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params(window_max=100000)
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params()
+    p.root_mode = 2
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params()
+    p.level_order = -1
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params(block_threads=100)
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params()
@@ -237,7 +252,12 @@ def _fuzz_case(seed):
     eps0 = float(rng.choice([0.5, 0.6, 0.7, 0.8, 0.9]))
     kw = dict(eps=(eps0, float(rng.choice([0.5, 0.8])), 0.5), balance=str(rng.choice(["nnz", "rows"])),
               max_stages=int(rng.integers(1, 6)), global_lb=bool(rng.integers(2)))
-    return m, int(rng.choice([2, 5, 8, 16, 32, 64, 128, 256])), kw
+    nt = int(rng.choice([2, 5, 8, 16, 32, 64, 128, 256]))
+    kw["root"] = str(rng.choice(["first", "first", "peripheral"]))
+    kw["level_order"] = str(rng.choice(["input", "input", "cm"]))
+    if rng.integers(4) == 0:
+        m = matgen.relabel(m, seed)
+    return m, nt, kw
 
 
 @pytest.mark.parametrize("seed", range(150))

@@ -268,3 +268,140 @@ def test_trivial_inputs():
               matgen.stencil2d_5pt(2, seed=3)]:
         sch = S.build_schedule(m.n, m.row_ptr, m.col, 4)
         _check(m, sch)
+
+
+# ---------------------------------------------------------------------------
+# Stage-0 root and in-level numbering (pseudo-peripheral root, Cuthill-McKee)
+
+def _graph(n, edges):
+    """Upper CSR (unit values, unit diagonal) of an undirected edge list."""
+    rows, cols = [], []
+    for i in range(n):
+        rows.append(i)
+        cols.append(i)
+    for a, b in edges:
+        rows.append(min(a, b))
+        cols.append(max(a, b))
+    rows, cols = np.array(rows), np.array(cols)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return matgen.UpperCSR(n, rp, cols.astype(np.int32), np.ones(len(cols)))
+
+
+def _ecc_all(ptr, idx, n):
+    """Eccentricity of every vertex by one BFS each (brute force)."""
+    out = np.zeros(n, dtype=np.int64)
+    for v in range(n):
+        dist = np.full(n, -1)
+        dist[v] = 0
+        q = [v]
+        for u in q:
+            for w in idx[ptr[u]:ptr[u + 1]]:
+                if dist[w] < 0:
+                    dist[w] = dist[u] + 1
+                    q.append(int(w))
+        out[v] = dist.max()
+    return out
+
+
+def test_pseudo_peripheral_path_and_grid():
+    # a path from its middle: the finder ends at an end vertex (eccentricity n - 1)
+    n = 11
+    m = _graph(n, [(i, i + 1) for i in range(n - 1)])
+    ptr, idx = S.full_adjacency(m.n, m.row_ptr, m.col)
+    assert S.pseudo_peripheral(ptr, idx, 5, n) in (0, n - 1)
+    # a 2D grid from its centre: a corner (the diameter is reached)
+    side = 9
+    m = matgen.stencil2d_5pt(side)
+    ptr, idx = S.full_adjacency(m.n, m.row_ptr, m.col)
+    x = S.pseudo_peripheral(ptr, idx, (side // 2) * side + side // 2, m.n)
+    assert x in (0, side - 1, side * (side - 1), side * side - 1)
+
+
+def test_pseudo_peripheral_trees_reach_the_diameter():
+    # on a tree, a farthest vertex of any vertex is peripheral, so the finder
+    # reaches the diameter exactly
+    rng = np.random.default_rng(3)
+    for t in range(20):
+        n = int(rng.integers(2, 60))
+        edges = [(i, int(rng.integers(0, i))) for i in range(1, n)]
+        m = _graph(n, edges)
+        ptr, idx = S.full_adjacency(m.n, m.row_ptr, m.col)
+        ecc = _ecc_all(ptr, idx, n)
+        start = int(rng.integers(0, n))
+        x = S.pseudo_peripheral(ptr, idx, start, n)
+        assert ecc[x] == ecc.max(), t
+
+
+def test_pseudo_peripheral_never_worse_than_the_start():
+    rng = np.random.default_rng(4)
+    for t in range(20):
+        m = matgen.random_symmetric(int(rng.integers(5, 80)), 0.08, seed=100 + t)
+        ptr, idx = S.full_adjacency(m.n, m.row_ptr, m.col)
+        ecc = _ecc_all(ptr, idx, m.n)
+        start = int(rng.integers(0, m.n))
+        x = S.pseudo_peripheral(ptr, idx, start, m.n)
+        dist, _ = S.level_structure(ptr, idx, start, m.n)
+        assert dist[x] >= 0                      # same component
+        assert ecc[start] <= ecc[x] <= ecc[dist >= 0].max()
+
+
+def _check_cm_numbering(ptr, idx, n, lev, order):
+    """Cuthill-McKee properties, checked from the definition: levels never
+    decrease along the numbering; a vertex's parent (its lowest-numbered
+    neighbour one level up) is numbered no later than the parent of the next
+    vertex of the same island; children of one parent come by
+    non-decreasing degree, equal degrees by index."""
+    num = np.empty(n, dtype=np.int64)
+    num[order] = np.arange(n)
+    deg = np.diff(ptr)
+    assert sorted(order.tolist()) == list(range(n))
+    prev = None
+    for v in order.tolist():
+        up = [int(u) for u in idx[ptr[v]:ptr[v + 1]] if lev[u] == lev[v] - 1]
+        parent = min(up, key=lambda u: num[u]) if up else None
+        if prev is not None:
+            pv, pp = prev
+            assert lev[v] >= lev[pv] or parent is None
+            if parent is not None and pp is not None:
+                assert num[parent] >= num[pp]
+                if parent == pp:
+                    assert (deg[v], v) > (deg[pv], pv)
+        prev = (v, parent)
+
+
+def test_cuthill_mckee_numbering_properties():
+    for m in (matgen.stencil2d_5pt(12), matgen.relabel(matgen.stencil2d_5pt(12), 5),
+              matgen.random_symmetric(300, 0.01, seed=6), matgen.relabel(matgen.stencil3d_27pt(7, seed=2), 8)):
+        ptr, idx = S.full_adjacency(m.n, m.row_ptr, m.col)
+        for root_of in (None, lambda v: S.pseudo_peripheral(ptr, idx, v, m.n)):
+            lev, order = S.cuthill_mckee_levels(ptr, idx, m.n, root_of)
+            ref = levels_full(m) if root_of is None else None
+            if ref is not None:
+                assert np.array_equal(lev, ref)   # the same BFS levels as the input-order build
+            _check_cm_numbering(ptr, idx, m.n, lev, order)
+
+
+def test_cuthill_mckee_restores_a_banded_order():
+    # a randomly relabelled path or grid gets its bandwidth back
+    for m0, bw_max in ((_graph(40, [(i, i + 1) for i in range(39)]), 1), (matgen.stencil2d_5pt(15), 15)):
+        m = matgen.relabel(m0, 9)
+        ptr, idx = S.full_adjacency(m.n, m.row_ptr, m.col)
+        _, order = S.cuthill_mckee_levels(ptr, idx, m.n, lambda v: S.pseudo_peripheral(ptr, idx, v, m.n))
+        num = np.empty(m.n, dtype=np.int64)
+        num[order] = np.arange(m.n)
+        rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+        bw = int(np.abs(num[rows] - num[m.col]).max())
+        bw_rand = int(np.abs(rows - m.col).max())
+        assert bw <= bw_max < bw_rand, (bw, bw_rand)
+
+
+def test_root_and_order_schedules_pass_the_checker():
+    for root in ("first", "peripheral"):
+        for lo in ("input", "cm"):
+            m = matgen.relabel(matgen.stencil3d_27pt(9, seed=3), 4)
+            sch = S.build_schedule(m.n, m.row_ptr, m.col, 16, root=root, level_order=lo)
+            C.check_schedule(m.n, m.row_ptr, m.col, sch.perm, [nd.lo for nd in sch.nodes], [nd.hi for nd in sch.nodes],
+                             [nd.color for nd in sch.nodes], [nd.parent for nd in sch.nodes], sch.leaves, sch.leaf_phase)
