@@ -473,7 +473,8 @@ def main():
         same = (tr.get("source_hash") == kernel_source_hash() and tr.get("bytes_kernel") == st["bytes_kernel"]
                 and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
                 and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode
-                and tr.get("shared_atomics", 0) == args.shared_atomics)
+                and tr.get("shared_atomics", 0) == args.shared_atomics and tr.get("root", "first") == args.root
+                and tr.get("level_order", "input") == args.level_order)
         if same and args.value_type == "f64":
             traffic = tr.get("bytes_per_launch")
 

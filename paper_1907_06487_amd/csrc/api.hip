@@ -267,12 +267,14 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     const int64_t vb = prm.value_type == 1 ? 4 : 8;
     // slices: value + 2-byte slot per element; per lane: slot + diagonal;
     // per slice: offset + length; per unit: 4 ints; halo: index;
-    // x: own rows + halo read once; y: own rows + halo written, RMW and
-    // atomic touches read; cleared entries: index read, zero written.
+    // unit descriptors (32 B), conflict edges (index and flag), x: own rows
+    // + halo read once; y: own rows + halo written, RMW and atomic touches
+    // read; cleared entries: index read, zero written.
     st.shared_touches = L.shared_touches;
     st.n_zeroed = static_cast<int64_t>(L.zero_idx.size());
     st.bytes_kernel = st.sell_elems * (vb + 2) + static_cast<int64_t>(st.n_chunks) * (8 + race::kSlice * (2 + vb)) +
-                      static_cast<int64_t>(st.n_units) * 16 + st.halo_total * 4 +
+                      static_cast<int64_t>(st.n_units) * 32 + static_cast<int64_t>(L.dep_idx.size()) * 8 +
+                      st.halo_total * 4 +
                       (static_cast<int64_t>(n) + 15) / 16 * 4 +
                       8 * (static_cast<int64_t>(n) + st.halo_total) + 8 * (static_cast<int64_t>(n) + st.halo_total) +
                       8 * (st.rows_rmw + st.halo_rmw + st.shared_touches) + 12 * st.n_zeroed;
