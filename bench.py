@@ -299,6 +299,65 @@ def run_learned_ab(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_complex(args, torch):
+    """Complex SymmSpMV (complex symmetric, or Hermitian with c128h) on the
+    workload's pattern: values a*(1 + 0.5i) + i*N(0, 1) (seeded), one JSON
+    line.  A complex multiply-add is 8 real flops; the CRS minimum moves
+    20 B per stored upper entry (16 value + 4 column), 36 B per row (x read,
+    y written, row pointer) and 4 more."""
+    import numpy as np
+
+    import paper_1907_06487_amd as R
+    from oracle import symmspmv as O
+    herm = args.value_type == "c128h"
+    m, desc = workload(args.workload)
+    rng = np.random.default_rng(21)
+    vals = m.val * (1 + 0.5j) + 1j * rng.standard_normal(m.nnz)
+    s = R.Schedule(m.n, m.row_ptr, m.col, vals, n_workers=args.n_workers, max_stages=args.max_stages,
+                   block_threads=args.block, window_max=args.window, value_type=args.value_type, root=args.root,
+                   level_order=args.level_order)
+    st = s.stats()
+    dev = torch.device("cuda:0")
+    nring = max(2, -(-RING_BYTES // (16 * m.n)))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4321)
+    xs = [torch.complex(torch.rand(m.n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1,
+                        torch.rand(m.n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1) for _ in range(nring)]
+    ys = [torch.empty_like(xs[0]) for _ in range(nring)]
+    # correctness in input order against the complex oracle
+    x0 = xs[0].cpu().numpy()
+    perm = s.perm()
+    xo = np.empty(m.n, dtype=np.complex128)
+    xo[perm] = x0
+    s.spmv(xs[0], ys[0])
+    torch.cuda.synchronize()
+    s.check()
+    ref = O.symm_spmv_complex(m.n, m.row_ptr, m.col, vals, xo, herm)[perm]
+    got = ys[0].cpu().numpy()
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    ms = time_ring(lambda x, y: s.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
+    s.check()
+    flops = 8 * st["nnz_full"]
+    bytes_min = 20 * st["nnz_upper"] + 36 * m.n + 4
+    achieved = bytes_min / (ms * 1e-3) / 1e9
+    log(f"complex {'Hermitian' if herm else 'symmetric'} {args.workload}: {ms * 1e3:.2f} us/product, "
+        f"{flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, {achieved:.1f} GB/s algorithmic, error {err:.2e}")
+    out = {
+        "metric": "complex SymmSpMV GFLOP/s (8 flop per complex multiply-add)",
+        "value": round(flops / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "hermitian": herm, "n": m.n,
+                   "nnz_upper": m.nnz, "n_workers": args.n_workers, "block_threads": args.block,
+                   "window_max": args.window, "units": st["n_units"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_min},
+        "error": {"norm": err},
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,7 +368,7 @@ def main():
     ap.add_argument("--max-stages", type=int, default=4)
     ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--window", type=int, default=3840)
-    ap.add_argument("--value-type", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--value-type", default="f64", choices=["f64", "f32", "c128", "c128h"])
     ap.add_argument("--exec-mode", default="flow", choices=["flow", "phases"])
     ap.add_argument("--shared-atomics", type=int, default=1, choices=[0, 1],
                     help="units of one leaf run concurrently, combining shared y entries atomically (1) or in order (0)")
@@ -348,6 +407,9 @@ def main():
         return
     if args.workload == "learned_ab":
         run_learned_ab(args, torch)
+        return
+    if args.value_type.startswith("c"):
+        run_complex(args, torch)
         return
     if args.spmm_k:
         m, _ = workload(args.workload)

@@ -56,7 +56,11 @@ typedef struct {
                             BFS level is cut into window-sized pieces, each piece's predicted cost is shared among
                             its rows in proportion to 1 + their stored off-diagonals */
   int32_t global_lb;     /* 1: run Algorithm "Load Balancing" over all children after the pair split */
-  int32_t value_type;    /* 0: float64 matrix values, 1: float32 values (promoted; FP64 accumulation) */
+  int32_t value_type;    /* 0: float64 matrix values, 1: float32 values (promoted; FP64 accumulation),
+                            2: complex symmetric (a_ji = a_ij), 3: complex Hermitian (a_ji = conj(a_ij)); complex
+                            values are float64 (re, im) pairs, the diagonal is used as stored, and products run in
+                            the dataflow mode with one right-hand side (x and y hold n interleaved (re, im) pairs;
+                            race_permute moves them with k = 2); a unit window needs 36 B of LDS per entry */
   int32_t window_max;    /* max LDS window entries (rows + halo) of one unit, 2..8000; 0 = 3840 (20 B of LDS each per
                             right-hand side pair of x/y plus the index) */
   int32_t block_threads; /* workgroup size of the RACE kernel: 64, 128, 256, 512 or 1024; 0 = 256 */
@@ -125,7 +129,8 @@ typedef struct {
 int race_params_default(race_params* p);
 
 /* Build the RACE schedule and the kernel's data layout on the host.
- * n: rows; row_ptr (n+1), col (nnz), val (nnz): host, the upper triangle in
+ * n: rows; row_ptr (n+1), col (nnz), val (nnz; 2 nnz interleaved (re, im)
+ * for complex value types): host, the upper triangle in
  * CRS, columns strictly ascending within a row and >= the row (the diagonal,
  * when stored, is the row's first entry); val may be NULL (pattern only: the
  * schedule can be inspected but not uploaded).  Disconnected matrices are
@@ -176,7 +181,8 @@ int race_schedule_units(race_schedule_t s, int32_t* n_units, int64_t* n_halo, in
 int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx);
 
 /* y = A x (Algorithm "SymmSpMV"): x, y device float64 arrays of n in
- * permuted order, y overwritten (no clearing needed), x and y must not
+ * permuted order (n (re, im) pairs for complex values; the paper notes that
+ * the method covers complex matrices), y overwritten (no clearing needed), x and y must not
  * overlap.  exec_mode 0: one launch per non-empty phase on `stream`, in
  * phase order; exec_mode 1: one persistent launch in which every unit waits
  * only for the earlier units whose touch sets meet its own.  Products on

@@ -7,6 +7,10 @@ A[r, c] * x[c] to y[r] (the gather) and A[r, c] * x[r] to y[c] (the
 scatter); the diagonal contributes once.  The full-matrix CRS SpMV of
 Section 3.1 (Algorithm "SpMV") is the yardstick.
 
+Complex values (complex symmetric or Hermitian) follow the same
+algorithm with a_ij or conj(a_ij) in the scatter: ``symm_spmv_complex_loop``
+and ``symm_spmv_complex``.
+
 Three independent renderings of the same definition:
 
 * ``symm_spmv_loop``  -- the serial algorithm, pure Python (small inputs);
@@ -95,6 +99,49 @@ def errors(y, y_ref, absprod=None):
             r = np.where(a > 0, d / np.where(a > 0, a, 1.0), np.where(d > 0, np.inf, 0.0))
         err_comp = float(np.max(r, initial=0.0))
     return err_norm, err_comp
+
+
+# --- complex values -----------------------------------------------------------
+#
+# The paper notes that the method carries over to complex matrices.  With
+# only the upper triangle U stored, the full matrix is U + U^T - diag(U)
+# when it is complex symmetric (a_ji = a_ij) and U + U^H - diag(U) when it is
+# Hermitian (a_ji = conj(a_ij)); the scatter of the serial algorithm then
+# uses a_ij or conj(a_ij).  The diagonal is used as stored.
+
+def symm_spmv_complex_loop(n, row_ptr, col, val, x, hermitian):
+    """The serial algorithm for complex values (pure Python, small inputs)."""
+    b = [0j] * n
+    for row in range(n):
+        start, end = int(row_ptr[row]), int(row_ptr[row + 1])
+        xr = complex(x[row])
+        if start < end and int(col[start]) == row:
+            b[row] += complex(val[start]) * xr
+            start += 1
+        tmp = 0j
+        for idx in range(start, end):
+            c = int(col[idx])
+            a = complex(val[idx])
+            tmp += a * complex(x[c])
+            b[c] += (a.conjugate() if hermitian else a) * xr
+        b[row] += tmp
+    return np.array(b, dtype=np.complex128)
+
+
+def symm_spmv_complex(n, row_ptr, col, val, x, hermitian):
+    """y = (U + U^T - diag(U)) x, or (U + U^H - conj(diag(U))) x when hermitian
+    (the stored diagonal either way)."""
+    u = sp.csr_matrix((np.asarray(val, dtype=np.complex128), np.asarray(col), np.asarray(row_ptr)), shape=(n, n))
+    d = u.diagonal()
+    x = np.asarray(x, dtype=np.complex128)
+    low = u.conj().T if hermitian else u.T
+    # low repeats the diagonal (conjugated when hermitian): take that copy out
+    return u @ x + low @ x - (np.conj(d) if hermitian else d) * x
+
+
+def abs_product_complex(n, row_ptr, col, val, x):
+    """(|A| |x|) for complex values: the rounding scale of any order."""
+    return symm_spmv(n, row_ptr, col, np.abs(np.asarray(val)), np.abs(np.asarray(x)))
 
 
 # --- the plain C serial algorithm ------------------------------------------

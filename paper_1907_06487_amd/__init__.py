@@ -34,7 +34,7 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.max_stages = int(max_stages)
     p.balance_by = BALANCE[balance]
     p.global_lb = int(bool(global_lb))
-    p.value_type = {"f64": 0, "f32": 1}[value_type]
+    p.value_type = {"f64": 0, "f32": 1, "c128": 2, "c128h": 3}[value_type]
     p.window_max = int(window_max)
     p.block_threads = int(block_threads)
     p.exec_mode = {"phases": 0, "flow": 1}[exec_mode]
@@ -120,6 +120,8 @@ class Schedule:
 
     def permute(self, inp, out, to_permuted=True, stream=None):
         k = inp.shape[1] if inp.dim() == 2 else 1
+        if inp.is_complex():  # (re, im) pairs move as two columns
+            k *= 2
         race_permute(self.handle, k, inp, out, to_permuted, stream)
 
     def close(self):

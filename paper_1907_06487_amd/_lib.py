@@ -182,7 +182,12 @@ def race_params_default():
 def race_build_schedule(n, row_ptr, col, val, params=None):
     """Host CRS arrays (upper triangle); returns an opaque handle (c_void_p)."""
     rp, c = _i32(row_ptr), _i32(col)
-    v = None if val is None else np.ascontiguousarray(val, dtype=np.float64)
+    if val is None:
+        v = None
+    elif np.iscomplexobj(val):  # complex values go over as interleaved (re, im) pairs
+        v = np.ascontiguousarray(val, dtype=np.complex128).view(np.float64)
+    else:
+        v = np.ascontiguousarray(val, dtype=np.float64)
     h = _P()
     p = params if params is not None else race_params_default()
     check(lib().race_build_schedule(int(n), _np_ptr(rp, ctypes.c_int32), _np_ptr(c, ctypes.c_int32),

@@ -101,6 +101,7 @@ struct race_schedule {
   DevBuf<uint16_t> lane_slot, sell_slot;
   DevBuf<double> lane_diag64, sell_val64;
   DevBuf<float> lane_diag32, sell_val32;
+  DevBuf<race::Cplx<false>> lane_diagc, sell_valc;  // complex values (value_type 2 or 3)
   DevBuf<double> tiles_x, tiles_y;  // column tiles of X and Y for products with many passes (grown on demand)
 
   void free_device() {
@@ -108,7 +109,7 @@ struct race_schedule {
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
-    release(sell_val32); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
+    release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
     uploaded = false;
   }
 };
@@ -187,7 +188,10 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     return fail(RACE_EINVAL, "balance_by must be 0 (nonzeros), 1 (rows) or 2 (cost model)");
   if (prm.balance_by == 2 && (!prm.cost_model || prm.cost_model_len != race::kMlpParams))
     return fail(RACE_EINVAL, "balance_by 2 needs cost_model with RACE_MLP_PARAMS floats");
-  if (prm.value_type < 0 || prm.value_type > 1) return fail(RACE_EINVAL, "value_type must be 0 or 1");
+  if (prm.value_type < 0 || prm.value_type > 3) return fail(RACE_EINVAL, "value_type must be in 0..3");
+  const bool cplx = prm.value_type >= 2;
+  if (cplx && prm.exec_mode != 1)
+    return fail(RACE_EUNSUPPORTED, "complex values run in the dataflow mode (exec_mode 1) only");
   if (prm.exec_mode < 0 || prm.exec_mode > 1) return fail(RACE_EINVAL, "exec_mode must be 0 or 1");
   if (prm.shared_atomics < 0 || prm.shared_atomics > 1) return fail(RACE_EINVAL, "shared_atomics must be 0 or 1");
   if (prm.rhs_tile < 0 || prm.rhs_tile > 16) return fail(RACE_EINVAL, "rhs_tile must be in 0..16");
@@ -228,8 +232,20 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
       return fail(RACE_EINVAL, err);
     }
     int code = RACE_OK;
-    err = race::build_layout(n, row_ptr, col, val, s->tree, prm.window_max, prm.value_type, prm.shared_atomics != 0,
-                             s->L, &code);
+    // complex values arrive as interleaved (re, im) pairs
+    std::vector<double> v_re, v_im;
+    if (cplx && val) {
+      const int64_t nnz = row_ptr[n];
+      v_re.resize(static_cast<size_t>(nnz));
+      v_im.resize(static_cast<size_t>(nnz));
+      for (int64_t i = 0; i < nnz; ++i) {
+        v_re[i] = val[2 * i];
+        v_im[i] = val[2 * i + 1];
+      }
+    }
+    err = race::build_layout(n, row_ptr, col, cplx ? (val ? v_re.data() : nullptr) : val,
+                             cplx ? (val ? v_im.data() : nullptr) : nullptr, s->tree, prm.window_max, prm.value_type,
+                             prm.shared_atomics != 0, s->L, &code);
     if (!err.empty()) {
       delete s;
       return fail(code, err);
@@ -264,7 +280,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     st.rows_rmw = L.rows_rmw;
     st.halo_rmw = L.halo_rmw;
     st.bytes_min = 12 * st.nnz_upper + 20 * static_cast<int64_t>(n) + 4;
-    const int64_t vb = prm.value_type == 1 ? 4 : 8;
+    const int64_t vb = prm.value_type == 1 ? 4 : (cplx ? 16 : 8);
     // slices: value + 2-byte slot per element; per lane: slot + diagonal;
     // per slice: offset + length; per unit: 4 ints; halo: index;
     // unit descriptors (32 B), conflict edges (index and flag), x: own rows
@@ -346,6 +362,12 @@ int race_schedule_upload(race_schedule_t s) {
   if (s->params.value_type == 0) {
     UP(lane_diag64, L.lane_diag)
     UP(sell_val64, L.sell_val)
+  } else if (s->params.value_type >= 2) {
+    std::vector<race::Cplx<false>> dc(L.lane_diag.size()), vc(L.sell_val.size());
+    for (size_t i = 0; i < dc.size(); ++i) dc[i] = {L.lane_diag[i], L.lane_diag_im[i]};
+    for (size_t i = 0; i < vc.size(); ++i) vc[i] = {L.sell_val[i], L.sell_val_im[i]};
+    UP(lane_diagc, dc)
+    UP(sell_valc, vc)
   } else {
     std::vector<float> d32(L.lane_diag.begin(), L.lane_diag.end());
     std::vector<float> v32(L.sell_val.begin(), L.sell_val.end());
@@ -472,8 +494,12 @@ int race_schedule_flow_grid(race_schedule_t s, int32_t k, int32_t* grid) {
   if (e != hipSuccess) return hip_fail(e, "device query");
   const int32_t wmax = std::max(1, s->L.max_window);
   int32_t per_cu = 0;
-  e = s->params.value_type == 0 ? race::race_flow_occupancy<double>(k, s->params.block_threads, wmax, &per_cu)
-                                : race::race_flow_occupancy<float>(k, s->params.block_threads, wmax, &per_cu);
+  if (s->params.value_type >= 2)  // a complex product: one vector, two columns
+    e = k == 1 ? race::race_flow_occupancy<race::Cplx<false>>(2, s->params.block_threads, wmax, &per_cu)
+               : hipErrorInvalidValue;
+  else
+    e = s->params.value_type == 0 ? race::race_flow_occupancy<double>(k, s->params.block_threads, wmax, &per_cu)
+                                  : race::race_flow_occupancy<float>(k, s->params.block_threads, wmax, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   const int32_t n_units = static_cast<int32_t>(s->L.unit_lo.size());
   *grid = std::max(1, std::min(n_units, per_cu * cus));
@@ -611,6 +637,20 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
   if (s->tree.n == 0) return RACE_OK;
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
+  if (s->params.value_type >= 2) {
+    // complex: one vector of n interleaved (re, im) pairs, run as two columns
+    if (k != 1) return fail(RACE_EUNSUPPORTED, "complex values take one right-hand side");
+    if (rhs_tile(s, 2) < 2)
+      return fail(RACE_EUNSUPPORTED, "a complex unit window does not fit the LDS; rebuild with a smaller window_max");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->params.value_type == 2) {
+      const auto a = unit_args<race::Cplx<false>>(s, s->lane_diagc.p, s->sell_valc.p);
+      return run_flow<race::Cplx<false>>(s, a, 2, x, y, 2, trace, st);
+    }
+    const auto a = unit_args<race::Cplx<true>>(s, reinterpret_cast<const race::Cplx<true>*>(s->lane_diagc.p),
+                                               reinterpret_cast<const race::Cplx<true>*>(s->sell_valc.p));
+    return run_flow<race::Cplx<true>>(s, a, 2, x, y, 2, trace, st);
+  }
   const int32_t kt = rhs_tile(s, k);
   if (kt < 1) return fail(RACE_EUNSUPPORTED, "a unit window does not fit the LDS; rebuild with a smaller window_max");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -813,6 +853,7 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   for (int32_t m = 0; m < count; ++m) {
     if (!s[m] || !s[m]->uploaded) return fail(RACE_ESTATE, "every schedule must be uploaded");
     if (s[m]->device != dev) return fail(RACE_EINVAL, "schedules live on different devices");
+    if (s[m]->params.value_type >= 2) return fail(RACE_EUNSUPPORTED, "batches take real values only");
     if (vt >= 0 && s[m]->params.value_type != vt) return fail(RACE_EINVAL, "schedules mix value types");
     vt = s[m]->params.value_type;
     threads = std::max(threads, s[m]->params.block_threads);

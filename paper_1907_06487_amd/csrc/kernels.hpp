@@ -7,6 +7,14 @@
 
 namespace race {
 
+// A complex matrix value (real and imaginary part).  kHermitian: the
+// matrix is Hermitian (a_ji = conj(a_ij)), else complex symmetric
+// (a_ji = a_ij); only the upper triangle is stored either way.
+template <bool kHermitian>
+struct alignas(16) Cplx {
+  double re, im;
+};
+
 // One unit's index ranges, read by a workgroup with a single scalar load:
 // own rows [lo, hi), halo list [h0, h1), slices [c0, c1) and conflict edges
 // [d0, d1) (indices into the dataflow edge list).
@@ -125,6 +133,8 @@ hipError_t launch_race_flow(const UnitArgs<ValT>& a, const FlowArgs& f, int32_t 
 
 template <typename ValT>
 hipError_t race_flow_occupancy(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu);
+// ValT = Cplx<...>: x and y hold n complex values as interleaved (re, im)
+// pairs, so k must be 2 (the two parts) and ld 2.
 
 // Kernel attributes of the batch kernel (call once before stream capture).
 template <typename ValT>

@@ -9,7 +9,7 @@
 namespace race {
 
 static void permute_upper(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                          const std::vector<int32_t>& perm, Layout& L) {
+                          const double* val_im, const std::vector<int32_t>& perm, Layout& L) {
   std::vector<int32_t> old2new(static_cast<size_t>(n));
   for (int32_t i = 0; i < n; ++i) old2new[perm[i]] = i;
   const int64_t nnz = row_ptr[n];
@@ -22,6 +22,7 @@ static void permute_upper(int32_t n, const int32_t* row_ptr, const int32_t* col,
   for (int32_t i = 0; i < n; ++i) L.prow_ptr[i + 1] += L.prow_ptr[i];
   L.pcol.resize(static_cast<size_t>(nnz));
   L.pval.resize(static_cast<size_t>(nnz));
+  if (val_im) L.pval_im.resize(static_cast<size_t>(nnz));
   std::vector<int32_t> fill(L.prow_ptr.begin(), L.prow_ptr.end() - 1);
   for (int32_t r = 0; r < n; ++r)
     for (int32_t i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
@@ -30,24 +31,33 @@ static void permute_upper(int32_t n, const int32_t* row_ptr, const int32_t* col,
       const int32_t at = fill[lo]++;
       L.pcol[at] = hi;
       L.pval[at] = val ? val[i] : 0.0;
+      // a Hermitian entry that lands below the diagonal is stored as its
+      // mirror above it, which holds the conjugate
+      if (val_im) L.pval_im[at] = (L.value_type == 3 && a > b) ? -val_im[i] : val_im[i];
     }
-  std::vector<std::pair<int32_t, double>> tmp;
+  struct Entry {
+    int32_t c;
+    double v, w;
+  };
+  std::vector<Entry> tmp;
   L.n_diag = 0;
   for (int32_t r = 0; r < n; ++r) {
     const int32_t s = L.prow_ptr[r], e = L.prow_ptr[r + 1];
     tmp.clear();
-    for (int32_t i = s; i < e; ++i) tmp.emplace_back(L.pcol[i], L.pval[i]);
-    std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (int32_t i = s; i < e; ++i) tmp.push_back({L.pcol[i], L.pval[i], val_im ? L.pval_im[i] : 0.0});
+    std::sort(tmp.begin(), tmp.end(), [](const Entry& x, const Entry& y) { return x.c < y.c; });
     for (int32_t i = s; i < e; ++i) {
-      L.pcol[i] = tmp[i - s].first;
-      L.pval[i] = tmp[i - s].second;
+      L.pcol[i] = tmp[i - s].c;
+      L.pval[i] = tmp[i - s].v;
+      if (val_im) L.pval_im[i] = tmp[i - s].w;
     }
     if (s < e && L.pcol[s] == r) ++L.n_diag;
   }
 }
 
-std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, const Tree& tree,
-                         int32_t window_max, int32_t value_type, bool shared_atomics, Layout& L, int* code) {
+std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                         const double* val_im, const Tree& tree, int32_t window_max, int32_t value_type,
+                         bool shared_atomics, Layout& L, int* code) {
   *code = RACE_OK;
   L = Layout();
   if (n >= (1 << 30)) {
@@ -56,7 +66,7 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
   }
   L.n = n;
   L.value_type = value_type;
-  permute_upper(n, row_ptr, col, val, tree.perm, L);
+  permute_upper(n, row_ptr, col, val, val_im, tree.perm, L);
   const std::vector<int32_t>& rp = L.prow_ptr;
   const std::vector<int32_t>& pc = L.pcol;
 
@@ -147,29 +157,35 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
         L.chunk_off.push_back(static_cast<uint32_t>(elems));
         L.chunk_len.push_back(len | (cn << 16));
         const size_t base = L.sell_val.size();
+        const bool cplx = !L.pval_im.empty();
         L.sell_val.resize(base + static_cast<size_t>(len) * cn, 0.0);
+        if (cplx) L.sell_val_im.resize(base + static_cast<size_t>(len) * cn, 0.0);
         L.sell_slot.resize(base + static_cast<size_t>(len) * cn, 0);
         for (int32_t l = 0; l < kSlice; ++l) {
           if (l >= cn) {
             L.lane_slot.push_back(kNoRow);
             L.lane_diag.push_back(0.0);
+            if (cplx) L.lane_diag_im.push_back(0.0);
             continue;
           }
           const int32_t r = rows_sorted[c0 + l];
           const uint16_t own = static_cast<uint16_t>(r - a);
           L.lane_slot.push_back(own);
           int32_t i = rp[r];
-          double d = 0.0;
+          double d = 0.0, d_im = 0.0;
           if (i < rp[r + 1] && pc[i] == r) {
             d = L.pval[i];
+            if (cplx) d_im = L.pval_im[i];
             ++i;
           }
           L.lane_diag.push_back(d);
+          if (cplx) L.lane_diag_im.push_back(d_im);
           int32_t j = 0;
           for (; i < rp[r + 1]; ++i, ++j) {
             const int32_t c = pc[i];
             const int32_t s = c < b ? c - a : slot_of[c];
             L.sell_val[base + static_cast<size_t>(j) * cn + l] = L.pval[i];
+            if (cplx) L.sell_val_im[base + static_cast<size_t>(j) * cn + l] = L.pval_im[i];
             L.sell_slot[base + static_cast<size_t>(j) * cn + l] = static_cast<uint16_t>(s);
           }
           for (; j < len; ++j) L.sell_slot[base + static_cast<size_t>(j) * cn + l] = own;

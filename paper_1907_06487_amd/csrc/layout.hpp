@@ -42,6 +42,7 @@ struct Layout {
   // upper(P A P^T): CRS, columns ascending
   std::vector<int32_t> prow_ptr, pcol;
   std::vector<double> pval;
+  std::vector<double> pval_im;  // imaginary parts (complex values only, else empty)
   int64_t n_diag = 0;
 
   // execution structure
@@ -61,6 +62,7 @@ struct Layout {
   std::vector<uint16_t> lane_slot;      // n_chunks * 64: window slot of each lane's row
   std::vector<double> lane_diag;        // n_chunks * 64: diagonal of that row (0 if none)
   std::vector<double> sell_val;         // padded slice elements
+  std::vector<double> lane_diag_im, sell_val_im;  // imaginary parts (complex values only, else empty)
   std::vector<uint16_t> sell_slot;
   std::vector<int32_t> phase_max_window;  // per phase, largest unit window
   // conflict edges for dataflow execution: unit u waits for dep_idx[dep_ptr[u]
@@ -82,7 +84,9 @@ inline uint32_t row_flag(const std::vector<uint32_t>& f, int32_t r) {
 // RACE_E* code for errors (RACE_EUNSUPPORTED when a single row does not fit
 // the window or n >= 2^30, RACE_EINTERNAL when units of two leaves of one
 // phase would touch one index).
-std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, const Tree& tree,
-                         int32_t window_max, int32_t value_type, bool shared_atomics, Layout& out, int* code);
+// val_im: imaginary parts of the values (complex matrices), else NULL.
+std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                         const double* val_im, const Tree& tree, int32_t window_max, int32_t value_type,
+                         bool shared_atomics, Layout& out, int* code);
 
 }  // namespace race

@@ -16,8 +16,47 @@ constexpr uint16_t kNoRow = 0xFFFF;
 // each, so a batch of 24 costs what 16 FP64 values do
 template <typename ValT>
 struct BatchSize {
-  static constexpr int value = sizeof(ValT) == 4 ? 24 : 16;
+  static constexpr int value = sizeof(ValT) == 4 ? 24 : (sizeof(ValT) == 8 ? 16 : 8);
 };
+
+// A value as a lane holds it in registers: real values in double, complex
+// ones as they are; zero test and the zero of each type.
+template <typename ValT>
+struct RegOf {
+  using type = double;
+};
+template <bool H>
+struct RegOf<Cplx<H>> {
+  using type = Cplx<H>;
+};
+__device__ __forceinline__ double to_reg(double v) { return v; }
+__device__ __forceinline__ double to_reg(float v) { return static_cast<double>(v); }
+template <bool H>
+__device__ __forceinline__ Cplx<H> to_reg(Cplx<H> v) { return v; }
+template <typename ValT>
+__device__ __forceinline__ ValT zero_value() { return ValT(0); }
+template <>
+__device__ __forceinline__ Cplx<false> zero_value<Cplx<false>>() { return Cplx<false>{0.0, 0.0}; }
+template <>
+__device__ __forceinline__ Cplx<true> zero_value<Cplx<true>>() { return Cplx<true>{0.0, 0.0}; }
+__device__ __forceinline__ bool nonzero(double v) { return v != 0.0; }
+__device__ __forceinline__ bool nonzero(float v) { return v != 0.0f; }
+template <bool H>
+__device__ __forceinline__ bool nonzero(Cplx<H> v) { return v.re != 0.0 || v.im != 0.0; }
+
+// acc = diag * x_r: per column for real values; one complex product (the
+// two columns are the real and imaginary part) for complex ones
+template <int K>
+__device__ __forceinline__ void init_acc(double d, const double (&xr)[K], double (&acc)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = d * xr[k];
+}
+template <int K, bool H>
+__device__ __forceinline__ void init_acc(Cplx<H> d, const double (&xr)[K], double (&acc)[K]) {
+  static_assert(K == 2, "complex values take two columns");
+  acc[0] = d.re * xr[0] - d.im * xr[1];
+  acc[1] = d.re * xr[1] + d.im * xr[0];
+}
 constexpr uint32_t kSpinLimit = 1u << 16;  // bounded wait (milliseconds), then report and go on
 
 // Load of a layout word that no kernel writes, at an index that is the same
@@ -43,7 +82,7 @@ struct SliceRegs {
   int32_t len = 0, width = 0;
   uint32_t off = 0;
   uint16_t rs = kNoRow;
-  double d = 0.0;
+  typename RegOf<ValT>::type d{};
   ValT v[kBatch];
   int32_t sl[kBatch];
 };
@@ -56,7 +95,7 @@ __device__ __forceinline__ void load_slice_head(const UnitArgs<ValT>& a, int32_t
   r.width = meta >> 16;
   r.off = uniform_load(a.chunk_off, c);
   r.rs = a.lane_slot[static_cast<size_t>(c) * kSlice + lane];
-  r.d = static_cast<double>(a.lane_diag[static_cast<size_t>(c) * kSlice + lane]);
+  r.d = to_reg(a.lane_diag[static_cast<size_t>(c) * kSlice + lane]);
 }
 
 // Loads entries j0 .. j0 + kBatch - 1 of every lane's row.  The bound on j
@@ -78,7 +117,7 @@ __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane
       r.v[b] = *reinterpret_cast<const ValT*>(vp + e * static_cast<uint32_t>(sizeof(ValT)));
       r.sl[b] = *reinterpret_cast<const uint16_t*>(sp + e * 2u);
     } else {
-      r.v[b] = ValT(0);
+      r.v[b] = zero_value<ValT>();
       r.sl[b] = r.rs;
     }
   }
@@ -123,6 +162,27 @@ __device__ __forceinline__ void apply_batch(const ValT* v, const int32_t* sl, co
         acc[k] += vb * (nz ? xg[b][k] : 0.0);
         atomicAdd(&yw[sl[g + b] * K + k], nz ? vb * xr[k] : 0.0);
       }
+    }
+  }
+}
+
+// Complex values: the columns are the real and imaginary part of x and y.
+// The gather takes a_rj x_j, the scatter a_jr x_r with a_jr = a_rj
+// (complex symmetric) or conj(a_rj) (Hermitian).
+template <int K, int B, bool H>
+__device__ __forceinline__ void apply_batch(const Cplx<H>* v, const int32_t* sl, const double* xw, double* yw,
+                                            const double (&xr)[K], double (&acc)[K]) {
+  static_assert(K == 2, "complex values take two columns");
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    if (nonzero(v[b])) {
+      const double re = v[b].re, im = v[b].im;
+      const double xj_re = xw[sl[b] * 2], xj_im = xw[sl[b] * 2 + 1];
+      acc[0] += re * xj_re - im * xj_im;
+      acc[1] += re * xj_im + im * xj_re;
+      const double sim = H ? -im : im;
+      atomicAdd(&yw[sl[b] * 2], re * xr[0] - sim * xr[1]);
+      atomicAdd(&yw[sl[b] * 2 + 1], re * xr[1] + sim * xr[0]);
     }
   }
 }
@@ -236,10 +296,8 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const Unit
     if (cur.rs != kNoRow) {
       double xr[K], acc[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        xr[k] = xw[cur.rs * K + k];
-        acc[k] = cur.d * xr[k];
-      }
+      for (int k = 0; k < K; ++k) xr[k] = xw[cur.rs * K + k];
+      init_acc<K>(cur.d, xr, acc);
       constexpr int B = SliceRegs<ValT>::kBatch;
       apply_batch<K, B>(cur.v, cur.sl, xw, yw, xr, acc);
       for (int32_t j0 = B; j0 < cur.len; j0 += B) {
@@ -254,7 +312,7 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const Unit
       cur.width = meta_n >> 16;
       cur.off = off_n;
       cur.rs = rs_n;
-      cur.d = static_cast<double>(d_n);
+      cur.d = to_reg(d_n);
       load_batch(a, lane, 0, cur);
     }
     c = cn;
@@ -924,6 +982,33 @@ template hipError_t launch_race_flow<float>(const UnitArgs<float>&, const FlowAr
                                             int32_t, int32_t, int32_t, int32_t, uint32_t, uint64_t, hipStream_t);
 template hipError_t race_flow_occupancy<double>(int32_t, int32_t, int32_t, int32_t*);
 template hipError_t race_flow_occupancy<float>(int32_t, int32_t, int32_t, int32_t*);
+
+// Complex values: one instantiation, the two columns being the real and
+// imaginary part of x and y.
+template <>
+hipError_t launch_race_flow<Cplx<false>>(const UnitArgs<Cplx<false>>& a, const FlowArgs& f, int32_t k,
+                                         const double* x, double* y, int32_t ld, int32_t wmax, int32_t threads,
+                                         int32_t grid, uint32_t epoch, uint64_t ticket_base, hipStream_t st) {
+  if (k != 2) return hipErrorInvalidValue;
+  return launch_flow<Cplx<false>, 2>(a, f, x, y, ld, wmax, threads, grid, epoch, ticket_base, st);
+}
+template <>
+hipError_t launch_race_flow<Cplx<true>>(const UnitArgs<Cplx<true>>& a, const FlowArgs& f, int32_t k,
+                                        const double* x, double* y, int32_t ld, int32_t wmax, int32_t threads,
+                                        int32_t grid, uint32_t epoch, uint64_t ticket_base, hipStream_t st) {
+  if (k != 2) return hipErrorInvalidValue;
+  return launch_flow<Cplx<true>, 2>(a, f, x, y, ld, wmax, threads, grid, epoch, ticket_base, st);
+}
+template <>
+hipError_t race_flow_occupancy<Cplx<false>>(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu) {
+  if (k != 2) return hipErrorInvalidValue;
+  return flow_occupancy<Cplx<false>, 2>(threads, wmax, blocks_per_cu);
+}
+template <>
+hipError_t race_flow_occupancy<Cplx<true>>(int32_t k, int32_t threads, int32_t wmax, int32_t* blocks_per_cu) {
+  if (k != 2) return hipErrorInvalidValue;
+  return flow_occupancy<Cplx<true>, 2>(threads, wmax, blocks_per_cu);
+}
 
 template <typename ValT, int K>
 struct BatchTag {};

@@ -429,6 +429,66 @@ def test_flow_late_workgroups_taken_over(stride, shared):
         s.close()
 
 
+COMPLEX = [
+    ("3d27pt_24", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256, window_max=2176)),
+    ("3d27pt_24_w3840", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256, block_threads=512)),
+    ("banded_40k", lambda: matgen.banded_irregular(40000, seed=6, band=4000), dict(n_workers=256, window_max=2176)),
+    ("banded_40k_w96", lambda: matgen.banded_irregular(40000, seed=6, band=4000), dict(n_workers=16, window_max=96)),
+    ("rand_islands", lambda: matgen.random_symmetric(500, 0.003, seed=8), dict(n_workers=16)),
+    ("rand_nodiag", lambda: matgen.random_symmetric(300, 0.02, seed=9, with_diag=False), dict(n_workers=12)),
+]
+
+
+@pytest.mark.parametrize("hermitian", [False, True], ids=["symmetric", "hermitian"])
+@pytest.mark.parametrize("name,make,params", COMPLEX, ids=[c[0] for c in COMPLEX])
+def test_race_complex(name, make, params, hermitian):
+    """Complex symmetric and Hermitian matrices against the complex oracle:
+    normwise within 1e-12, componentwise within the summation bound of
+    |A||x| (a complex product adds two real products per part)."""
+    m = make()
+    rng = np.random.default_rng(77)
+    vals = m.val * (1 + 0.5j) + 1j * rng.standard_normal(m.nnz)
+    x = rng.standard_normal(m.n) + 1j * rng.standard_normal(m.n)
+    print(f"case complex {name} hermitian={hermitian}: n={m.n} nnz={m.nnz} {params}", flush=True)
+    s = R.Schedule(m.n, m.row_ptr, m.col, vals, value_type="c128h" if hermitian else "c128", **params)
+    try:
+        xd = torch.as_tensor(x, device=DEV)
+        xp = torch.empty_like(xd)
+        yp = torch.full_like(xd, complex(float("nan"), float("nan")))
+        y = torch.empty_like(xd)
+        s.permute(xd, xp, to_permuted=True)
+        s.spmv(xp, yp)
+        s.permute(yp, y, to_permuted=False)
+        torch.cuda.synchronize()
+        s.check()
+        got = y.cpu().numpy()
+    finally:
+        s.close()
+    ref = O.symm_spmv_complex(m.n, m.row_ptr, m.col, vals, x, hermitian)
+    scale = O.abs_product_complex(m.n, m.row_ptr, m.col, vals, x)
+    err = np.abs(got - ref)
+    en = float(err.max() / np.abs(ref).max())
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ec = float(np.max(np.where(scale > 0, err / scale, 0.0)))
+    bound = 4 * gamma(2 * (_full_row_len(m) + 1))
+    print(f"[complex {name}] err_norm={en:.3e} err_comp={ec:.3e} (bound {bound:.3e})", flush=True)
+    assert en <= 1e-12 and ec <= bound
+
+
+def test_complex_unsupported_paths():
+    m = matgen.stencil3d_27pt(8, seed=2)
+    vc = m.val + 0.5j
+    s = R.Schedule(m.n, m.row_ptr, m.col, vc, value_type="c128", n_workers=32, window_max=2176)
+    try:
+        X = torch.zeros(m.n, 3, dtype=torch.complex128, device=DEV)
+        with pytest.raises(R.RaceError):
+            s.spmm(X, torch.empty_like(X))
+        with pytest.raises(R.RaceError):
+            R.Batch([s], 1)
+    finally:
+        s.close()
+
+
 def test_product_fuzz():
     """Seeded random matrices and parameters (window, workgroup size,
     execution mode, shared atomics, value type, right-hand sides) against the

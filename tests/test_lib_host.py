@@ -272,3 +272,25 @@ def test_schedule_fuzz_bit_exact_and_valid(seed):
         C.check_schedule(m.n, m.row_ptr, m.col, s.perm(), tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase)
     finally:
         s.close()
+
+
+def test_complex_schedules_host():
+    """Complex value types build on the host (same schedule as real values)
+    and refuse the modes that take real values only."""
+    m = matgen.stencil3d_27pt(8, seed=2)
+    vc = m.val + 1j * np.linspace(-1, 1, m.nnz)
+    s_r = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, n_workers=32, window_max=2176)
+    for vt in ("c128", "c128h"):
+        s = R.Schedule(m.n, m.row_ptr, m.col, vc, upload=False, n_workers=32, value_type=vt, window_max=2176)
+        try:
+            assert np.array_equal(s.perm(), s_r.perm())
+            assert s.stats()["n_units"] == s_r.stats()["n_units"]
+            assert s.stats()["bytes_kernel"] > s_r.stats()["bytes_kernel"]
+        finally:
+            s.close()
+    s_r.close()
+    p = R.make_params(value_type="c128", exec_mode="phases")
+    _expect(-4, lambda: R.race_build_schedule(m.n, m.row_ptr, m.col, vc, p))
+    p = R.make_params()
+    p.value_type = 4
+    _expect(-1, lambda: R.race_build_schedule(m.n, m.row_ptr, m.col, m.val, p))

@@ -152,3 +152,58 @@ def test_error_metrics():
     en, ec = O.errors(y, y_ref, np.array([1.0, 1.0, 2.0]))
     assert en == pytest.approx(2e-13 / 4.0)
     assert ec == pytest.approx(1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Complex values (complex symmetric and Hermitian)
+
+def _dense_upper(m, vals):
+    u = np.zeros((m.n, m.n), dtype=np.complex128)
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    u[rows, m.col] = vals
+    return u
+
+
+def _complex_case(seed, n=40):
+    m = matgen.random_symmetric(n, 0.15, seed=seed)
+    rng = np.random.default_rng(seed)
+    vals = m.val + 1j * rng.standard_normal(m.nnz)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return m, vals, x
+
+
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_complex_loop_and_sparse_match_dense(hermitian):
+    """Both complex renderings equal the dense product of the assembled
+    matrix: A = U + U^T - D (complex symmetric) or U + U^H - conj(D) with the
+    stored diagonal D (Hermitian), numpy's matmul as the library routine."""
+    for seed in range(5):
+        m, vals, x = _complex_case(30 + seed)
+        u = _dense_upper(m, vals)
+        d = np.diag(np.diag(u))
+        a = u + (u.conj().T - d.conj() if hermitian else u.T - d)
+        ref = a @ x
+        for y in (O.symm_spmv_complex_loop(m.n, m.row_ptr, m.col, vals, x, hermitian),
+                  O.symm_spmv_complex(m.n, m.row_ptr, m.col, vals, x, hermitian)):
+            assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_complex_properties():
+    m, vals, x = _complex_case(7)
+    # real values: both complex forms reduce to the real product
+    xr = np.real(x)
+    for h in (False, True):
+        y = O.symm_spmv_complex(m.n, m.row_ptr, m.col, m.val.astype(np.complex128), xr, h)
+        assert np.abs(y - O.symm_spmv(m.n, m.row_ptr, m.col, m.val, xr)).max() <= 1e-13 * np.abs(y).max()
+    # a Hermitian matrix with a real diagonal: x^H A x is real
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    herm_vals = np.where(rows == m.col, np.real(vals), vals)
+    q = np.vdot(x, O.symm_spmv_complex(m.n, m.row_ptr, m.col, herm_vals, x, True))
+    assert abs(q.imag) <= 1e-12 * abs(q)
+    # the transpose identity of a complex symmetric matrix: y^T (A x) = x^T (A y)
+    z = np.random.default_rng(8).standard_normal(m.n) + 1j
+    ax = O.symm_spmv_complex(m.n, m.row_ptr, m.col, vals, x, False)
+    az = O.symm_spmv_complex(m.n, m.row_ptr, m.col, vals, z, False)
+    assert abs(z @ ax - x @ az) <= 1e-12 * abs(z @ ax)
+    # the two kinds differ once off-diagonal values have imaginary parts
+    assert np.abs(O.symm_spmv_complex(m.n, m.row_ptr, m.col, vals, x, True) - ax).max() > 1e-3
