@@ -389,8 +389,8 @@ def main():
                     help="n_workers:block[:window[:mode[:shared]]] list, e.g. 256:256,512:512:2048:phases:0 (stderr)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
-              "not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is described "
+              "as a design, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -38,7 +38,7 @@ extern "C" {
 #define RACE_EINVAL (-1)       /* malformed input: bad CRS, bad sizes, NULL pointers */
 #define RACE_ENOMEM (-2)       /* host or device allocation failed */
 #define RACE_EHIP (-3)         /* a HIP runtime call failed (message holds hipGetErrorString) */
-#define RACE_EUNSUPPORTED (-4) /* valid input this build cannot run (dist_k != 2, a row whose window does not fit, k > 16) */
+#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (dist_k != 2, a row whose window does not fit, k > 16) */
 #define RACE_ESTATE (-5)       /* wrong object state (e.g. product before race_schedule_upload) */
 #define RACE_EINTERNAL (-6)    /* an internal consistency check failed (e.g. two concurrent units touch one index) */
 

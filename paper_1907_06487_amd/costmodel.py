@@ -12,7 +12,7 @@ The trained network then
   * picks the efficiency parameters eps_0, eps_1, the recursion depth and
     N_t (Section 5 tunes these by hand) by the predicted makespan of each
     candidate schedule (race_schedule_simulate).
-The nonzero heuristic is the fallback and the judge: the same candidates
+The nonzero heuristic is the fallback and the yardstick: the same candidates
 scored with unit cost = stored entries give the choice the method makes
 without the network.
 
