@@ -376,6 +376,7 @@ def main():
                     help="stage-0 BFS root of every island: its first vertex or a pseudo-peripheral one")
     ap.add_argument("--level-order", default="input", choices=["input", "cm"],
                     help="stage-0 order inside a level: input order or Cuthill-McKee numbering")
+    ap.add_argument("--dist-k", type=int, default=2, help="distance of the coloring (2 for SymmSpMV; 3..8 wider)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
@@ -424,7 +425,7 @@ def main():
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
                    block_threads=args.block, window_max=args.window, value_type=args.value_type,
                    exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics), root=args.root,
-                   level_order=args.level_order)
+                   level_order=args.level_order, dist_k=args.dist_k)
     t_build = time.perf_counter() - t0
     st = s.stats()
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
@@ -536,7 +537,7 @@ def main():
                 and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
                 and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode
                 and tr.get("shared_atomics", 0) == args.shared_atomics and tr.get("root", "first") == args.root
-                and tr.get("level_order", "input") == args.level_order)
+                and tr.get("level_order", "input") == args.level_order and args.dist_k == 2)
         if same and args.value_type == "f64":
             traffic = tr.get("bytes_per_launch")
 
@@ -547,7 +548,8 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_upper": m.nnz,
                    "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
                    "window_max": args.window, "exec_mode": args.exec_mode, "shared_atomics": args.shared_atomics,
-                   "root": args.root, "level_order": args.level_order, "levels0": st["n_levels0"],
+                   "root": args.root, "level_order": args.level_order, "dist_k": args.dist_k,
+                   "levels0": st["n_levels0"],
                    "phases": st["n_phases_used"], "leaves": st["n_leaves"], "eta": st["eta"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

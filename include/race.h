@@ -38,7 +38,7 @@ extern "C" {
 #define RACE_EINVAL (-1)       /* malformed input: bad CRS, bad sizes, NULL pointers */
 #define RACE_ENOMEM (-2)       /* host or device allocation failed */
 #define RACE_EHIP (-3)         /* a HIP runtime call failed (message holds hipGetErrorString) */
-#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (dist_k != 2, a row whose window does not fit, k > 16) */
+#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (dist_k = 1, a row whose window does not fit, k > 16) */
 #define RACE_ESTATE (-5)       /* wrong object state (e.g. product before race_schedule_upload) */
 #define RACE_EINTERNAL (-6)    /* an internal consistency check failed (e.g. two concurrent units touch one index) */
 
@@ -49,7 +49,9 @@ typedef struct race_batch* race_batch_t;
 /* Parameters of the schedule (Section 5: {eps_s}, N_t; Section 4.3: rows or
  * nonzeros as load; Section 4.2: distance k). */
 typedef struct {
-  int32_t dist_k;        /* distance of the coloring; SymmSpMV needs 2 (the only value accepted) */
+  int32_t dist_k;        /* distance of the coloring (Section 4.2): 2 for SymmSpMV; 3..8 give wider, also
+                            race-free colorings (rows of one color at distance > k, the recursion subgraph T plus
+                            its distance-(k-1) neighbourhood) with fewer, larger level groups; 1 is refused */
   int32_t n_workers;     /* N_t: concurrent workers the tree is built for (>= 1) */
   int32_t max_stages;    /* recursion stages including stage 0 (1..16) */
   int32_t balance_by;    /* 0: nonzeros of the full row, 1: rows, 2: learned cost model (cost_model): every stage-0

@@ -100,12 +100,23 @@ def check_schedule(n, row_ptr, col, perm, node_lo, node_hi, node_color, node_par
 def check_dense_distance2(n, row_ptr, col, perm, leaf_lo, leaf_hi, leaf_phase):
     """Small N: rows of different leaves of one phase are at distance > 2 in
     the graph of A, i.e. (I + A)^2 has a zero there."""
+    return check_dense_distance_k(n, row_ptr, col, perm, leaf_lo, leaf_hi, leaf_phase, 2)
+
+
+def check_dense_distance_k(n, row_ptr, col, perm, leaf_lo, leaf_hi, leaf_phase, k):
+    """Small N: rows of different leaves of one phase are at distance > k in
+    the graph of A, i.e. (I + A)^k has a zero there (distance-k coloring,
+    Section 4.2)."""
     assert n <= 2000
     rows, cols = permuted_upper_pattern(n, row_ptr, col, perm)
-    b = np.eye(n, dtype=np.int64)
-    b[rows, cols] = 1
-    b[cols, rows] = 1
-    b2 = (b @ b) > 0
+    # float64 products (exact for these 0/1 patterns) so BLAS does the work
+    b = np.eye(n, dtype=np.float64)
+    b[rows, cols] = 1.0
+    b[cols, rows] = 1.0
+    b2 = b.copy()
+    for _ in range(k - 1):
+        b2 = ((b2 @ b) > 0).astype(np.float64)
+    b2 = b2 > 0
     owner = np.full(n, -1, dtype=np.int64)
     for t, (lo, hi) in enumerate(zip(leaf_lo, leaf_hi)):
         owner[lo:hi] = t
@@ -114,5 +125,5 @@ def check_dense_distance2(n, row_ptr, col, perm, leaf_lo, leaf_hi, leaf_phase):
         phase_of_row[lo:hi] = leaf_phase[t]
     i, j = np.nonzero(b2)
     bad = (owner[i] != owner[j]) & (phase_of_row[i] == phase_of_row[j])
-    assert not np.any(bad), f"{int(bad.sum())} distance-2 pairs share a phase across leaves"
+    assert not np.any(bad), f"{int(bad.sum())} distance-{k} pairs share a phase across leaves"
     return True

@@ -155,11 +155,18 @@ def _neighbors(ptr, idx, frontier):
     return idx[base + np.arange(total, dtype=np.int64)]
 
 
-def subgraph_vertices(ptr, idx, members):
-    """Vertices of the recursion subgraph of a group T: T and its distance-1
-    neighbourhood N(T), so no vertex outside can link two of T's vertices
-    at distance 2 (Section 4.4.2)."""
-    return np.concatenate([members, _neighbors(ptr, idx, members)])
+def subgraph_vertices(ptr, idx, members, k=2):
+    """Vertices of the recursion subgraph of a group T: T and every vertex
+    within distance k - 1 of it, so no vertex outside can link two of T's
+    vertices at distance k (Section 4.4.2; for k = 2 the distance-1
+    neighbourhood N(T))."""
+    seen = np.unique(np.asarray(members, dtype=np.int64))
+    frontier = seen
+    for _ in range(k - 1):
+        nb = np.unique(_neighbors(ptr, idx, frontier))
+        frontier = np.setdiff1d(nb, seen, assume_unique=True)
+        seen = np.union1d(seen, frontier)
+    return seen
 
 
 def level_structure(ptr, idx, root, n):
@@ -457,8 +464,8 @@ def load_balance(t_ptr, worker, m_levels, k):
 
 def build_schedule(n, row_ptr, col, n_t, eps=DEFAULT_EPS, k=2, balance="nnz", max_stages=4,
                    global_lb=False, root="first", level_order="input"):
-    if k != 2:
-        raise ValueError("SymmSpMV needs distance-2 coloring (k = 2)")
+    if not 1 <= k <= 8:
+        raise ValueError("k must be in 1..8 (SymmSpMV needs k >= 2)")
     if root not in ("first", "peripheral"):
         raise ValueError("root must be 'first' or 'peripheral'")
     if level_order not in ("input", "cm"):
@@ -480,7 +487,7 @@ def build_schedule(n, row_ptr, col, n_t, eps=DEFAULT_EPS, k=2, balance="nnz", ma
         if hi - lo == 0:
             return
         members = perm[lo:hi].copy()
-        sub = None if node.stage < 0 else subgraph_vertices(ptr, idx, members)
+        sub = None if node.stage < 0 else subgraph_vertices(ptr, idx, members, k)
         if sub is None:
             in_sub[:] = True
         else:

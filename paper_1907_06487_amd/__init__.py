@@ -23,13 +23,14 @@ BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
-                shared_atomics=True, cost_model=None, rhs_tile=0, root="first", level_order="input"):
+                shared_atomics=True, cost_model=None, rhs_tile=0, root="first", level_order="input", dist_k=2):
     """race_params from keywords.  balance="model" needs cost_model: the
     network's MLP_PARAMS float32 weights (kept alive on the returned struct).
     root: "first" (stage-0 islands start at their first vertex in the input
     order) or "peripheral" (at a pseudo-peripheral vertex).  level_order:
     "input" or "cm" (Cuthill-McKee discovery order inside stage-0 levels)."""
     p = race_params_default()
+    p.dist_k = int(dist_k)
     p.n_workers = int(n_workers)
     p.max_stages = int(max_stages)
     p.balance_by = BALANCE[balance]

@@ -181,7 +181,9 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   race_params prm;
   if (p) prm = *p;
   else race_params_default(&prm);
-  if (prm.dist_k != 2) return fail(RACE_EUNSUPPORTED, "only distance-2 coloring (dist_k = 2) is implemented");
+  if (prm.dist_k < 1 || prm.dist_k > 8) return fail(RACE_EINVAL, "dist_k must be in 1..8");
+  if (prm.dist_k < 2)
+    return fail(RACE_EUNSUPPORTED, "SymmSpMV needs a distance-2 (or wider) coloring: dist_k >= 2");
   if (prm.n_workers < 1) return fail(RACE_EINVAL, "n_workers must be >= 1");
   if (prm.max_stages < 1 || prm.max_stages > 16) return fail(RACE_EINVAL, "max_stages must be in 1..16");
   if (prm.balance_by < 0 || prm.balance_by > 2)

@@ -404,13 +404,22 @@ struct Builder {
     std::vector<int32_t> lev;
     const bool all = stage < 0;
     if (!all) {
+      // the recursion subgraph: T and every vertex within distance k - 1 of
+      // it, so no outside vertex can join two of T's vertices at distance k
       sub_list.clear();
-      for (int32_t v : members) {
+      for (int32_t v : members)
         if (!in_sub[v]) { in_sub[v] = 1; sub_list.push_back(v); }
-        for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
-          const int32_t u = g.adj[e];
-          if (!in_sub[u]) { in_sub[u] = 1; sub_list.push_back(u); }
+      size_t f0 = 0;
+      for (int32_t d = 1; d < p.dist_k; ++d) {
+        const size_t f1 = sub_list.size();
+        for (size_t q = f0; q < f1; ++q) {
+          const int32_t v = sub_list[q];
+          for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
+            const int32_t u = g.adj[e];
+            if (!in_sub[u]) { in_sub[u] = 1; sub_list.push_back(u); }
+          }
         }
+        f0 = f1;
       }
     }
     if (all) {
@@ -466,7 +475,7 @@ struct Builder {
 }  // namespace
 
 std::string build_tree(const Graph& g, const std::vector<int64_t>& row_load, const TreeParams& p, Tree& out) {
-  if (p.dist_k != 2) return "dist_k must be 2 for SymmSpMV";
+  if (p.dist_k < 1 || p.dist_k > 8) return "dist_k must be in 1..8";
   if (p.n_workers < 1) return "n_workers must be >= 1";
   if (p.max_stages < 1 || p.max_stages > 16) return "max_stages must be in 1..16";
   Builder bld(g, row_load, p);

@@ -106,6 +106,9 @@ SMALL = [
     ("3d27pt_24_relabel", lambda: matgen.relabel(matgen.stencil3d_27pt(24, seed=5), 3), dict(n_workers=256)),
     ("banded_40k_cm_phases", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
      dict(n_workers=256, level_order="cm", exec_mode="phases")),
+    # wider colorings (distance 3 and 4): still race-free, fewer groups
+    ("3d27pt_24_k3", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256, dist_k=3)),
+    ("banded_40k_k4", lambda: matgen.banded_irregular(40000, seed=6, band=4000), dict(n_workers=256, dist_k=4)),
     ("batch_family_irregular", lambda: matgen.batch_family(2, 102), dict(n_workers=4)),
     ("batch_family_irregular_b1024", lambda: matgen.batch_family(5, 105), dict(n_workers=30, block_threads=1024)),
 ]

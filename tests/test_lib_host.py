@@ -37,7 +37,7 @@ def _oracle(m, nt, **kw):
     return S.build_schedule(m.n, m.row_ptr, m.col, nt, eps=kw.get("eps", S.DEFAULT_EPS),
                             balance=kw.get("balance", "nnz"), max_stages=kw.get("max_stages", 4),
                             global_lb=kw.get("global_lb", False), root=kw.get("root", "first"),
-                            level_order=kw.get("level_order", "input"))
+                            level_order=kw.get("level_order", "input"), k=kw.get("dist_k", 2))
 
 
 def _compare(m, nt, **kw):
@@ -82,6 +82,11 @@ CASES = [
     ("banded_30k_cm", lambda: matgen.banded_irregular(30000, seed=6, band=3000), 256, dict(level_order="cm")),
     ("rand_islands_peripheral_cm", lambda: matgen.random_symmetric(400, 0.003, seed=8), 16,
      dict(root="peripheral", level_order="cm", global_lb=True)),
+    # wider colorings (distance 3 and 4)
+    ("2d5pt_100_k3", matgen.config_2d_small, 64, dict(dist_k=3)),
+    ("3d27pt_20_k3", lambda: matgen.stencil3d_27pt(20, seed=4), 128, dict(dist_k=3)),
+    ("banded_30k_k4_global", lambda: matgen.banded_irregular(30000, seed=6, band=3000), 256,
+     dict(dist_k=4, global_lb=True)),
 ]
 
 
@@ -207,6 +212,8 @@ def test_error_codes():
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params(window_max=100000)
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params(dist_k=9)
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params()
     p.root_mode = 2
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
@@ -255,6 +262,7 @@ def _fuzz_case(seed):
     nt = int(rng.choice([2, 5, 8, 16, 32, 64, 128, 256]))
     kw["root"] = str(rng.choice(["first", "first", "peripheral"]))
     kw["level_order"] = str(rng.choice(["input", "input", "cm"]))
+    kw["dist_k"] = int(rng.choice([2, 2, 2, 3, 4]))
     if rng.integers(4) == 0:
         m = matgen.relabel(m, seed)
     return m, nt, kw
@@ -270,6 +278,9 @@ def test_schedule_fuzz_bit_exact_and_valid(seed):
         tr = s.tree()
         node, phase = s.leaves()
         C.check_schedule(m.n, m.row_ptr, m.col, s.perm(), tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase)
+        if kw["dist_k"] > 2 and m.n <= 2000:
+            lo, hi = np.asarray(tr["lo"])[node], np.asarray(tr["hi"])[node]
+            C.check_dense_distance_k(m.n, m.row_ptr, m.col, s.perm(), lo, hi, phase, kw["dist_k"])
     finally:
         s.close()
 

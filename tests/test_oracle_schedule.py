@@ -223,7 +223,7 @@ def test_checker_rejects_planted_conflicts():
     orig = S.subgraph_vertices
     caught = 0
     try:
-        S.subgraph_vertices = lambda ptr, idx, members: members
+        S.subgraph_vertices = lambda ptr, idx, members, k=2: members
         for seed in range(4):
             g = matgen.banded_irregular(3000, seed=100 + seed, band=300)
             bad = S.build_schedule(g.n, g.row_ptr, g.col, 32)
@@ -405,3 +405,51 @@ def test_root_and_order_schedules_pass_the_checker():
             sch = S.build_schedule(m.n, m.row_ptr, m.col, 16, root=root, level_order=lo)
             C.check_schedule(m.n, m.row_ptr, m.col, sch.perm, [nd.lo for nd in sch.nodes], [nd.hi for nd in sch.nodes],
                              [nd.color for nd in sch.nodes], [nd.parent for nd in sch.nodes], sch.leaves, sch.leaf_phase)
+
+
+# ---------------------------------------------------------------------------
+# Distance-k colorings, k >= 3 (Section 4.2): wider, still race-free
+
+def _leaf_ranges(sch):
+    return [sch.nodes[i].lo for i in sch.leaves], [sch.nodes[i].hi for i in sch.leaves]
+
+
+@pytest.mark.parametrize("k", [1, 3, 4])
+def test_distance_k_schedules_pass_the_dense_check(k):
+    """Rows of different leaves of one phase are more than k apart ((I+A)^k
+    has zeros there); for k >= 2 the touch-set checks hold as well."""
+    for m in (matgen.stencil2d_5pt(30), matgen.random_symmetric(600, 0.005, seed=4),
+              matgen.banded_irregular(1500, seed=5, band=120), matgen.stencil3d_27pt(9, seed=2)):
+        sch = S.build_schedule(m.n, m.row_ptr, m.col, 32, k=k)
+        lo, hi = _leaf_ranges(sch)
+        C.check_dense_distance_k(m.n, m.row_ptr, m.col, sch.perm, lo, hi, sch.leaf_phase, k)
+        if k >= 2:
+            _check(m, sch)
+
+
+def test_distance_k_recursion_needs_the_subgraph():
+    """Recursing on the group T alone (no neighbourhood) lets two rows of a
+    group meet within distance k through outside vertices; the dense
+    distance-3 check catches it (planted in the oracle), and the correct
+    recursion passes on the same inputs.  (A path of length k between two
+    vertices of T runs within distance floor(k/2) of one of them, so the
+    distance-(k-1) neighbourhood the recursion uses is more than enough.)"""
+    orig = S.subgraph_vertices
+    caught = 0
+    mats = [matgen.banded_irregular(1500, seed=100 + s, band=60) for s in range(6)]
+    try:
+        S.subgraph_vertices = lambda ptr, idx, members, k=2: members
+        for g in mats:
+            bad = S.build_schedule(g.n, g.row_ptr, g.col, 64, k=3)
+            lo, hi = _leaf_ranges(bad)
+            try:
+                C.check_dense_distance_k(g.n, g.row_ptr, g.col, bad.perm, lo, hi, bad.leaf_phase, 3)
+            except AssertionError:
+                caught += 1
+    finally:
+        S.subgraph_vertices = orig
+    assert caught > 0
+    for g in mats:
+        sch = S.build_schedule(g.n, g.row_ptr, g.col, 64, k=3)
+        lo, hi = _leaf_ranges(sch)
+        C.check_dense_distance_k(g.n, g.row_ptr, g.col, sch.perm, lo, hi, sch.leaf_phase, 3)
