@@ -3,7 +3,8 @@
 * BFS levels against closed forms on grids and the edge invariant.
 * The epsilon aggregation, pair balancing, recursion and eta against the
   numbers the paper prints for its 16 x 16 example (tests/golden).
-* Load-balancing invariants (its numeric result has no printed example).
+* Load-balancing invariants (its worked examples and plants are in
+  test_oracle_loadbalance.py).
 * Every schedule passes the independent brute-force conflict checker, and the
   checker rejects planted conflicts.
 """
