@@ -56,6 +56,8 @@ def kernel_source_hash():
 
 
 def time_ring(fn, xs, ys, steps, warmup, torch):
+    """Mean milliseconds per call over `steps` calls after `warmup`, HIP
+    events on the current stream (the stream the library launches on)."""
     nr = len(xs)
     for i in range(warmup):
         fn(xs[i % nr], ys[i % nr])
@@ -70,7 +72,116 @@ def time_ring(fn, xs, ys, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps
 
 
+def time_ring_median(fn, xs, ys, steps, torch):
+    """Median milliseconds per call: an event between consecutive calls
+    (a separate pass, so the mean above has no events inside it)."""
+    import numpy as np
+    nr = len(xs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        fn(xs[i % nr], ys[(i + 1) % nr])
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
+
+
+def attainable_bandwidth(torch, gib=4, reps=10):
+    """Read-only and copy bandwidth of the library's 16-byte stream kernels
+    over 4 GiB arrays (larger than every cache), the best over a few grid
+    sizes: what a kernel can reach on this device, the input of the paper's
+    roofline bound (Table 1, Eq. upper_performance)."""
+    import paper_1907_06487_amd as R
+    dev = torch.device("cuda:0")
+    nbytes = gib << 30
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    sink = torch.zeros(4, dtype=torch.int32, device=dev)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    res = {"bytes": nbytes, "grids": {}}
+    best_r = best_c = (0.0, 0)
+    for mult in (4, 8, 16, 32):
+        grid = cus * mult
+        tr = time_ring(lambda x, y: R.race_stream_read(src, sink, grid), [0], [0], reps, 2, torch)
+        tc = time_ring(lambda x, y: R.race_stream_copy(src, dst, grid), [0], [0], reps, 2, torch)
+        rg, cg = nbytes / (tr * 1e-3) / 1e9, 2 * nbytes / (tc * 1e-3) / 1e9
+        res["grids"][grid] = {"read_GBs": round(rg, 1), "copy_GBs": round(cg, 1)}
+        best_r = max(best_r, (rg, grid))
+        best_c = max(best_c, (cg, grid))
+    assert torch.equal(src, dst)
+    res.update(read_GBs=round(best_r[0], 1), read_grid=best_r[1], copy_GBs=round(best_c[0], 1), copy_grid=best_c[1])
+    log(f"attainable bandwidth over {gib} GiB: read {best_r[0]:.0f} GB/s (grid {best_r[1]}), "
+        f"copy {best_c[0]:.0f} GB/s (grid {best_c[1]})")
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
+def host_cpu():
+    """Model name of the host CPU and the threads this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0)), os.cpu_count()
+
+
+def yardsticks(m, perm, flops, nnz_full, xs, ys, args, torch):
+    """Same-GPU baselines, each in input order and in the RACE order, the
+    best setting reported: CRS SpMV on the full matrix with 1..64 lanes per
+    row (Algorithm "SpMV"), rocSPARSE's SpMV with each of its CSR
+    algorithms on the full matrix and as its own symmetric product on the
+    upper triangle, and SymmSpMV with global atomics with 1..32 lanes per
+    row.  Inputs come from matgen's format conversions."""
+    import matgen
+    import paper_1907_06487_amd as R
+    orders = {"input": m, "race": matgen.permuted(m, perm)}
+    bytes_spmv = 12 * nnz_full + 20 * m.n + 4
+    t_all = {"crs_spmv": [], "vendor_general": [], "vendor_symmetric": [], "atomic_symmspmv": []}
+    T = lambda fn: time_ring(lambda x, y: fn(x, y), xs, ys, args.steps, args.warmup, torch)
+    for oname, mo in orders.items():
+        rp, c, v = matgen.full_crs(mo)
+        for lpr in (1, 2, 4, 8, 16, 32, 64):
+            h = R.race_csr_create(m.n, rp, c, v, lpr)
+            t_all["crs_spmv"].append((T(lambda x, y: R.race_csr_spmv(h, x, y)), {"order": oname, "lanes_per_row": lpr}))
+            R.race_csr_destroy(h)
+        for sym in (False, True):
+            for alg in ("adaptive", "rowsplit", "lrb", "nnzsplit"):
+                try:
+                    h = (R.race_vendor_create(m.n, mo.row_ptr, mo.col, mo.val, True, alg) if sym
+                         else R.race_vendor_create(m.n, rp, c, v, False, alg))
+                except R.RaceError as e:
+                    log(f"rocSPARSE {alg} symmetric={sym}: {e}")
+                    continue
+                key = "vendor_symmetric" if sym else "vendor_general"
+                t_all[key].append((T(lambda x, y: R.race_vendor_spmv(h, x, y)), {"order": oname, "alg": alg}))
+                R.race_vendor_destroy(h)
+        del rp, c, v
+        for lpr in (1, 2, 4, 8, 16, 32):
+            h = R.race_atomic_create(m.n, mo.row_ptr, mo.col, mo.val, lpr)
+            t_all["atomic_symmspmv"].append((T(lambda x, y: R.race_symm_spmv_atomic(h, x, y)),
+                                             {"order": oname, "lanes_per_row": lpr}))
+            R.race_csr_destroy(h)
+    out = {}
+    for key, runs in t_all.items():
+        for t, cfg in runs:
+            log(f"{key} {cfg}: {t * 1e3:.2f} us")
+        if not runs:
+            continue
+        t, cfg = min(runs, key=lambda r: r[0])
+        b = bytes_spmv if key in ("crs_spmv", "vendor_general") else 12 * m.nnz + 20 * m.n + 4
+        out[key] = {"us": t * 1e3, **cfg, "gflops": flops / (t * 1e-3) / 1e9,
+                    "algorithmic_GBs": b / (t * 1e-3) / 1e9, "settings_timed": len(runs)}
+    return out
+
+
 def cpu_baseline(m, budget_s):
+    """The serial C oracle on one host core, the process pinned to that
+    core while it runs: mean and median seconds per product."""
     import numpy as np
 
     import matgen
@@ -79,16 +190,22 @@ def cpu_baseline(m, budget_s):
     ob.build(force=False)
     x = matgen.rhs(m.n, 99)
     y = np.empty(m.n)
-    O.symm_spmv_c(m.n, m.row_ptr, m.col, m.val, x, y)  # warm
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        O.symm_spmv_c(m.n, m.row_ptr, m.col, m.val, x, y)
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    return dt, reps
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        O.symm_spmv_c(m.n, m.row_ptr, m.col, m.val, x, y)  # warm
+        times = []
+        t0 = time.perf_counter()
+        while True:
+            t1 = time.perf_counter()
+            O.symm_spmv_c(m.n, m.row_ptr, m.col, m.val, x, y)
+            times.append(time.perf_counter() - t1)
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, allowed)
+    return float(np.mean(times)), float(np.median(times)), len(times), core
 
 
 def run_batch(args, k, torch):
@@ -377,6 +494,9 @@ def main():
     ap.add_argument("--level-order", default="input", choices=["input", "cm"],
                     help="stage-0 order inside a level: input order or Cuthill-McKee numbering")
     ap.add_argument("--dist-k", type=int, default=2, help="distance of the coloring (2 for SymmSpMV; 3..8 wider)")
+    ap.add_argument("--global-lb", type=int, default=0, choices=[0, 1],
+                    help="also run Algorithm \"Load Balancing\" over all children of every refined node")
+    ap.add_argument("--no-attainable", action="store_true", help="skip the attainable-bandwidth measurement")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
@@ -425,7 +545,7 @@ def main():
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
                    block_threads=args.block, window_max=args.window, value_type=args.value_type,
                    exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics), root=args.root,
-                   level_order=args.level_order, dist_k=args.dist_k)
+                   level_order=args.level_order, dist_k=args.dist_k, global_lb=bool(args.global_lb))
     t_build = time.perf_counter() - t0
     st = s.stats()
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
@@ -451,6 +571,7 @@ def main():
     log(f"error vs oracle: norm {err_norm:.3e} comp {err_comp:.3e}")
 
     ms = time_ring(lambda x, y: s.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
+    ms_median = time_ring_median(lambda x, y: s.spmv(x, y), xs, ys, args.steps, torch)
     s.check()
     flops = 2 * st["nnz_full"]
     gflops = flops / (ms * 1e-3) / 1e9
@@ -461,8 +582,9 @@ def main():
     # the dataflow mode is one launch (it clears shared-first entries in its
     # first tickets); the phase mode launches once per phase plus the clearing
     launches = 1 if args.exec_mode == "flow" else st["n_phases_used"] + (1 if st["n_zeroed"] else 0)
-    log(f"RACE: {ms * 1e3:.2f} us/product, {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s algorithmic "
-        f"({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes {st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
+    log(f"RACE: {ms * 1e3:.2f} us/product (median {ms_median * 1e3:.2f}), {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s "
+        f"algorithmic ({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes "
+        f"{st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
 
     for item in filter(None, args.sweep.split(",")):
         nt, blk = (int(v) for v in item.split(":")[:2])
@@ -493,39 +615,30 @@ def main():
 
     baselines = {}
     if not args.no_baselines:
-        rp, c, v = O.expand_full(m.n, m.row_ptr, m.col, m.val)
-        best = None
-        for order in ("input", "race"):
-            if order == "race":
-                import scipy.sparse as sp
-                a = sp.csr_matrix((v, c, rp), shape=(m.n, m.n))[perm][:, perm].tocsr()
-                a.sort_indices()
-                brp, bc, bv = a.indptr.astype(np.int32), a.indices.astype(np.int32), a.data
-            else:
-                brp, bc, bv = rp, c, v
-            h = R.race_csr_create(m.n, brp, bc, bv, 0)
-            t = time_ring(lambda x, y: R.race_csr_spmv(h, x, y), xs, ys, args.steps, args.warmup, torch)
-            R.race_csr_destroy(h)
-            log(f"CRS SpMV ({order} order): {t * 1e3:.2f} us")
-            if best is None or t < best[0]:
-                best = (t, order)
-        bytes_spmv = 12 * int(rp[-1]) + 20 * m.n + 4
-        baselines["crs_spmv"] = {"us": best[0] * 1e3, "order": best[1], "gflops": flops / (best[0] * 1e-3) / 1e9,
-                                 "algorithmic_GBs": bytes_spmv / (best[0] * 1e-3) / 1e9}
-        h = R.race_atomic_create(m.n, m.row_ptr, m.col, m.val)
-        t = time_ring(lambda x, y: R.race_symm_spmv_atomic(h, x, y), xs, ys, args.steps, args.warmup, torch)
-        R.race_csr_destroy(h)
-        log(f"atomic SymmSpMV (input order): {t * 1e3:.2f} us")
-        baselines["atomic_symmspmv"] = {"us": t * 1e3, "gflops": flops / (t * 1e-3) / 1e9}
-        baselines["race_speedup_vs_crs"] = best[0] / ms
+        baselines = yardsticks(m, perm, flops, st["nnz_full"], xs, ys, args, torch)
+        best = min((b["us"], k) for k, b in baselines.items() if k in ("crs_spmv", "vendor_general"))
+        baselines["best_spmv"] = best[1]
+        baselines["race_speedup_vs_best_spmv"] = best[0] / (ms * 1e3)
+        baselines["race_speedup_vs_crs"] = baselines["crs_spmv"]["us"] / (ms * 1e3)
+        if "vendor_symmetric" in baselines:
+            baselines["race_speedup_vs_vendor_symmetric"] = baselines["vendor_symmetric"]["us"] / (ms * 1e3)
+        baselines["race_speedup_vs_atomic"] = baselines["atomic_symmspmv"]["us"] / (ms * 1e3)
+        log(f"RACE vs best full-matrix SpMV ({best[1]}, {best[0]:.2f} us): {baselines['race_speedup_vs_best_spmv']:.3f}x")
+
+    attain = None
+    if not args.no_attainable:
+        attain = attainable_bandwidth(torch)
 
     cpu = None
     if not args.no_cpu:
-        dt, reps = cpu_baseline(m, args.cpu_seconds)
+        dt, dt_med, reps, core = cpu_baseline(m, args.cpu_seconds)
+        model, threads, ncpu = host_cpu()
         cpu = {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps} full products of the same matrix with the serial C oracle (-O2), "
-                         f"{dt * 1e3:.1f} ms each"}
-        log(f"CPU oracle: {dt * 1e3:.1f} ms/product ({cpu['value']:.3f} GFLOP/s)")
+                         f"{dt * 1e3:.1f} ms each (median {dt_med * 1e3:.1f} ms), one thread pinned to core {core}",
+               "median_value": flops / dt_med / 1e9, "host_cpu": model, "host_threads_allowed": threads,
+               "host_nproc": ncpu}
+        log(f"CPU oracle: {dt * 1e3:.1f} ms/product ({cpu['value']:.3f} GFLOP/s) on {model}")
 
     # HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     # runs, valid only while the kernel, layout and parameters are unchanged
@@ -554,7 +667,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "launches_per_step": launches,
-                     "bytes_per_step": bytes_alg, "kernel_format_bytes_per_step": st["bytes_kernel"]},
+                     "bytes_per_step": bytes_alg, "kernel_format_bytes_per_step": st["bytes_kernel"],
+                     "attainable_read_GBs": attain["read_GBs"] if attain else None,
+                     "attainable_copy_GBs": attain["copy_GBs"] if attain else None,
+                     "frac_of_attainable_read": round(achieved / attain["read_GBs"], 4) if attain else None,
+                     "ms_per_step_median": ms_median},
+        "schedule": {"shared_touches": st["shared_touches"], "halo_total": st["halo_total"],
+                     "units": st["n_units"], "global_lb": args.global_lb},
+        "attainable": attain,
         "error": {"norm": err_norm, "componentwise": err_comp},
         "baselines": baselines,
         "cpu_baseline": cpu,

@@ -38,7 +38,7 @@ extern "C" {
 #define RACE_EINVAL (-1)       /* malformed input: bad CRS, bad sizes, NULL pointers */
 #define RACE_ENOMEM (-2)       /* host or device allocation failed */
 #define RACE_EHIP (-3)         /* a HIP runtime call failed (message holds hipGetErrorString) */
-#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (dist_k = 1, a row whose window does not fit, k > 16) */
+#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (dist_k = 1 for SymmSpMV, a row whose window does not fit, k > 16) */
 #define RACE_ESTATE (-5)       /* wrong object state (e.g. product before race_schedule_upload) */
 #define RACE_EINTERNAL (-6)    /* an internal consistency check failed (e.g. two concurrent units touch one index) */
 
@@ -51,7 +51,10 @@ typedef struct race_batch* race_batch_t;
 typedef struct {
   int32_t dist_k;        /* distance of the coloring (Section 4.2): 2 for SymmSpMV; 3..8 give wider, also
                             race-free colorings (rows of one color at distance > k, the recursion subgraph T plus
-                            its distance-(k-1) neighbourhood) with fewer, larger level groups; 1 is refused */
+                            its distance-(k-1) neighbourhood) with fewer, larger level groups; 1 gives the
+                            distance-1 coloring of Gauss-Seidel sweeps (race_symm_gs; level groups of single
+                            levels allowed, the recursion takes the subgraph of the group alone, Section 4.4.1),
+                            on which the SymmSpMV products are refused */
   int32_t n_workers;     /* N_t: concurrent workers the tree is built for (>= 1) */
   int32_t max_stages;    /* recursion stages including stage 0 (1..16) */
   int32_t balance_by;    /* 0: nonzeros of the full row, 1: rows, 2: learned cost model (cost_model): every stage-0
@@ -139,7 +142,8 @@ int race_params_default(race_params* p);
  * accepted (islands).  *out receives a new schedule owned by the caller
  * (race_schedule_destroy).  No device is needed.
  * Errors: RACE_EINVAL for malformed CRS or parameters, RACE_EUNSUPPORTED when
- * dist_k != 2 or one row alone exceeds the window, RACE_EINTERNAL if the
+ * dist_k is 1 (SymmSpMV needs distance 2 or more; 2..8 are accepted) or one
+ * row alone exceeds the window, RACE_EINTERNAL if the
  * built-in independence check finds two concurrent units touching one index. */
 int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                         const race_params* p, race_schedule_t* out);
@@ -189,8 +193,28 @@ int race_schedule_zero_list(race_schedule_t s, int64_t* count, int32_t* idx);
  * phase order; exec_mode 1: one persistent launch in which every unit waits
  * only for the earlier units whose touch sets meet its own.  Products on
  * one schedule must be ordered (one stream, or synchronised): they share the
- * schedule's dataflow state. */
+ * schedule's dataflow state.  A dataflow product cannot be captured into a
+ * hipGraph (its epoch is a launch argument): on a capturing stream the call
+ * returns RACE_EUNSUPPORTED; race_symm_spmv_noalloc can be captured. */
 int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as race_symm_spmv in the dataflow mode (exec_mode 1, real values),
+ * with the launch's dataflow state (completion flags, ticket counter,
+ * static-ticket claims) in a fixed per-device array of 4 MiB that the
+ * library holds until the process ends, instead of the schedule's own.
+ * Allocates nothing: each call clears the part of the array it uses with a
+ * kernel on `stream`, then launches the product, so a captured graph
+ * replays correctly.  A bounded-wait failure is reported by
+ * race_schedule_check.  Every call on one device shares that device's
+ * array, which keeps the last call's contents: calls that may overlap on
+ * one device (different streams, without ordering) race and give wrong
+ * results.  Errors: RACE_EUNSUPPORTED when the schedule needs more than
+ * 2^20 words of state (units + clearing tasks + workgroups of the launch +
+ * 5), for complex values or exec_mode 0; RACE_EINVAL when the current device
+ * is not the schedule's. */
+int race_symm_spmv_noalloc(race_schedule_t s, const double* x, double* y, void* stream);
 
 /* Y = A X for k right-hand sides, X and Y device float64 row-major n x k
  * (k in 1..16), permuted order, Y overwritten.  Runs in passes of
@@ -222,6 +246,24 @@ int race_schedule_flow_takeovers(race_schedule_t s, int64_t* count);
  * launches joins about 0.2 ms late without claiming its own ticket, so
  * running workgroups take its ticket over; 0 turns this off. */
 int race_schedule_flow_test_late(race_schedule_t s, int32_t stride);
+
+/* Gauss-Seidel sweep on A x = b over a distance-1 schedule (dist_k = 1,
+ * float64 values; the paper names Gauss-Seidel as the prime user of such
+ * colorings, Sections 1 and 4.2): every row i takes
+ *     x_i <- (b_i - sum_{j != i} a_ij x_j) / a_ii
+ * with the newest x, in the schedule's order: phase by phase (colors of
+ * the level-group tree), leaves of one phase at the same time (they share
+ * no edge, so the result equals running them one after another), the rows
+ * of a leaf in ascending permuted order.  direction 0: forward sweep;
+ * 1: backward sweep (phases and rows reversed); 2: symmetric sweep
+ * (forward, then backward).  b (read) and x (updated in place): device
+ * float64 arrays of n in permuted order.  One launch per non-empty phase
+ * and direction on `stream`.  Every row needs a nonzero stored diagonal
+ * (checked by race_build_schedule, RACE_EINVAL), and every leaf's window
+ * (its rows plus the rows outside it that they read) at most 16384 entries
+ * (RACE_EUNSUPPORTED at build time: raise n_workers).  RACE_EUNSUPPORTED for
+ * a schedule with dist_k != 1. */
+int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t direction, void* stream);
 
 /* Reorder device float64 row-major n x k arrays between input order and the
  * permuted order: to_permuted != 0: out[i] = in[new2old[i]]; else
@@ -269,10 +311,35 @@ int race_csr_spmv(race_csr_t h, const double* x, double* y, void* stream);
 
 /* SymmSpMV with global float64 atomics: takes the UPPER triangle (host,
  * copied to the device); y is cleared on the stream, then every scatter and
- * every row total is an atomic add. */
-int race_atomic_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, race_csr_t* out);
+ * every row total is an atomic add.  lanes_per_row as for race_csr_create. */
+int race_atomic_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                       int32_t lanes_per_row, race_csr_t* out);
 int race_symm_spmv_atomic(race_csr_t h, const double* x, double* y, void* stream);
 void race_csr_destroy(race_csr_t h);
+
+/* Vendor SpMV (rocSPARSE) as a black-box yardstick (Section 6 compares
+ * against the best variant of the vendor library).  symmetric_upper 0: the
+ * FULL matrix in CRS, a general product; 1: the UPPER triangle of a
+ * symmetric matrix, rocSPARSE's own symmetric product.  alg: 0 adaptive,
+ * 1 row split, 2 LRB, 3 nnz split (rocSPARSE's CSR algorithms).  Host
+ * arrays are copied to the current device and analysed once here.
+ * RACE_EUNSUPPORTED when rocSPARSE does not implement that combination. */
+typedef struct race_vendor* race_vendor_t;
+int race_vendor_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                       int32_t symmetric_upper, int32_t alg, race_vendor_t* out);
+/* y = A x, device float64 arrays of n, y overwritten. */
+int race_vendor_spmv(race_vendor_t h, const double* x, double* y, void* stream);
+void race_vendor_destroy(race_vendor_t h);
+
+/* ---- attainable bandwidth (the load-only and copy measurements that feed
+ * the roofline bound, Table 1 and Eq. upper_performance) ---- */
+
+/* Read `bytes` (a multiple of 16) of device memory at src (16-byte aligned)
+ * once with 16-byte loads on `grid` workgroups of 256 threads; nothing is
+ * written except, with negligible probability, one word at sink (device). */
+int race_stream_read(const void* src, int64_t bytes, uint32_t* sink, int32_t grid, void* stream);
+/* dst = src over `bytes` (a multiple of 16; both 16-byte aligned, not overlapping). */
+int race_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* race_last_error(void);

@@ -232,3 +232,35 @@ def batch_family(index: int, seed: int) -> UpperCSR:
 
 def config_batch(count: int = 64, first_seed: int = 100) -> list[UpperCSR]:
     return [batch_family(i, first_seed + i) for i in range(count)]
+
+
+# --- format conversions for the yardsticks --------------------------------
+# (input preparation only: the same matrix in other storage, for the
+# baselines that need it)
+
+def full_crs(m: UpperCSR):
+    """The full symmetric matrix of ``m`` (both triangles, columns
+    ascending) as int32 row pointers, int32 columns and float64 values: the
+    storage a plain CRS SpMV reads."""
+    rows = np.repeat(np.arange(m.n, dtype=np.int64), np.diff(m.row_ptr))
+    cols = m.col.astype(np.int64)
+    off = rows != cols
+    r = np.concatenate([rows, cols[off]])
+    c = np.concatenate([cols, rows[off]])
+    v = np.concatenate([m.val, m.val[off]])
+    order = np.argsort(r * m.n + c, kind="stable")
+    rp = np.zeros(m.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=m.n), out=rp[1:])
+    return rp.astype(np.int32), c[order].astype(np.int32), np.ascontiguousarray(v[order])
+
+
+def permuted(m: UpperCSR, new2old: np.ndarray) -> UpperCSR:
+    """The upper triangle of P A P^T, where row i of the result is row
+    new2old[i] of ``m`` (columns ascending)."""
+    inv = np.empty(m.n, dtype=np.int64)
+    inv[np.asarray(new2old, dtype=np.int64)] = np.arange(m.n, dtype=np.int64)
+    rows = inv[np.repeat(np.arange(m.n, dtype=np.int64), np.diff(m.row_ptr))]
+    cols = inv[m.col.astype(np.int64)]
+    lo, hi = np.minimum(rows, cols), np.maximum(rows, cols)
+    order = np.argsort(lo * m.n + hi, kind="stable")
+    return _csr_from_sorted(m.n, lo[order], hi[order], m.val[order], f"{m.name}_permuted")

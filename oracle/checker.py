@@ -53,8 +53,20 @@ def _touch_counts(n, rows, cols, ranges):
     return count
 
 
-def check_schedule(n, row_ptr, col, perm, node_lo, node_hi, node_color, node_parent, leaf_ids, leaf_phase):
-    """Raise AssertionError on the first violated condition; return a summary."""
+def _edge_conflicts(n, rows, cols, ranges):
+    """Edges of the matrix graph whose two ends lie in two different ranges
+    of the given list (distance-1 dependence between them)."""
+    owner = np.full(n, -1, dtype=np.int64)
+    for t, (lo, hi) in enumerate(ranges):
+        owner[lo:hi] = t
+    a, b = owner[rows], owner[cols]
+    return int(np.count_nonzero((a >= 0) & (b >= 0) & (a != b)))
+
+
+def check_schedule(n, row_ptr, col, perm, node_lo, node_hi, node_color, node_parent, leaf_ids, leaf_phase, dist=2):
+    """Raise AssertionError on the first violated condition; return a summary.
+    dist=2: concurrent row sets have disjoint touch sets (SymmSpMV);
+    dist=1: no edge joins two concurrent row sets (Gauss-Seidel, Kaczmarz)."""
     perm = np.asarray(perm, dtype=np.int64)
     assert perm.shape == (n,) and np.array_equal(np.sort(perm), np.arange(n)), "perm is not a permutation"
     rows, cols = permuted_upper_pattern(n, row_ptr, col, perm)
@@ -85,15 +97,23 @@ def check_schedule(n, row_ptr, col, perm, node_lo, node_hi, node_color, node_par
             if j:
                 assert node_lo[c] == node_hi[ch[j - 1]], f"children of {i} are not contiguous"
         for color in (0, 1):
-            cnt = _touch_counts(n, rows, cols, [(node_lo[c], node_hi[c]) for c in ch if int(node_color[c]) == color])
-            assert cnt.max(initial=0) <= 1, f"same-color children of node {i} conflict"
+            ranges = [(node_lo[c], node_hi[c]) for c in ch if int(node_color[c]) == color]
+            if dist == 1:
+                assert _edge_conflicts(n, rows, cols, ranges) == 0, f"same-color children of node {i} share an edge"
+            else:
+                cnt = _touch_counts(n, rows, cols, ranges)
+                assert cnt.max(initial=0) <= 1, f"same-color children of node {i} conflict"
     # flattened phases
     phases = {}
     for i, ph in zip(leaf_ids, leaf_phase):
         phases.setdefault(int(ph), []).append(i)
     for ph, ids in phases.items():
-        cnt = _touch_counts(n, rows, cols, [(node_lo[i], node_hi[i]) for i in ids])
-        assert cnt.max(initial=0) <= 1, f"leaves of phase {ph} conflict"
+        ranges = [(node_lo[i], node_hi[i]) for i in ids]
+        if dist == 1:
+            assert _edge_conflicts(n, rows, cols, ranges) == 0, f"leaves of phase {ph} share an edge"
+        else:
+            cnt = _touch_counts(n, rows, cols, ranges)
+            assert cnt.max(initial=0) <= 1, f"leaves of phase {ph} conflict"
     return {"leaves": len(leaf_ids), "phases": len(phases)}
 
 

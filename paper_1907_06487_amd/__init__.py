@@ -16,7 +16,8 @@ from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_ch
                    race_schedule_flow_takeovers, race_schedule_flow_test_late,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
-                   race_symm_spmv_atomic)
+                   race_symm_gs, race_symm_spmv_atomic, race_symm_spmv_noalloc, race_stream_copy, race_stream_read,
+                   race_vendor_create, race_vendor_destroy, race_vendor_spmv)
 
 BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 
@@ -112,6 +113,14 @@ class Schedule:
 
     def spmv(self, x, y, stream=None):
         race_symm_spmv(self.handle, x, y, stream)
+
+    def gauss_seidel(self, b, x, direction="symmetric", stream=None):
+        """Gauss-Seidel sweep(s) on A x = b in place (distance-1 schedules)."""
+        race_symm_gs(self.handle, b, x, direction, stream)
+
+    def spmv_noalloc(self, x, y, stream=None):
+        """The product through the entry point that allocates nothing."""
+        race_symm_spmv_noalloc(self.handle, x, y, stream)
 
     def spmm(self, X, Y, stream=None):
         race_symm_spmm(self.handle, X.shape[1] if X.dim() == 2 else 1, X, Y, stream)

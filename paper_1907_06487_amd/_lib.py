@@ -29,6 +29,8 @@ EXPORTS = [
     "race_batch_create", "race_batch_bind", "race_batch_run", "race_batch_check", "race_batch_info",
     "race_batch_destroy", "race_schedule_features", "race_schedule_simulate", "race_schedule_flow_grid",
     "race_mlp_forward_host", "race_mlp_forward", "race_mlp_workspace", "race_mlp_loss_grad", "race_mlp_adam",
+    "race_symm_spmv_noalloc", "race_vendor_create", "race_vendor_spmv", "race_vendor_destroy", "race_stream_read",
+    "race_stream_copy", "race_symm_gs",
 ]
 
 MLP_INPUTS = 12
@@ -108,7 +110,16 @@ def lib():
         "race_permute": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
         "race_csr_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
         "race_csr_spmv": ([_P, _P, _P, _P], ctypes.c_int),
-        "race_atomic_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.POINTER(_P)], ctypes.c_int),
+        "race_atomic_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.c_int32, ctypes.POINTER(_P)],
+                               ctypes.c_int),
+        "race_symm_spmv_noalloc": ([_P, _P, _P, _P], ctypes.c_int),
+        "race_symm_gs": ([_P, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+        "race_vendor_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.POINTER(_P)], ctypes.c_int),
+        "race_vendor_spmv": ([_P, _P, _P, _P], ctypes.c_int),
+        "race_vendor_destroy": ([_P], None),
+        "race_stream_read": ([_P, ctypes.c_int64, _P, ctypes.c_int32, _P], ctypes.c_int),
+        "race_stream_copy": ([_P, _P, ctypes.c_int64, ctypes.c_int32, _P], ctypes.c_int),
         "race_symm_spmv_atomic": ([_P, _P, _P, _P], ctypes.c_int),
         "race_csr_destroy": ([_P], None),
         "race_last_error": ([], ctypes.c_char_p),
@@ -307,13 +318,59 @@ def race_csr_spmv(h, x, y, stream=None):
     check(lib().race_csr_spmv(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
 
 
-def race_atomic_create(n, row_ptr, col, val):
+def race_atomic_create(n, row_ptr, col, val, lanes_per_row=0):
     rp, c = _i32(row_ptr), _i32(col)
     v = np.ascontiguousarray(val, dtype=np.float64)
     h = _P()
     check(lib().race_atomic_create(int(n), _np_ptr(rp, ctypes.c_int32), _np_ptr(c, ctypes.c_int32),
-                                   _np_ptr(v, ctypes.c_double), ctypes.byref(h)))
+                                   _np_ptr(v, ctypes.c_double), int(lanes_per_row), ctypes.byref(h)))
     return h
+
+
+GS_DIRECTIONS = {"forward": 0, "backward": 1, "symmetric": 2}
+
+
+def race_symm_gs(h, b, x, direction="symmetric", stream=None):
+    check(lib().race_symm_gs(h, _dev_ptr(b), _dev_ptr(x), GS_DIRECTIONS.get(direction, direction),
+                             _stream_ptr(stream)))
+
+
+def race_symm_spmv_noalloc(h, x, y, stream=None):
+    check(lib().race_symm_spmv_noalloc(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
+
+
+VENDOR_ALGS = {"adaptive": 0, "rowsplit": 1, "lrb": 2, "nnzsplit": 3}
+
+
+def race_vendor_create(n, row_ptr, col, val, symmetric_upper, alg):
+    rp, c = _i32(row_ptr), _i32(col)
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    h = _P()
+    check(lib().race_vendor_create(int(n), _np_ptr(rp, ctypes.c_int32), _np_ptr(c, ctypes.c_int32),
+                                   _np_ptr(v, ctypes.c_double), int(bool(symmetric_upper)),
+                                   VENDOR_ALGS.get(alg, alg), ctypes.byref(h)))
+    return h
+
+
+def race_vendor_spmv(h, x, y, stream=None):
+    check(lib().race_vendor_spmv(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
+
+
+def race_vendor_destroy(h):
+    lib().race_vendor_destroy(h)
+
+
+def race_stream_read(src, sink, grid, stream=None):
+    """src: device tensor (its bytes are read); sink: device int32 tensor of >= 1 element."""
+    check(lib().race_stream_read(_dev_ptr(src), src.numel() * src.element_size(), _dev_ptr(sink), int(grid),
+                                 _stream_ptr(stream)))
+
+
+def race_stream_copy(src, dst, grid, stream=None):
+    if dst.numel() * dst.element_size() != src.numel() * src.element_size():
+        raise ValueError("src and dst must hold the same number of bytes")
+    check(lib().race_stream_copy(_dev_ptr(src), _dev_ptr(dst), src.numel() * src.element_size(), int(grid),
+                                 _stream_ptr(stream)))
 
 
 def race_symm_spmv_atomic(h, x, y, stream=None):

@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librace.so")
 
-HOST_SRC = ["schedule.cpp", "layout.cpp", "costmodel.cpp"]
-HIP_SRC = ["race_kernels.hip", "mlp_kernels.hip", "api.hip"]
+HOST_SRC = ["schedule.cpp", "layout.cpp", "costmodel.cpp", "gauss_seidel.cpp"]
+HIP_SRC = ["race_kernels.hip", "mlp_kernels.hip", "bandwidth.hip", "vendor.hip", "gs_kernels.hip", "api.hip"]
 ARCH = os.environ.get("RACE_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
@@ -44,7 +44,7 @@ def build(verbose=False):
         _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs], verbose)
+    _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lrocsparse"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -5,12 +5,16 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/race.h"
 #include "costmodel.hpp"
+#include "errors.hpp"
+#include "gauss_seidel.hpp"
+#include "gs_kernels.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 #include "schedule.hpp"
@@ -76,6 +80,11 @@ void release(DevBuf<T>& b) {
 
 }  // namespace
 
+namespace race {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace race
+
 // Claim words per CU for the dataflow launch's static tickets: at least the
 // workgroups one CU can hold (32 wavefronts).
 constexpr int32_t kClaimsPerCu = 32;
@@ -103,8 +112,16 @@ struct race_schedule {
   DevBuf<float> lane_diag32, sell_val32;
   DevBuf<race::Cplx<false>> lane_diagc, sell_valc;  // complex values (value_type 2 or 3)
   DevBuf<double> tiles_x, tiles_y;  // column tiles of X and Y for products with many passes (grown on demand)
+  // distance-1 schedules: the Gauss-Seidel layout and its device copies
+  bool gs = false;
+  race::GsLayout G;
+  DevBuf<int32_t> gs_leaf_lo, gs_leaf_hi, gs_halo_ptr, gs_halo, gs_row_ptr;
+  DevBuf<uint16_t> gs_slot;
+  DevBuf<double> gs_val, gs_diag;
 
   void free_device() {
+    release(gs_leaf_lo); release(gs_leaf_hi); release(gs_halo_ptr); release(gs_halo); release(gs_row_ptr);
+    release(gs_slot); release(gs_val); release(gs_diag);
     release(leaf_units); release(unit_desc);
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
@@ -182,8 +199,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (p) prm = *p;
   else race_params_default(&prm);
   if (prm.dist_k < 1 || prm.dist_k > 8) return fail(RACE_EINVAL, "dist_k must be in 1..8");
-  if (prm.dist_k < 2)
-    return fail(RACE_EUNSUPPORTED, "SymmSpMV needs a distance-2 (or wider) coloring: dist_k >= 2");
+  if (prm.dist_k == 1 && prm.value_type != 0)
+    return fail(RACE_EUNSUPPORTED, "distance-1 schedules (Gauss-Seidel sweeps) take float64 values only");
   if (prm.n_workers < 1) return fail(RACE_EINVAL, "n_workers must be >= 1");
   if (prm.max_stages < 1 || prm.max_stages > 16) return fail(RACE_EINVAL, "max_stages must be in 1..16");
   if (prm.balance_by < 0 || prm.balance_by > 2)
@@ -234,6 +251,18 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
       return fail(RACE_EINVAL, err);
     }
     int code = RACE_OK;
+    if (prm.dist_k == 1) {
+      // a distance-1 coloring serves Gauss-Seidel sweeps; its leaves may
+      // share scatter targets, so no SymmSpMV layout is built
+      s->gs = true;
+      if (val) {
+        err = race::build_gs_layout(n, row_ptr, col, val, s->tree, s->G, &code);
+        if (!err.empty()) {
+          delete s;
+          return fail(code, err);
+        }
+      }
+    }
     // complex values arrive as interleaved (re, im) pairs
     std::vector<double> v_re, v_im;
     if (cplx && val) {
@@ -245,9 +274,10 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
         v_im[i] = val[2 * i + 1];
       }
     }
-    err = race::build_layout(n, row_ptr, col, cplx ? (val ? v_re.data() : nullptr) : val,
-                             cplx ? (val ? v_im.data() : nullptr) : nullptr, s->tree, prm.window_max, prm.value_type,
-                             prm.shared_atomics != 0, s->L, &code);
+    if (!s->gs)
+      err = race::build_layout(n, row_ptr, col, cplx ? (val ? v_re.data() : nullptr) : val,
+                               cplx ? (val ? v_im.data() : nullptr) : nullptr, s->tree, prm.window_max,
+                               prm.value_type, prm.shared_atomics != 0, s->L, &code);
     if (!err.empty()) {
       delete s;
       return fail(code, err);
@@ -265,20 +295,33 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     st.n_leaves = static_cast<int32_t>(t.leaves.size());
     st.n_phases = t.n_phases;
     int32_t used = 0;
-    for (int32_t ph = 0; ph < t.n_phases; ++ph)
-      if (L.phase_leaf_ptr[ph + 1] > L.phase_leaf_ptr[ph]) ++used;
+    {
+      // phases holding a leaf (the leaves are sorted by phase)
+      int32_t last = -1;
+      for (const int32_t ph : t.leaf_phase)
+        if (ph != last) {
+          ++used;
+          last = ph;
+        }
+    }
     st.n_phases_used = used;
     st.n_units = static_cast<int32_t>(L.unit_lo.size());
-    st.max_window = L.max_window;
+    st.max_window = s->gs ? s->G.max_window : L.max_window;
     st.n_chunks = static_cast<int32_t>(L.chunk_len.size());
     st.n_eff_root = t.n_eff_root;
     st.n_workers = prm.n_workers;
     st.eta = t.eta;
     st.nnz_upper = n > 0 ? row_ptr[n] : 0;
-    st.n_diag = L.n_diag;
+    if (s->gs) {
+      int64_t nd = 0;
+      for (int32_t r = 0; r < n; ++r) nd += row_ptr[r + 1] > row_ptr[r] && col[row_ptr[r]] == r;
+      st.n_diag = nd;
+    } else {
+      st.n_diag = L.n_diag;
+    }
     st.nnz_full = 2 * st.nnz_upper - st.n_diag;
     st.sell_elems = static_cast<int64_t>(L.sell_val.size());
-    st.halo_total = L.halo_total;
+    st.halo_total = s->gs ? s->G.halo_total : L.halo_total;
     st.rows_rmw = L.rows_rmw;
     st.halo_rmw = L.halo_rmw;
     st.bytes_min = 12 * st.nnz_upper + 20 * static_cast<int64_t>(n) + 4;
@@ -325,6 +368,22 @@ int race_schedule_upload(race_schedule_t s) {
   if (e != hipSuccess) {                                           \
     s->free_device();                                              \
     return hip_fail(e, "upload of " #buf);                         \
+  }
+  if (s->gs) {
+    const race::GsLayout& G = s->G;
+    UP(gs_leaf_lo, G.leaf_lo)
+    UP(gs_leaf_hi, G.leaf_hi)
+    UP(gs_halo_ptr, G.halo_ptr)
+    UP(gs_halo, G.halo)
+    UP(gs_row_ptr, G.row_ptr)
+    UP(gs_slot, G.slot)
+    UP(gs_val, G.val)
+    UP(gs_diag, G.diag)
+    UP(new2old, s->tree.perm)
+    s->device = dev;
+    s->uploaded = true;
+    s->stats.device_bytes = total;
+    return RACE_OK;
   }
   UP(leaf_units, L.leaf_units)
   {
@@ -569,9 +628,19 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   const race::Layout& L = s->L;
   const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
   if (n_units == 0) return RACE_OK;
+  // the launch identifies itself by an epoch and a ticket base passed as
+  // arguments, against state that lives on the device: a captured launch
+  // would replay the same epoch and find every ticket already taken
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cap);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(RACE_EUNSUPPORTED,
+                "the dataflow product cannot be captured into a graph; use race_symm_spmv_noalloc, which resets its "
+                "state inside the stream");
   const int32_t wmax = std::max(1, L.max_window);
   int32_t per_cu = 0;
-  hipError_t e = race::race_flow_occupancy<ValT>(k, s->params.block_threads, wmax, &per_cu);
+  e = race::race_flow_occupancy<ValT>(k, s->params.block_threads, wmax, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(RACE_EUNSUPPORTED, "dataflow kernel does not fit a CU with this window and block size");
   // the first tickets clear the y entries whose first touch is a shared atomic add
@@ -633,8 +702,12 @@ static int32_t rhs_tile(race_schedule_t s, int32_t k) {
   return race::window_lds_bytes(wmax, kt) > lds_limit ? 0 : kt;
 }
 
+static const char* kDist1Product =
+    "a distance-1 schedule serves Gauss-Seidel sweeps (race_symm_gs); SymmSpMV needs dist_k >= 2";
+
 static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, uint64_t* trace, void* stream) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
   if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
   if (s->tree.n == 0) return RACE_OK;
@@ -716,6 +789,7 @@ int race_schedule_check(race_schedule_t s) {
   if (!s->uploaded) return RACE_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  if (s->gs) return RACE_OK;  // Gauss-Seidel sweeps have no bounded waits
   const int32_t n_flags = static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
   uint32_t status = 0;
   e = hipMemcpy(&status, s->flow_state.p + n_flags, sizeof(uint32_t), hipMemcpyDeviceToHost);
@@ -732,7 +806,7 @@ int race_schedule_check(race_schedule_t s) {
 int race_schedule_flow_takeovers(race_schedule_t s, int64_t* count) {
   if (!s || !count) return fail(RACE_EINVAL, "NULL argument");
   *count = 0;
-  if (!s->uploaded) return RACE_OK;
+  if (!s->uploaded || s->gs) return RACE_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
   uint32_t v = 0;
@@ -753,6 +827,99 @@ int race_symm_spmv(race_schedule_t s, const double* x, double* y, void* stream) 
   return run_products(s, 1, x, y, nullptr, stream);
 }
 
+}  // extern "C"
+
+// Dataflow state of race_symm_spmv_noalloc: completion flags, the ticket
+// counter, the static-ticket claims and the takeover count of one product,
+// in a fixed array that every device holds once for the life of the
+// process.  Host code never uses the array's name as an address: each
+// device's copy is reached through the address hipGetSymbolAddress returns
+// with that device current.
+constexpr int64_t kNoallocWords = int64_t(1) << 20;  // 4 MiB
+static __device__ __align__(256) uint32_t scratch[kNoallocWords];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch` (looked up once per device).
+int noalloc_scratch(int dev, uint32_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RACE_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the no-allocation state");
+    g_scratch[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch[dev];
+  return RACE_OK;
+}
+
+template <typename ValT>
+int run_flow_noalloc(race_schedule_t s, const race::UnitArgs<ValT>& a, const double* x, double* y, uint32_t* scr,
+                     hipStream_t st) {
+  const race::Layout& L = s->L;
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  if (n_units == 0) return RACE_OK;
+  const int32_t wmax = std::max(1, L.max_window);
+  int32_t per_cu = 0;
+  hipError_t e = race::race_flow_occupancy<ValT>(1, s->params.block_threads, wmax, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (per_cu < 1) return fail(RACE_EUNSUPPORTED, "dataflow kernel does not fit a CU with this window and block size");
+  const int32_t n_flags = n_units + L.n_zero_tasks;
+  const int32_t grid = std::max(1, std::min(n_flags, per_cu * s->n_cus));
+  const int32_t n_static = grid;
+  // [done flags][pad to 8 bytes][64-bit counter][claims][takeover count]
+  const int64_t counter_word = (static_cast<int64_t>(n_flags) + 1) / 2 * 2;
+  const int64_t claim_word = counter_word + 2;
+  const int64_t words = claim_word + n_static + 1;
+  if (words > kNoallocWords)
+    return fail(RACE_EUNSUPPORTED, "schedule needs " + std::to_string(words) +
+                                       " words of dataflow state; race_symm_spmv_noalloc holds at most " +
+                                       std::to_string(kNoallocWords) + " (units + clearing tasks + workgroups)");
+  // every call starts from cleared state, so the launch can always use
+  // epoch 1 and ticket base 0 (and a captured graph replays correctly)
+  e = race::launch_clear_words(scr, words, st);
+  if (e != hipSuccess) return hip_fail(e, "clearing the dataflow state");
+  race::FlowArgs f{s->dep_idx.p, scr, reinterpret_cast<uint64_t*>(scr + counter_word),
+                   s->flow_state.p + n_flags,  // the schedule's own status word (race_schedule_check)
+                   scr + claim_word, scr + claim_word + n_static, n_static, 0, nullptr, n_flags, n_units,
+                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size())};
+  e = race::launch_race_flow<ValT>(a, f, 1, x, y, 1, wmax, s->params.block_threads, grid, 1u, 0u, st);
+  if (e != hipSuccess) return hip_fail(e, "RACE dataflow launch");
+  return RACE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int race_symm_spmv_noalloc(race_schedule_t s, const double* x, double* y, void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
+  if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  if (s->params.value_type > 1) return fail(RACE_EUNSUPPORTED, "race_symm_spmv_noalloc takes real values only");
+  if (s->params.exec_mode != 1) return fail(RACE_EUNSUPPORTED, "race_symm_spmv_noalloc runs the dataflow mode only");
+  if (s->tree.n == 0) return RACE_OK;
+  if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
+  if (rhs_tile(s, 1) < 1)
+    return fail(RACE_EUNSUPPORTED, "a unit window does not fit the LDS; rebuild with a smaller window_max");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != s->device) return fail(RACE_EINVAL, "the schedule was uploaded to another device");
+  uint32_t* scr = nullptr;
+  int rc = noalloc_scratch(dev, &scr);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->params.value_type == 0)
+    return run_flow_noalloc<double>(s, unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p), x, y, scr, st);
+  return run_flow_noalloc<float>(s, unit_args<float>(s, s->lane_diag32.p, s->sell_val32.p), x, y, scr, st);
+}
+
 int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, void* stream) {
   return run_products(s, k, X, Y, nullptr, stream);
 }
@@ -760,6 +927,35 @@ int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, voi
 int race_symm_spmm_traced(race_schedule_t s, int32_t k, const double* X, double* Y, uint64_t* trace, void* stream) {
   if (!trace) return fail(RACE_EINVAL, "trace is NULL");
   return run_products(s, k, X, Y, trace, stream);
+}
+
+int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t direction, void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  if (direction < 0 || direction > 2) return fail(RACE_EINVAL, "direction must be 0 (forward), 1 (backward) or 2 (both)");
+  if (s->tree.n == 0) return RACE_OK;
+  if (!b || !x) return fail(RACE_EINVAL, "b or x is NULL");
+  const race::GsLayout& G = s->G;
+  const race::GsArgs a{s->gs_leaf_lo.p, s->gs_leaf_hi.p, s->gs_halo_ptr.p, s->gs_halo.p,
+                       s->gs_row_ptr.p, s->gs_slot.p,    s->gs_val.p,      s->gs_diag.p};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t np = s->tree.n_phases;
+  auto phase = [&](int32_t ph, bool backward) {
+    const int32_t l0 = G.phase_leaf_ptr[ph], l1 = G.phase_leaf_ptr[ph + 1];
+    return race::launch_gs_phase(a, l0, l1 - l0, G.phase_max_window[ph], backward, b, x, st);
+  };
+  if (direction != 1)
+    for (int32_t ph = 0; ph < np; ++ph) {
+      hipError_t e = phase(ph, false);
+      if (e != hipSuccess) return hip_fail(e, "Gauss-Seidel phase launch");
+    }
+  if (direction != 0)
+    for (int32_t ph = np - 1; ph >= 0; --ph) {
+      hipError_t e = phase(ph, true);
+      if (e != hipSuccess) return hip_fail(e, "Gauss-Seidel phase launch");
+    }
+  return RACE_OK;
 }
 
 int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, int32_t to_permuted, void* stream) {
@@ -853,6 +1049,7 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   int32_t wmax = 1, threads = 0, vt = -1;
   for (int32_t m = 0; m < count; ++m) {
+    if (s[m] && s[m]->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
     if (!s[m] || !s[m]->uploaded) return fail(RACE_ESTATE, "every schedule must be uploaded");
     if (s[m]->device != dev) return fail(RACE_EINVAL, "schedules live on different devices");
     if (s[m]->params.value_type >= 2) return fail(RACE_EUNSUPPORTED, "batches take real values only");
@@ -1089,8 +1286,9 @@ int race_csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const
   return csr_create(n, row_ptr, col, val, lanes_per_row, false, out);
 }
 
-int race_atomic_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val, race_csr_t* out) {
-  return csr_create(n, row_ptr, col, val, 0, true, out);
+int race_atomic_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                       int32_t lanes_per_row, race_csr_t* out) {
+  return csr_create(n, row_ptr, col, val, lanes_per_row, true, out);
 }
 
 int race_csr_spmv(race_csr_t h, const double* x, double* y, void* stream) {

@@ -1,0 +1,118 @@
+// Host construction of the Gauss-Seidel layout (see gauss_seidel.hpp).
+#include "gauss_seidel.hpp"
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/race.h"
+
+namespace race {
+
+std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                            const Tree& tree, GsLayout& L, int* code) {
+  L = GsLayout();
+  L.n = n;
+  *code = RACE_OK;
+  std::vector<int32_t> inv(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) inv[tree.perm[i]] = i;
+  // full permuted rows: every stored off-diagonal (r, c) appears in the rows
+  // of both ends
+  const int64_t nnz_u = n > 0 ? row_ptr[n] : 0;
+  std::vector<int64_t> cnt(static_cast<size_t>(n) + 1, 0);
+  L.diag.assign(static_cast<size_t>(n), 0.0);
+  std::vector<char> has_diag(static_cast<size_t>(n), 0);
+  for (int32_t r = 0; r < n; ++r)
+    for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+      if (col[k] == r) {
+        L.diag[inv[r]] = val[k];
+        has_diag[inv[r]] = 1;
+      } else {
+        ++cnt[inv[r] + 1];
+        ++cnt[inv[col[k]] + 1];
+      }
+    }
+  for (int32_t i = 0; i < n; ++i)
+    if (!has_diag[i] || L.diag[i] == 0.0) {
+      *code = RACE_EINVAL;
+      return "Gauss-Seidel needs a nonzero stored diagonal in every row (row " + std::to_string(tree.perm[i]) +
+             " of the input)";
+    }
+  for (int32_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  if (cnt[n] >= (int64_t(1) << 31)) {
+    *code = RACE_EUNSUPPORTED;
+    return "the full matrix has 2^31 or more off-diagonal entries";
+  }
+  (void)nnz_u;
+  std::vector<int32_t> pcol(static_cast<size_t>(cnt[n]));
+  std::vector<double> pval(static_cast<size_t>(cnt[n]));
+  {
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t r = 0; r < n; ++r)
+      for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+        const int32_t c = col[k];
+        if (c == r) continue;
+        const int32_t a = inv[r], b = inv[c];
+        pcol[fill[a]] = b;
+        pval[fill[a]++] = val[k];
+        pcol[fill[b]] = a;
+        pval[fill[b]++] = val[k];
+      }
+  }
+  // columns ascending within every row
+  {
+    std::vector<std::pair<int32_t, double>> tmp;
+    for (int32_t i = 0; i < n; ++i) {
+      tmp.clear();
+      for (int64_t k = cnt[i]; k < cnt[i + 1]; ++k) tmp.emplace_back(pcol[k], pval[k]);
+      std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      for (size_t t = 0; t < tmp.size(); ++t) {
+        pcol[cnt[i] + static_cast<int64_t>(t)] = tmp[t].first;
+        pval[cnt[i] + static_cast<int64_t>(t)] = tmp[t].second;
+      }
+      L.max_row = std::max<int32_t>(L.max_row, static_cast<int32_t>(tmp.size()));
+    }
+  }
+  L.row_ptr.assign(cnt.begin(), cnt.end());
+  L.val = std::move(pval);
+  L.slot.assign(L.val.size(), 0);
+  // leaves in execution order, their halos and window slots
+  const size_t nl = tree.leaves.size();
+  L.phase_leaf_ptr.assign(static_cast<size_t>(tree.n_phases) + 1, 0);
+  L.phase_max_window.assign(static_cast<size_t>(tree.n_phases), 0);
+  L.halo_ptr.assign(nl + 1, 0);
+  std::vector<int32_t> hl;
+  for (size_t t = 0; t < nl; ++t) {
+    const TreeNode& nd = tree.nodes[tree.leaves[t]];
+    const int32_t lo = nd.lo, hi = nd.hi, R = hi - lo;
+    L.leaf_lo.push_back(lo);
+    L.leaf_hi.push_back(hi);
+    ++L.phase_leaf_ptr[tree.leaf_phase[t] + 1];
+    hl.clear();
+    for (int64_t k = cnt[lo]; k < cnt[hi]; ++k)
+      if (pcol[k] < lo || pcol[k] >= hi) hl.push_back(pcol[k]);
+    std::sort(hl.begin(), hl.end());
+    hl.erase(std::unique(hl.begin(), hl.end()), hl.end());
+    const int64_t window = static_cast<int64_t>(R) + static_cast<int64_t>(hl.size());
+    if (window > kGsMaxWindow) {
+      *code = RACE_EUNSUPPORTED;
+      return "a leaf of " + std::to_string(R) + " rows reads " + std::to_string(hl.size()) +
+             " rows outside it: its window exceeds " + std::to_string(kGsMaxWindow) +
+             " entries; rebuild with more n_workers or more stages";
+    }
+    for (int64_t k = cnt[lo]; k < cnt[hi]; ++k) {
+      const int32_t c = pcol[k];
+      L.slot[k] = static_cast<uint16_t>(
+          c >= lo && c < hi ? c - lo : R + (std::lower_bound(hl.begin(), hl.end(), c) - hl.begin()));
+    }
+    L.halo.insert(L.halo.end(), hl.begin(), hl.end());
+    L.halo_ptr[t + 1] = static_cast<int32_t>(L.halo.size());
+    L.max_window = std::max<int32_t>(L.max_window, static_cast<int32_t>(window));
+    int32_t& pm = L.phase_max_window[tree.leaf_phase[t]];
+    pm = std::max<int32_t>(pm, static_cast<int32_t>(window));
+  }
+  for (int32_t p = 0; p < tree.n_phases; ++p) L.phase_leaf_ptr[p + 1] += L.phase_leaf_ptr[p];
+  L.halo_total = static_cast<int64_t>(L.halo.size());
+  return "";
+}
+
+}  // namespace race

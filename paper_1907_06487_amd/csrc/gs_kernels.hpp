@@ -1,0 +1,30 @@
+// Device arguments and launcher of the Gauss-Seidel sweep kernel.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace race {
+
+constexpr int32_t kGsMaxWindowBytes = 16384 * 8;  // LDS of the largest leaf window
+
+// Device copies of a GsLayout (gauss_seidel.hpp).
+struct GsArgs {
+  const int32_t* leaf_lo;
+  const int32_t* leaf_hi;
+  const int32_t* halo_ptr;
+  const int32_t* halo;
+  const int32_t* row_ptr;
+  const uint16_t* slot;
+  const double* val;
+  const double* diag;
+};
+
+// Leaves leaf0 .. leaf0 + count - 1 (one phase) on one wavefront each, with
+// windows of at most wmax entries; rows in order (backward: reversed).
+// b and x are device arrays of n in the permuted order; x is updated in place.
+hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,
+                           const double* b, double* x, hipStream_t st);
+
+}  // namespace race

@@ -151,6 +151,10 @@ template <typename ValT>
 hipError_t launch_race_batch(const BatchMat<ValT>* mats, const BatchArgs& b, int32_t k, int32_t wmax, int32_t threads,
                              int32_t grid, hipStream_t st);
 
+// p[0 .. words) = 0 with plain stores (a kernel, so a captured graph can
+// replay it).
+hipError_t launch_clear_words(uint32_t* p, int64_t words, hipStream_t st);
+
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                            double* y, int32_t lanes_per_row, hipStream_t st);
 hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,

@@ -1058,6 +1058,12 @@ template hipError_t launch_race_batch<double>(const BatchMat<double>*, const Bat
 template hipError_t launch_race_batch<float>(const BatchMat<float>*, const BatchArgs&, int32_t, int32_t, int32_t,
                                              int32_t, hipStream_t);
 
+hipError_t launch_clear_words(uint32_t* p, int64_t words, hipStream_t st) {
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::batch_reset_kernel, fill_grid(words), dim3(256), 0, st, p, words);
+  return hipGetLastError();
+}
+
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                            double* y, int32_t lpr, hipStream_t st) {
   if (n == 0) return hipSuccess;

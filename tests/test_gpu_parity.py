@@ -205,17 +205,19 @@ def test_baseline_csr_spmv():
                f"csr lpr={lpr}")
 
 
-def test_baseline_atomic_symm():
+@pytest.mark.parametrize("lpr", [0, 1, 8, 64])
+def test_baseline_atomic_symm(lpr):
     m = matgen.banded_irregular(30000, seed=13, band=3000)
     x = matgen.rhs(m.n, 13)
     y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
-    h = R.race_atomic_create(m.n, m.row_ptr, m.col, m.val)
+    h = R.race_atomic_create(m.n, m.row_ptr, m.col, m.val, lpr)
     xd = torch.as_tensor(x, device=DEV)
     yd = torch.full_like(xd, float("nan"))
     R.race_symm_spmv_atomic(h, xd, yd)
     torch.cuda.synchronize()
     R.race_csr_destroy(h)
-    _check(yd.cpu().numpy(), y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), "atomic")
+    _check(yd.cpu().numpy(), y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m),
+           f"atomic lpr={lpr}")
 
 
 def test_race_repeated_calls_and_streams():
@@ -260,13 +262,17 @@ def _sampled_rows_exact(m, x, rows):
     return np.array([math.fsum(t + cols_i[int(i)]) for t, i in zip(out, rows)])
 
 
-@pytest.mark.parametrize("nt,mode", [(256, "flow"), (1024, "flow"), (512, "phases")])
-def test_race_full_size_3d27pt_128(nt, mode):
+@pytest.mark.parametrize("nt,mode,block", [(256, "flow", 512), (256, "flow", 256), (1024, "flow", 256),
+                                           (512, "phases", 256)])
+def test_race_full_size_3d27pt_128(nt, mode, block):
+    """The 128^3 stencil at full size; the first case is the benchmark's
+    configuration (N_t 256, 512 threads, window 3840, dataflow, shared
+    atomics)."""
     m = matgen.config_3d_128()
-    print(f"case 3d27pt_128 n_workers={nt} mode={mode}: n={m.n} nnz={m.nnz}", flush=True)
+    print(f"case 3d27pt_128 n_workers={nt} mode={mode} block={block}: n={m.n} nnz={m.nnz}", flush=True)
     x = matgen.rhs(m.n, 2)
     y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
-    y, st = run_race(m, x, n_workers=nt, exec_mode=mode)
+    y, st = run_race(m, x, n_workers=nt, exec_mode=mode, block_threads=block, window_max=3840, shared_atomics=True)
     _check(y, y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), f"3d27pt_128 nt={nt}")
     rows = np.random.default_rng(0).choice(m.n, size=200, replace=False)
     exact = _sampled_rows_exact(m, x, rows)
@@ -524,3 +530,54 @@ def test_product_fuzz():
         for j in range(k):
             sl = (slice(None), j) if k > 1 else slice(None)
             _check(Y[sl], Y_ref[sl], absax[sl], _full_row_len(m), f"fuzz seed={seed} col={j}")
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    """The 64 seeded matrices of the batch workload (10k..500k rows, 2D
+    5-point / 3D 27-point / irregular banded), generated once."""
+    return matgen.config_batch(64, 100)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_batch_full_64(batch64, k):
+    """The full 64-matrix batch of the benchmark for k = 1, 4, 16 in one
+    graph replay, every matrix and column element-wise against the oracle
+    (shapes: N_t of one worker per 4000 rows, the widest window holding all
+    k columns, 512 threads; for k = 16 also the largest window in passes)."""
+    from paper_1907_06487_amd import autotune
+    mats = batch64
+    windows = [autotune.max_window(k)] + ([3840] if k > 2 else [])
+    for window in windows:
+        print(f"case batch64 k={k} window={window}: {sum(m.n for m in mats)} rows", flush=True)
+        scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=int(min(4096, max(4, m.n // 4000))),
+                             window_max=window, block_threads=512) for m in mats]
+        batch = R.Batch(scheds, k, threads=512)
+        gen = torch.Generator(device=DEV)
+        gen.manual_seed(1000 + k)
+        xs = [torch.rand((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=DEV, generator=gen) * 2 - 1
+              for m in mats]
+        ys = [torch.full_like(x, float("nan")) for x in xs]
+        batch.bind(xs, ys)
+        batch.run(use_graph=True)
+        torch.cuda.synchronize()
+        batch.check()
+        worst = 0.0
+        for m, s, x, y in zip(mats, scheds, xs, ys):
+            perm = s.perm()
+            xp = x.cpu().numpy()
+            x_orig = np.empty_like(xp)
+            x_orig[perm] = xp
+            y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x_orig)[perm]
+            absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(x_orig))[perm]
+            yh = y.cpu().numpy()
+            mlen = _full_row_len(m)
+            for j in range(k):
+                sl = (slice(None), j) if k > 1 else slice(None)
+                en, _ = _check(yh[sl], y_ref[sl], absax[sl], mlen, f"batch64 k={k} w={window} {m.name} col={j}")
+                worst = max(worst, en)
+        print(f"  batch64 k={k} window={window}: worst err_norm {worst:.3e}", flush=True)
+        batch.close()
+        for s in scheds:
+            s.close()

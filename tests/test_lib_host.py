@@ -87,6 +87,12 @@ CASES = [
     ("3d27pt_20_k3", lambda: matgen.stencil3d_27pt(20, seed=4), 128, dict(dist_k=3)),
     ("banded_30k_k4_global", lambda: matgen.banded_irregular(30000, seed=6, band=3000), 256,
      dict(dist_k=4, global_lb=True)),
+    # distance-1 colorings (Gauss-Seidel sweeps)
+    ("worked_16x16_k1", lambda: matgen.stencil2d_7pt(16), 8, dict(eps=(0.6, 0.6), balance="rows", dist_k=1)),
+    ("2d5pt_100_k1", matgen.config_2d_small, 64, dict(dist_k=1)),
+    ("3d27pt_20_k1", lambda: matgen.stencil3d_27pt(20, seed=4), 512, dict(dist_k=1)),
+    ("banded_30k_k1_cm", lambda: matgen.banded_irregular(30000, seed=6, band=3000), 1024,
+     dict(dist_k=1, level_order="cm", global_lb=True)),
 ]
 
 
@@ -205,9 +211,12 @@ def test_error_codes():
     _expect(-1, lambda: R.race_build_schedule(2, np.array([1, 2, 3], np.int32), ok_col, v))       # row_ptr[0]
     _expect(-1, lambda: R.race_build_schedule(2, np.array([0, 2, 1], np.int32), ok_col, v))       # decreasing
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, np.array([0, 0, 1], np.int32), v))       # duplicate
-    p = R.make_params()
-    p.dist_k = 1
+    p = R.make_params(dist_k=1, value_type="f32")  # distance-1 schedules take float64 values only
     _expect(-4, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
+    p = R.make_params(dist_k=1)  # Gauss-Seidel needs every diagonal
+    _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, np.array([1.0, 1.0, 0.0]), p))
+    h = R.race_build_schedule(2, ok_rp, ok_col, v, p)
+    R.race_schedule_destroy(h)
     p = R.make_params(n_workers=0)
     _expect(-1, lambda: R.race_build_schedule(2, ok_rp, ok_col, v, p))
     p = R.make_params(window_max=100000)
@@ -262,10 +271,18 @@ def _fuzz_case(seed):
     nt = int(rng.choice([2, 5, 8, 16, 32, 64, 128, 256]))
     kw["root"] = str(rng.choice(["first", "first", "peripheral"]))
     kw["level_order"] = str(rng.choice(["input", "input", "cm"]))
-    kw["dist_k"] = int(rng.choice([2, 2, 2, 3, 4]))
+    kw["dist_k"] = int(rng.choice([2, 2, 2, 3, 4, 1]))
     if rng.integers(4) == 0:
         m = matgen.relabel(m, seed)
+    if kw["dist_k"] == 1 and not _full_diagonal(m):
+        kw["dist_k"] = 2  # distance-1 schedules carry a Gauss-Seidel layout, which needs every diagonal
     return m, nt, kw
+
+
+def _full_diagonal(m):
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    d = rows == m.col
+    return np.count_nonzero(d & (m.val != 0)) == m.n
 
 
 @pytest.mark.parametrize("seed", range(150))
@@ -277,8 +294,9 @@ def test_schedule_fuzz_bit_exact_and_valid(seed):
     try:
         tr = s.tree()
         node, phase = s.leaves()
-        C.check_schedule(m.n, m.row_ptr, m.col, s.perm(), tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase)
-        if kw["dist_k"] > 2 and m.n <= 2000:
+        C.check_schedule(m.n, m.row_ptr, m.col, s.perm(), tr["lo"], tr["hi"], tr["color"], tr["parent"], node, phase,
+                         dist=1 if kw["dist_k"] == 1 else 2)
+        if kw["dist_k"] != 2 and m.n <= 2000:
             lo, hi = np.asarray(tr["lo"])[node], np.asarray(tr["hi"])[node]
             C.check_dense_distance_k(m.n, m.row_ptr, m.col, s.perm(), lo, hi, phase, kw["dist_k"])
     finally:
