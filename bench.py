@@ -150,7 +150,7 @@ def yardsticks(m, perm, flops, nnz_full, xs, ys, args, torch):
             t_all["crs_spmv"].append((T(lambda x, y: R.race_csr_spmv(h, x, y)), {"order": oname, "lanes_per_row": lpr}))
             R.race_csr_destroy(h)
         for sym in (False, True):
-            for alg in ("adaptive", "rowsplit", "lrb", "nnzsplit"):
+            for alg in ("adaptive", "rowsplit", "lrb"):
                 try:
                     h = (R.race_vendor_create(m.n, mo.row_ptr, mo.col, mo.val, True, alg) if sym
                          else R.race_vendor_create(m.n, rp, c, v, False, alg))

@@ -321,8 +321,8 @@ void race_csr_destroy(race_csr_t h);
  * against the best variant of the vendor library).  symmetric_upper 0: the
  * FULL matrix in CRS, a general product; 1: the UPPER triangle of a
  * symmetric matrix, rocSPARSE's own symmetric product.  alg: 0 adaptive,
- * 1 row split, 2 LRB, 3 nnz split (rocSPARSE's CSR algorithms).  Host
- * arrays are copied to the current device and analysed once here.
+ * 1 row split, 2 LRB (rocSPARSE's CSR algorithms); RACE_EINVAL otherwise.
+ * Host arrays are copied to the current device and analysed once here.
  * RACE_EUNSUPPORTED when rocSPARSE does not implement that combination. */
 typedef struct race_vendor* race_vendor_t;
 int race_vendor_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,

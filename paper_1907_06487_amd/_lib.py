@@ -339,7 +339,7 @@ def race_symm_spmv_noalloc(h, x, y, stream=None):
     check(lib().race_symm_spmv_noalloc(h, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
 
 
-VENDOR_ALGS = {"adaptive": 0, "rowsplit": 1, "lrb": 2, "nnzsplit": 3}
+VENDOR_ALGS = {"adaptive": 0, "rowsplit": 1, "lrb": 2}
 
 
 def race_vendor_create(n, row_ptr, col, val, symmetric_upper, alg):

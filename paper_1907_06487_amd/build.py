@@ -7,6 +7,7 @@ are HIP built by hipcc for gfx950.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -34,15 +35,16 @@ def _run(cmd, verbose):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in HOST_SRC:
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
-    for src in HIP_SRC:
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+    steps = [(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+             for src in HOST_SRC]
+    steps += [(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+              for src in HIP_SRC]
+    objs = [cmd[-1] for cmd in steps]
+    # the objects are independent: compile them side by side
+    jobs = max(1, min(len(steps), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd in steps]:
+            f.result()
     tmp = LIB + ".tmp"
     _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lrocsparse"], verbose)
     os.replace(tmp, LIB)

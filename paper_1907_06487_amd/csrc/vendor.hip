@@ -71,8 +71,10 @@ int race_vendor_create(int32_t n, const int32_t* row_ptr, const int32_t* col, co
         return race::set_error(RACE_EINVAL, "column out of range (upper triangle: col >= row)");
   }
   static const rocsparse_spmv_alg algs[] = {rocsparse_spmv_alg_csr_adaptive, rocsparse_spmv_alg_csr_rowsplit,
-                                            rocsparse_spmv_alg_csr_lrb, rocsparse_spmv_alg_csr_nnzsplit};
-  if (alg < 0 || alg > 3) return race::set_error(RACE_EINVAL, "alg must be 0 (adaptive), 1 (row split), 2 (LRB) or 3 (nnz split)");
+                                            rocsparse_spmv_alg_csr_lrb};
+  // (the library's nnz-split CSR algorithm answers "invalid value" to the
+  // stage-wise interface on this ROCm, so it is not offered)
+  if (alg < 0 || alg > 2) return race::set_error(RACE_EINVAL, "alg must be 0 (adaptive), 1 (row split) or 2 (LRB)");
   race_vendor* h = new (std::nothrow) race_vendor();
   if (!h) return race::set_error(RACE_ENOMEM, "out of host memory");
   h->n = n;

@@ -31,7 +31,7 @@ def _check(y, y_ref, absax, mlen, tag):
 
 
 @pytest.mark.parametrize("symmetric", [False, True], ids=["general", "symmetric"])
-@pytest.mark.parametrize("alg", ["adaptive", "rowsplit", "lrb", "nnzsplit"])
+@pytest.mark.parametrize("alg", ["adaptive", "rowsplit", "lrb"])
 def test_vendor_spmv(alg, symmetric):
     m = matgen.banded_irregular(30000, seed=14, band=3000)
     x = matgen.rhs(m.n, 14)
