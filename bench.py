@@ -496,6 +496,11 @@ def main():
     ap.add_argument("--dist-k", type=int, default=2, help="distance of the coloring (2 for SymmSpMV; 3..8 wider)")
     ap.add_argument("--global-lb", type=int, default=0, choices=[0, 1],
                     help="also run Algorithm \"Load Balancing\" over all children of every refined node")
+    ap.add_argument("--order", default="default", choices=["default", "critical"],
+                    help="dataflow ticket order: the layout's execution order, or the critical path of unit costs "
+                         "measured by traced products on this device (part of the schedule's preparation)")
+    ap.add_argument("--order-rounds", type=int, default=1,
+                    help="critical order: trace-and-reorder rounds (each traces under the previous order)")
     ap.add_argument("--no-attainable", action="store_true", help="skip the attainable-bandwidth measurement")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -557,6 +562,23 @@ def main():
     gen.manual_seed(12345)
     xs = [torch.rand(m.n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1 for _ in range(nring)]
     ys = [torch.empty(m.n, dtype=torch.float64, device=dev) for _ in range(nring)]
+
+    order_info = {"order": args.order}
+    if args.order == "critical":
+        # preparation, outside the timed region: unit costs from traced
+        # products, then the critical-path ticket order for them
+        t0 = time.perf_counter()
+        s.order_tickets(None)
+        for rnd in range(args.order_rounds):
+            cost, frac = s.unit_costs(xs[0], ys[0], reps=3)
+            grid = s.flow_grid(1)
+            pred_before = s.simulate(cost, frac, grid)
+            s.order_tickets(cost)
+            pred_after = s.simulate(cost, frac, grid)
+            log(f"ticket order round {rnd}: measured unit costs sum {cost.sum():.0f} us, flush share {frac:.2f}; "
+                f"predicted makespan {pred_before:.1f} -> {pred_after:.1f} us")
+        order_info.update(rounds=args.order_rounds, predicted_us=round(pred_after, 2),
+                          prep_s=round(time.perf_counter() - t0, 2))
 
     # correctness of the timed configuration against the oracle (input order)
     x0 = xs[0].cpu().numpy()
@@ -662,7 +684,7 @@ def main():
                    "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
                    "window_max": args.window, "exec_mode": args.exec_mode, "shared_atomics": args.shared_atomics,
                    "root": args.root, "level_order": args.level_order, "dist_k": args.dist_k,
-                   "levels0": st["n_levels0"],
+                   "levels0": st["n_levels0"], "ticket_order": order_info,
                    "phases": st["n_phases_used"], "leaves": st["n_leaves"], "eta": st["eta"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

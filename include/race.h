@@ -247,6 +247,29 @@ int race_schedule_flow_takeovers(race_schedule_t s, int64_t* count);
  * running workgroups take its ticket over; 0 turns this off. */
 int race_schedule_flow_test_late(race_schedule_t s, int32_t stride);
 
+/* Ticket order of the dataflow product (Section 5's critical path N_eff,
+ * generalised to per-unit costs).  Units are numbered in the layout's
+ * execution order (phase, then heaviest leaf first); a product hands them
+ * out as tickets in this order unless another is set.  Any order in which
+ * every conflict edge points to an earlier ticket gives the same y (the
+ * first-writer flags and edges do not change), only the waiting differs.
+ *
+ * race_schedule_set_ticket_order: ticket_unit (host, n_units) lists the
+ * units by ticket; NULL restores the default.  RACE_EINVAL when it is not a
+ * permutation or a unit would precede one it waits for; RACE_EUNSUPPORTED
+ * for distance-1 schedules.  Synchronises the device: no product of this
+ * schedule may be running.
+ * race_schedule_order_tickets: sets the critical-path order for unit costs
+ * cost (host, n_units, finite, >= 0, e.g. measured by race_symm_spmm_traced):
+ * a unit's bottom level is its cost plus the largest bottom level of the
+ * units that wait for it; the next ticket goes to the unit with the largest
+ * bottom level among those whose edges point to tickets already given (ties:
+ * lower unit).  cost NULL restores the default.
+ * race_schedule_ticket_order: the current order into ticket_unit (host, n_units). */
+int race_schedule_set_ticket_order(race_schedule_t s, const int32_t* ticket_unit);
+int race_schedule_order_tickets(race_schedule_t s, const float* cost);
+int race_schedule_ticket_order(race_schedule_t s, int32_t* ticket_unit);
+
 /* Gauss-Seidel sweep on A x = b over a distance-1 schedule (dist_k = 1,
  * float64 values; the paper names Gauss-Seidel as the prime user of such
  * colorings, Sections 1 and 4.2): every row i takes
@@ -366,8 +389,8 @@ const char* race_last_error(void);
  * Works on pattern-only schedules (no device needed). */
 int race_schedule_features(race_schedule_t s, int32_t k, float* out);
 
-/* Predicted makespan of a dataflow product: tickets in execution order on
- * `workers` workgroups, unit u computes for (1 - flush_frac) cost[u], waits
+/* Predicted makespan of a dataflow product: tickets in the schedule's ticket
+ * order (race_schedule_set_ticket_order) on `workers` workgroups, unit u computes for (1 - flush_frac) cost[u], waits
  * for the earlier units it conflicts with, then flushes for flush_frac
  * cost[u] (clearing tasks are not modelled).  cost: host, n_units values (any time unit; the result is in the
  * same unit).  flush_frac in [0, 1], workers >= 1. */

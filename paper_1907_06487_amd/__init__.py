@@ -13,7 +13,8 @@ from . import _lib
 from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_check, race_batch_create,
                    race_batch_destroy, race_batch_info, race_batch_run, race_build_schedule, race_csr_create, race_csr_destroy,
                    race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
-                   race_schedule_flow_takeovers, race_schedule_flow_test_late,
+                   race_schedule_flow_takeovers, race_schedule_flow_test_late, race_schedule_order_tickets,
+                   race_schedule_set_ticket_order, race_schedule_ticket_order,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
                    race_symm_gs, race_symm_spmv_atomic, race_symm_spmv_noalloc, race_stream_copy, race_stream_read,
@@ -110,6 +111,45 @@ class Schedule:
 
     def flow_grid(self, k=1):
         return _lib.race_schedule_flow_grid(self.handle, k)
+
+    def ticket_order(self):
+        """Units by dataflow ticket."""
+        return race_schedule_ticket_order(self.handle, self.stats()["n_units"])
+
+    def set_ticket_order(self, ticket_unit):
+        race_schedule_set_ticket_order(self.handle, ticket_unit)
+
+    def order_tickets(self, cost):
+        """Critical-path ticket order for per-unit costs (None: the default order)."""
+        race_schedule_order_tickets(self.handle, cost)
+
+    def unit_costs(self, x, y, reps=3, stream=None):
+        """Measured per-unit costs (microseconds: arithmetic plus flush,
+        waits excluded; the median over `reps` traced products) and the
+        flush's mean share of them."""
+        import numpy as np
+        import torch
+        nu = self.stats()["n_units"]
+        hz = self.stats()["wall_clock_hz"]
+        tr = torch.empty(4 * nu, dtype=torch.int64, device=x.device)
+        costs, flush = [], []
+        for _ in range(reps):
+            self.traced(x, y, tr, stream)
+            torch.cuda.synchronize()
+            t = tr.cpu().numpy().reshape(nu, 4).astype(np.float64) * (1e6 / hz)
+            comp, fl = t[:, 1] - t[:, 0], t[:, 3] - t[:, 2]
+            costs.append(comp + fl)
+            flush.append(fl.sum() / max((comp + fl).sum(), 1e-30))
+        self.check()
+        return np.median(np.stack(costs), axis=0).astype(np.float32), float(np.median(flush))
+
+    def tune_order(self, x, y, reps=3, stream=None):
+        """Critical-path ticket order from this device's measured unit costs
+        (one traced product per rep, default order first)."""
+        self.order_tickets(None)
+        cost, flush_frac = self.unit_costs(x, y, reps, stream)
+        self.order_tickets(cost)
+        return cost, flush_frac
 
     def spmv(self, x, y, stream=None):
         race_symm_spmv(self.handle, x, y, stream)

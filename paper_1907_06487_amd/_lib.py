@@ -30,7 +30,8 @@ EXPORTS = [
     "race_batch_destroy", "race_schedule_features", "race_schedule_simulate", "race_schedule_flow_grid",
     "race_mlp_forward_host", "race_mlp_forward", "race_mlp_workspace", "race_mlp_loss_grad", "race_mlp_adam",
     "race_symm_spmv_noalloc", "race_vendor_create", "race_vendor_spmv", "race_vendor_destroy", "race_stream_read",
-    "race_stream_copy", "race_symm_gs",
+    "race_stream_copy", "race_symm_gs", "race_schedule_set_ticket_order", "race_schedule_order_tickets",
+    "race_schedule_ticket_order",
 ]
 
 MLP_INPUTS = 12
@@ -104,6 +105,9 @@ def lib():
         "race_schedule_check": ([_P], ctypes.c_int),
         "race_schedule_flow_takeovers": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "race_schedule_flow_test_late": ([_P, ctypes.c_int32], ctypes.c_int),
+        "race_schedule_set_ticket_order": ([_P, _I32P], ctypes.c_int),
+        "race_schedule_order_tickets": ([_P, _FP], ctypes.c_int),
+        "race_schedule_ticket_order": ([_P, _I32P], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
@@ -286,6 +290,30 @@ def race_schedule_flow_takeovers(h):
 
 def race_schedule_flow_test_late(h, stride):
     check(lib().race_schedule_flow_test_late(h, int(stride)))
+
+
+def race_schedule_set_ticket_order(h, ticket_unit):
+    """ticket_unit: int32 array of n_units (units by ticket), or None for the default order."""
+    if ticket_unit is None:
+        check(lib().race_schedule_set_ticket_order(h, None))
+        return
+    t = np.ascontiguousarray(ticket_unit, dtype=np.int32)
+    check(lib().race_schedule_set_ticket_order(h, _np_ptr(t, ctypes.c_int32)))
+
+
+def race_schedule_order_tickets(h, cost):
+    """cost: float32 array of n_units (critical-path order), or None for the default order."""
+    if cost is None:
+        check(lib().race_schedule_order_tickets(h, None))
+        return
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    check(lib().race_schedule_order_tickets(h, _np_ptr(c, ctypes.c_float)))
+
+
+def race_schedule_ticket_order(h, n_units):
+    out = np.empty(n_units, dtype=np.int32)
+    check(lib().race_schedule_ticket_order(h, _np_ptr(out, ctypes.c_int32)))
+    return out
 
 
 def race_symm_spmv(h, x, y, stream=None):

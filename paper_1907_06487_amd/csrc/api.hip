@@ -99,6 +99,10 @@ struct race_schedule {
   int device = -1;
   DevBuf<int32_t> leaf_units, chunk_len, new2old, dep_idx;
   DevBuf<race::UnitDesc> unit_desc;
+  // ticket order of the dataflow product (units by ticket; empty: the
+  // layout's execution order) and its device copies with the inverse
+  std::vector<int32_t> ticket_unit;
+  DevBuf<int32_t> ticket_unit_d, unit_ticket_d;
   DevBuf<uint32_t> flow_state;  // done[n_units + n_zero_tasks], status, padding, counter (64-bit, 8-byte aligned)
   DevBuf<uint32_t> claims;      // claim words of static tickets (32 per CU), then the takeover count
   int32_t late_stride = 0;      // tests only (race_schedule_flow_test_late)
@@ -122,7 +126,7 @@ struct race_schedule {
   void free_device() {
     release(gs_leaf_lo); release(gs_leaf_hi); release(gs_halo_ptr); release(gs_halo); release(gs_row_ptr);
     release(gs_slot); release(gs_val); release(gs_diag);
-    release(leaf_units); release(unit_desc);
+    release(leaf_units); release(unit_desc); release(ticket_unit_d); release(unit_ticket_d);
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
@@ -354,6 +358,19 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   return RACE_OK;
 }
 
+}  // extern "C"
+
+// The ticket order's device arrays: unit of each ticket and its inverse.
+static void ticket_arrays(race_schedule_t s, std::vector<int32_t>& tu, std::vector<int32_t>& ut) {
+  const size_t n_units = s->L.unit_lo.size();
+  tu.resize(n_units);
+  ut.resize(n_units);
+  for (size_t i = 0; i < n_units; ++i) tu[i] = s->ticket_unit.empty() ? static_cast<int32_t>(i) : s->ticket_unit[i];
+  for (size_t i = 0; i < n_units; ++i) ut[static_cast<size_t>(tu[i])] = static_cast<int32_t>(i);
+}
+
+extern "C" {
+
 int race_schedule_upload(race_schedule_t s) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (s->uploaded) return RACE_OK;
@@ -402,6 +419,12 @@ int race_schedule_upload(race_schedule_t s) {
   UP(lane_slot, L.lane_slot)
   UP(sell_slot, L.sell_slot)
   UP(dep_idx, L.dep_idx)
+  {
+    std::vector<int32_t> tu, ut;
+    ticket_arrays(s, tu, ut);
+    UP(ticket_unit_d, tu)
+    UP(unit_ticket_d, ut)
+  }
   {
     // done[] per unit and clearing task, then status, then an aligned 64-bit counter
     const size_t words = (L.unit_lo.size() + static_cast<size_t>(L.n_zero_tasks) + 2 + 1) / 2 * 2 + 2;
@@ -539,10 +562,78 @@ int race_schedule_simulate(race_schedule_t s, const float* cost, double flush_fr
   if (!(flush_frac >= 0.0 && flush_frac <= 1.0)) return fail(RACE_EINVAL, "flush_frac must be in [0, 1]");
   if (workers < 1) return fail(RACE_EINVAL, "workers must be >= 1");
   try {
-    *makespan = race::simulate(s->L, cost, flush_frac, workers);
+    *makespan = race::simulate(s->L, cost, flush_frac, workers, s->ticket_unit);
   } catch (const std::bad_alloc&) {
     return fail(RACE_ENOMEM, "out of host memory");
   }
+  return RACE_OK;
+}
+
+int race_schedule_set_ticket_order(race_schedule_t s, const int32_t* ticket_unit) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, "a distance-1 schedule has no dataflow tickets");
+  const race::Layout& L = s->L;
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  std::vector<int32_t> order;
+  try {
+    if (ticket_unit) {
+      // a permutation of the units in which every conflict edge points to an earlier ticket
+      std::vector<int32_t> pos(static_cast<size_t>(n_units), -1);
+      for (int32_t i = 0; i < n_units; ++i) {
+        const int32_t u = ticket_unit[i];
+        if (u < 0 || u >= n_units || pos[u] >= 0) return fail(RACE_EINVAL, "ticket_unit is not a permutation of the units");
+        pos[u] = i;
+      }
+      for (int32_t u = 0; u < n_units; ++u)
+        for (int32_t i = L.dep_ptr[u]; i < L.dep_ptr[u + 1]; ++i)
+          if (L.dep_idx[i] < n_units && pos[L.dep_idx[i]] > pos[u])
+            return fail(RACE_EINVAL, "unit " + std::to_string(u) + " would take its ticket before unit " +
+                                         std::to_string(L.dep_idx[i]) + ", which it waits for");
+      order.assign(ticket_unit, ticket_unit + n_units);
+    }
+    if (s->uploaded && n_units > 0) {
+      std::vector<int32_t> keep;
+      keep.swap(s->ticket_unit);
+      s->ticket_unit = order;
+      std::vector<int32_t> tu, ut;
+      ticket_arrays(s, tu, ut);
+      hipError_t e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(s->ticket_unit_d.p, tu.data(), sizeof(int32_t) * tu.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(s->unit_ticket_d.p, ut.data(), sizeof(int32_t) * ut.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        s->ticket_unit.swap(keep);
+        return hip_fail(e, "upload of the ticket order");
+      }
+    } else {
+      s->ticket_unit = order;
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory");
+  }
+  return RACE_OK;
+}
+
+int race_schedule_order_tickets(race_schedule_t s, const float* cost) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!cost) return race_schedule_set_ticket_order(s, nullptr);
+  const int32_t n_units = static_cast<int32_t>(s->L.unit_lo.size());
+  for (int32_t u = 0; u < n_units; ++u)
+    if (!(cost[u] >= 0.0f) || std::isinf(cost[u])) return fail(RACE_EINVAL, "unit costs must be finite and >= 0");
+  std::vector<int32_t> order;
+  try {
+    race::critical_path_order(s->L, cost, order);
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory");
+  }
+  if (static_cast<int32_t>(order.size()) != n_units) return fail(RACE_EINTERNAL, "conflict edges form a cycle");
+  return race_schedule_set_ticket_order(s, order.data());
+}
+
+int race_schedule_ticket_order(race_schedule_t s, int32_t* ticket_unit) {
+  if (!s || !ticket_unit) return fail(RACE_EINVAL, "NULL argument");
+  const size_t n_units = s->L.unit_lo.size();
+  for (size_t i = 0; i < n_units; ++i)
+    ticket_unit[i] = s->ticket_unit.empty() ? static_cast<int32_t>(i) : s->ticket_unit[i];
   return RACE_OK;
 }
 
@@ -655,7 +746,8 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
   if (static_cast<size_t>(n_static) > claim_cap) return fail(RACE_EINTERNAL, "more workgroups than claim words");
   race::FlowArgs f{s->dep_idx.p, base, reinterpret_cast<uint64_t*>(base + counter_word), base + n_flags,
                    s->claims.p, s->claims.p + claim_cap, n_static, s->late_stride, trace, n_tickets, n_units,
-                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size())};
+                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size()),
+                   s->ticket_unit_d.p, s->unit_ticket_d.p};
   s->epoch += 1;
   if (s->epoch == 0) {  // wrapped: every done flag and claim must differ from the new epoch
     e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_flags, st);
@@ -887,7 +979,8 @@ int run_flow_noalloc(race_schedule_t s, const race::UnitArgs<ValT>& a, const dou
   race::FlowArgs f{s->dep_idx.p, scr, reinterpret_cast<uint64_t*>(scr + counter_word),
                    s->flow_state.p + n_flags,  // the schedule's own status word (race_schedule_check)
                    scr + claim_word, scr + claim_word + n_static, n_static, 0, nullptr, n_flags, n_units,
-                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size())};
+                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size()),
+                   s->ticket_unit_d.p, s->unit_ticket_d.p};
   e = race::launch_race_flow<ValT>(a, f, 1, x, y, 1, wmax, s->params.block_threads, grid, 1u, 0u, st);
   if (e != hipSuccess) return hip_fail(e, "RACE dataflow launch");
   return RACE_OK;

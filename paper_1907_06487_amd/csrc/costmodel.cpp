@@ -100,13 +100,15 @@ void unit_features(const Layout& L, const Tree& t, int32_t k, std::vector<float>
   }
 }
 
-double simulate(const Layout& L, const float* cost, double flush_frac, int32_t workers) {
+double simulate(const Layout& L, const float* cost, double flush_frac, int32_t workers,
+                const std::vector<int32_t>& order) {
   const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
   std::vector<double> finish(static_cast<size_t>(n_units), 0.0);
   std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
   for (int32_t w = 0; w < std::max(1, workers); ++w) free_at.push(0.0);
   double end = 0.0;
-  for (int32_t u = 0; u < n_units; ++u) {
+  for (int32_t i = 0; i < n_units; ++i) {
+    const int32_t u = order.empty() ? i : order[static_cast<size_t>(i)];
     const double start = free_at.top();
     free_at.pop();
     double ready = start + (1.0 - flush_frac) * cost[u];
@@ -225,6 +227,47 @@ void learned_row_loads(const Graph& g, int32_t n, const int32_t* row_ptr, const 
       const double share = cost_ns * (1.0 + upper_offd(order[p])) / wsum;
       m[order[p]] = std::max<int64_t>(1, std::llround(share));
     }
+  }
+}
+
+void critical_path_order(const Layout& L, const float* cost, std::vector<int32_t>& order) {
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  // successors: the units whose edges point to u (edges to clearing tasks
+  // carry no order among units)
+  std::vector<int32_t> succ_ptr(static_cast<size_t>(n_units) + 1, 0), indeg(static_cast<size_t>(n_units), 0);
+  for (int32_t u = 0; u < n_units; ++u)
+    for (int32_t i = L.dep_ptr[u]; i < L.dep_ptr[u + 1]; ++i)
+      if (L.dep_idx[i] < n_units) {
+        ++succ_ptr[L.dep_idx[i] + 1];
+        ++indeg[u];
+      }
+  for (int32_t u = 0; u < n_units; ++u) succ_ptr[u + 1] += succ_ptr[u];
+  std::vector<int32_t> succ(static_cast<size_t>(succ_ptr[n_units]));
+  {
+    std::vector<int32_t> fill(succ_ptr.begin(), succ_ptr.end() - 1);
+    for (int32_t u = 0; u < n_units; ++u)
+      for (int32_t i = L.dep_ptr[u]; i < L.dep_ptr[u + 1]; ++i)
+        if (L.dep_idx[i] < n_units) succ[fill[L.dep_idx[i]]++] = u;
+  }
+  // edges point to smaller units, so successors have larger indices
+  std::vector<double> bl(static_cast<size_t>(n_units), 0.0);
+  for (int32_t u = n_units - 1; u >= 0; --u) {
+    double m = 0.0;
+    for (int32_t i = succ_ptr[u]; i < succ_ptr[u + 1]; ++i) m = std::max(m, bl[succ[i]]);
+    bl[u] = static_cast<double>(cost[u]) + m;
+  }
+  auto lower = [&](int32_t a, int32_t b) { return bl[a] < bl[b] || (bl[a] == bl[b] && a > b); };
+  std::priority_queue<int32_t, std::vector<int32_t>, decltype(lower)> ready(lower);
+  for (int32_t u = 0; u < n_units; ++u)
+    if (indeg[u] == 0) ready.push(u);
+  order.clear();
+  order.reserve(static_cast<size_t>(n_units));
+  while (!ready.empty()) {
+    const int32_t u = ready.top();
+    ready.pop();
+    order.push_back(u);
+    for (int32_t i = succ_ptr[u]; i < succ_ptr[u + 1]; ++i)
+      if (--indeg[succ[i]] == 0) ready.push(succ[i]);
   }
 }
 

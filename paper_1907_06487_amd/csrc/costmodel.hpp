@@ -31,11 +31,24 @@ void mlp_forward_host(const float* theta, const float* X, int64_t n, float* y);
 //  9 log2(1 + units of the unit's phase)   10 phase / phases   11 log2(k)
 void unit_features(const Layout& L, const Tree& t, int32_t k, std::vector<float>& out);
 
-// Predicted makespan of a dataflow product: tickets in execution order on
-// `workers` workgroups; unit u computes for (1 - flush_frac) cost[u], waits
-// for its conflict edges, then flushes for flush_frac cost[u].  The clearing
-// tasks are not modelled (their edges count as met).
-double simulate(const Layout& L, const float* cost, double flush_frac, int32_t workers);
+// Predicted makespan of a dataflow product: tickets in the given order
+// (`order` lists the units by ticket; empty: the layout's execution order)
+// on `workers` workgroups, each taking the next ticket when it becomes free;
+// unit u computes for (1 - flush_frac) cost[u], waits for its conflict
+// edges, then flushes for flush_frac cost[u].  The clearing tasks are not
+// modelled (their edges count as met).
+double simulate(const Layout& L, const float* cost, double flush_frac, int32_t workers,
+                const std::vector<int32_t>& order);
+
+// Ticket order by critical path (Section 5's N_eff generalised to per-unit
+// costs, with the longest remaining path as list-scheduling priority): the
+// bottom level of a unit is its cost plus the largest bottom level among
+// the units whose conflict edges point to it (float64, cost[u] added to
+// that maximum); units are emitted one at a time, always the unit with the
+// largest bottom level among those whose edges all point to emitted units
+// (ties: lower unit index).  The result is a topological order of the
+// conflict edges, so every first-writer flag and edge stays valid.
+void critical_path_order(const Layout& L, const float* cost, std::vector<int32_t>& order);
 
 // Row loads from the network (see above); loads are in nanoseconds, >= 1.
 void learned_row_loads(const Graph& g, int32_t n, const int32_t* row_ptr, const int32_t* col, const float* theta,

@@ -44,8 +44,11 @@ struct UnitArgs {
 //
 // Clearing tasks: the first n_zero_tasks tickets each clear zero_chunk
 // entries of zero_idx (y entries whose first touch is a shared atomic add);
-// ticket n_zero_tasks + u is unit u.  A task's completion flag is
-// done[n_units + task].
+// ticket n_zero_tasks + i runs unit ticket_unit[i] (unit_ticket is the
+// inverse).  The order is a topological order of the conflict edges (every
+// edge points to an earlier ticket): the layout's execution order, or one
+// chosen by critical path.  A task's completion flag is done[n_units + task],
+// a unit's done[unit].
 //
 // Static tickets: workgroup b starts on ticket b (b < n_static) after
 // claiming it, so the launch does not queue every workgroup on the counter
@@ -68,6 +71,8 @@ struct FlowArgs {
   int32_t zero_chunk;
   const int32_t* zero_idx;
   int64_t n_zero;
+  const int32_t* ticket_unit;  // n_units: unit of ticket n_zero_tasks + i
+  const int32_t* unit_ticket;  // n_units: inverse of ticket_unit
 };
 
 // One matrix of a batch: its layout, conflict edges, completion flags (a

@@ -492,12 +492,9 @@ __device__ __forceinline__ void clear_task(const int32_t* __restrict__ zero_idx,
 constexpr int kSetAside = 8;          // tickets a workgroup can set aside to run an ownerless one first
 constexpr uint32_t kOwnerCheck = 64;  // polls of a flag between checks that its ticket has an owner
 
-// Ticket of completion flag v (units follow the clearing tasks) and back.
+// Ticket of completion flag v (units follow the clearing tasks).
 __device__ __forceinline__ int32_t ticket_of_flag(const FlowArgs& f, int32_t v) {
-  return v < f.n_units ? v + f.n_zero_tasks : v - f.n_units;
-}
-__device__ __forceinline__ int32_t flag_of_ticket(const FlowArgs& f, int32_t t) {
-  return t < f.n_zero_tasks ? f.n_units + t : t - f.n_zero_tasks;
+  return v < f.n_units ? f.unit_ticket[v] + f.n_zero_tasks : v - f.n_units;
 }
 
 // Claims static ticket t for this launch: true when no workgroup had it yet.
@@ -521,7 +518,6 @@ __device__ __forceinline__ int32_t wait_edges(const FlowArgs& f, int32_t d0, int
   for (;;) {
     for (int32_t i = d0 + tid; i < d1; i += nthr) {
       const int32_t v = f.dep_idx[i];
-      const int32_t tv = ticket_of_flag(f, v);
       uint32_t spins = 0;
       while (coherent_load(f.done + v) != epoch) {
         __builtin_amdgcn_s_sleep(1);
@@ -529,9 +525,12 @@ __device__ __forceinline__ int32_t wait_edges(const FlowArgs& f, int32_t d0, int
           atomicOr(f.status, 1u);
           break;
         }
-        if (may_take && tv < f.n_static && spins % kOwnerCheck == 0 && coherent_load(f.claim + tv) != epoch) {
-          atomicMin(s_red, tv);
-          break;
+        if (may_take && spins % kOwnerCheck == 0) {
+          const int32_t tv = ticket_of_flag(f, v);
+          if (tv < f.n_static && coherent_load(f.claim + tv) != epoch) {
+            atomicMin(s_red, tv);
+            break;
+          }
         }
       }
     }
@@ -596,8 +595,9 @@ __device__ __forceinline__ int32_t next_ticket(const FlowArgs& f, uint32_t epoch
 }
 
 // Dataflow execution in one persistent launch.  Tickets are the clearing
-// tasks and the units in execution order (phase, then heaviest leaf first,
-// a leaf's units in row order).  Workgroup b starts on static ticket b,
+// tasks, then the units in ticket order (by default the execution order:
+// phase, then heaviest leaf first, a leaf's units in row order; or any other
+// topological order of the conflict edges).  Workgroup b starts on static ticket b,
 // later tickets come from a counter once every static ticket is claimed.  A
 // unit computes right away and, before its flush, waits until every earlier
 // unit whose touch set meets its own has published completion (the conflict
@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(1024) race_flow_kernel(UnitArgs<ValT> a, FlowA
       t = -1;
       continue;
     }
-    const int32_t u = t - f.n_zero_tasks;
+    const int32_t u = uniform_load(f.ticket_unit, t - f.n_zero_tasks);
     const uint64_t t0 = f.trace ? wall_clock() : 0;
     // the unit's arithmetic needs nothing from other units; only its flush
     // must follow the earlier units it conflicts with

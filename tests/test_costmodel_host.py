@@ -150,6 +150,71 @@ def test_simulate_matches_oracle(name, make, kw, workers):
         s.close()
 
 
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_critical_path_order_matches_oracle(name, make, kw):
+    """The library's critical-path ticket order is the oracle's, bit for bit,
+    on conflict edges derived independently from the flags; the predicted
+    makespan under that order matches the oracle's simulation."""
+    m = make()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, **kw)
+    try:
+        u = s.units()
+        n_units = len(u["lo"])
+        deps = independent_deps(u)
+        assert list(s.ticket_order()) == list(range(n_units))
+        for seed in range(3):
+            cost = np.random.default_rng(seed).uniform(0.5, 3.0, n_units).astype(np.float32)
+            if seed == 2:
+                cost[:] = 1.0  # all ties: bottom levels are path lengths
+            s.order_tickets(cost)
+            got = list(s.ticket_order())
+            want = D.critical_path_order([float(c) for c in cost], deps)
+            assert got == want
+            frac = 0.3
+            c64 = cost.astype(np.float64)
+            ms = s.simulate(cost, frac, 16)
+            ref, _ = D.makespan(list((1 - frac) * c64), list(frac * c64), deps, 16, want)
+            assert ms == pytest.approx(ref, rel=1e-12)
+        s.order_tickets(None)
+        assert list(s.ticket_order()) == list(range(n_units))
+    finally:
+        s.close()
+
+
+def test_set_ticket_order_validation():
+    m = matgen.stencil3d_27pt(16, seed=3)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, n_workers=64, window_max=256)
+    try:
+        u = s.units()
+        n_units = len(u["lo"])
+        deps = independent_deps(u)
+        v = next(i for i in range(n_units) if deps[i])
+        bad = list(range(n_units))
+        d = deps[v][0]
+        bad[d], bad[v] = bad[v], bad[d]  # v before a unit it waits for
+        for order in (bad, list(range(n_units - 1)) + [0], [n_units] + list(range(1, n_units))):
+            with pytest.raises(_lib.RaceError) as e:
+                s.set_ticket_order(np.asarray(order, np.int32))
+            assert e.value.code == -1
+        assert list(s.ticket_order()) == list(range(n_units))  # a refused order changes nothing
+        with pytest.raises(_lib.RaceError):
+            s.order_tickets(np.full(n_units, np.nan, np.float32))
+        # any topological order is accepted, e.g. dependency depth first, then descending unit
+        depth = _depth(deps)
+        rev = sorted(range(n_units), key=lambda i: (depth[i], -i))
+        s.set_ticket_order(np.asarray(rev, np.int32))
+        assert list(s.ticket_order()) == rev
+    finally:
+        s.close()
+
+
+def _depth(deps):
+    d = [0] * len(deps)
+    for u in range(len(deps)):
+        d[u] = max([d[x] + 1 for x in deps[u]], default=0)
+    return d
+
+
 def _constant_net(log_cost):
     theta = np.zeros(M.N_PARAMS, dtype=np.float32)
     theta[-1] = log_cost

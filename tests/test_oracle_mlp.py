@@ -203,3 +203,103 @@ def test_makespan_lower_bounds():
         for u in range(n):
             longest[u] = max([c[u]] + [longest[d] for d in deps[u]]) + f[u]
         assert ms >= max(longest) - 1e-9
+
+
+# --- critical-path ticket order ---------------------------------------------
+
+def _all_paths_longest(cost, deps):
+    """Tiny DAGs: the longest path from every unit to a sink by enumerating
+    every path explicitly (no memoisation, no shared maxima)."""
+    n = len(cost)
+    succ = [[v for v in range(n) if u in deps[v]] for u in range(n)]
+    out = []
+    for u in range(n):
+        best = 0.0
+        stack = [(u, cost[u])]
+        while stack:
+            w, acc = stack.pop()
+            if not succ[w]:
+                best = max(best, acc)
+            for v in succ[w]:
+                stack.append((v, acc + cost[v]))
+        out.append(best)
+    return out
+
+
+def test_bottom_levels_equal_longest_paths_by_enumeration():
+    rng = np.random.default_rng(21)
+    for trial in range(100):
+        n = int(rng.integers(1, 9))
+        cost = [float(v) for v in rng.integers(1, 10, n)]  # integers: sums are exact in any order
+        deps = [sorted(set(rng.integers(0, u, size=int(rng.integers(0, 3))).tolist())) if u else [] for u in range(n)]
+        assert D.bottom_levels(cost, deps) == _all_paths_longest(cost, deps)
+
+
+def test_critical_path_order_closed_forms():
+    # independent units: descending cost, ties to the lower index
+    assert D.critical_path_order([1.0, 5.0, 3.0, 5.0], [[], [], [], []]) == [1, 3, 2, 0]
+    # a chain has one order
+    assert D.critical_path_order([1.0, 1.0, 1.0], [[], [0], [1]]) == [0, 1, 2]
+    # two roots: the one heading the longer chain goes first even though it is cheaper
+    #   0 (cost 1) -> 2 (cost 10);  1 (cost 5) alone
+    assert D.critical_path_order([1.0, 5.0, 10.0], [[], [], [0]]) == [0, 2, 1]
+    # fork-join: 0 -> {1 (2), 2 (7)} -> 3; after 0, unit 2 precedes unit 1
+    assert D.critical_path_order([1.0, 2.0, 7.0, 1.0], [[], [0], [0], [1, 2]]) == [0, 2, 1, 3]
+
+
+def test_critical_path_order_is_topological_and_greedy():
+    rng = np.random.default_rng(22)
+    for trial in range(100):
+        n = int(rng.integers(1, 30))
+        cost = list(rng.uniform(0.1, 5, n))
+        deps = [sorted(set(rng.integers(0, u, size=int(rng.integers(0, 3))).tolist())) if u else [] for u in range(n)]
+        order = D.critical_path_order(cost, deps)
+        assert sorted(order) == list(range(n))
+        pos = {u: i for i, u in enumerate(order)}
+        assert all(pos[d] < pos[u] for u in range(n) for d in deps[u])
+        # every step took a ready unit of maximal bottom level
+        b = D.bottom_levels(cost, deps)
+        done = set()
+        for u in order:
+            ready = [v for v in range(n) if v not in done and all(d in done for d in deps[v])]
+            assert b[u] == max(b[v] for v in ready)
+            done.add(u)
+
+
+def _priority_order(prio, deps):
+    n = len(prio)
+    done, order = set(), []
+    while len(order) < n:
+        ready = [v for v in range(n) if v not in done and all(d in done for d in deps[v])]
+        u = max(ready, key=lambda v: (prio[v], -v))
+        done.add(u)
+        order.append(u)
+    return order
+
+
+def test_critical_path_order_planted_priorities_fail():
+    """Plausible mistakes fail the closed forms above: priority by a unit's
+    own cost, and bottom levels that forget the unit's own cost."""
+    cost, deps = [1.0, 5.0, 10.0], [[], [], [0]]
+    assert D.critical_path_order(cost, deps) == [0, 2, 1]
+    assert _priority_order(cost, deps) == [1, 0, 2]
+    cost, deps = [1.0, 2.0, 7.0, 1.0], [[], [0], [0], [1, 2]]
+    no_own = [b - c for b, c in zip(D.bottom_levels(cost, deps), cost)]
+    assert _priority_order(no_own, deps) == [0, 1, 2, 3] != D.critical_path_order(cost, deps)
+
+
+def test_makespan_with_order_is_the_reordered_simulation():
+    """Reordering is the same simulation over the renumbered units."""
+    rng = np.random.default_rng(23)
+    for trial in range(50):
+        n = int(rng.integers(1, 12))
+        c = list(rng.uniform(0.1, 3, n))
+        f = list(rng.uniform(0.1, 1, n))
+        deps = [sorted(set(rng.integers(0, u, size=int(rng.integers(0, 3))).tolist())) if u else [] for u in range(n)]
+        order = D.critical_path_order(list(np.add(c, f)), deps)
+        pos = {u: i for i, u in enumerate(order)}
+        c2 = [c[u] for u in order]
+        f2 = [f[u] for u in order]
+        deps2 = [sorted(pos[d] for d in deps[u]) for u in order]
+        w = int(rng.integers(1, 4))
+        assert D.makespan(c, f, deps, w, order)[0] == pytest.approx(_brute_force(c2, f2, deps2, w))
