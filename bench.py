@@ -49,7 +49,7 @@ def kernel_source_hash():
     """Hash of the sources that decide what the RACE kernel moves."""
     import hashlib
     h = hashlib.sha256()
-    for f in ["race_kernels.hip", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp", "api.hip"]:
+    for f in ["race_kernels.hip", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp"]:
         with open(os.path.join(ROOT, "paper_1907_06487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -100,7 +100,7 @@ def attainable_bandwidth(torch, gib=4, reps=10):
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     res = {"bytes": nbytes, "grids": {}}
     best_r = best_c = (0.0, 0)
-    for mult in (4, 8, 16, 32):
+    for mult in (8, 16, 32, 64, 128):
         grid = cus * mult
         tr = time_ring(lambda x, y: R.race_stream_read(src, sink, grid), [0], [0], reps, 2, torch)
         tc = time_ring(lambda x, y: R.race_stream_copy(src, dst, grid), [0], [0], reps, 2, torch)
@@ -475,6 +475,72 @@ def run_complex(args, torch):
     s.close()
 
 
+def run_gs(args, torch):
+    """Symmetric Gauss-Seidel sweeps (forward then backward) over a
+    distance-1 RACE schedule of the workload's matrix (diagonal made
+    dominant): time per symmetric sweep, checked against the serial C
+    oracle over the same row order.  One JSON line.  A sweep direction
+    reads the off-diagonal entries of the full matrix (value + column),
+    the diagonal, b and x, and writes x: 12 (nnz_full - N) + 4 (N + 1) + 32 N
+    bytes in CRS."""
+    import numpy as np
+
+    import matgen
+    import paper_1907_06487_amd as R
+    from oracle import gauss_seidel as G
+    from oracle import symmspmv as O
+    m, desc = workload(args.workload)
+    absrow = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.ones(m.n))
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    d = rows == m.col
+    v = m.val.copy()
+    v[d] = 1.0 + absrow[rows[d]] - np.abs(m.val[d])
+    m = matgen.UpperCSR(m.n, m.row_ptr, m.col, v, m.name + "_dominant")
+    t0 = time.perf_counter()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, dist_k=1, n_workers=args.gs_workers, root=args.root,
+                   level_order=args.level_order)
+    st = s.stats()
+    log(f"Gauss-Seidel schedule built in {time.perf_counter() - t0:.2f}s: leaves {st['n_leaves']}, phases "
+        f"{st['n_phases_used']}, largest window {st['max_window']}")
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    b = rng.uniform(-1, 1, m.n)
+    bd = torch.as_tensor(b, device=dev)
+    bp = torch.empty_like(bd)
+    s.permute(bd, bp, True)
+    xp = torch.zeros_like(bp)
+    s.gauss_seidel(bp, xp)
+    x = torch.empty_like(xp)
+    s.permute(xp, x, False)
+    torch.cuda.synchronize()
+    tr = s.tree()
+    node, phase = s.leaves()
+    order = G.race_order(s.perm(), np.asarray(tr["lo"])[node], np.asarray(tr["hi"])[node], phase)
+    ref = G.symmetric_sweep_c(m.n, m.row_ptr, m.col, m.val, b, np.zeros(m.n), order)
+    err = float(np.max(np.abs(x.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    ms = time_ring(lambda x_, y_: s.gauss_seidel(bp, xp), [0], [0], args.steps, args.warmup, torch)
+    nnz_full = st["nnz_full"]
+    flops = 2 * 2 * nnz_full  # both directions: a multiply-add per off-diagonal, the diagonal division
+    bytes_min = 2 * (12 * (nnz_full - m.n) + 4 * (m.n + 1) + 32 * m.n)
+    achieved = bytes_min / (ms * 1e-3) / 1e9
+    log(f"Gauss-Seidel {args.workload}: {ms * 1e3:.1f} us per symmetric sweep, {flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, "
+        f"{achieved:.1f} GB/s algorithmic, error vs oracle {err:.2e}")
+    out = {
+        "metric": "symmetric Gauss-Seidel sweeps over a distance-1 RACE schedule, GFLOP/s",
+        "value": round(flops / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload + "_dominant", "description": desc + ", diagonal 1 + row abs-sum",
+                   "n": m.n, "nnz_full": nnz_full, "n_workers": args.gs_workers, "leaves": st["n_leaves"],
+                   "phases": st["n_phases_used"], "max_window": st["max_window"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_min},
+        "error": {"norm": err}, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -496,6 +562,12 @@ def main():
     ap.add_argument("--dist-k", type=int, default=2, help="distance of the coloring (2 for SymmSpMV; 3..8 wider)")
     ap.add_argument("--global-lb", type=int, default=0, choices=[0, 1],
                     help="also run Algorithm \"Load Balancing\" over all children of every refined node")
+    ap.add_argument("--low-locality", default="auto", choices=["auto", "race", "expanded"],
+                    help="single-vector products: the library's choice (auto: a CRS product of the expanded permuted "
+                         "matrix when the schedule predicts no window reuse), the RACE kernels, or always expanded")
+    ap.add_argument("--gs", action="store_true",
+                    help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
+    ap.add_argument("--gs-workers", type=int, default=4096, help="--gs: n_workers of the distance-1 schedule")
     ap.add_argument("--order", default="default", choices=["default", "critical"],
                     help="dataflow ticket order: the layout's execution order, or the critical path of unit costs "
                          "measured by traced products on this device (part of the schedule's preparation)")
@@ -511,6 +583,9 @@ def main():
     ap.add_argument("--spmm-k", default="", help="SymmSpMM on the workload's matrix instead, e.g. 4,16 (one line each)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a device copy of this many MiB (reference for the traffic counters)")
+    ap.add_argument("--calibrate-stream", type=int, default=0,
+                    help="also run the library's read-only and copy stream kernels over this many MiB, three "
+                         "times each (references for FETCH_SIZE and WRITE_SIZE larger than every cache)")
     ap.add_argument("--sweep", default="",
                     help="n_workers:block[:window[:mode[:shared]]] list, e.g. 256:256,512:512:2048:phases:0 (stderr)")
     args = ap.parse_args()
@@ -537,6 +612,9 @@ def main():
     if args.value_type.startswith("c"):
         run_complex(args, torch)
         return
+    if args.gs:
+        run_gs(args, torch)
+        return
     if args.spmm_k:
         m, _ = workload(args.workload)
         for k in (int(v) for v in args.spmm_k.split(",")):
@@ -550,12 +628,14 @@ def main():
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
                    block_threads=args.block, window_max=args.window, value_type=args.value_type,
                    exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics), root=args.root,
-                   level_order=args.level_order, dist_k=args.dist_k, global_lb=bool(args.global_lb))
+                   level_order=args.level_order, dist_k=args.dist_k, global_lb=bool(args.global_lb),
+                   low_locality=args.low_locality)
     t_build = time.perf_counter() - t0
     st = s.stats()
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
         "n_levels0", "depth", "n_leaves", "n_phases_used", "n_units", "max_window", "eta", "halo_total",
-        "sell_elems", "bytes_min", "bytes_kernel", "n_deps", "shared_touches", "n_zeroed")}))
+        "sell_elems", "bytes_min", "bytes_kernel", "n_deps", "shared_touches", "n_zeroed", "product_path",
+        "expanded_lanes")}))
 
     nring = max(2, -(-RING_BYTES // (8 * m.n)))
     gen = torch.Generator(device=dev)
@@ -604,9 +684,33 @@ def main():
     # the dataflow mode is one launch (it clears shared-first entries in its
     # first tickets); the phase mode launches once per phase plus the clearing
     launches = 1 if args.exec_mode == "flow" else st["n_phases_used"] + (1 if st["n_zeroed"] else 0)
-    log(f"RACE: {ms * 1e3:.2f} us/product (median {ms_median * 1e3:.2f}), {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s "
+    path_name = "expanded CRS product" if st["product_path"] == 1 else "RACE"
+    log(f"{path_name}: {ms * 1e3:.2f} us/product (median {ms_median * 1e3:.2f}), {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s "
         f"algorithmic ({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes "
         f"{st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
+
+    race_kernels = None
+    if st["product_path"] == 1:
+        # the schedule predicted no window reuse and runs the expanded CRS
+        # product; the RACE kernels on the same schedule, for the record
+        s3 = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
+                        block_threads=args.block, window_max=args.window, value_type=args.value_type,
+                        exec_mode=args.exec_mode, shared_atomics=bool(args.shared_atomics), root=args.root,
+                        level_order=args.level_order, dist_k=args.dist_k, global_lb=bool(args.global_lb),
+                        low_locality="race")
+        s3.spmv(xs[0], ys[0])
+        torch.cuda.synchronize()
+        e3 = O.errors(ys[0].cpu().numpy(), y_ref[perm])[0]
+        ms3 = time_ring(lambda x, y: s3.spmv(x, y), xs, ys, args.steps, args.warmup, torch)
+        s3.check()
+        share = st["shared_touches"] / (m.n + st["halo_total"])
+        race_kernels = {"us": ms3 * 1e3, "gflops": flops / (ms3 * 1e-3) / 1e9, "err_norm": e3,
+                        "shared_touch_share": share,
+                        "note": "RACE kernels on this matrix: shared window entries combine through global float64 "
+                                "atomics, so the library runs the expanded CRS product instead"}
+        log(f"RACE kernels on the same schedule: {ms3 * 1e3:.2f} us ({share * 100:.1f}% of window touches shared), "
+            f"error {e3:.2e}; expanded CRS product: {ms * 1e3:.2f} us")
+        s3.close()
 
     for item in filter(None, args.sweep.split(",")):
         nt, blk = (int(v) for v in item.split(":")[:2])
@@ -634,6 +738,20 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         log(f"calibration: elementwise copy reading and writing {nbytes} bytes, 3 times")
+    if args.calibrate_stream:
+        nbytes = args.calibrate_stream << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        sink = torch.zeros(4, dtype=torch.int32, device=dev)
+        grid = torch.cuda.get_device_properties(dev).multi_processor_count * 32
+        for _ in range(3):
+            R.race_stream_read(src, sink, grid)
+        for _ in range(3):
+            R.race_stream_copy(src, dst, grid)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        log(f"calibration: stream read of {nbytes} bytes (3 times), stream copy of {nbytes} bytes each way (3 times)")
 
     baselines = {}
     if not args.no_baselines:
@@ -664,7 +782,7 @@ def main():
 
     # HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     # runs, valid only while the kernel, layout and parameters are unchanged
-    traffic = None
+    traffic = traffic_rw = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if os.path.exists(tpath):
         tr = json.load(open(tpath))
@@ -672,9 +790,11 @@ def main():
                 and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
                 and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode
                 and tr.get("shared_atomics", 0) == args.shared_atomics and tr.get("root", "first") == args.root
-                and tr.get("level_order", "input") == args.level_order and args.dist_k == 2)
+                and tr.get("level_order", "input") == args.level_order and args.dist_k == 2
+                and st["product_path"] == 0)
         if same and args.value_type == "f64":
             traffic = tr.get("bytes_per_launch")
+            traffic_rw = {"read": tr.get("read_bytes_per_launch"), "write": tr.get("write_bytes_per_launch")}
 
     out = {
         "metric": METRIC, "value": round(gflops, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -688,14 +808,17 @@ def main():
                    "phases": st["n_phases_used"], "leaves": st["n_leaves"], "eta": st["eta"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "launches_per_step": launches,
+                     "traffic": traffic, "traffic_read_write": traffic_rw, "launches_per_step": launches,
                      "bytes_per_step": bytes_alg, "kernel_format_bytes_per_step": st["bytes_kernel"],
                      "attainable_read_GBs": attain["read_GBs"] if attain else None,
                      "attainable_copy_GBs": attain["copy_GBs"] if attain else None,
                      "frac_of_attainable_read": round(achieved / attain["read_GBs"], 4) if attain else None,
                      "ms_per_step_median": ms_median},
         "schedule": {"shared_touches": st["shared_touches"], "halo_total": st["halo_total"],
-                     "units": st["n_units"], "global_lb": args.global_lb},
+                     "units": st["n_units"], "global_lb": args.global_lb,
+                     "product_path": "expanded CRS" if st["product_path"] == 1 else "RACE kernels",
+                     "expanded_lanes": st["expanded_lanes"]},
+        "race_kernels": race_kernels,
         "attainable": attain,
         "error": {"norm": err_norm, "componentwise": err_comp},
         "baselines": baselines,

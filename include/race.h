@@ -90,6 +90,13 @@ typedef struct {
                               discovery order (each vertex's new neighbours by increasing degree, ties by index), the
                               order a bandwidth-reducing level construction gives; it keeps the unit windows local
                               when the input order is not */
+  int32_t low_locality;    /* what race_symm_spmv and race_symm_spmv_noalloc run when the layout predicts no reuse
+                              in the unit windows (more than half of all window touches are shared entries, which
+                              the RACE kernels add with global float64 atomics, about 24 G/s on this chip): 0
+                              (default) = the RACE kernels anyway; 1 = a full-matrix CRS product of the permuted
+                              matrix (the schedule then also holds the expanded matrix; value_type 0 or 1; stats
+                              product_path 1); 2 = the CRS product always (tests).  SymmSpMM with k > 1, traced
+                              products, batches and complex values always run the RACE kernels */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */
@@ -125,6 +132,9 @@ typedef struct {
   int64_t wall_clock_hz;     /* rate of the device clock used by traced products (set by race_schedule_upload) */
   int64_t shared_touches;    /* (unit, index) touches combined by atomic adds (shared_atomics) */
   int64_t n_zeroed;          /* y entries cleared before each product (first touched by a shared unit) */
+  int32_t product_path;      /* what race_symm_spmv runs: 0 the RACE kernels, 1 the expanded CRS product
+                                (race_params.low_locality) */
+  int32_t expanded_lanes;    /* lanes per row of the expanded CRS product (0 when not expanded) */
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by

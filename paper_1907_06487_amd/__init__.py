@@ -25,12 +25,16 @@ BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
-                shared_atomics=True, cost_model=None, rhs_tile=0, root="first", level_order="input", dist_k=2):
+                shared_atomics=True, cost_model=None, rhs_tile=0, root="first", level_order="input", dist_k=2,
+                low_locality="race"):
     """race_params from keywords.  balance="model" needs cost_model: the
     network's MLP_PARAMS float32 weights (kept alive on the returned struct).
     root: "first" (stage-0 islands start at their first vertex in the input
     order) or "peripheral" (at a pseudo-peripheral vertex).  level_order:
-    "input" or "cm" (Cuthill-McKee discovery order inside stage-0 levels)."""
+    "input" or "cm" (Cuthill-McKee discovery order inside stage-0 levels).
+    low_locality: "race" (always the RACE kernels), "auto" (single-vector
+    products switch to a full-matrix CRS product of the permuted matrix when
+    the layout predicts no window reuse) or "expanded" (always that)."""
     p = race_params_default()
     p.dist_k = int(dist_k)
     p.n_workers = int(n_workers)
@@ -45,6 +49,7 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.rhs_tile = int(rhs_tile)
     p.root_mode = {"first": 0, "peripheral": 1}[root]
     p.level_order = {"input": 0, "cm": 1}[level_order]
+    p.low_locality = {"race": 0, "auto": 1, "expanded": 2}[low_locality]
     if cost_model is not None:
         import ctypes
 

@@ -52,7 +52,7 @@ class race_params(ctypes.Structure):
         ("window_max", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("eps", ctypes.c_double * 8),
         ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("shared_atomics", ctypes.c_int32), ("rhs_tile", ctypes.c_int32),
-        ("root_mode", ctypes.c_int32), ("level_order", ctypes.c_int32),
+        ("root_mode", ctypes.c_int32), ("level_order", ctypes.c_int32), ("low_locality", ctypes.c_int32),
     ]
 
 
@@ -67,7 +67,7 @@ class race_stats(ctypes.Structure):
         ("halo_rmw", ctypes.c_int64), ("bytes_min", ctypes.c_int64), ("bytes_kernel", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64), ("shared_touches", ctypes.c_int64),
-        ("n_zeroed", ctypes.c_int64),
+        ("n_zeroed", ctypes.c_int64), ("product_path", ctypes.c_int32), ("expanded_lanes", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -116,6 +116,13 @@ struct race_schedule {
   DevBuf<float> lane_diag32, sell_val32;
   DevBuf<race::Cplx<false>> lane_diagc, sell_valc;  // complex values (value_type 2 or 3)
   DevBuf<double> tiles_x, tiles_y;  // column tiles of X and Y for products with many passes (grown on demand)
+  // the full permuted matrix in CRS, when single-vector products run as a
+  // CRS product (race_params.low_locality)
+  bool expanded = false;
+  int32_t exp_lpr = 0;
+  DevBuf<int32_t> exp_rp, exp_col;
+  DevBuf<double> exp_val64;
+  DevBuf<float> exp_val32;
   // distance-1 schedules: the Gauss-Seidel layout and its device copies
   bool gs = false;
   race::GsLayout G;
@@ -131,6 +138,7 @@ struct race_schedule {
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
+    release(exp_rp); release(exp_col); release(exp_val64); release(exp_val32);
     uploaded = false;
   }
 };
@@ -192,6 +200,7 @@ int race_params_default(race_params* p) {
   p->rhs_tile = 0;
   p->root_mode = 0;
   p->level_order = 0;
+  p->low_locality = 0;
   return RACE_OK;
 }
 
@@ -220,6 +229,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (prm.rhs_tile < 0 || prm.rhs_tile > 16) return fail(RACE_EINVAL, "rhs_tile must be in 0..16");
   if (prm.root_mode < 0 || prm.root_mode > 1) return fail(RACE_EINVAL, "root_mode must be 0 or 1");
   if (prm.level_order < 0 || prm.level_order > 1) return fail(RACE_EINVAL, "level_order must be 0 or 1");
+  if (prm.low_locality < 0 || prm.low_locality > 2) return fail(RACE_EINVAL, "low_locality must be 0, 1 or 2");
   if (prm.window_max == 0) prm.window_max = 3840;
   if (prm.window_max < 2 || prm.window_max > 8000) return fail(RACE_EINVAL, "window_max must be in 2..8000");
   if (prm.block_threads == 0) prm.block_threads = 256;
@@ -347,6 +357,14 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     st.n_deps = static_cast<int64_t>(L.dep_idx.size());
     st.flow_grid = 0;
     st.exec_mode = prm.exec_mode;
+    // no reuse in the windows: most touches of y are shared entries, added
+    // with global atomics; a CRS product of the expanded matrix needs none
+    const int64_t touches = static_cast<int64_t>(n) + st.halo_total;
+    s->expanded = !s->gs && prm.value_type <= 1 && n > 0 &&
+                  (prm.low_locality == 2 || (prm.low_locality == 1 && 2 * st.shared_touches > touches));
+    st.product_path = s->expanded ? 1 : 0;
+    st.expanded_lanes = s->expanded ? race::expanded_lanes(n, st.nnz_full) : 0;
+    s->exp_lpr = st.expanded_lanes;
   } catch (const std::bad_alloc&) {
     delete s;
     return fail(RACE_ENOMEM, "out of host memory while building the schedule");
@@ -359,6 +377,48 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
 }
 
 }  // extern "C"
+
+namespace race {
+// Lanes per row of the expanded CRS product: the smallest power of two of
+// at least half the mean row length, 4..32 (4 lanes on the 5-point stencil,
+// 16 on the irregular banded matrices, where the yardstick sweep finds 16
+// fastest and 32 about 10% slower).
+int32_t expanded_lanes(int32_t n, int64_t nnz_full) {
+  const double mean = n > 0 ? static_cast<double>(nnz_full) / n : 1.0;
+  int32_t l = 4;
+  while (l < 32 && 2.0 * l < mean) l *= 2;
+  return l;
+}
+}  // namespace race
+
+// The full permuted matrix in CRS from the permuted upper triangle: every
+// off-diagonal entry (r, c) also appears as (c, r); columns ascending.
+static void expand_permuted(const race::Layout& L, std::vector<int32_t>& rp, std::vector<int32_t>& col,
+                            std::vector<double>& val) {
+  const int32_t n = L.n;
+  rp.assign(static_cast<size_t>(n) + 1, 0);
+  for (int32_t r = 0; r < n; ++r)
+    for (int32_t i = L.prow_ptr[r]; i < L.prow_ptr[r + 1]; ++i) {
+      ++rp[r + 1];
+      if (L.pcol[i] != r) ++rp[L.pcol[i] + 1];
+    }
+  for (int32_t r = 0; r < n; ++r) rp[r + 1] += rp[r];
+  col.resize(static_cast<size_t>(rp[n]));
+  val.resize(static_cast<size_t>(rp[n]));
+  std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+  // rows in ascending order, so each row's lower entries arrive before its
+  // own (upper) ones, both ascending: the row ends up sorted
+  for (int32_t r = 0; r < n; ++r)
+    for (int32_t i = L.prow_ptr[r]; i < L.prow_ptr[r + 1]; ++i) {
+      const int32_t c = L.pcol[i];
+      col[fill[r]] = c;
+      val[fill[r]++] = L.pval[i];
+      if (c != r) {
+        col[fill[c]] = r;
+        val[fill[c]++] = L.pval[i];
+      }
+    }
+}
 
 // The ticket order's device arrays: unit of each ticket and its inverse.
 static void ticket_arrays(race_schedule_t s, std::vector<int32_t>& tu, std::vector<int32_t>& ut) {
@@ -430,6 +490,24 @@ int race_schedule_upload(race_schedule_t s) {
     const size_t words = (L.unit_lo.size() + static_cast<size_t>(L.n_zero_tasks) + 2 + 1) / 2 * 2 + 2;
     std::vector<uint32_t> zeros(words, 0u);
     UP(flow_state, zeros)
+  }
+  if (s->expanded) {
+    std::vector<int32_t> erp, ecol;
+    std::vector<double> eval;
+    try {
+      expand_permuted(L, erp, ecol, eval);
+    } catch (const std::bad_alloc&) {
+      s->free_device();
+      return fail(RACE_ENOMEM, "out of host memory while expanding the matrix");
+    }
+    UP(exp_rp, erp)
+    UP(exp_col, ecol)
+    if (s->params.value_type == 0) {
+      UP(exp_val64, eval)
+    } else {
+      std::vector<float> e32(eval.begin(), eval.end());
+      UP(exp_val32, e32)
+    }
   }
   e = hipDeviceGetAttribute(&s->n_cus, hipDeviceAttributeMultiprocessorCount, dev);
   int clock_khz = 0;
@@ -797,6 +875,17 @@ static int32_t rhs_tile(race_schedule_t s, int32_t k) {
 static const char* kDist1Product =
     "a distance-1 schedule serves Gauss-Seidel sweeps (race_symm_gs); SymmSpMV needs dist_k >= 2";
 
+// y = A x as a CRS product of the expanded permuted matrix (schedules whose
+// windows predict no reuse, race_params.low_locality).
+static int run_expanded(race_schedule_t s, const double* x, double* y, hipStream_t st) {
+  const hipError_t e =
+      s->params.value_type == 0
+          ? race::launch_csr_spmv<double>(s->tree.n, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, s->exp_lpr, st)
+          : race::launch_csr_spmv<float>(s->tree.n, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, s->exp_lpr, st);
+  if (e != hipSuccess) return hip_fail(e, "expanded CRS product launch");
+  return RACE_OK;
+}
+
 static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, uint64_t* trace, void* stream) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (s->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
@@ -804,6 +893,7 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
   if (s->tree.n == 0) return RACE_OK;
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
+  if (s->expanded && k == 1 && !trace) return run_expanded(s, x, y, static_cast<hipStream_t>(stream));
   if (s->params.value_type >= 2) {
     // complex: one vector of n interleaved (re, im) pairs, run as two columns
     if (k != 1) return fail(RACE_EUNSUPPORTED, "complex values take one right-hand side");
@@ -995,9 +1085,11 @@ int race_symm_spmv_noalloc(race_schedule_t s, const double* x, double* y, void* 
   if (s->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
   if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
   if (s->params.value_type > 1) return fail(RACE_EUNSUPPORTED, "race_symm_spmv_noalloc takes real values only");
-  if (s->params.exec_mode != 1) return fail(RACE_EUNSUPPORTED, "race_symm_spmv_noalloc runs the dataflow mode only");
   if (s->tree.n == 0) return RACE_OK;
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
+  // the expanded product uses no dataflow state
+  if (s->expanded) return run_expanded(s, x, y, static_cast<hipStream_t>(stream));
+  if (s->params.exec_mode != 1) return fail(RACE_EUNSUPPORTED, "race_symm_spmv_noalloc runs the dataflow mode only");
   if (rhs_tile(s, 1) < 1)
     return fail(RACE_EUNSUPPORTED, "a unit window does not fit the LDS; rebuild with a smaller window_max");
   int dev = 0;
@@ -1388,7 +1480,8 @@ int race_csr_spmv(race_csr_t h, const double* x, double* y, void* stream) {
   if (!h) return fail(RACE_EINVAL, "handle is NULL");
   if (h->atomic) return fail(RACE_ESTATE, "handle holds an upper triangle; use race_symm_spmv_atomic");
   if (h->n > 0 && (!x || !y)) return fail(RACE_EINVAL, "x or y is NULL");
-  hipError_t e = race::launch_csr_spmv(h->n, h->rp.p, h->col.p, h->val.p, x, y, h->lpr, static_cast<hipStream_t>(stream));
+  hipError_t e =
+      race::launch_csr_spmv<double>(h->n, h->rp.p, h->col.p, h->val.p, x, y, h->lpr, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "CSR SpMV launch");
   return RACE_OK;
 }

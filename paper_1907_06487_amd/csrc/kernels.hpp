@@ -160,8 +160,10 @@ hipError_t launch_race_batch(const BatchMat<ValT>* mats, const BatchArgs& b, int
 // replay it).
 hipError_t launch_clear_words(uint32_t* p, int64_t words, hipStream_t st);
 
-hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
+template <typename ValT>
+hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const ValT* val, const double* x,
                            double* y, int32_t lanes_per_row, hipStream_t st);
+int32_t expanded_lanes(int32_t n, int64_t nnz_full);
 hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                               double* y, int32_t lanes_per_row, hipStream_t st);
 hipError_t launch_permute(int32_t n, int32_t k, const int32_t* new2old, const double* in, double* out,

@@ -280,18 +280,21 @@ def test_race_full_size_3d27pt_128(nt, mode, block):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("value_type", ["f64", "f32"])
-def test_race_full_size_banded_4m(value_type):
+@pytest.mark.parametrize("value_type,path", [("f64", "race"), ("f32", "race"), ("f64", "auto"), ("f32", "auto")])
+def test_race_full_size_banded_4m(value_type, path):
     """Irregular banded N = 4M: FP64 values within the FP64 bound; FP32 values
     (promoted, FP64 accumulation) against the oracle on the same FP32-rounded
-    values, and their error against the FP64 matrix stated."""
+    values, and their error against the FP64 matrix stated.  With
+    low_locality=auto the schedule predicts no window reuse here and the
+    product runs as a CRS product of the expanded permuted matrix."""
     m = matgen.config_banded_4m()
-    print(f"case banded_4m {value_type}: n={m.n} nnz={m.nnz}", flush=True)
+    print(f"case banded_4m {value_type} {path}: n={m.n} nnz={m.nnz}", flush=True)
     x = matgen.rhs(m.n, 3)
     vals = m.val if value_type == "f64" else m.val.astype(np.float32).astype(np.float64)
-    y, st = run_race(m, x, n_workers=1024, value_type=value_type)
+    y, st = run_race(m, x, n_workers=1024, value_type=value_type, low_locality=path)
     print(f"  units={st['n_units']} leaves={st['n_leaves']} eta={st['eta']:.3f} shared={st['shared_touches']} "
-          f"zeroed={st['n_zeroed']}", flush=True)
+          f"zeroed={st['n_zeroed']} product_path={st['product_path']}", flush=True)
+    assert st["product_path"] == (1 if path == "auto" else 0)
     y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, vals, x)
     _check(y, y_ref, O.abs_product(m.n, m.row_ptr, m.col, vals, x), _full_row_len(m), f"banded_4m {value_type}")
     if value_type == "f32":
@@ -581,3 +584,52 @@ def test_batch_full_64(batch64, k):
         batch.close()
         for s in scheds:
             s.close()
+
+
+EXPANDED = [
+    ("banded_40k_w96_auto", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
+     dict(n_workers=16, window_max=96, low_locality="auto"), 1),
+    ("3d27pt_24_auto", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256, low_locality="auto"), 0),
+    ("3d27pt_24_expanded", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256, low_locality="expanded"), 1),
+    ("rand_nodiag_expanded", lambda: matgen.random_symmetric(300, 0.02, seed=9, with_diag=False),
+     dict(n_workers=12, low_locality="expanded"), 1),
+]
+
+
+@pytest.mark.parametrize("value_type", ["f64", "f32"])
+@pytest.mark.parametrize("name,make,params,path", EXPANDED, ids=[c[0] for c in EXPANDED])
+def test_expanded_product_path(name, make, params, path, value_type):
+    """Products of schedules that switch to the expanded CRS product (and of
+    those that do not) against the oracle, through race_symm_spmv and
+    race_symm_spmv_noalloc; SymmSpMM with several columns keeps the RACE
+    kernels on the same schedule."""
+    m = make()
+    vals = m.val if value_type == "f64" else m.val.astype(np.float32).astype(np.float64)
+    x = matgen.rhs(m.n, 41)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, value_type=value_type, **params)
+    try:
+        st = s.stats()
+        print(f"case {name} {value_type}: n={m.n} product_path={st['product_path']} lanes={st['expanded_lanes']}",
+              flush=True)
+        assert st["product_path"] == path
+        perm = s.perm()
+        y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, vals, x)[perm]
+        absax = O.abs_product(m.n, m.row_ptr, m.col, vals, x)[perm]
+        xd = torch.as_tensor(x, device=DEV)
+        xp = torch.empty_like(xd)
+        s.permute(xd, xp, True)
+        for entry in ("spmv", "noalloc"):
+            yp = torch.full_like(xp, float("nan"))
+            (s.spmv if entry == "spmv" else s.spmv_noalloc)(xp, yp)
+            torch.cuda.synchronize()
+            s.check()
+            _check(yp.cpu().numpy(), y_ref, absax, _full_row_len(m), f"{name} {value_type} {entry}")
+        X = torch.stack([xp, -xp, 2 * xp], dim=1).contiguous()
+        Y = torch.full_like(X, float("nan"))
+        s.spmm(X, Y)
+        torch.cuda.synchronize()
+        s.check()
+        for j, f in enumerate((1.0, -1.0, 2.0)):
+            _check(Y[:, j].cpu().numpy(), f * y_ref, abs(f) * absax, _full_row_len(m), f"{name} spmm col {j}")
+    finally:
+        s.close()

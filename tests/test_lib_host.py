@@ -323,3 +323,39 @@ def test_complex_schedules_host():
     p = R.make_params()
     p.value_type = 4
     _expect(-1, lambda: R.race_build_schedule(m.n, m.row_ptr, m.col, m.val, p))
+
+
+@pytest.mark.parametrize("name,make,kw,want", [
+    ("banded_40k_w96", lambda: matgen.banded_irregular(40000, seed=6, band=4000), dict(n_workers=16, window_max=96), 1),
+    ("3d27pt_24", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256), 0),
+    ("2d5pt_100", matgen.config_2d_small, dict(n_workers=64), 0),
+])
+def test_low_locality_decision(name, make, kw, want):
+    """low_locality=auto expands exactly when more than half of all window
+    touches (own rows plus halo entries of every unit) carry the shared
+    flag, recounted here from the unit flags; race never expands, expanded
+    always does; distance-1 and complex schedules never do."""
+    m = make()
+    for mode, expect in (("auto", None), ("race", 0), ("expanded", 1)):
+        s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, low_locality=mode, **kw)
+        try:
+            st = s.stats()
+            if expect is None:
+                u = s.units()
+                shared = sum(int(np.count_nonzero(u["row_flags"][lo:hi] & 2)) for lo, hi in zip(u["lo"], u["hi"]))
+                shared += int(np.count_nonzero(u["halo_flags"] & 2))
+                touches = m.n + len(u["halo"])
+                expect = int(2 * shared > touches)
+                assert expect == want, (shared, touches)
+            assert st["product_path"] == expect, mode
+            assert (st["expanded_lanes"] > 0) == bool(expect)
+        finally:
+            s.close()
+    g = matgen.config_2d_small()
+    s = R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, low_locality="expanded", dist_k=1, n_workers=64)
+    assert s.stats()["product_path"] == 0
+    s.close()
+    with pytest.raises(_lib.RaceError):
+        p = R.make_params()
+        p.low_locality = 3
+        R.race_build_schedule(m.n, m.row_ptr, m.col, m.val, p)
