@@ -541,6 +541,73 @@ def run_gs(args, torch):
     s.close()
 
 
+def run_mpk(args, torch):
+    """Matrix powers y_p = A^p x, p = 1..P, of the workload's matrix scaled
+    by its largest absolute row sum: one race_symm_mpk launch against P
+    separate race_symm_spmv products, each error against the oracle's
+    power.  One JSON line; each power moves the product's algorithmic
+    bytes."""
+    import numpy as np
+
+    import matgen
+    import paper_1907_06487_amd as R
+    from oracle import powers as OP
+    from oracle import symmspmv as O
+    P = args.mpk
+    m, desc = workload(args.workload)
+    scale = float(np.max(O.abs_product(m.n, m.row_ptr, m.col, m.val, np.ones(m.n))))
+    m = matgen.UpperCSR(m.n, m.row_ptr, m.col, m.val / scale, m.name + "_scaled")
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
+                   block_threads=args.block, window_max=args.window, value_type=args.value_type)
+    st = s.stats()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(61)
+    x = rng.uniform(-1, 1, m.n)
+    xd = torch.as_tensor(x, device=dev)
+    xp = torch.empty_like(xd)
+    s.permute(xd, xp, True)
+    nring = max(2, -(-RING_BYTES // (8 * m.n * P)))
+    Ys = [torch.empty((P, m.n), dtype=torch.float64, device=dev) for _ in range(nring)]
+    s.mpk(xp, Ys[0])
+    torch.cuda.synchronize()
+    s.check()
+    perm = s.perm()
+    vals = m.val if args.value_type == "f64" else m.val.astype(np.float32).astype(np.float64)
+    refs = OP.powers(m.n, m.row_ptr, m.col, vals, x, P)
+    Yh = Ys[0].cpu().numpy()
+    errs = [float(np.max(np.abs(Yh[p] - refs[p][perm])) / np.max(np.abs(refs[p]))) for p in range(P)]
+    ms = time_ring(lambda a, y: s.mpk(xp, y), Ys, Ys, args.steps, args.warmup, torch)
+    s.check()
+
+    def separate(a, Y):
+        s.spmv(xp, Y[0])
+        for p in range(1, P):
+            s.spmv(Y[p - 1], Y[p])
+
+    ms_sep = time_ring(separate, Ys, Ys, args.steps, args.warmup, torch)
+    flops = 2 * st["nnz_full"] * P
+    bytes_alg = (st["bytes_min"] - (4 * st["nnz_upper"] if args.value_type == "f32" else 0)) * P
+    achieved = bytes_alg / (ms * 1e-3) / 1e9
+    log(f"matrix powers P={P} {args.workload}: {ms * 1e3:.1f} us in one launch, {ms_sep * 1e3:.1f} us as {P} products "
+        f"({ms_sep / ms:.3f}x), {flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, {achieved:.1f} GB/s algorithmic, "
+        f"worst power error {max(errs):.2e}")
+    out = {
+        "metric": f"matrix powers A^p x, p = 1..{P}, GFLOP/s", "value": round(flops / (ms * 1e-3) / 1e9, 3),
+        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.value_type == "f64" else "f32-values/f64-accumulate", "data": "synthetic",
+        "config": {"workload": args.workload + "_scaled", "description": desc + ", scaled by its largest row sum",
+                   "powers": P, "n": m.n, "n_workers": args.n_workers, "block_threads": args.block,
+                   "window_max": args.window, "units": st["n_units"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_alg},
+        "separate_products": {"ms": ms_sep, "speedup_of_one_launch": ms_sep / ms},
+        "error": {"per_power_norm": errs}, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -565,6 +632,7 @@ def main():
     ap.add_argument("--low-locality", default="auto", choices=["auto", "race", "expanded"],
                     help="single-vector products: the library's choice (auto: a CRS product of the expanded permuted "
                          "matrix when the schedule predicts no window reuse), the RACE kernels, or always expanded")
+    ap.add_argument("--mpk", type=int, default=0, help="matrix powers A^p x, p = 1..MPK, in one launch instead")
     ap.add_argument("--gs", action="store_true",
                     help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
     ap.add_argument("--gs-workers", type=int, default=4096, help="--gs: n_workers of the distance-1 schedule")
@@ -614,6 +682,9 @@ def main():
         return
     if args.gs:
         run_gs(args, torch)
+        return
+    if args.mpk:
+        run_mpk(args, torch)
         return
     if args.spmm_k:
         m, _ = workload(args.workload)

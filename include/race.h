@@ -280,6 +280,38 @@ int race_schedule_set_ticket_order(race_schedule_t s, const int32_t* ticket_unit
 int race_schedule_order_tickets(race_schedule_t s, const float* cost);
 int race_schedule_ticket_order(race_schedule_t s, int32_t* ticket_unit);
 
+/* Matrix powers (Section 7 names in-place matrix powers and polynomials as
+ * the next kernels RACE schedules serve): Y[p] = A^(p+1) x for p = 0 ..
+ * powers - 1, i.e. y_1 = A x, y_(p+1) = A y_p, in ONE persistent launch.
+ * Tickets are (power, unit) pairs, power-major; a unit of power p waits
+ * until every unit whose touch set meets its window has flushed power
+ * p - 1, and like a single product waits for its conflict edges before its
+ * flush, so the end of one power overlaps the start of the next.
+ * x: device float64 array of n, Y: device float64 array of powers * n
+ * (power-major: Y + p * n is A^(p+1) x), both in the permuted order; Y must
+ * not overlap x.  powers in 1..64.  Real values only (value_type 0 or 1),
+ * any exec_mode (the launch is always a dataflow launch).
+ * Allocates its launch state (4 bytes per unit and power) on first use and
+ * keeps it with the schedule.  RACE_EUNSUPPORTED for complex values,
+ * distance-1 schedules or stream capture; RACE_EINVAL for powers out of
+ * range or NULL vectors.  A bounded wait that gave up is reported by
+ * race_schedule_check. */
+int race_symm_mpk(race_schedule_t s, int32_t powers, const double* x, double* Y, void* stream);
+
+/* Polynomial of the matrix: z = sum_{p=0..degree} coeffs[p] A^p x, through
+ * race_symm_mpk into work (device, degree * n doubles; holds the powers
+ * afterwards) and one combining pass.  coeffs: host, degree + 1 values;
+ * degree in 0..32.  x, z: device, n, permuted order; z may not overlap x or
+ * work. */
+int race_symm_poly(race_schedule_t s, int32_t degree, const double* coeffs, const double* x, double* work, double* z,
+                   void* stream);
+
+/* Read dependencies of the matrix powers: for every unit u, the units whose
+ * touch sets (own rows and halo) meet u's, u included, ascending; CSR over
+ * units in *ptr (n_units + 1, host) and *idx (*count entries, host).  Pass
+ * NULL ptr and idx to query *count first. */
+int race_schedule_read_deps(race_schedule_t s, int64_t* count, int32_t* ptr, int32_t* idx);
+
 /* Gauss-Seidel sweep on A x = b over a distance-1 schedule (dist_k = 1,
  * float64 values; the paper names Gauss-Seidel as the prime user of such
  * colorings, Sections 1 and 4.2): every row i takes

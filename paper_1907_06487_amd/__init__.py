@@ -14,7 +14,8 @@ from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_ch
                    race_batch_destroy, race_batch_info, race_batch_run, race_build_schedule, race_csr_create, race_csr_destroy,
                    race_csr_spmv, race_last_error, race_params_default, race_permute, race_schedule_check, race_schedule_destroy,
                    race_schedule_flow_takeovers, race_schedule_flow_test_late, race_schedule_order_tickets,
-                   race_schedule_set_ticket_order, race_schedule_ticket_order,
+                   race_schedule_set_ticket_order, race_schedule_ticket_order, race_symm_mpk, race_symm_poly,
+                   race_schedule_read_deps,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
                    race_symm_gs, race_symm_spmv_atomic, race_symm_spmv_noalloc, race_stream_copy, race_stream_read,
@@ -162,6 +163,17 @@ class Schedule:
     def gauss_seidel(self, b, x, direction="symmetric", stream=None):
         """Gauss-Seidel sweep(s) on A x = b in place (distance-1 schedules)."""
         race_symm_gs(self.handle, b, x, direction, stream)
+
+    def mpk(self, x, Y, stream=None):
+        """Y[p] = A^(p+1) x for p < Y.shape[0] (Y: powers x n) in one launch."""
+        race_symm_mpk(self.handle, Y.shape[0], x, Y, stream)
+
+    def poly(self, coeffs, x, work, z, stream=None):
+        """z = sum_p coeffs[p] A^p x; work holds (len(coeffs) - 1) x n doubles."""
+        race_symm_poly(self.handle, coeffs, x, work, z, stream)
+
+    def read_deps(self):
+        return race_schedule_read_deps(self.handle, self.stats()["n_units"])
 
     def spmv_noalloc(self, x, y, stream=None):
         """The product through the entry point that allocates nothing."""

@@ -31,7 +31,7 @@ EXPORTS = [
     "race_mlp_forward_host", "race_mlp_forward", "race_mlp_workspace", "race_mlp_loss_grad", "race_mlp_adam",
     "race_symm_spmv_noalloc", "race_vendor_create", "race_vendor_spmv", "race_vendor_destroy", "race_stream_read",
     "race_stream_copy", "race_symm_gs", "race_schedule_set_ticket_order", "race_schedule_order_tickets",
-    "race_schedule_ticket_order",
+    "race_schedule_ticket_order", "race_symm_mpk", "race_symm_poly", "race_schedule_read_deps",
 ]
 
 MLP_INPUTS = 12
@@ -108,6 +108,9 @@ def lib():
         "race_schedule_set_ticket_order": ([_P, _I32P], ctypes.c_int),
         "race_schedule_order_tickets": ([_P, _FP], ctypes.c_int),
         "race_schedule_ticket_order": ([_P, _I32P], ctypes.c_int),
+        "race_symm_mpk": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+        "race_symm_poly": ([_P, ctypes.c_int32, _DP, _P, _P, _P, _P], ctypes.c_int),
+        "race_schedule_read_deps": ([_P, _I64P, _I32P, _I32P], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
@@ -314,6 +317,26 @@ def race_schedule_ticket_order(h, n_units):
     out = np.empty(n_units, dtype=np.int32)
     check(lib().race_schedule_ticket_order(h, _np_ptr(out, ctypes.c_int32)))
     return out
+
+
+def race_symm_mpk(h, powers, x, Y, stream=None):
+    """Y: device tensor of powers * n (power-major)."""
+    check(lib().race_symm_mpk(h, int(powers), _dev_ptr(x), _dev_ptr(Y), _stream_ptr(stream)))
+
+
+def race_symm_poly(h, coeffs, x, work, z, stream=None):
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    check(lib().race_symm_poly(h, int(c.size - 1), _np_ptr(c, ctypes.c_double), _dev_ptr(x),
+                               _dev_ptr(work) if work is not None else None, _dev_ptr(z), _stream_ptr(stream)))
+
+
+def race_schedule_read_deps(h, n_units):
+    cnt = ctypes.c_int64()
+    check(lib().race_schedule_read_deps(h, ctypes.byref(cnt), None, None))
+    ptr = np.empty(n_units + 1, dtype=np.int32)
+    idx = np.empty(cnt.value, dtype=np.int32)
+    check(lib().race_schedule_read_deps(h, ctypes.byref(cnt), _np_ptr(ptr, ctypes.c_int32), _np_ptr(idx, ctypes.c_int32)))
+    return ptr, idx
 
 
 def race_symm_spmv(h, x, y, stream=None):

@@ -116,6 +116,12 @@ struct race_schedule {
   DevBuf<float> lane_diag32, sell_val32;
   DevBuf<race::Cplx<false>> lane_diagc, sell_valc;  // complex values (value_type 2 or 3)
   DevBuf<double> tiles_x, tiles_y;  // column tiles of X and Y for products with many passes (grown on demand)
+  // matrix powers: read dependencies (host and device, built on first use)
+  // and the launch state (P * flags + counter), grown on demand
+  std::vector<int32_t> rdep_ptr_h, rdep_idx_h;
+  DevBuf<int32_t> rdep_ptr, rdep_idx;
+  DevBuf<uint32_t> mpk_state;
+  uint64_t mpk_ticket_next = 0;
   // the full permuted matrix in CRS, when single-vector products run as a
   // CRS product (race_params.low_locality)
   bool expanded = false;
@@ -139,6 +145,7 @@ struct race_schedule {
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
     release(exp_rp); release(exp_col); release(exp_val64); release(exp_val32);
+    release(rdep_ptr); release(rdep_idx); release(mpk_state);
     uploaded = false;
   }
 };
@@ -791,6 +798,23 @@ static race::UnitArgs<ValT> unit_args(race_schedule_t s, const ValT* diag, const
                               s->chunk_len.p,  s->lane_slot.p, diag,      vals,          s->sell_slot.p};
 }
 
+// Advances the schedule's launch epoch (shared by products and matrix
+// powers, whose claim words are the same); on wrap-around every done flag
+// and claim is cleared, so none equals the new epoch.
+static hipError_t next_epoch(race_schedule_t s, hipStream_t st) {
+  s->epoch += 1;
+  if (s->epoch != 0) return hipSuccess;
+  const size_t n_flags = s->L.unit_lo.size() + static_cast<size_t>(s->L.n_zero_tasks);
+  hipError_t e = hipMemsetAsync(s->flow_state.p, 0, sizeof(uint32_t) * n_flags, st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->claims.p, 0, sizeof(uint32_t) * (s->claims.count - 1), st);
+  if (e == hipSuccess && s->mpk_state.p) {
+    e = hipMemsetAsync(s->mpk_state.p, 0, sizeof(uint32_t) * s->mpk_state.count, st);
+    s->mpk_ticket_next = 0;  // the counter lives in that state
+  }
+  s->epoch = 1;
+  return e;
+}
+
 template <typename ValT>
 static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k, const double* x, double* y,
                     int32_t ld, uint64_t* trace, hipStream_t st) {
@@ -826,13 +850,8 @@ static int run_flow(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t k,
                    s->claims.p, s->claims.p + claim_cap, n_static, s->late_stride, trace, n_tickets, n_units,
                    L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size()),
                    s->ticket_unit_d.p, s->unit_ticket_d.p};
-  s->epoch += 1;
-  if (s->epoch == 0) {  // wrapped: every done flag and claim must differ from the new epoch
-    e = hipMemsetAsync(base, 0, sizeof(uint32_t) * n_flags, st);
-    if (e == hipSuccess) e = hipMemsetAsync(s->claims.p, 0, sizeof(uint32_t) * claim_cap, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
-    s->epoch = 1;
-  }
+  e = next_epoch(s, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   // the counter moves once per counter ticket and once more per workgroup
   // (its last, empty request)
   const uint64_t ticket_base = s->ticket_next;
@@ -1112,6 +1131,140 @@ int race_symm_spmm(race_schedule_t s, int32_t k, const double* X, double* Y, voi
 int race_symm_spmm_traced(race_schedule_t s, int32_t k, const double* X, double* Y, uint64_t* trace, void* stream) {
   if (!trace) return fail(RACE_EINVAL, "trace is NULL");
   return run_products(s, k, X, Y, trace, stream);
+}
+
+}  // extern "C"
+
+// Read dependencies of matrix powers (built once, uploaded when the schedule is).
+static int ensure_read_deps(race_schedule_t s, bool device) {
+  try {
+    if (s->rdep_ptr_h.empty()) race::build_read_deps(s->L, s->rdep_ptr_h, s->rdep_idx_h);
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory while building the read dependencies");
+  }
+  if (device && !s->rdep_ptr.p) {
+    int64_t total = 0;
+    hipError_t e = upload(s->rdep_ptr, s->rdep_ptr_h.data(), s->rdep_ptr_h.size(), &total);
+    if (e == hipSuccess) e = upload(s->rdep_idx, s->rdep_idx_h.data(), s->rdep_idx_h.size(), &total);
+    if (e != hipSuccess) {
+      release(s->rdep_ptr);
+      release(s->rdep_idx);
+      return hip_fail(e, "upload of the read dependencies");
+    }
+  }
+  return RACE_OK;
+}
+
+template <typename ValT>
+static int run_mpk(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t P, const double* x, double* Y,
+                   hipStream_t st) {
+  const race::Layout& L = s->L;
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  if (n_units == 0) return RACE_OK;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cap);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(RACE_EUNSUPPORTED, "matrix powers cannot be captured into a graph (the launch epoch is an argument)");
+  int rc = ensure_read_deps(s, true);
+  if (rc) return rc;
+  const int32_t wmax = std::max(1, L.max_window);
+  int32_t per_cu = 0;
+  e = race::race_mpk_occupancy<ValT>(s->params.block_threads, wmax, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (per_cu < 1) return fail(RACE_EUNSUPPORTED, "matrix-power kernel does not fit a CU with this window and block size");
+  const int32_t n_flags = n_units + L.n_zero_tasks;
+  const int64_t n_tickets64 = static_cast<int64_t>(P) * n_flags;
+  if (n_tickets64 >= (int64_t(1) << 31)) return fail(RACE_EUNSUPPORTED, "too many tickets (powers x units)");
+  const int32_t n_tickets = static_cast<int32_t>(n_tickets64);
+  const int32_t grid = std::max(1, std::min(n_tickets, per_cu * s->n_cus));
+  // static tickets stay within the first power: a later power's ticket is
+  // handed out only once every static ticket has a running owner
+  const int32_t n_static = std::min(grid, n_flags);
+  const size_t claim_cap = s->claims.count - 1;
+  if (static_cast<size_t>(n_static) > claim_cap) return fail(RACE_EINTERNAL, "more workgroups than claim words");
+  // [done flags of every power][pad to 8 bytes][64-bit counter]
+  const size_t flag_words = static_cast<size_t>(n_tickets);
+  const size_t counter_word = (flag_words + 1) / 2 * 2;
+  const size_t words = counter_word + 2;
+  if (s->mpk_state.count < words) {
+    release(s->mpk_state);
+    e = hipMalloc(&s->mpk_state.p, words * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(s->mpk_state.p, 0, words * sizeof(uint32_t), st);
+    if (e != hipSuccess) {
+      release(s->mpk_state);
+      return hip_fail(e, "allocation of the matrix-power state");
+    }
+    s->mpk_state.count = words;
+    s->mpk_ticket_next = 0;
+  }
+  e = next_epoch(s, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+  uint32_t* state = s->mpk_state.p;
+  const size_t counter_at = (s->mpk_state.count - 2) / 2 * 2;
+  const uint64_t ticket_base = s->mpk_ticket_next;
+  s->mpk_ticket_next += static_cast<uint64_t>(n_tickets - n_static) + static_cast<uint64_t>(grid);
+  race::FlowArgs f{s->dep_idx.p, state, reinterpret_cast<uint64_t*>(state + counter_at),
+                   s->flow_state.p + n_flags,  // the schedule's status word (race_schedule_check)
+                   s->claims.p, s->claims.p + claim_cap, n_static, s->late_stride, nullptr, n_tickets, n_units,
+                   L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size()),
+                   s->ticket_unit_d.p, s->unit_ticket_d.p};
+  race::MpkArgs m{s->rdep_ptr.p, s->rdep_idx.p, P, n_flags, static_cast<int64_t>(s->tree.n)};
+  e = race::launch_race_mpk<ValT>(a, f, m, x, Y, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
+  if (e != hipSuccess) return hip_fail(e, "matrix-power launch");
+  return RACE_OK;
+}
+
+extern "C" {
+
+int race_symm_mpk(race_schedule_t s, int32_t powers, const double* x, double* Y, void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
+  if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  if (powers < 1 || powers > 64) return fail(RACE_EINVAL, "powers must be in 1..64");
+  if (s->params.value_type > 1) return fail(RACE_EUNSUPPORTED, "matrix powers take real values only");
+  if (s->tree.n == 0) return RACE_OK;
+  if (!x || !Y) return fail(RACE_EINVAL, "x or Y is NULL");
+  if (rhs_tile(s, 1) < 1)
+    return fail(RACE_EUNSUPPORTED, "a unit window does not fit the LDS; rebuild with a smaller window_max");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != s->device) return fail(RACE_EINVAL, "the schedule was uploaded to another device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->params.value_type == 0)
+    return run_mpk<double>(s, unit_args<double>(s, s->lane_diag64.p, s->sell_val64.p), powers, x, Y, st);
+  return run_mpk<float>(s, unit_args<float>(s, s->lane_diag32.p, s->sell_val32.p), powers, x, Y, st);
+}
+
+int race_symm_poly(race_schedule_t s, int32_t degree, const double* coeffs, const double* x, double* work, double* z,
+                   void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (degree < 0 || degree > race::kMaxPolyDegree) return fail(RACE_EINVAL, "degree must be in 0..32");
+  if (!coeffs) return fail(RACE_EINVAL, "coeffs is NULL");
+  if (s->tree.n > 0 && (!x || !z || (degree > 0 && !work))) return fail(RACE_EINVAL, "x, work or z is NULL");
+  if (degree > 0) {
+    const int rc = race_symm_mpk(s, degree, x, work, stream);
+    if (rc) return rc;
+  } else if (!s->uploaded) {
+    return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  }
+  race::PolyCoeffs c{};
+  for (int32_t p = 0; p <= degree; ++p) c.c[p] = coeffs[p];
+  const hipError_t e = race::launch_poly_combine(s->tree.n, degree, c, x, work, z, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "polynomial combination launch");
+  return RACE_OK;
+}
+
+int race_schedule_read_deps(race_schedule_t s, int64_t* count, int32_t* ptr, int32_t* idx) {
+  if (!s || !count) return fail(RACE_EINVAL, "NULL argument");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, "a distance-1 schedule has no units");
+  const int rc = ensure_read_deps(s, false);
+  if (rc) return rc;
+  *count = static_cast<int64_t>(s->rdep_idx_h.size());
+  if (ptr) std::copy(s->rdep_ptr_h.begin(), s->rdep_ptr_h.end(), ptr);
+  if (idx) std::copy(s->rdep_idx_h.begin(), s->rdep_idx_h.end(), idx);
+  return RACE_OK;
 }
 
 int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t direction, void* stream) {

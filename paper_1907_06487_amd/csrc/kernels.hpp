@@ -75,6 +75,23 @@ struct FlowArgs {
   const int32_t* unit_ticket;  // n_units: inverse of ticket_unit
 };
 
+// Matrix powers (race_mpk_kernel): read dependencies of every unit (the
+// units whose touch sets meet its window, itself included; CSR over units),
+// the number of powers, tickets per power (clearing tasks + units) and the
+// stride between the power vectors.
+struct MpkArgs {
+  const int32_t* rdep_ptr;
+  const int32_t* rdep_idx;
+  int32_t powers;
+  int32_t per_power;
+  int64_t n;
+};
+
+constexpr int kMaxPolyDegree = 32;
+struct PolyCoeffs {
+  double c[kMaxPolyDegree + 1];
+};
+
 // One matrix of a batch: its layout, conflict edges, completion flags (a
 // slice of the batch's state) and its x/y (row-major n x k).
 template <typename ValT>
@@ -155,6 +172,20 @@ hipError_t launch_batch_tile(const BatchMat<ValT>* mats, int32_t count, int32_t 
 template <typename ValT>
 hipError_t launch_race_batch(const BatchMat<ValT>* mats, const BatchArgs& b, int32_t k, int32_t wmax, int32_t threads,
                              int32_t grid, hipStream_t st);
+
+// Powers y_p = A y_(p-1), p = 1..m.powers (y_0 = x), into Y (m.powers
+// vectors of m.n, power-major) in one persistent launch; f holds the launch
+// state for m.powers * (n_units + n_zero_tasks) flags and its static tickets
+// (all of the first power).
+template <typename ValT>
+hipError_t launch_race_mpk(const UnitArgs<ValT>& a, const FlowArgs& f, const MpkArgs& m, const double* x, double* Y,
+                           int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
+                           hipStream_t st);
+template <typename ValT>
+hipError_t race_mpk_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_per_cu);
+// z = c[0] x + sum_{p=1..P} c[p] Y[p - 1] (P <= kMaxPolyDegree).
+hipError_t launch_poly_combine(int64_t n, int32_t P, const PolyCoeffs& c, const double* x, const double* Y, double* z,
+                               hipStream_t st);
 
 // p[0 .. words) = 0 with plain stores (a kernel, so a captured graph can
 // replay it).

@@ -340,4 +340,43 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
   return std::string();
 }
 
+void build_read_deps(const Layout& L, std::vector<int32_t>& ptr, std::vector<int32_t>& idx) {
+  const int32_t n = L.n;
+  const int32_t n_units = static_cast<int32_t>(L.unit_lo.size());
+  // touchers of every index: the unit owning the row, then the units holding it in their halo
+  std::vector<int64_t> tptr(static_cast<size_t>(n) + 1, 0);
+  for (int32_t u = 0; u < n_units; ++u) {
+    for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) ++tptr[g + 1];
+    for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j) ++tptr[(L.halo[j] & kIndexMask) + 1];
+  }
+  for (int32_t g = 0; g < n; ++g) tptr[g + 1] += tptr[g];
+  std::vector<int32_t> touchers(static_cast<size_t>(tptr[n]));
+  {
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int32_t u = 0; u < n_units; ++u) {
+      for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) touchers[fill[g]++] = u;
+      for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j)
+        touchers[fill[L.halo[j] & kIndexMask]++] = u;
+    }
+  }
+  ptr.assign(1, 0);
+  idx.clear();
+  std::vector<int32_t> stamp(static_cast<size_t>(n_units), -1), mine;
+  auto add = [&](int32_t u, int32_t g) {
+    for (int64_t q = tptr[g]; q < tptr[g + 1]; ++q)
+      if (stamp[touchers[q]] != u) {
+        stamp[touchers[q]] = u;
+        mine.push_back(touchers[q]);
+      }
+  };
+  for (int32_t u = 0; u < n_units; ++u) {
+    mine.clear();
+    for (int32_t g = L.unit_lo[u]; g < L.unit_hi[u]; ++g) add(u, g);
+    for (int32_t j = L.unit_halo_ptr[u]; j < L.unit_halo_ptr[u + 1]; ++j) add(u, static_cast<int32_t>(L.halo[j] & kIndexMask));
+    std::sort(mine.begin(), mine.end());
+    idx.insert(idx.end(), mine.begin(), mine.end());
+    ptr.push_back(static_cast<int32_t>(idx.size()));
+  }
+}
+
 }  // namespace race

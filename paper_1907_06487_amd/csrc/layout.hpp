@@ -89,4 +89,10 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
                          const double* val_im, const Tree& tree, int32_t window_max, int32_t value_type,
                          bool shared_atomics, Layout& out, int* code);
 
+// Read dependencies for matrix powers: for every unit u, the units whose
+// touch sets (own rows and halo) meet u's touch set, u included, ascending
+// (CSR over units).  A unit of power p reads x = y_(p-1) on exactly its
+// touch set, which is final once these units have flushed power p - 1.
+void build_read_deps(const Layout& L, std::vector<int32_t>& ptr, std::vector<int32_t>& idx);
+
 }  // namespace race

@@ -359,3 +359,26 @@ def test_low_locality_decision(name, make, kw, want):
         p = R.make_params()
         p.low_locality = 3
         R.race_build_schedule(m.n, m.row_ptr, m.col, m.val, p)
+
+
+@pytest.mark.parametrize("name,make,kw", [
+    ("3d27pt_16_w256", lambda: matgen.stencil3d_27pt(16, seed=3), dict(n_workers=64, window_max=256)),
+    ("banded_8k_w200", lambda: matgen.banded_irregular(8000, seed=4, band=800), dict(n_workers=32, window_max=200)),
+    ("rand_islands", lambda: matgen.random_symmetric(400, 0.004, seed=6), dict(n_workers=8, window_max=64)),
+])
+def test_matrix_power_read_deps(name, make, kw):
+    """A unit of power p reads y_(p-1) on its touch set (own rows and halo):
+    it must wait for exactly the units whose touch sets meet it, itself
+    included.  Recomputed here by brute force over pairs of units."""
+    m = make()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, **kw)
+    try:
+        u = s.units()
+        touch = [set(range(u["lo"][i], u["hi"][i])) | set(u["halo"][u["halo_ptr"][i]:u["halo_ptr"][i + 1]].tolist())
+                 for i in range(len(u["lo"]))]
+        ptr, idx = s.read_deps()
+        for i in range(len(touch)):
+            want = [j for j in range(len(touch)) if touch[i] & touch[j]]
+            assert idx[ptr[i]:ptr[i + 1]].tolist() == want, i
+    finally:
+        s.close()
