@@ -38,7 +38,7 @@ extern "C" {
 #define RACE_EINVAL (-1)       /* malformed input: bad CRS, bad sizes, NULL pointers */
 #define RACE_ENOMEM (-2)       /* host or device allocation failed */
 #define RACE_EHIP (-3)         /* a HIP runtime call failed (message holds hipGetErrorString) */
-#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (dist_k = 1 for SymmSpMV, a row whose window does not fit, k > 16) */
+#define RACE_EUNSUPPORTED (-4) /* valid input the library cannot run (a SymmSpMV product on a dist_k = 1 schedule, a row whose window does not fit, k > 16) */
 #define RACE_ESTATE (-5)       /* wrong object state (e.g. product before race_schedule_upload) */
 #define RACE_EINTERNAL (-6)    /* an internal consistency check failed (e.g. two concurrent units touch one index) */
 
@@ -140,7 +140,7 @@ typedef struct {
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
  * nonzeros, no global pass, float64 values, window 3840, 256 threads,
  * eps = {0.8, 0.8, 0.5, ...} (Section 5.2 choice), exec_mode 1,
- * shared_atomics 1. */
+ * shared_atomics 1, root_mode 0, level_order 0, low_locality 0. */
 int race_params_default(race_params* p);
 
 /* Build the RACE schedule and the kernel's data layout on the host.
@@ -151,10 +151,14 @@ int race_params_default(race_params* p);
  * schedule can be inspected but not uploaded).  Disconnected matrices are
  * accepted (islands).  *out receives a new schedule owned by the caller
  * (race_schedule_destroy).  No device is needed.
- * Errors: RACE_EINVAL for malformed CRS or parameters, RACE_EUNSUPPORTED when
- * dist_k is 1 (SymmSpMV needs distance 2 or more; 2..8 are accepted) or one
- * row alone exceeds the window, RACE_EINTERNAL if the
- * built-in independence check finds two concurrent units touching one index. */
+ * dist_k 1..8 are accepted: 2..8 give SymmSpMV schedules, 1 a distance-1
+ * schedule for Gauss-Seidel sweeps (race_symm_gs), on which the products
+ * are refused.
+ * Errors: RACE_EINVAL for malformed CRS or parameters (dist_k outside 1..8),
+ * RACE_EUNSUPPORTED when one row alone exceeds the window (or, for dist_k 1
+ * with values, a leaf window exceeds 16,384 entries or a diagonal is zero or
+ * missing), RACE_EINTERNAL if the built-in independence check finds two
+ * concurrent units touching one index. */
 int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                         const race_params* p, race_schedule_t* out);
 
