@@ -370,7 +370,10 @@ def run_learned_ab(args, torch):
     xs = [torch.rand(m.n, dtype=torch.float64, device=dev, generator=gen) * 2 - 1 for _ in range(nring)]
     ys = [torch.empty(m.n, dtype=torch.float64, device=dev) for _ in range(nring)]
     x0 = xs[0].cpu().numpy()
-    arms = {"heuristic": res["heuristic"], "learned": res["learned"],
+    # the network's best schedule with learned loads, reported on its own
+    learned_loads = min((c for c in res["candidates"] if c["params"]["balance"] == "model"),
+                        key=lambda c: c["pred_us"])
+    arms = {"heuristic": res["heuristic"], "learned": res["learned"], "learned_loads": learned_loads,
             "default": {"params": dict(n_workers=args.n_workers, block_threads=args.block, window_max=args.window,
                                        balance="nnz"), "pred_us": None, "pred_nnz": None}}
     out_arms = {}
@@ -401,8 +404,12 @@ def run_learned_ab(args, torch):
         log(f"{name}: {out_arms[name]['us_median']:.2f} us (min {min(rounds):.2f}, max {max(rounds):.2f}), "
             f"predicted {arm['pred_us']:.2f} us, params {arm['params']}, err {err:.2e}")
         s.close()
-    h, l = out_arms["heuristic"], out_arms["learned"]
+    h, l, d = out_arms["heuristic"], out_arms["learned"], out_arms["default"]
     flops = 2 * (2 * m.nnz - m.n)
+    spread = max((a["us_max"] - a["us_min"]) / a["us_median"] for a in out_arms.values())
+    without = min(h["us_median"], d["us_median"])
+    log(f"learned vs the best arm without the network: {without / l['us_median']:.4f}x "
+        f"(round-to-round spread up to {spread * 100:.1f}%)")
     out = {
         "metric": "learned cost model: time per SymmSpMV product, learned vs nonzero-heuristic schedule choice",
         "value": round(h["us_median"] / l["us_median"], 4), "unit": "speedup (heuristic time / learned time)",
@@ -411,6 +418,8 @@ def run_learned_ab(args, torch):
         "config": {"workload": "3d27pt_160 (held out)", "n": m.n, "nnz_upper": m.nnz, "rounds": args.rounds,
                    "candidates": len(res["candidates"])},
         "arms": out_arms, "gflops_learned": flops / (l["us_median"] * 1e-6) / 1e9,
+        "speedup_vs_default": d["us_median"] / l["us_median"],
+        "speedup_vs_best_without_network": without / l["us_median"], "round_spread": spread,
         "candidates": res["candidates"], "model": meta, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

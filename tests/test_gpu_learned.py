@@ -51,7 +51,7 @@ def _time(s, xs, ys, reps=50, rounds=3):
         e1.record()
         torch.cuda.synchronize()
         out.append(e0.elapsed_time(e1) / reps * 1e3)
-    return float(np.median(out))
+    return float(np.median(out)), float((max(out) - min(out)) / np.median(out))
 
 
 @pytest.mark.timeout(600)
@@ -64,13 +64,14 @@ def test_learned_choice_on_held_out_160():
     gen.manual_seed(5)
     xs = [torch.rand(m.n, dtype=torch.float64, device=DEV, generator=gen) * 2 - 1 for _ in range(18)]
     ys = [torch.empty_like(xs[0]) for _ in xs]
-    times = {}
-    for arm in ("heuristic", "learned"):
+    times, spread = {}, {}
+    res["default"] = {"params": dict(n_workers=256, block_threads=512, window_max=3840, balance="nnz"), "pred_us": float("nan")}
+    for arm in ("heuristic", "learned", "default"):
         kw = dict(res[arm]["params"])
         if kw["balance"] == "model":
             kw["cost_model"] = theta
         s = R.Schedule(m.n, m.row_ptr, m.col, m.val, **kw)
-        times[arm] = _time(s, xs, ys)
+        times[arm], spread[arm] = _time(s, xs, ys)
         s.check()
         x0 = xs[0].cpu().numpy()
         perm = s.perm()
@@ -84,5 +85,12 @@ def test_learned_choice_on_held_out_160():
               f"params {res[arm]['params']}, error {err:.2e}", flush=True)
         assert err <= 1e-12
         s.close()
-    print(f"  learned / heuristic time: {times['learned'] / times['heuristic']:.3f}", flush=True)
-    assert times["learned"] <= 1.02 * times["heuristic"]
+    best_without = min(times["heuristic"], times["default"])
+    gain = best_without / times["learned"]
+    print(f"  learned / heuristic time: {times['learned'] / times['heuristic']:.3f}; gain over the best arm without "
+          f"the network (heuristic choice or library defaults): {gain:.4f}x, round-to-round spread up to "
+          f"{max(spread.values()) * 100:.1f}%", flush=True)
+    # the network's choice must not lose to the method without it beyond
+    # the 2% tolerance; on this stencil it does not win beyond the spread
+    # either (the defaults are already near the best the candidates offer)
+    assert times["learned"] <= 1.02 * best_without
