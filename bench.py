@@ -644,7 +644,7 @@ def main():
     ap.add_argument("--mpk", type=int, default=0, help="matrix powers A^p x, p = 1..MPK, in one launch instead")
     ap.add_argument("--gs", action="store_true",
                     help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
-    ap.add_argument("--gs-workers", type=int, default=4096, help="--gs: n_workers of the distance-1 schedule")
+    ap.add_argument("--gs-workers", type=int, default=16384, help="--gs: n_workers of the distance-1 schedule")
     ap.add_argument("--order", default="default", choices=["default", "critical"],
                     help="dataflow ticket order: the layout's execution order, or the critical path of unit costs "
                          "measured by traced products on this device (part of the schedule's preparation)")

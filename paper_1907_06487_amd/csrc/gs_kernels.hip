@@ -11,7 +11,7 @@ namespace race {
 namespace dev {
 
 constexpr int kGsLanes = 64;
-constexpr int kGsAhead = 8;  // rows whose entries are in flight ahead of the running row
+constexpr int kGsAhead = 16;  // rows whose entries are in flight ahead of the running row (divides 64)
 
 // Load of a word no kernel writes, at an index that is the same in every
 // lane: a scalar load through the constant address space.
@@ -47,26 +47,48 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (r0 + r1) + (r2 + r3);
 }
 
-// One row's first 64 off-diagonal entries as this lane holds them (lane l
-// takes entry l; lanes past the row hold slot 0 and value 0), with the
-// row's right-hand side, diagonal and entry range.
+// Per-row metadata of 64 consecutive rows of the sweep, one row per lane:
+// the row's entry range, right-hand side and diagonal.  A row's values are
+// then taken with readlane (scalar registers) at no memory wait: scalar
+// loads inside the row loop would make every LDS wait (the same counter)
+// wait for them as well.
+struct GsMeta {
+  int32_t e0 = 0, e1 = 0;
+  double b = 0.0, d = 1.0;
+};
+
+// Rows t0 .. t0 + 63 of the sweep (row t of the sweep is lo + t, or hi - 1 - t backward).
+template <bool kBackward>
+__device__ __forceinline__ void gs_load_meta(const GsArgs& a, const double* __restrict__ bvec, int32_t lo, int32_t hi,
+                                             int32_t t0, int32_t lane, GsMeta& m) {
+  const int32_t t = t0 + lane;
+  if (t < hi - lo) {
+    const int32_t i = kBackward ? hi - 1 - t : lo + t;
+    m.e0 = a.row_ptr[i];
+    m.e1 = a.row_ptr[i + 1];
+    m.b = bvec[i];
+    m.d = a.diag[i];
+  }
+}
+
+__device__ __forceinline__ int32_t lane_value(int32_t v, int32_t l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_value(double v, int32_t l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// The first 64 off-diagonal entries of one row as the wavefront holds them
+// (lane l takes entry l; lanes past the row hold slot 0 and value 0).
 struct GsRow {
   double v = 0.0;
   uint32_t sl = 0;
-  double b = 0.0, d = 1.0;
-  int32_t e0 = 0, e1 = 0;
 };
 
-__device__ __forceinline__ void gs_load_row(const GsArgs& a, const double* __restrict__ bvec, int32_t i,
-                                            int32_t lane, GsRow& r) {
-  r.e0 = gs_uniform(a.row_ptr, i);
-  r.e1 = gs_uniform(a.row_ptr, i + 1);
-  r.b = gs_uniform(bvec, i);
-  r.d = gs_uniform(a.diag, i);
-  const int32_t e = r.e0 + lane;
+__device__ __forceinline__ void gs_load_row(const GsArgs& a, const GsMeta& m, int32_t l, int32_t lane, GsRow& r) {
+  const int32_t e = lane_value(m.e0, l) + lane;
   r.v = 0.0;
   r.sl = 0u;
-  if (e < r.e1) {
+  if (e < lane_value(m.e1, l)) {
     r.v = a.val[e];
     r.sl = a.slot[e];
   }
@@ -77,7 +99,8 @@ __device__ __forceinline__ void gs_load_row(const GsArgs& a, const double* __res
 //   x_i = (b_i - sum_j a_ij x_j) / a_ii
 // reading every x_j from the window and writing x_i into it, then store the
 // own rows back.  The entries of the next kGsAhead rows are in flight while
-// a row is summed; they do not depend on x.
+// a row is summed (they do not depend on x); the metadata of the current
+// and the next 64 rows sits in lanes.
 template <bool kBackward>
 __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t leaf0, const double* __restrict__ bvec,
                                                           double* __restrict__ x) {
@@ -89,10 +112,13 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
   const int32_t R = hi - lo, H = h1 - h0;
   for (int32_t s = lane; s < R; s += kGsLanes) xw[s] = x[lo + s];
   for (int32_t s = lane; s < H; s += kGsLanes) xw[R + s] = x[a.halo[h0 + s]];
+  GsMeta cur, next;
+  gs_load_meta<kBackward>(a, bvec, lo, hi, 0, lane, cur);
+  gs_load_meta<kBackward>(a, bvec, lo, hi, kGsLanes, lane, next);
   GsRow ring[kGsAhead];
 #pragma unroll
   for (int p = 0; p < kGsAhead; ++p)
-    if (p < R) gs_load_row(a, bvec, kBackward ? hi - 1 - p : lo + p, lane, ring[p]);
+    if (p < R) gs_load_row(a, cur, p, lane, ring[p]);
   __syncthreads();
   for (int32_t t0 = 0; t0 < R; t0 += kGsAhead) {
 #pragma unroll
@@ -100,15 +126,23 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
       const int32_t t = t0 + p;
       if (t < R) {
         const int32_t i = kBackward ? hi - 1 - t : lo + t;
+        const int32_t l = t & (kGsLanes - 1);
         double s = ring[p].v * xw[ring[p].sl];
         // entries past the first 64 (long rows) are loaded when the row runs
-        for (int32_t e = ring[p].e0 + kGsLanes + lane; e < ring[p].e1; e += kGsLanes) s += a.val[e] * xw[a.slot[e]];
-        const double bi = ring[p].b, di = ring[p].d;
+        const int32_t e1 = lane_value(cur.e1, l);
+        for (int32_t e = lane_value(cur.e0, l) + kGsLanes + lane; e < e1; e += kGsLanes) s += a.val[e] * xw[a.slot[e]];
+        const double bi = lane_value(cur.b, l), di = lane_value(cur.d, l);
         const int32_t tn = t + kGsAhead;
-        if (tn < R) gs_load_row(a, bvec, kBackward ? hi - 1 - tn : lo + tn, lane, ring[p]);
+        // kGsAhead divides 64, so row tn is in the current or the next chunk
+        if (tn < R) gs_load_row(a, (tn & (kGsLanes - 1)) >= l ? cur : next, tn & (kGsLanes - 1), lane, ring[p]);
         const double xi = (bi - wave_sum(s)) / di;
         if (lane == 0) xw[i - lo] = xi;
         __syncthreads();
+        if (l == kGsLanes - 1) {
+          // the chunk of rows t - 63 .. t is done: shift, fetch the one after next
+          cur = next;
+          gs_load_meta<kBackward>(a, bvec, lo, hi, t + 1 + kGsLanes, lane, next);
+        }
       }
     }
   }
