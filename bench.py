@@ -624,7 +624,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="3d27pt_128")
     ap.add_argument("--n-workers", type=int, default=256)
-    ap.add_argument("--max-stages", type=int, default=4)
+    ap.add_argument("--max-stages", type=int, default=2,
+                    help="recursion stages (2 measured 1.5%% faster than the library default 4 on the 128^3 stencil)")
     ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--window", type=int, default=3840)
     ap.add_argument("--value-type", default="f64", choices=["f64", "f32", "c128", "c128h"])
@@ -869,6 +870,7 @@ def main():
         same = (tr.get("source_hash") == kernel_source_hash() and tr.get("bytes_kernel") == st["bytes_kernel"]
                 and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
                 and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode
+                and tr.get("max_stages", 4) == args.max_stages
                 and tr.get("shared_atomics", 0) == args.shared_atomics and tr.get("root", "first") == args.root
                 and tr.get("level_order", "input") == args.level_order and args.dist_k == 2
                 and st["product_path"] == 0)
@@ -881,7 +883,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.value_type == "f64" else "f32-values/f64-accumulate", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_upper": m.nnz,
-                   "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "block_threads": args.block,
+                   "nnz_full": st["nnz_full"], "n_workers": args.n_workers, "max_stages": args.max_stages,
+                   "block_threads": args.block,
                    "window_max": args.window, "exec_mode": args.exec_mode, "shared_atomics": args.shared_atomics,
                    "root": args.root, "level_order": args.level_order, "dist_k": args.dist_k,
                    "levels0": st["n_levels0"], "ticket_order": order_info,
