@@ -133,7 +133,8 @@ def host_cpu():
 def yardsticks(m, perm, flops, nnz_full, xs, ys, args, torch):
     """Same-GPU baselines, each in input order and in the RACE order, the
     best setting reported: CRS SpMV on the full matrix with 1..64 lanes per
-    row (Algorithm "SpMV"), rocSPARSE's SpMV with each of its CSR
+    row and over row blocks of 4, 8 or 16 entries per thread (Algorithm
+    "SpMV"), rocSPARSE's SpMV with each of its CSR
     algorithms on the full matrix and as its own symmetric product on the
     upper triangle, and SymmSpMV with global atomics with 1..32 lanes per
     row.  Inputs come from matgen's format conversions."""
@@ -145,9 +146,10 @@ def yardsticks(m, perm, flops, nnz_full, xs, ys, args, torch):
     T = lambda fn: time_ring(lambda x, y: fn(x, y), xs, ys, args.steps, args.warmup, torch)
     for oname, mo in orders.items():
         rp, c, v = matgen.full_crs(mo)
-        for lpr in (1, 2, 4, 8, 16, 32, 64):
+        for lpr in (1, 2, 4, 8, 16, 32, 64, -4, -8, -16):
             h = R.race_csr_create(m.n, rp, c, v, lpr)
-            t_all["crs_spmv"].append((T(lambda x, y: R.race_csr_spmv(h, x, y)), {"order": oname, "lanes_per_row": lpr}))
+            cfg = {"order": oname, "lanes_per_row": lpr} if lpr > 0 else {"order": oname, "row_blocks_per_thread": -lpr}
+            t_all["crs_spmv"].append((T(lambda x, y: R.race_csr_spmv(h, x, y)), cfg))
             R.race_csr_destroy(h)
         for sym in (False, True):
             for alg in ("adaptive", "rowsplit", "lrb"):
@@ -716,7 +718,7 @@ def main():
     log(f"schedule built in {t_build:.2f}s: " + json.dumps({k: st[k] for k in (
         "n_levels0", "depth", "n_leaves", "n_phases_used", "n_units", "max_window", "eta", "halo_total",
         "sell_elems", "bytes_min", "bytes_kernel", "n_deps", "shared_touches", "n_zeroed", "product_path",
-        "expanded_lanes")}))
+        "expanded_per_thread")}))
 
     nring = max(2, -(-RING_BYTES // (8 * m.n)))
     gen = torch.Generator(device=dev)
@@ -766,9 +768,17 @@ def main():
     # first tickets); the phase mode launches once per phase plus the clearing
     launches = 1 if args.exec_mode == "flow" else st["n_phases_used"] + (1 if st["n_zeroed"] else 0)
     path_name = "expanded CRS product" if st["product_path"] == 1 else "RACE"
+    # bytes in the format the running kernel reads: the RACE layout's, or for
+    # the expanded product the full CRS matrix (value + column per entry, row
+    # pointers), x and y
+    if st["product_path"] == 1:
+        vb = 4 if args.value_type == "f32" else 8
+        bytes_fmt = (vb + 4) * st["nnz_full"] + 20 * m.n + 4
+    else:
+        bytes_fmt = st["bytes_kernel"]
     log(f"{path_name}: {ms * 1e3:.2f} us/product (median {ms_median * 1e3:.2f}), {gflops:.1f} GFLOP/s, {achieved:.1f} GB/s "
         f"algorithmic ({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes "
-        f"{st['bytes_kernel'] / (ms * 1e-3) / 1e9:.1f} GB/s")
+        f"{bytes_fmt / (ms * 1e-3) / 1e9:.1f} GB/s")
 
     race_kernels = None
     if st["product_path"] == 1:
@@ -873,7 +883,7 @@ def main():
                 and tr.get("max_stages", 4) == args.max_stages
                 and tr.get("shared_atomics", 0) == args.shared_atomics and tr.get("root", "first") == args.root
                 and tr.get("level_order", "input") == args.level_order and args.dist_k == 2
-                and st["product_path"] == 0)
+                and tr.get("product_path", 0) == st["product_path"])
         if same and args.value_type == "f64":
             traffic = tr.get("bytes_per_launch")
             traffic_rw = {"read": tr.get("read_bytes_per_launch"), "write": tr.get("write_bytes_per_launch")}
@@ -892,7 +902,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "traffic_read_write": traffic_rw, "launches_per_step": launches,
-                     "bytes_per_step": bytes_alg, "kernel_format_bytes_per_step": st["bytes_kernel"],
+                     "bytes_per_step": bytes_alg, "kernel_format_bytes_per_step": bytes_fmt,
                      "attainable_read_GBs": attain["read_GBs"] if attain else None,
                      "attainable_copy_GBs": attain["copy_GBs"] if attain else None,
                      "frac_of_attainable_read": round(achieved / attain["read_GBs"], 4) if attain else None,
@@ -900,7 +910,7 @@ def main():
         "schedule": {"shared_touches": st["shared_touches"], "halo_total": st["halo_total"],
                      "units": st["n_units"], "global_lb": args.global_lb,
                      "product_path": "expanded CRS" if st["product_path"] == 1 else "RACE kernels",
-                     "expanded_lanes": st["expanded_lanes"]},
+                     "expanded_per_thread": st["expanded_per_thread"]},
         "race_kernels": race_kernels,
         "attainable": attain,
         "error": {"norm": err_norm, "componentwise": err_comp},

@@ -94,8 +94,8 @@ typedef struct {
                               in the unit windows (more than half of all window touches are shared entries, which
                               the RACE kernels add with global float64 atomics, about 24 G/s on this chip): 0
                               (default) = the RACE kernels anyway; 1 = a full-matrix CRS product of the permuted
-                              matrix (the schedule then also holds the expanded matrix; value_type 0 or 1; stats
-                              product_path 1); 2 = the CRS product always (tests).  SymmSpMM with k > 1, traced
+                              matrix over row blocks, as race_csr_create with lanes_per_row -8 (the schedule then
+                              also holds the expanded matrix; value_type 0 or 1; stats product_path 1); 2 = the CRS product always (tests).  SymmSpMM with k > 1, traced
                               products, batches and complex values always run the RACE kernels */
 } race_params;
 
@@ -134,7 +134,7 @@ typedef struct {
   int64_t n_zeroed;          /* y entries cleared before each product (first touched by a shared unit) */
   int32_t product_path;      /* what race_symm_spmv runs: 0 the RACE kernels, 1 the expanded CRS product
                                 (race_params.low_locality) */
-  int32_t expanded_lanes;    /* lanes per row of the expanded CRS product (0 when not expanded) */
+  int32_t expanded_per_thread; /* entries per thread of the expanded CRS product's row blocks (0 when not expanded) */
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
@@ -372,7 +372,12 @@ void race_batch_destroy(race_batch_t b);
 /* ---- same-GPU baselines (not RACE; the yardsticks of Section 6) ---- */
 
 /* Full-matrix CRS SpMV (Algorithm "SpMV"): takes the FULL symmetric matrix in
- * CRS (host arrays, copied to the current device).  lanes_per_row 0 = choose. */
+ * CRS (host arrays, copied to the current device).  lanes_per_row: 1..64
+ * (a power of two) lanes of a wavefront share a row; 0 = choose; -4, -8 or
+ * -16: row blocks instead -- consecutive rows with at most 256 * 4, 8 or 16
+ * entries per 256-thread workgroup, streamed with unit stride, their
+ * products summed per row in LDS (a longer row gets a block of its own).
+ * Other values: RACE_EINVAL. */
 int race_csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                     int32_t lanes_per_row, race_csr_t* out);
 /* b = A x, device float64 arrays of n. */

@@ -67,7 +67,7 @@ class race_stats(ctypes.Structure):
         ("halo_rmw", ctypes.c_int64), ("bytes_min", ctypes.c_int64), ("bytes_kernel", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64), ("shared_touches", ctypes.c_int64),
-        ("n_zeroed", ctypes.c_int64), ("product_path", ctypes.c_int32), ("expanded_lanes", ctypes.c_int32),
+        ("n_zeroed", ctypes.c_int64), ("product_path", ctypes.c_int32), ("expanded_per_thread", ctypes.c_int32),
     ]
 
     def as_dict(self):

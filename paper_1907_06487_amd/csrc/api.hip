@@ -125,8 +125,9 @@ struct race_schedule {
   // the full permuted matrix in CRS, when single-vector products run as a
   // CRS product (race_params.low_locality)
   bool expanded = false;
-  int32_t exp_lpr = 0;
-  DevBuf<int32_t> exp_rp, exp_col;
+  int32_t exp_per = 0;   // entries per thread of its row blocks
+  int32_t exp_nblk = 0;  // row blocks
+  DevBuf<int32_t> exp_rp, exp_col, exp_blk;
   DevBuf<double> exp_val64;
   DevBuf<float> exp_val32;
   // distance-1 schedules: the Gauss-Seidel layout and its device copies
@@ -144,7 +145,7 @@ struct race_schedule {
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
-    release(exp_rp); release(exp_col); release(exp_val64); release(exp_val32);
+    release(exp_rp); release(exp_col); release(exp_blk); release(exp_val64); release(exp_val32);
     release(rdep_ptr); release(rdep_idx); release(mpk_state);
     uploaded = false;
   }
@@ -152,10 +153,11 @@ struct race_schedule {
 
 struct race_csr {
   int32_t n = 0;
-  int32_t lpr = 8;
+  int32_t lpr = 8;     // lanes per row, or (negative) row blocks of -lpr entries per thread
+  int32_t n_blk = 0;   // row blocks (lpr < 0)
   bool atomic = false;
   int device = -1;
-  DevBuf<int32_t> rp, col;
+  DevBuf<int32_t> rp, col, blk;
   DevBuf<double> val;
 };
 
@@ -370,8 +372,8 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     s->expanded = !s->gs && prm.value_type <= 1 && n > 0 &&
                   (prm.low_locality == 2 || (prm.low_locality == 1 && 2 * st.shared_touches > touches));
     st.product_path = s->expanded ? 1 : 0;
-    st.expanded_lanes = s->expanded ? race::expanded_lanes(n, st.nnz_full) : 0;
-    s->exp_lpr = st.expanded_lanes;
+    st.expanded_per_thread = s->expanded ? race::kExpandedPerThread : 0;
+    s->exp_per = st.expanded_per_thread;
   } catch (const std::bad_alloc&) {
     delete s;
     return fail(RACE_ENOMEM, "out of host memory while building the schedule");
@@ -385,18 +387,6 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
 
 }  // extern "C"
 
-namespace race {
-// Lanes per row of the expanded CRS product: the smallest power of two of
-// at least half the mean row length, 4..32 (4 lanes on the 5-point stencil,
-// 16 on the irregular banded matrices, where the yardstick sweep finds 16
-// fastest and 32 about 10% slower).
-int32_t expanded_lanes(int32_t n, int64_t nnz_full) {
-  const double mean = n > 0 ? static_cast<double>(nnz_full) / n : 1.0;
-  int32_t l = 4;
-  while (l < 32 && 2.0 * l < mean) l *= 2;
-  return l;
-}
-}  // namespace race
 
 // The full permuted matrix in CRS from the permuted upper triangle: every
 // off-diagonal entry (r, c) also appears as (c, r); columns ascending.
@@ -506,6 +496,12 @@ int race_schedule_upload(race_schedule_t s) {
     } catch (const std::bad_alloc&) {
       s->free_device();
       return fail(RACE_ENOMEM, "out of host memory while expanding the matrix");
+    }
+    {
+      std::vector<int32_t> blk;
+      race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), s->exp_per, blk);
+      s->exp_nblk = static_cast<int32_t>(blk.size()) - 1;
+      UP(exp_blk, blk)
     }
     UP(exp_rp, erp)
     UP(exp_col, ecol)
@@ -894,13 +890,15 @@ static int32_t rhs_tile(race_schedule_t s, int32_t k) {
 static const char* kDist1Product =
     "a distance-1 schedule serves Gauss-Seidel sweeps (race_symm_gs); SymmSpMV needs dist_k >= 2";
 
-// y = A x as a CRS product of the expanded permuted matrix (schedules whose
-// windows predict no reuse, race_params.low_locality).
+// y = A x as a CRS product of the expanded permuted matrix over row blocks
+// (schedules whose windows predict no reuse, race_params.low_locality).
 static int run_expanded(race_schedule_t s, const double* x, double* y, hipStream_t st) {
   const hipError_t e =
       s->params.value_type == 0
-          ? race::launch_csr_spmv<double>(s->tree.n, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, s->exp_lpr, st)
-          : race::launch_csr_spmv<float>(s->tree.n, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, s->exp_lpr, st);
+          ? race::launch_csr_block<double>(s->exp_nblk, s->exp_blk.p, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y,
+                                           s->exp_per, st)
+          : race::launch_csr_block<float>(s->exp_nblk, s->exp_blk.p, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y,
+                                          s->exp_per, st);
   if (e != hipSuccess) return hip_fail(e, "expanded CRS product launch");
   return RACE_OK;
 }
@@ -1599,7 +1597,9 @@ static int csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, con
   const int64_t nnz = n > 0 ? row_ptr[n] : 0;
   if (nnz > 0 && !val) return fail(RACE_EINVAL, "val is NULL");
   if (lpr == 0) lpr = pick_lpr(n, nnz);
-  if (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8 && lpr != 16 && lpr != 32 && lpr != 64)
+  if (lpr < 0 && (upper || (lpr != -4 && lpr != -8 && lpr != -16)))
+    return fail(RACE_EINVAL, "row blocks take lanes_per_row -4, -8 or -16, full matrices only");
+  if (lpr > 0 && lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8 && lpr != 16 && lpr != 32 && lpr != 64)
     return fail(RACE_EINVAL, "lanes_per_row must be a power of two in 1..64");
   race_csr* h = new (std::nothrow) race_csr();
   if (!h) return fail(RACE_ENOMEM, "out of host memory");
@@ -1611,6 +1611,12 @@ static int csr_create(int32_t n, const int32_t* row_ptr, const int32_t* col, con
   if (e == hipSuccess) e = upload(h->rp, row_ptr, static_cast<size_t>(n) + 1, &total);
   if (e == hipSuccess) e = upload(h->col, col, static_cast<size_t>(nnz), &total);
   if (e == hipSuccess) e = upload(h->val, val, static_cast<size_t>(nnz), &total);
+  if (e == hipSuccess && lpr < 0) {
+    std::vector<int32_t> blk;
+    race::csr_row_blocks(n, row_ptr, -lpr, blk);
+    h->n_blk = static_cast<int32_t>(blk.size()) - 1;
+    e = upload(h->blk, blk.data(), blk.size(), &total);
+  }
   if (e != hipSuccess) {
     race_csr_destroy(h);
     return hip_fail(e, "baseline upload");
@@ -1634,7 +1640,10 @@ int race_csr_spmv(race_csr_t h, const double* x, double* y, void* stream) {
   if (h->atomic) return fail(RACE_ESTATE, "handle holds an upper triangle; use race_symm_spmv_atomic");
   if (h->n > 0 && (!x || !y)) return fail(RACE_EINVAL, "x or y is NULL");
   hipError_t e =
-      race::launch_csr_spmv<double>(h->n, h->rp.p, h->col.p, h->val.p, x, y, h->lpr, static_cast<hipStream_t>(stream));
+      h->lpr < 0 ? race::launch_csr_block<double>(h->n_blk, h->blk.p, h->rp.p, h->col.p, h->val.p, x, y, -h->lpr,
+                                                  static_cast<hipStream_t>(stream))
+                 : race::launch_csr_spmv<double>(h->n, h->rp.p, h->col.p, h->val.p, x, y, h->lpr,
+                                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "CSR SpMV launch");
   return RACE_OK;
 }
@@ -1656,6 +1665,7 @@ void race_csr_destroy(race_csr_t h) {
   if (h->device >= 0) (void)hipSetDevice(h->device);
   release(h->rp);
   release(h->col);
+  release(h->blk);
   release(h->val);
   (void)hipSetDevice(cur);
   delete h;

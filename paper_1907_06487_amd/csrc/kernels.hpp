@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace race {
 
@@ -194,7 +195,18 @@ hipError_t launch_clear_words(uint32_t* p, int64_t words, hipStream_t st);
 template <typename ValT>
 hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const ValT* val, const double* x,
                            double* y, int32_t lanes_per_row, hipStream_t st);
-int32_t expanded_lanes(int32_t n, int64_t nnz_full);
+// Entries per thread of the expanded CRS product's row blocks (the sweep of
+// 4, 8 and 16 on the irregular banded 2^22 matrix finds 8 fastest).
+constexpr int32_t kExpandedPerThread = 8;
+// Row blocks of the full CRS matrix for csr_block_kernel: consecutive rows
+// with at most 256 * per entries and kCsrBlockRows rows each (a row longer
+// than that alone); blk[0] = 0, blk.back() = n, one more entry than blocks.
+constexpr int32_t kCsrBlockRows = 1024;
+void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk);
+// CRS SpMV over those blocks (per = 4, 8 or 16 entries per thread).
+template <typename ValT>
+hipError_t launch_csr_block(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
+                            const ValT* val, const double* x, double* y, int32_t per, hipStream_t st);
 hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                               double* y, int32_t lanes_per_row, hipStream_t st);
 hipError_t launch_permute(int32_t n, int32_t k, const int32_t* new2old, const double* in, double* out,

@@ -215,8 +215,7 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
 }
 
 // Full-matrix CRS SpMV (Algorithm "SpMV"), LPR lanes per row; values
-// float64 or float32 (promoted, float64 arithmetic).  The matrix streams
-// through non-temporal loads.
+// float64 or float32 (promoted, float64 arithmetic).
 template <int LPR, typename ValT>
 __global__ void __launch_bounds__(256) csr_spmv_kernel(int32_t n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ col, const ValT* __restrict__ val,
@@ -227,11 +226,72 @@ __global__ void __launch_bounds__(256) csr_spmv_kernel(int32_t n, const int32_t*
   if (row >= n) return;  // whole lane groups leave together
   double s = 0.0;
   const int32_t e = rp[row + 1];
-  for (int32_t i = rp[row] + l; i < e; i += LPR)
-    s += static_cast<double>(stream_load(val + i)) * x[stream_load(col + i)];
+  // plain loads: a lane group takes a row's entries a part of a cache line
+  // at a time, so a line that is not kept would be fetched again
+  for (int32_t i = rp[row] + l; i < e; i += LPR) s += static_cast<double>(val[i]) * x[col[i]];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
   if (l == 0) y[row] = s;
+}
+
+// Full-matrix CRS SpMV over row blocks (Algorithm "SpMV" with the entries
+// of consecutive rows streamed together).  Block b covers rows
+// [blk[b], blk[b+1]); their entries, at most 256 * PER, are consecutive in
+// the CRS arrays, so thread t loads entries t, t + 256, ... with unit
+// stride across the workgroup (every load instruction takes whole cache
+// lines, read non-temporally), multiplies each by its x entry and keeps the
+// product in LDS; after a barrier one thread per row adds its row's
+// products in entry order.  A block of a single row longer than 256 * PER
+// strides over the row and reduces across the workgroup instead.  Loads of
+// the lanes past the block's last entry repeat that entry (no per-lane
+// branch around the loads) and their products are dropped.
+template <typename ValT, int PER>
+__global__ void __launch_bounds__(256) csr_block_kernel(const int32_t* __restrict__ blk,
+                                                        const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const ValT* __restrict__ val,
+                                                        const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int32_t kCap = 256 * PER;
+  __shared__ double prod[kCap];
+  const int32_t t = static_cast<int32_t>(threadIdx.x);
+  const int32_t r0 = uniform_load(blk, static_cast<int32_t>(blockIdx.x));
+  const int32_t r1 = uniform_load(blk, static_cast<int32_t>(blockIdx.x) + 1);
+  const int32_t e0 = uniform_load(rp, r0);
+  const int32_t ne = uniform_load(rp, r1) - e0;
+  if (ne > kCap) {
+    // one long row (the partition gives such a row a block of its own)
+    double s = 0.0;
+    for (int32_t i = e0 + t; i < e0 + ne; i += 256) s += static_cast<double>(val[i]) * x[col[i]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((t & 63) == 0) prod[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) y[r0] = (prod[0] + prod[1]) + (prod[2] + prod[3]);
+    return;
+  }
+  if (ne > 0) {
+    int32_t c[PER];
+    ValT v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int32_t i = e0 + min(t + k * 256, ne - 1);
+      c[k] = stream_load(col + i);
+      v[k] = stream_load(val + i);
+    }
+    double xv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) xv[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (t + k * 256 < ne) prod[t + k * 256] = static_cast<double>(v[k]) * xv[k];
+  }
+  __syncthreads();
+  for (int32_t r = r0 + t; r < r1; r += 256) {
+    const int32_t a = rp[r] - e0, b = rp[r + 1] - e0;
+    double s = 0.0;
+    for (int32_t j = a; j < b; ++j) s += prod[j];
+    y[r] = s;
+  }
 }
 
 // SymmSpMV with device-wide float64 atomics for every update of y.
@@ -539,6 +599,42 @@ template hipError_t launch_csr_spmv<double>(int32_t, const int32_t*, const int32
                                             double*, int32_t, hipStream_t);
 template hipError_t launch_csr_spmv<float>(int32_t, const int32_t*, const int32_t*, const float*, const double*,
                                            double*, int32_t, hipStream_t);
+
+template <typename ValT>
+hipError_t launch_csr_block(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
+                            const ValT* val, const double* x, double* y, int32_t per, hipStream_t st) {
+  if (n_blocks == 0) return hipSuccess;
+  const dim3 grid(static_cast<uint32_t>(n_blocks));
+  switch (per) {
+#define CSR_B(P)                                                                                         \
+  case P:                                                                                                \
+    hipLaunchKernelGGL((dev::csr_block_kernel<ValT, P>), grid, dim3(256), 0, st, blk, rp, col, val, x, y); \
+    break;
+    CSR_B(4) CSR_B(8) CSR_B(16)
+#undef CSR_B
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_csr_block<double>(int32_t, const int32_t*, const int32_t*, const int32_t*, const double*,
+                                             const double*, double*, int32_t, hipStream_t);
+template hipError_t launch_csr_block<float>(int32_t, const int32_t*, const int32_t*, const int32_t*, const float*,
+                                            const double*, double*, int32_t, hipStream_t);
+
+void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk) {
+  const int64_t cap = 256 * static_cast<int64_t>(per);
+  blk.clear();
+  blk.push_back(0);
+  int32_t r = 0;
+  while (r < n) {
+    int32_t e = r + 1;  // a row longer than cap still gets a block of its own
+    while (e < n && e - r < kCsrBlockRows && rp[e + 1] - rp[r] <= cap) ++e;
+    blk.push_back(e);
+    r = e;
+  }
+}
 
 hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
                               double* y, int32_t lpr, hipStream_t st) {

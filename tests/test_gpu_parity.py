@@ -205,6 +205,60 @@ def test_baseline_csr_spmv():
                f"csr lpr={lpr}")
 
 
+def _ragged_crs(n, seed):
+    """A general CRS matrix with empty rows (single ones and a run of 3000,
+    longer than a row block's row limit), rows longer than every row-block
+    capacity (5000 entries), and short rows of random length."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 40, size=n)
+    lens[rng.choice(n, n // 10, replace=False)] = 0
+    lens[100:3100] = 0
+    lens[[0, 7, n // 2, n - 1]] = 5000
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, int(k), replace=False)) for k in lens]).astype(np.int32)
+    val = rng.standard_normal(int(rp[-1]))
+    return rp, col, val
+
+
+@pytest.mark.parametrize("per", [4, 8, 16])
+@pytest.mark.parametrize("case", ["3d27pt_20", "ragged_9000", "one_row"])
+def test_baseline_csr_row_blocks(case, per):
+    """The row-block CRS product (lanes_per_row -4/-8/-16) against the
+    oracle's SpMV: several blocks and a ragged last one, empty rows, rows
+    longer than a block's capacity, a single row."""
+    if case == "3d27pt_20":
+        m = matgen.stencil3d_27pt(20, seed=9)
+        n = m.n
+        rp, c, v = O.expand_full(m.n, m.row_ptr, m.col, m.val)
+    elif case == "ragged_9000":
+        n = 9000
+        rp, c, v = _ragged_crs(n, 5)
+    else:
+        n = 1
+        rp, c, v = np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32), np.array([3.0])
+    x = matgen.rhs(n, 17) if n > 1 else np.array([-2.0])
+    y_ref = O.spmv_full(n, rp, c, v, x)
+    absax = O.spmv_full(n, rp, c, np.abs(v), np.abs(x))
+    print(f"case csr row blocks {case} per={per}: n={n} nnz={int(rp[-1])}", flush=True)
+    h = R.race_csr_create(n, rp, c, v, -per)
+    try:
+        xd = torch.as_tensor(x, device=DEV)
+        yd = torch.full_like(xd, float("nan"))
+        R.race_csr_spmv(h, xd, yd)
+        torch.cuda.synchronize()
+    finally:
+        R.race_csr_destroy(h)
+    y = yd.cpu().numpy()
+    mlen = int(np.diff(rp).max(initial=0))
+    u = 2.0 ** -53
+    g = (mlen + 1) * u / (1 - (mlen + 1) * u)
+    en, ec = O.errors(y, y_ref, absax)
+    print(f"[csr row blocks {case} per={per}] err_norm={en:.3e} err_comp={ec:.3e}", flush=True)
+    assert en <= 1e-12 and ec <= 4 * g
+    assert np.all(y[np.diff(rp) == 0] == 0.0)
+
+
 @pytest.mark.parametrize("lpr", [0, 1, 8, 64])
 def test_baseline_atomic_symm(lpr):
     m = matgen.banded_irregular(30000, seed=13, band=3000)
@@ -610,7 +664,7 @@ def test_expanded_product_path(name, make, params, path, value_type):
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, value_type=value_type, **params)
     try:
         st = s.stats()
-        print(f"case {name} {value_type}: n={m.n} product_path={st['product_path']} lanes={st['expanded_lanes']}",
+        print(f"case {name} {value_type}: n={m.n} product_path={st['product_path']} per_thread={st['expanded_per_thread']}",
               flush=True)
         assert st["product_path"] == path
         perm = s.perm()

@@ -348,7 +348,7 @@ def test_low_locality_decision(name, make, kw, want):
                 expect = int(2 * shared > touches)
                 assert expect == want, (shared, touches)
             assert st["product_path"] == expect, mode
-            assert (st["expanded_lanes"] > 0) == bool(expect)
+            assert (st["expanded_per_thread"] > 0) == bool(expect)
         finally:
             s.close()
     g = matgen.config_2d_small()
