@@ -316,17 +316,19 @@ def _sampled_rows_exact(m, x, rows):
     return np.array([math.fsum(t + cols_i[int(i)]) for t, i in zip(out, rows)])
 
 
-@pytest.mark.parametrize("nt,mode,block,stages", [(256, "flow", 512, 2), (256, "flow", 512, 4), (256, "flow", 256, 4),
-                                                  (1024, "flow", 256, 4), (512, "phases", 256, 4)])
-def test_race_full_size_3d27pt_128(nt, mode, block, stages):
+@pytest.mark.parametrize("nt,mode,block,stages,window", [(256, "flow", 512, 2, 4064), (256, "flow", 512, 4, 3840),
+                                                         (256, "flow", 256, 4, 3840), (1024, "flow", 256, 4, 3840),
+                                                         (512, "phases", 256, 4, 3840)])
+def test_race_full_size_3d27pt_128(nt, mode, block, stages, window):
     """The 128^3 stencil at full size; the first case is the benchmark's
-    configuration (N_t 256, 2 stages, 512 threads, window 3840, dataflow,
+    configuration (N_t 256, 2 stages, 512 threads, window 4064, dataflow,
     shared atomics)."""
     m = matgen.config_3d_128()
-    print(f"case 3d27pt_128 n_workers={nt} mode={mode} block={block} stages={stages}: n={m.n} nnz={m.nnz}", flush=True)
+    print(f"case 3d27pt_128 n_workers={nt} mode={mode} block={block} stages={stages} window={window}: n={m.n} "
+          f"nnz={m.nnz}", flush=True)
     x = matgen.rhs(m.n, 2)
     y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x)
-    y, st = run_race(m, x, n_workers=nt, exec_mode=mode, block_threads=block, window_max=3840, shared_atomics=True,
+    y, st = run_race(m, x, n_workers=nt, exec_mode=mode, block_threads=block, window_max=window, shared_atomics=True,
                      max_stages=stages)
     _check(y, y_ref, O.abs_product(m.n, m.row_ptr, m.col, m.val, x), _full_row_len(m), f"3d27pt_128 nt={nt}")
     rows = np.random.default_rng(0).choice(m.n, size=200, replace=False)
