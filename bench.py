@@ -49,7 +49,7 @@ def kernel_source_hash():
     """Hash of the sources that decide what the RACE kernel moves."""
     import hashlib
     h = hashlib.sha256()
-    for f in ["race_kernels.hip", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp"]:
+    for f in ["race_kernels.hip", "unit_device.hpp", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp"]:
         with open(os.path.join(ROOT, "paper_1907_06487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

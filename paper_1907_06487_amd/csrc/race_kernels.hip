@@ -244,18 +244,26 @@ __global__ void __launch_bounds__(256) csr_spmv_kernel(int32_t n, const int32_t*
 // products in entry order.  A block of a single row longer than 256 * PER
 // strides over the row and reduces across the workgroup instead.  Loads of
 // the lanes past the block's last entry repeat that entry (no per-lane
-// branch around the loads) and their products are dropped.
+// branch around the loads) and their products are dropped.  Workgroups are
+// dealt to the 8 XCDs in turn, so workgroup g runs block (g % 8) * G8 + g / 8
+// (G8 = grid / 8, the grid padded to a multiple of 8): each XCD streams a
+// contiguous eighth of the rows, and the x entries its rows gather stay in
+// its own L2 instead of being fetched by all eight.
 template <typename ValT, int PER>
 __global__ void __launch_bounds__(256) csr_block_kernel(const int32_t* __restrict__ blk,
                                                         const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ col,
                                                         const ValT* __restrict__ val,
-                                                        const double* __restrict__ x, double* __restrict__ y) {
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        int32_t n_blocks) {
   constexpr int32_t kCap = 256 * PER;
   __shared__ double prod[kCap];
   const int32_t t = static_cast<int32_t>(threadIdx.x);
-  const int32_t r0 = uniform_load(blk, static_cast<int32_t>(blockIdx.x));
-  const int32_t r1 = uniform_load(blk, static_cast<int32_t>(blockIdx.x) + 1);
+  const uint32_t g8 = gridDim.x / 8u;
+  const int32_t b = static_cast<int32_t>((blockIdx.x % 8u) * g8 + blockIdx.x / 8u);
+  if (b >= n_blocks) return;  // padding of the grid (uniform per workgroup)
+  const int32_t r0 = uniform_load(blk, b);
+  const int32_t r1 = uniform_load(blk, b + 1);
   const int32_t e0 = uniform_load(rp, r0);
   const int32_t ne = uniform_load(rp, r1) - e0;
   if (ne > kCap) {
@@ -604,11 +612,11 @@ template <typename ValT>
 hipError_t launch_csr_block(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
                             const ValT* val, const double* x, double* y, int32_t per, hipStream_t st) {
   if (n_blocks == 0) return hipSuccess;
-  const dim3 grid(static_cast<uint32_t>(n_blocks));
+  const dim3 grid(static_cast<uint32_t>((static_cast<int64_t>(n_blocks) + 7) / 8 * 8));
   switch (per) {
 #define CSR_B(P)                                                                                         \
   case P:                                                                                                \
-    hipLaunchKernelGGL((dev::csr_block_kernel<ValT, P>), grid, dim3(256), 0, st, blk, rp, col, val, x, y); \
+    hipLaunchKernelGGL((dev::csr_block_kernel<ValT, P>), grid, dim3(256), 0, st, blk, rp, col, val, x, y, n_blocks); \
     break;
     CSR_B(4) CSR_B(8) CSR_B(16)
 #undef CSR_B
