@@ -245,12 +245,22 @@ def run_batch(args, k, torch):
 
     ms_plain = time_ring(lambda x, y: run_plain(), [0], [0], args.steps, args.warmup, torch)
     t0 = time.perf_counter()
-    scheds, batch, chosen = autotune.tune_batch(mats, k, log=log)
+    scheds, batch, chosen = autotune.tune_batch(mats, k, log=log, low_locality=args.low_locality)
     t_tune = time.perf_counter() - t0
     batch.bind(xs, ys)
     ms_graph = time_ring(lambda x, y: batch.run(use_graph=True), [0], [0], args.steps, args.warmup, torch)
     ms_direct = time_ring(lambda x, y: batch.run(use_graph=False), [0], [0], args.steps, args.warmup, torch)
     batch.check()
+    n_expanded = sum(1 for sc in scheds if sc.stats()["product_path"] == 1) if k == 1 else 0
+
+    def run_tuned():
+        for sc, x, y in zip(scheds, xs, ys):
+            if k > 1:
+                sc.spmm(x, y)
+            else:
+                sc.spmv(x, y)
+
+    ms_tuned = time_ring(lambda x, y: run_tuned(), [0], [0], args.steps, args.warmup, torch)
     # error of every matrix against the oracle (permuted order)
     batch.run(use_graph=True)
     torch.cuda.synchronize()
@@ -262,8 +272,9 @@ def run_batch(args, k, torch):
         xo[perm] = xh
         y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, xo)[perm]
         worst = max(worst, O.errors(y.cpu().numpy(), y_ref)[0])
-    log(f"batch64 k={k}: graph {ms_graph * 1e3:.1f} us, direct {ms_direct * 1e3:.1f} us, 64 separate {ms_plain * 1e3:.1f} us, "
-        f"tuning {t_tune:.1f}s, worst error {worst:.2e}")
+    log(f"batch64 k={k}: graph {ms_graph * 1e3:.1f} us, direct {ms_direct * 1e3:.1f} us, 64 separate {ms_plain * 1e3:.1f} us "
+        f"(library defaults), 64 separate calls of the tuned schedules {ms_tuned * 1e3:.1f} us, {n_expanded} matrices "
+        f"on the row-block CRS product, tuning {t_tune:.1f}s, worst error {worst:.2e}")
     out = {
         "metric": "batched SymmSpMM GFLOP/s, 64 matrices in one hipGraph replay", "value": round(flops / (ms_graph * 1e-3) / 1e9, 3),
         "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
@@ -274,7 +285,11 @@ def run_batch(args, k, torch):
                    "window_max": [p["window_max"] for p in chosen["params"]]},
         "roofline": {"bound": "hbm", "achieved": round(bytes_min / (ms_graph * 1e-3) / 1e9, 3), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(bytes_min / (ms_graph * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": None},
-        "separate_launches": {"ms": ms_plain, "gflops": flops / (ms_plain * 1e-3) / 1e9},
+        "separate_launches": {"ms": ms_plain, "gflops": flops / (ms_plain * 1e-3) / 1e9,
+                              "shapes": "library defaults, RACE kernels"},
+        "separate_launches_tuned": {"ms": ms_tuned, "gflops": flops / (ms_tuned * 1e-3) / 1e9,
+                                    "shapes": "the batch's own schedules"},
+        "expanded_members": n_expanded, "low_locality": args.low_locality,
         "batch_direct_launch": {"ms": ms_direct},
         "speedup_vs_separate": ms_plain / ms_graph,
         "error": {"norm_worst": worst},

@@ -347,7 +347,10 @@ int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, in
  * order) for a single persistent dataflow launch of `threads` threads per
  * workgroup (0: the largest block_threads of the schedules); when the
  * largest unit window cannot hold k columns, the run takes passes of the
- * widest tile that fits, one launch each.  The schedules are borrowed and
+ * widest tile that fits, one launch each.  With k = 1, schedules whose
+ * product is the expanded CRS product (stats product_path 1, see
+ * race_params.low_locality) take no tickets: one row-block launch over all
+ * of them runs before the persistent launch.  The schedules are borrowed and
  * must outlive the batch. */
 int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_t threads, race_batch_t* out);
 

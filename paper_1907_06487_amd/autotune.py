@@ -22,12 +22,12 @@ def max_window(k: int) -> int:
     return min(3840, (159 * 1024) // (16 * k + 4) - 16)
 
 
-def candidates(n: int, k: int, block: int, window: int = 0):
+def candidates(n: int, k: int, block: int, window: int = 0, low_locality: str = "race"):
     """Worker counts of 8000, 4000 and 2000 rows per worker at the given
     window (0: the largest that holds all k columns)."""
     wm = window or max_window(k)
     nts = sorted({int(min(4096, max(4, n // r))) for r in (8000, 4000, 2000)})
-    return [dict(n_workers=nt, window_max=wm, block_threads=block) for nt in nts]
+    return [dict(n_workers=nt, window_max=wm, block_threads=block, low_locality=low_locality) for nt in nts]
 
 
 def _time(fn, reps):
@@ -44,13 +44,14 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0", window: int = 0):
+def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0", window: int = 0,
+                low_locality: str = "race"):
     """Best shape for one matrix: returns (params, ms, all results)."""
     shape = (m.n, k) if k > 1 else (m.n,)
     x = torch.rand(shape, dtype=torch.float64, device=device)
     y = torch.empty_like(x)
     results = []
-    for c in candidates(m.n, k, block, window):
+    for c in candidates(m.n, k, block, window, low_locality):
         s = Schedule(m.n, m.row_ptr, m.col, m.val, **c)
         ms = _time(lambda: s.spmm(x, y) if k > 1 else s.spmv(x, y), reps)
         s.close()
@@ -59,10 +60,12 @@ def tune_matrix(m, k: int, block: int, reps: int = 5, device: str = "cuda:0", wi
     return results[0][1], results[0][0], results
 
 
-def tune_batch(mats, k: int, blocks=(256, 512, 1024), reps: int = 5, device: str = "cuda:0", log=None):
+def tune_batch(mats, k: int, blocks=(256, 512, 1024), reps: int = 5, device: str = "cuda:0", log=None,
+               low_locality: str = "race"):
     """Per-matrix shapes (timed at 512 threads) for each window mode, then the
     mode and workgroup size whose whole batch replay runs fastest.  Returns
-    (schedules, batch, chosen)."""
+    (schedules, batch, chosen).  low_locality as for Schedule ("auto": with
+    k = 1 the matrices without window reuse run the row-block CRS product)."""
     modes = [0] if max_window(k) >= 3840 else [0, 3840]  # one pass of k columns; or the largest window, tiled
     xs = [torch.rand((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=device) for m in mats]
     ys = [torch.empty_like(x) for x in xs]
@@ -70,7 +73,7 @@ def tune_batch(mats, k: int, blocks=(256, 512, 1024), reps: int = 5, device: str
     for window in modes:
         params = []
         for i, m in enumerate(mats):
-            params.append(tune_matrix(m, k, 512, reps=3, device=device, window=window)[0])
+            params.append(tune_matrix(m, k, 512, reps=3, device=device, window=window, low_locality=low_locality)[0])
             if log and i % 16 == 15:
                 log(f"autotune k={k} window {window or max_window(k)}: {i + 1}/{len(mats)} matrices")
         scheds = [Schedule(m.n, m.row_ptr, m.col, m.val, **p) for m, p in zip(mats, params)]

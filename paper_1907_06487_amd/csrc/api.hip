@@ -179,6 +179,12 @@ struct race_batch {
   DevBuf<double> tiles_x, tiles_y;  // every matrix's column tiles (tiled runs), matrix m at tile_base[m]
   std::vector<int64_t> tile_base;
   void* d_mats = nullptr;          // BatchMat<ValT>[count]
+  // members that run the row-block CRS product (k = 1, schedules whose
+  // product is the expanded one): no tickets; one launch over their blocks
+  std::vector<int32_t> exp_members;
+  int32_t n_exp_blocks = 0;
+  DevBuf<int32_t> blk_mat;
+  void* d_bmats = nullptr;         // BlockMat<ValT>[exp_members.size()]
   bool bound = false;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -1334,6 +1340,9 @@ static void batch_release(race_batch_t b) {
   b->cap = nullptr;
   if (b->d_mats) (void)hipFree(b->d_mats);
   b->d_mats = nullptr;
+  if (b->d_bmats) (void)hipFree(b->d_bmats);
+  b->d_bmats = nullptr;
+  release(b->blk_mat);
   release(b->ticket_mat);
   release(b->ticket_unit);
   release(b->state);
@@ -1344,6 +1353,15 @@ static void batch_release(race_batch_t b) {
 // One pass per tile of right-hand sides, each a state reset and one
 // persistent launch over all tickets.
 static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
+  if (b->n_exp_blocks > 0) {
+    hipError_t e = b->value_type == 0
+                       ? race::launch_csr_block_batch<double>(static_cast<const race::BlockMat<double>*>(b->d_bmats),
+                                                              b->blk_mat.p, b->n_exp_blocks, st)
+                       : race::launch_csr_block_batch<float>(static_cast<const race::BlockMat<float>*>(b->d_bmats),
+                                                             b->blk_mat.p, b->n_exp_blocks, st);
+    if (e != hipSuccess) return e;
+  }
+  if (b->n_tickets == 0) return hipSuccess;
   if (b->tiled) {
     hipError_t e = b->value_type == 0
                        ? race::launch_batch_tile<double>(static_cast<const race::BatchMat<double>*>(b->d_mats),
@@ -1392,7 +1410,7 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     if (vt >= 0 && s[m]->params.value_type != vt) return fail(RACE_EINVAL, "schedules mix value types");
     vt = s[m]->params.value_type;
     threads = std::max(threads, s[m]->params.block_threads);
-    wmax = std::max(wmax, s[m]->L.max_window);
+    if (k > 1 || !s[m]->expanded) wmax = std::max(wmax, s[m]->L.max_window);
   }
   // right-hand sides per pass: all k if the largest window allows, else the widest tile that fits
   int32_t kt = k;
@@ -1427,10 +1445,17 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   std::vector<Tk> tk;
   int64_t total_units = 0;
   b->unit_base.resize(count);
+  std::vector<int32_t> blk_mat;
   for (int32_t m = 0; m < count; ++m) {
     const race::Layout& L = s[m]->L;
     const race::Tree& t = s[m]->tree;
     b->unit_base[m] = total_units;
+    if (k == 1 && s[m]->expanded) {
+      blk_mat.insert(blk_mat.end(), static_cast<size_t>(s[m]->exp_nblk),
+                     static_cast<int32_t>(b->exp_members.size()));
+      b->exp_members.push_back(m);
+      continue;
+    }
     const int32_t nu = static_cast<int32_t>(L.unit_lo.size());
     for (int32_t z = 0; z < L.n_zero_tasks; ++z) tk.push_back({-1.0, m, z});
     for (int32_t u = 0; u < nu; ++u)
@@ -1451,8 +1476,10 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
   int64_t total = 0;
   const size_t words = static_cast<size_t>((total_units + 4 + 1) / 2 * 2);
   std::vector<uint32_t> zeros(words, 0u);
+  b->n_exp_blocks = static_cast<int32_t>(blk_mat.size());
   e = upload(b->ticket_mat, tm.data(), tm.size(), &total);
   if (e == hipSuccess) e = upload(b->ticket_unit, tu.data(), tu.size(), &total);
+  if (e == hipSuccess && !blk_mat.empty()) e = upload(b->blk_mat, blk_mat.data(), blk_mat.size(), &total);
   if (e == hipSuccess) e = upload(b->state, zeros.data(), zeros.size(), &total);
   int32_t per_cu = 0;
   if (e == hipSuccess)
@@ -1515,6 +1542,32 @@ int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y) {
     e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (!b->exp_members.empty()) {
+    const size_t ne = b->exp_members.size();
+    const size_t bbytes = b->value_type == 0 ? sizeof(race::BlockMat<double>) * ne : sizeof(race::BlockMat<float>) * ne;
+    if (!b->d_bmats) {
+      e = hipMalloc(&b->d_bmats, bbytes);
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    }
+    auto fill = [&](auto& h, auto val_of) {
+      int32_t base = 0;
+      for (size_t i = 0; i < ne; ++i) {
+        const int32_t m = b->exp_members[i];
+        const race_schedule_t sm = b->mats[m];
+        h[i] = {sm->exp_blk.p, sm->exp_rp.p, sm->exp_col.p, val_of(sm), X[m], Y[m], base};
+        base += sm->exp_nblk;
+      }
+      return hipMemcpy(b->d_bmats, h.data(), bbytes, hipMemcpyHostToDevice);
+    };
+    if (b->value_type == 0) {
+      std::vector<race::BlockMat<double>> h(ne);
+      e = fill(h, [](race_schedule_t sm) -> const double* { return sm->exp_val64.p; });
+    } else {
+      std::vector<race::BlockMat<float>> h(ne);
+      e = fill(h, [](race_schedule_t sm) -> const float* { return sm->exp_val32.p; });
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
   // capture reset + persistent kernel once; replays reuse it
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);

@@ -203,6 +203,24 @@ constexpr int32_t kExpandedPerThread = 8;
 // than that alone); blk[0] = 0, blk.back() = n, one more entry than blocks.
 constexpr int32_t kCsrBlockRows = 1024;
 void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk);
+// One matrix of a batched row-block product (device pointers; blocks of
+// kExpandedPerThread entries per thread); `base` is the index of its first
+// block among all matrices' blocks.
+template <typename ValT>
+struct BlockMat {
+  const int32_t* blk;
+  const int32_t* rp;
+  const int32_t* col;
+  const ValT* val;
+  const double* x;
+  double* y;
+  int32_t base;
+};
+// The row-block products of several matrices in one launch; blk_mat[g] is
+// the matrix of global block g (n_blocks blocks in all).
+template <typename ValT>
+hipError_t launch_csr_block_batch(const BlockMat<ValT>* mats, const int32_t* blk_mat, int32_t n_blocks,
+                                  hipStream_t st);
 // CRS SpMV over those blocks (per = 4, 8 or 16 entries per thread).
 template <typename ValT>
 hipError_t launch_csr_block(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,

@@ -249,21 +249,14 @@ __global__ void __launch_bounds__(256) csr_spmv_kernel(int32_t n, const int32_t*
 // (G8 = grid / 8, the grid padded to a multiple of 8): each XCD streams a
 // contiguous eighth of the rows, and the x entries its rows gather stay in
 // its own L2 instead of being fetched by all eight.
+// One row block (rows r0..r1 of one matrix) of the row-block product, run
+// by a 256-thread workgroup with `prod` its LDS array of 256 * PER doubles.
 template <typename ValT, int PER>
-__global__ void __launch_bounds__(256) csr_block_kernel(const int32_t* __restrict__ blk,
-                                                        const int32_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ col,
-                                                        const ValT* __restrict__ val,
-                                                        const double* __restrict__ x, double* __restrict__ y,
-                                                        int32_t n_blocks) {
+__device__ __forceinline__ void csr_block_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                               const ValT* __restrict__ val, const double* __restrict__ x,
+                                               double* __restrict__ y, int32_t r0, int32_t r1, double* prod) {
   constexpr int32_t kCap = 256 * PER;
-  __shared__ double prod[kCap];
   const int32_t t = static_cast<int32_t>(threadIdx.x);
-  const uint32_t g8 = gridDim.x / 8u;
-  const int32_t b = static_cast<int32_t>((blockIdx.x % 8u) * g8 + blockIdx.x / 8u);
-  if (b >= n_blocks) return;  // padding of the grid (uniform per workgroup)
-  const int32_t r0 = uniform_load(blk, b);
-  const int32_t r1 = uniform_load(blk, b + 1);
   const int32_t e0 = uniform_load(rp, r0);
   const int32_t ne = uniform_load(rp, r1) - e0;
   if (ne > kCap) {
@@ -300,6 +293,41 @@ __global__ void __launch_bounds__(256) csr_block_kernel(const int32_t* __restric
     for (int32_t j = a; j < b; ++j) s += prod[j];
     y[r] = s;
   }
+}
+
+// Workgroup g of a grid padded to a multiple of 8 runs block
+// (g % 8) * (grid / 8) + g / 8 (see above).
+__device__ __forceinline__ int32_t xcd_block() {
+  const uint32_t g8 = gridDim.x / 8u;
+  return static_cast<int32_t>((blockIdx.x % 8u) * g8 + blockIdx.x / 8u);
+}
+
+template <typename ValT, int PER>
+__global__ void __launch_bounds__(256) csr_block_kernel(const int32_t* __restrict__ blk,
+                                                        const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const ValT* __restrict__ val,
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        int32_t n_blocks) {
+  __shared__ double prod[256 * PER];
+  const int32_t b = xcd_block();
+  if (b >= n_blocks) return;  // padding of the grid (uniform per workgroup)
+  csr_block_rows<ValT, PER>(rp, col, val, x, y, uniform_load(blk, b), uniform_load(blk, b + 1), prod);
+}
+
+// The row-block product of several matrices in one launch (the members of a
+// batch that run it): global block g belongs to matrix blk_mat[g] and is
+// block g - base of that matrix.
+template <typename ValT, int PER>
+__global__ void __launch_bounds__(256) csr_block_batch_kernel(const BlockMat<ValT>* __restrict__ mats,
+                                                              const int32_t* __restrict__ blk_mat,
+                                                              int32_t n_blocks) {
+  __shared__ double prod[256 * PER];
+  const int32_t g = xcd_block();
+  if (g >= n_blocks) return;
+  const BlockMat<ValT> m = mats[uniform_load(blk_mat, g)];
+  const int32_t b = g - m.base;
+  csr_block_rows<ValT, PER>(m.rp, m.col, m.val, m.x, m.y, uniform_load(m.blk, b), uniform_load(m.blk, b + 1), prod);
 }
 
 // SymmSpMV with device-wide float64 atomics for every update of y.
@@ -630,6 +658,19 @@ template hipError_t launch_csr_block<double>(int32_t, const int32_t*, const int3
                                              const double*, double*, int32_t, hipStream_t);
 template hipError_t launch_csr_block<float>(int32_t, const int32_t*, const int32_t*, const int32_t*, const float*,
                                             const double*, double*, int32_t, hipStream_t);
+
+template <typename ValT>
+hipError_t launch_csr_block_batch(const BlockMat<ValT>* mats, const int32_t* blk_mat, int32_t n_blocks,
+                                  hipStream_t st) {
+  if (n_blocks == 0) return hipSuccess;
+  const dim3 grid(static_cast<uint32_t>((static_cast<int64_t>(n_blocks) + 7) / 8 * 8));
+  hipLaunchKernelGGL((dev::csr_block_batch_kernel<ValT, kExpandedPerThread>), grid, dim3(256), 0, st, mats, blk_mat,
+                     n_blocks);
+  return hipGetLastError();
+}
+
+template hipError_t launch_csr_block_batch<double>(const BlockMat<double>*, const int32_t*, int32_t, hipStream_t);
+template hipError_t launch_csr_block_batch<float>(const BlockMat<float>*, const int32_t*, int32_t, hipStream_t);
 
 void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk) {
   const int64_t cap = 256 * static_cast<int64_t>(per);

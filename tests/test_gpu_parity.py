@@ -403,14 +403,26 @@ def _batch_mats():
             matgen.random_symmetric(300, 0.02, seed=55), matgen.stencil3d_27pt(9, seed=56)]
 
 
-@pytest.mark.parametrize("k", [1, 4, 16])
-def test_batch_graph_replays(k):
+@pytest.mark.parametrize("k,low_locality", [(1, "race"), (4, "race"), (16, "race"), (1, "auto"), (1, "expanded"),
+                                            (4, "expanded")])
+def test_batch_graph_replays(k, low_locality):
+    """Graph replays and direct launches of a small batch against the oracle.
+    With k = 1, members whose product is the expanded CRS product (all of
+    them with "expanded", the banded one with "auto") run the batched
+    row-block launch instead of tickets; with k > 1 they keep the RACE
+    kernels."""
     mats = _batch_mats()
     window = min(3840, (159 * 1024) // (16 * k + 4) - 16)  # x, y windows of k doubles + the index, per entry
-    scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500), window_max=window) for m in mats]
+    scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500), window_max=window,
+                         low_locality=low_locality) for m in mats]
+    paths = [sc.stats()["product_path"] for sc in scheds]
+    if low_locality == "expanded":
+        assert all(p == 1 for p in paths)
     batch = R.Batch(scheds, k)
     info = batch.info()
-    print(f"batch k={k}: {info}", flush=True)
+    print(f"batch k={k} low_locality={low_locality} paths={paths}: {info}", flush=True)
+    if k == 1 and low_locality == "expanded":
+        assert info["n_tickets"] == 0  # every member runs the row-block launch
     gen = torch.Generator(device=DEV)
     gen.manual_seed(7 + k)
     xs = [torch.empty((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=DEV) for m in mats]
@@ -605,15 +617,21 @@ def test_batch_full_64(batch64, k):
     """The full 64-matrix batch of the benchmark for k = 1, 4, 16 in one
     graph replay, every matrix and column element-wise against the oracle
     (shapes: N_t of one worker per 4000 rows, the widest window holding all
-    k columns, 512 threads; for k = 16 also the largest window in passes)."""
+    k columns, 512 threads; for k = 16 also the largest window in passes;
+    for k = 1 also with low_locality "auto", the low-locality members on the
+    batched row-block product)."""
     from paper_1907_06487_amd import autotune
     mats = batch64
-    windows = [autotune.max_window(k)] + ([3840] if k > 2 else [])
-    for window in windows:
-        print(f"case batch64 k={k} window={window}: {sum(m.n for m in mats)} rows", flush=True)
+    cases = [(autotune.max_window(k), "race")] + ([(3840, "race")] if k > 2 else []) + \
+        ([(autotune.max_window(k), "auto")] if k == 1 else [])
+    for window, low_locality in cases:
+        print(f"case batch64 k={k} window={window} low_locality={low_locality}: {sum(m.n for m in mats)} rows",
+              flush=True)
         scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=int(min(4096, max(4, m.n // 4000))),
-                             window_max=window, block_threads=512) for m in mats]
+                             window_max=window, block_threads=512, low_locality=low_locality) for m in mats]
         batch = R.Batch(scheds, k, threads=512)
+        print(f"  {sum(sc.stats()['product_path'] for sc in scheds)} members on the expanded product, "
+              f"{batch.info()}", flush=True)
         gen = torch.Generator(device=DEV)
         gen.manual_seed(1000 + k)
         xs = [torch.rand((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=DEV, generator=gen) * 2 - 1
