@@ -251,7 +251,7 @@ def run_batch(args, k, torch):
     ms_graph = time_ring(lambda x, y: batch.run(use_graph=True), [0], [0], args.steps, args.warmup, torch)
     ms_direct = time_ring(lambda x, y: batch.run(use_graph=False), [0], [0], args.steps, args.warmup, torch)
     batch.check()
-    n_expanded = sum(1 for sc in scheds if sc.stats()["product_path"] == 1) if k == 1 else 0
+    n_expanded = sum(1 for sc in scheds if sc.stats()["product_path"] == 1)
 
     def run_tuned():
         for sc, x, y in zip(scheds, xs, ys):
@@ -274,7 +274,7 @@ def run_batch(args, k, torch):
         worst = max(worst, O.errors(y.cpu().numpy(), y_ref)[0])
     log(f"batch64 k={k}: graph {ms_graph * 1e3:.1f} us, direct {ms_direct * 1e3:.1f} us, 64 separate {ms_plain * 1e3:.1f} us "
         f"(library defaults), 64 separate calls of the tuned schedules {ms_tuned * 1e3:.1f} us, {n_expanded} matrices "
-        f"on the row-block CRS product, tuning {t_tune:.1f}s, worst error {worst:.2e}")
+        f"on the expanded CRS product, tuning {t_tune:.1f}s, worst error {worst:.2e}")
     out = {
         "metric": "batched SymmSpMM GFLOP/s, 64 matrices in one hipGraph replay", "value": round(flops / (ms_graph * 1e-3) / 1e9, 3),
         "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
@@ -317,7 +317,7 @@ def run_spmm(args, k, torch, m=None, one_pass=False):
     win = min(args.window, autotune.max_window(k)) if one_pass else args.window
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.n_workers, max_stages=args.max_stages,
                    block_threads=args.block, window_max=win, value_type=args.value_type, exec_mode=args.exec_mode,
-                   shared_atomics=bool(args.shared_atomics))
+                   shared_atomics=bool(args.shared_atomics), low_locality=args.low_locality)
     st = s.stats()
     dev = "cuda:0"
     nring = max(2, -(-RING_BYTES // (8 * m.n * k)))
@@ -342,14 +342,16 @@ def run_spmm(args, k, torch, m=None, one_pass=False):
     tile = k
     while tile > 1 and st["max_window"] * (16 * tile + 4) > 159 * 1024:
         tile -= 1
-    log(f"SpMM k={k}: {ms * 1e3:.2f} us/product, {flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, {achieved:.1f} GB/s "
+    path = "expanded CRS SpMM" if st["product_path"] == 1 else "RACE kernels"
+    log(f"SpMM k={k} ({path}): {ms * 1e3:.2f} us/product, {flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, {achieved:.1f} GB/s "
         f"algorithmic, window {win}, passes of {tile} columns, worst column error {err:.2e}")
     out = {
         "metric": f"SymmSpMM GFLOP/s, {k} right-hand sides", "value": round(flops / (ms * 1e-3) / 1e9, 3),
         "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "k": k, "n_workers": args.n_workers, "block_threads": args.block,
-                   "window_max": win, "rhs_tile": tile, "units": st["n_units"]},
+                   "window_max": win, "rhs_tile": tile, "units": st["n_units"], "product_path": path,
+                   "low_locality": args.low_locality},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_min},
         "error": {"norm_worst_column": err}, "cpu_baseline": None,

@@ -95,8 +95,10 @@ typedef struct {
                               the RACE kernels add with global float64 atomics, about 24 G/s on this chip): 0
                               (default) = the RACE kernels anyway; 1 = a full-matrix CRS product of the permuted
                               matrix over row blocks, as race_csr_create with lanes_per_row -8 (the schedule then
-                              also holds the expanded matrix; value_type 0 or 1; stats product_path 1); 2 = the CRS product always (tests).  SymmSpMM with k > 1, traced
-                              products, batches and complex values always run the RACE kernels */
+                              also holds the expanded matrix; value_type 0 or 1; stats product_path 1); 2 = the
+                              CRS product always (tests).  On such schedules race_symm_spmm with k > 1 runs a CRS
+                              SpMM of the expanded matrix (a lane per column) and batches run them outside the
+                              persistent launch; traced products always run the RACE kernels */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */
@@ -347,11 +349,11 @@ int race_permute(race_schedule_t s, int32_t k, const double* in, double* out, in
  * order) for a single persistent dataflow launch of `threads` threads per
  * workgroup (0: the largest block_threads of the schedules); when the
  * largest unit window cannot hold k columns, the run takes passes of the
- * widest tile that fits, one launch each.  With k = 1, schedules whose
- * product is the expanded CRS product (stats product_path 1, see
- * race_params.low_locality) take no tickets: one row-block launch over all
- * of them runs before the persistent launch.  The schedules are borrowed and
- * must outlive the batch. */
+ * widest tile that fits, one launch each.  Schedules whose product is the
+ * expanded CRS product (stats product_path 1, see race_params.low_locality)
+ * take no tickets: before the persistent launch, one row-block launch over
+ * all of them runs (k = 1), or a CRS SpMM launch each (k > 1).  The
+ * schedules are borrowed and must outlive the batch. */
 int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_t threads, race_batch_t* out);
 
 /* Set the device arrays of every matrix (host arrays of `count` device

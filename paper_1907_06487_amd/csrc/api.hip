@@ -179,9 +179,11 @@ struct race_batch {
   DevBuf<double> tiles_x, tiles_y;  // every matrix's column tiles (tiled runs), matrix m at tile_base[m]
   std::vector<int64_t> tile_base;
   void* d_mats = nullptr;          // BatchMat<ValT>[count]
-  // members that run the row-block CRS product (k = 1, schedules whose
-  // product is the expanded one): no tickets; one launch over their blocks
+  // members whose product is the expanded one: no tickets; with k = 1 one
+  // row-block launch over all their blocks, with k > 1 a CRS SpMM each
   std::vector<int32_t> exp_members;
+  std::vector<const double*> exp_x;  // their X and Y (bound)
+  std::vector<double*> exp_y;
   int32_t n_exp_blocks = 0;
   DevBuf<int32_t> blk_mat;
   void* d_bmats = nullptr;         // BlockMat<ValT>[exp_members.size()]
@@ -909,6 +911,17 @@ static int run_expanded(race_schedule_t s, const double* x, double* y, hipStream
   return RACE_OK;
 }
 
+// Y = A X (k >= 2 columns, row-major) as a CRS SpMM of the expanded
+// permuted matrix.
+static int run_expanded_spmm(race_schedule_t s, int32_t k, const double* x, double* y, hipStream_t st) {
+  const hipError_t e =
+      s->params.value_type == 0
+          ? race::launch_csr_spmm<double>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, st)
+          : race::launch_csr_spmm<float>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, st);
+  if (e != hipSuccess) return hip_fail(e, "expanded CRS SpMM launch");
+  return RACE_OK;
+}
+
 static int run_products(race_schedule_t s, int32_t k, const double* x, double* y, uint64_t* trace, void* stream) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (s->gs) return fail(RACE_EUNSUPPORTED, kDist1Product);
@@ -916,7 +929,9 @@ static int run_products(race_schedule_t s, int32_t k, const double* x, double* y
   if (k < 1 || k > 16) return fail(RACE_EUNSUPPORTED, "k must be in 1..16");
   if (s->tree.n == 0) return RACE_OK;
   if (!x || !y) return fail(RACE_EINVAL, "x or y is NULL");
-  if (s->expanded && k == 1 && !trace) return run_expanded(s, x, y, static_cast<hipStream_t>(stream));
+  if (s->expanded && !trace)
+    return k == 1 ? run_expanded(s, x, y, static_cast<hipStream_t>(stream))
+                  : run_expanded_spmm(s, k, x, y, static_cast<hipStream_t>(stream));
   if (s->params.value_type >= 2) {
     // complex: one vector of n interleaved (re, im) pairs, run as two columns
     if (k != 1) return fail(RACE_EUNSUPPORTED, "complex values take one right-hand side");
@@ -1361,6 +1376,18 @@ static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
                                                              b->blk_mat.p, b->n_exp_blocks, st);
     if (e != hipSuccess) return e;
   }
+  if (b->k > 1) {
+    for (size_t i = 0; i < b->exp_members.size(); ++i) {
+      const race_schedule_t sm = b->mats[b->exp_members[i]];
+      hipError_t e =
+          b->value_type == 0
+              ? race::launch_csr_spmm<double>(sm->tree.n, b->k, sm->exp_rp.p, sm->exp_col.p, sm->exp_val64.p,
+                                              b->exp_x[i], b->exp_y[i], st)
+              : race::launch_csr_spmm<float>(sm->tree.n, b->k, sm->exp_rp.p, sm->exp_col.p, sm->exp_val32.p,
+                                             b->exp_x[i], b->exp_y[i], st);
+      if (e != hipSuccess) return e;
+    }
+  }
   if (b->n_tickets == 0) return hipSuccess;
   if (b->tiled) {
     hipError_t e = b->value_type == 0
@@ -1410,7 +1437,7 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     if (vt >= 0 && s[m]->params.value_type != vt) return fail(RACE_EINVAL, "schedules mix value types");
     vt = s[m]->params.value_type;
     threads = std::max(threads, s[m]->params.block_threads);
-    if (k > 1 || !s[m]->expanded) wmax = std::max(wmax, s[m]->L.max_window);
+    if (!s[m]->expanded) wmax = std::max(wmax, s[m]->L.max_window);
   }
   // right-hand sides per pass: all k if the largest window allows, else the widest tile that fits
   int32_t kt = k;
@@ -1450,9 +1477,10 @@ int race_batch_create(int32_t count, const race_schedule_t* s, int32_t k, int32_
     const race::Layout& L = s[m]->L;
     const race::Tree& t = s[m]->tree;
     b->unit_base[m] = total_units;
-    if (k == 1 && s[m]->expanded) {
-      blk_mat.insert(blk_mat.end(), static_cast<size_t>(s[m]->exp_nblk),
-                     static_cast<int32_t>(b->exp_members.size()));
+    if (s[m]->expanded) {
+      if (k == 1)
+        blk_mat.insert(blk_mat.end(), static_cast<size_t>(s[m]->exp_nblk),
+                       static_cast<int32_t>(b->exp_members.size()));
       b->exp_members.push_back(m);
       continue;
     }
@@ -1530,6 +1558,7 @@ int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y) {
       h[m] = batch_mat<double>(b->mats[m], b->mats[m]->lane_diag64.p, b->mats[m]->sell_val64.p,
                                b->state.p + b->unit_base[m], X[m], Y[m]);
       tiles(h[m], m);
+      if (b->mats[m]->expanded) h[m].n = 0;  // not in the RACE passes (no tickets, no tile copies)
     }
     e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
   } else {
@@ -1538,11 +1567,18 @@ int race_batch_bind(race_batch_t b, const double* const* X, double* const* Y) {
       h[m] = batch_mat<float>(b->mats[m], b->mats[m]->lane_diag32.p, b->mats[m]->sell_val32.p,
                               b->state.p + b->unit_base[m], X[m], Y[m]);
       tiles(h[m], m);
+      if (b->mats[m]->expanded) h[m].n = 0;  // not in the RACE passes (no tickets, no tile copies)
     }
     e = hipMemcpy(b->d_mats, h.data(), bytes, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-  if (!b->exp_members.empty()) {
+  b->exp_x.clear();
+  b->exp_y.clear();
+  for (const int32_t m : b->exp_members) {
+    b->exp_x.push_back(X[m]);
+    b->exp_y.push_back(Y[m]);
+  }
+  if (b->k == 1 && !b->exp_members.empty()) {
     const size_t ne = b->exp_members.size();
     const size_t bbytes = b->value_type == 0 ? sizeof(race::BlockMat<double>) * ne : sizeof(race::BlockMat<float>) * ne;
     if (!b->d_bmats) {

@@ -330,6 +330,44 @@ __global__ void __launch_bounds__(256) csr_block_batch_kernel(const BlockMat<Val
   csr_block_rows<ValT, PER>(m.rp, m.col, m.val, m.x, m.y, uniform_load(m.blk, b), uniform_load(m.blk, b + 1), prod);
 }
 
+// Full-matrix CRS SpMM Y = A X (Algorithm "SpMV" for k columns; X, Y
+// row-major n x k, 2 <= k <= KC): a group of KC lanes per row, lane j owns
+// column j.  The group steps through its row four entries at a time; every
+// lane loads the same value and column (one address per group) and its own
+// X entry, so the k entries of an X row arrive as one contiguous segment.
+// Lanes j >= k compute on column k - 1 and store nothing.
+template <typename ValT, int KC>
+__global__ void __launch_bounds__(256) csr_spmm_kernel(int32_t n, int32_t k, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const ValT* __restrict__ val,
+                                                       const double* __restrict__ X, double* __restrict__ Y) {
+  constexpr int kU = 4;
+  const int64_t gid = static_cast<int64_t>(xcd_block()) * blockDim.x + threadIdx.x;
+  const int64_t row = gid / KC;
+  const int32_t j = static_cast<int32_t>(gid % KC);
+  if (row >= n) return;  // whole lane groups leave together
+  const int32_t jj = j < k ? j : k - 1;
+  const int32_t b = rp[row], e = rp[row + 1];
+  double s = 0.0;
+  for (int32_t i = b; i < e; i += kU) {
+    int32_t c[kU];
+    ValT v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int32_t ii = i + u < e ? i + u : e - 1;
+      c[u] = col[ii];
+      v[u] = val[ii];
+    }
+    double xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) xv[u] = X[static_cast<int64_t>(c[u]) * k + jj];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (i + u < e) s += static_cast<double>(v[u]) * xv[u];
+  }
+  if (j < k) Y[row * k + j] = s;
+}
+
 // SymmSpMV with device-wide float64 atomics for every update of y.
 template <int LPR>
 __global__ void __launch_bounds__(256) atomic_symm_kernel(int32_t n, const int32_t* __restrict__ rp,
@@ -671,6 +709,30 @@ hipError_t launch_csr_block_batch(const BlockMat<ValT>* mats, const int32_t* blk
 
 template hipError_t launch_csr_block_batch<double>(const BlockMat<double>*, const int32_t*, int32_t, hipStream_t);
 template hipError_t launch_csr_block_batch<float>(const BlockMat<float>*, const int32_t*, int32_t, hipStream_t);
+
+template <typename ValT>
+hipError_t launch_csr_spmm(int32_t n, int32_t k, const int32_t* rp, const int32_t* col, const ValT* val,
+                           const double* X, double* Y, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (k < 2 || k > 16) return hipErrorInvalidValue;
+  const int32_t kc = k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+  const int64_t blocks = (static_cast<int64_t>(n) * kc + 255) / 256;
+  const dim3 grid(static_cast<uint32_t>((blocks + 7) / 8 * 8));
+  switch (kc) {
+#define CSR_M(C)                                                                                           \
+  case C:                                                                                                  \
+    hipLaunchKernelGGL((dev::csr_spmm_kernel<ValT, C>), grid, dim3(256), 0, st, n, k, rp, col, val, X, Y); \
+    break;
+    CSR_M(2) CSR_M(4) CSR_M(8) CSR_M(16)
+#undef CSR_M
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_csr_spmm<double>(int32_t, int32_t, const int32_t*, const int32_t*, const double*,
+                                            const double*, double*, hipStream_t);
+template hipError_t launch_csr_spmm<float>(int32_t, int32_t, const int32_t*, const int32_t*, const float*,
+                                           const double*, double*, hipStream_t);
 
 void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk) {
   const int64_t cap = 256 * static_cast<int64_t>(per);

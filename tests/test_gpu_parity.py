@@ -404,13 +404,12 @@ def _batch_mats():
 
 
 @pytest.mark.parametrize("k,low_locality", [(1, "race"), (4, "race"), (16, "race"), (1, "auto"), (1, "expanded"),
-                                            (4, "expanded")])
+                                            (4, "expanded"), (4, "auto"), (16, "auto")])
 def test_batch_graph_replays(k, low_locality):
     """Graph replays and direct launches of a small batch against the oracle.
-    With k = 1, members whose product is the expanded CRS product (all of
-    them with "expanded", the banded one with "auto") run the batched
-    row-block launch instead of tickets; with k > 1 they keep the RACE
-    kernels."""
+    Members whose product is the expanded CRS product (all of them with
+    "expanded", the banded one with "auto") take no tickets: with k = 1 they
+    run the batched row-block launch, with k > 1 a CRS SpMM each."""
     mats = _batch_mats()
     window = min(3840, (159 * 1024) // (16 * k + 4) - 16)  # x, y windows of k doubles + the index, per entry
     scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500), window_max=window,
@@ -421,8 +420,8 @@ def test_batch_graph_replays(k, low_locality):
     batch = R.Batch(scheds, k)
     info = batch.info()
     print(f"batch k={k} low_locality={low_locality} paths={paths}: {info}", flush=True)
-    if k == 1 and low_locality == "expanded":
-        assert info["n_tickets"] == 0  # every member runs the row-block launch
+    if low_locality == "expanded":
+        assert info["n_tickets"] == 0  # every member runs outside the persistent launch
     gen = torch.Generator(device=DEV)
     gen.manual_seed(7 + k)
     xs = [torch.empty((m.n, k) if k > 1 else (m.n,), dtype=torch.float64, device=DEV) for m in mats]
@@ -676,8 +675,8 @@ EXPANDED = [
 def test_expanded_product_path(name, make, params, path, value_type):
     """Products of schedules that switch to the expanded CRS product (and of
     those that do not) against the oracle, through race_symm_spmv and
-    race_symm_spmv_noalloc; SymmSpMM with several columns keeps the RACE
-    kernels on the same schedule."""
+    race_symm_spmv_noalloc, and SymmSpMM with 2, 3, 5 and 16 columns (the
+    expanded CRS SpMM on expanded schedules)."""
     m = make()
     vals = m.val if value_type == "f64" else m.val.astype(np.float32).astype(np.float64)
     x = matgen.rhs(m.n, 41)
@@ -699,12 +698,14 @@ def test_expanded_product_path(name, make, params, path, value_type):
             torch.cuda.synchronize()
             s.check()
             _check(yp.cpu().numpy(), y_ref, absax, _full_row_len(m), f"{name} {value_type} {entry}")
-        X = torch.stack([xp, -xp, 2 * xp], dim=1).contiguous()
-        Y = torch.full_like(X, float("nan"))
-        s.spmm(X, Y)
-        torch.cuda.synchronize()
-        s.check()
-        for j, f in enumerate((1.0, -1.0, 2.0)):
-            _check(Y[:, j].cpu().numpy(), f * y_ref, abs(f) * absax, _full_row_len(m), f"{name} spmm col {j}")
+        for k in (2, 3, 5, 16):  # lane groups of 2, 4 (one idle lane), 8 (three idle) and 16 columns
+            fs = [(j + 1.0) * (-1.0) ** j for j in range(k)]
+            X = torch.stack([f * xp for f in fs], dim=1).contiguous()
+            Y = torch.full_like(X, float("nan"))
+            s.spmm(X, Y)
+            torch.cuda.synchronize()
+            s.check()
+            for j, f in enumerate(fs):
+                _check(Y[:, j].cpu().numpy(), f * y_ref, abs(f) * absax, _full_row_len(m), f"{name} spmm k={k} col {j}")
     finally:
         s.close()
