@@ -127,7 +127,8 @@ struct race_schedule {
   bool expanded = false;
   int32_t exp_per = 0;   // entries per thread of its row blocks
   int32_t exp_nblk = 0;  // row blocks
-  DevBuf<int32_t> exp_rp, exp_col, exp_blk;
+  int32_t exp_nblk2 = 0; // row blocks of the SpMM with 2..4 columns
+  DevBuf<int32_t> exp_rp, exp_col, exp_blk, exp_blk2;
   DevBuf<double> exp_val64;
   DevBuf<float> exp_val32;
   // distance-1 schedules: the Gauss-Seidel layout and its device copies
@@ -145,7 +146,7 @@ struct race_schedule {
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
-    release(exp_rp); release(exp_col); release(exp_blk); release(exp_val64); release(exp_val32);
+    release(exp_rp); release(exp_col); release(exp_blk); release(exp_blk2); release(exp_val64); release(exp_val32);
     release(rdep_ptr); release(rdep_idx); release(mpk_state);
     uploaded = false;
   }
@@ -510,6 +511,9 @@ int race_schedule_upload(race_schedule_t s) {
       race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), s->exp_per, blk);
       s->exp_nblk = static_cast<int32_t>(blk.size()) - 1;
       UP(exp_blk, blk)
+      race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), race::kSpmmBlockPer, blk);
+      s->exp_nblk2 = static_cast<int32_t>(blk.size()) - 1;
+      UP(exp_blk2, blk)
     }
     UP(exp_rp, erp)
     UP(exp_col, ecol)
@@ -913,11 +917,20 @@ static int run_expanded(race_schedule_t s, const double* x, double* y, hipStream
 
 // Y = A X (k >= 2 columns, row-major) as a CRS SpMM of the expanded
 // permuted matrix.
+static hipError_t expanded_spmm(race_schedule_t s, int32_t k, const double* x, double* y, hipStream_t st) {
+  if (k <= 4)  // row blocks, k products per entry in LDS
+    return s->params.value_type == 0
+               ? race::launch_csr_block_spmm<double>(s->exp_nblk2, s->exp_blk2.p, s->exp_rp.p, s->exp_col.p,
+                                                     s->exp_val64.p, x, y, k, st)
+               : race::launch_csr_block_spmm<float>(s->exp_nblk2, s->exp_blk2.p, s->exp_rp.p, s->exp_col.p,
+                                                    s->exp_val32.p, x, y, k, st);
+  return s->params.value_type == 0
+             ? race::launch_csr_spmm<double>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, st)
+             : race::launch_csr_spmm<float>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, st);
+}
+
 static int run_expanded_spmm(race_schedule_t s, int32_t k, const double* x, double* y, hipStream_t st) {
-  const hipError_t e =
-      s->params.value_type == 0
-          ? race::launch_csr_spmm<double>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, st)
-          : race::launch_csr_spmm<float>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, st);
+  const hipError_t e = expanded_spmm(s, k, x, y, st);
   if (e != hipSuccess) return hip_fail(e, "expanded CRS SpMM launch");
   return RACE_OK;
 }
@@ -1378,13 +1391,7 @@ static hipError_t batch_enqueue(race_batch_t b, hipStream_t st) {
   }
   if (b->k > 1) {
     for (size_t i = 0; i < b->exp_members.size(); ++i) {
-      const race_schedule_t sm = b->mats[b->exp_members[i]];
-      hipError_t e =
-          b->value_type == 0
-              ? race::launch_csr_spmm<double>(sm->tree.n, b->k, sm->exp_rp.p, sm->exp_col.p, sm->exp_val64.p,
-                                              b->exp_x[i], b->exp_y[i], st)
-              : race::launch_csr_spmm<float>(sm->tree.n, b->k, sm->exp_rp.p, sm->exp_col.p, sm->exp_val32.p,
-                                             b->exp_x[i], b->exp_y[i], st);
+      hipError_t e = expanded_spmm(b->mats[b->exp_members[i]], b->k, b->exp_x[i], b->exp_y[i], st);
       if (e != hipSuccess) return e;
     }
   }

@@ -221,6 +221,12 @@ struct BlockMat {
 template <typename ValT>
 hipError_t launch_csr_block_batch(const BlockMat<ValT>* mats, const int32_t* blk_mat, int32_t n_blocks,
                                   hipStream_t st);
+// Full-matrix CRS SpMM over row blocks of at most kSpmmBlockPer * 256
+// entries (csr_row_blocks with per = kSpmmBlockPer), 2 <= k <= 4.
+constexpr int32_t kSpmmBlockPer = 2;
+template <typename ValT>
+hipError_t launch_csr_block_spmm(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
+                                 const ValT* val, const double* X, double* Y, int32_t k, hipStream_t st);
 // Full-matrix CRS SpMM Y = A X, X and Y row-major n x k, 2 <= k <= 16.
 template <typename ValT>
 hipError_t launch_csr_spmm(int32_t n, int32_t k, const int32_t* rp, const int32_t* col, const ValT* val,

@@ -330,6 +330,81 @@ __global__ void __launch_bounds__(256) csr_block_batch_kernel(const BlockMat<Val
   csr_block_rows<ValT, PER>(m.rp, m.col, m.val, m.x, m.y, uniform_load(m.blk, b), uniform_load(m.blk, b + 1), prod);
 }
 
+// Full-matrix CRS SpMM over row blocks for k = 2..KB columns (KB = 2 or 4;
+// X, Y row-major n x k): blocks of at most 512 entries (two per thread),
+// each entry's k products kept in LDS (entry-major, KB per entry), then one
+// thread per (row, column) adds its row's products in entry order.  Column
+// indices past k are computed on column k - 1 and never stored.  A block
+// of one row longer than 512 entries strides over it and reduces across
+// the workgroup per column.  Blocks go to the XCDs in contiguous eighths.
+template <typename ValT, int KB>
+__global__ void __launch_bounds__(256) csr_block_spmm_kernel(const int32_t* __restrict__ blk,
+                                                             const int32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ col,
+                                                             const ValT* __restrict__ val,
+                                                             const double* __restrict__ X, double* __restrict__ Y,
+                                                             int32_t k, int32_t n_blocks) {
+  constexpr int32_t kPer = 2, kCap = 256 * kPer;
+  __shared__ double prod[kCap * KB];
+  const int32_t t = static_cast<int32_t>(threadIdx.x);
+  const int32_t b = xcd_block();
+  if (b >= n_blocks) return;  // padding of the grid (uniform per workgroup)
+  const int32_t r0 = uniform_load(blk, b), r1 = uniform_load(blk, b + 1);
+  const int32_t e0 = uniform_load(rp, r0);
+  const int32_t ne = uniform_load(rp, r1) - e0;
+  if (ne > kCap) {
+    double s[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) s[j] = 0.0;
+    for (int32_t i = e0 + t; i < e0 + ne; i += 256) {
+      const double a = static_cast<double>(val[i]);
+      const int64_t c = static_cast<int64_t>(col[i]) * k;
+#pragma unroll
+      for (int j = 0; j < KB; ++j) s[j] += a * X[c + (j < k ? j : k - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
+    if ((t & 63) == 0)
+#pragma unroll
+      for (int j = 0; j < KB; ++j) prod[(t >> 6) * KB + j] = s[j];
+    __syncthreads();
+    if (t < k) Y[static_cast<int64_t>(r0) * k + t] = (prod[t] + prod[KB + t]) + (prod[2 * KB + t] + prod[3 * KB + t]);
+    return;
+  }
+  if (ne > 0) {
+    int32_t c[kPer];
+    ValT v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t i = e0 + min(t + u * 256, ne - 1);
+      c[u] = stream_load(col + i);
+      v[u] = stream_load(val + i);
+    }
+    double xv[kPer][KB];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+#pragma unroll
+      for (int j = 0; j < KB; ++j) xv[u][j] = X[static_cast<int64_t>(c[u]) * k + (j < k ? j : k - 1)];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (t + u * 256 < ne)
+#pragma unroll
+        for (int j = 0; j < KB; ++j) prod[(t + u * 256) * KB + j] = static_cast<double>(v[u]) * xv[u][j];
+  }
+  __syncthreads();
+  const int32_t pairs = (r1 - r0) * KB;
+  for (int32_t p = t; p < pairs; p += 256) {
+    const int32_t r = r0 + p / KB, j = p % KB;
+    if (j >= k) continue;
+    const int32_t a = rp[r] - e0, e = rp[r + 1] - e0;
+    double s = 0.0;
+    for (int32_t q = a; q < e; ++q) s += prod[q * KB + j];
+    Y[static_cast<int64_t>(r) * k + j] = s;
+  }
+}
+
 // Full-matrix CRS SpMM Y = A X (Algorithm "SpMV" for k columns; X, Y
 // row-major n x k, 2 <= k <= KC): a group of KC lanes per row, lane j owns
 // column j.  The group steps through its row four entries at a time; every
@@ -733,6 +808,26 @@ template hipError_t launch_csr_spmm<double>(int32_t, int32_t, const int32_t*, co
                                             const double*, double*, hipStream_t);
 template hipError_t launch_csr_spmm<float>(int32_t, int32_t, const int32_t*, const int32_t*, const float*,
                                            const double*, double*, hipStream_t);
+
+template <typename ValT>
+hipError_t launch_csr_block_spmm(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
+                                 const ValT* val, const double* X, double* Y, int32_t k, hipStream_t st) {
+  if (n_blocks == 0) return hipSuccess;
+  if (k < 2 || k > 4) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<uint32_t>((static_cast<int64_t>(n_blocks) + 7) / 8 * 8));
+  if (k == 2)
+    hipLaunchKernelGGL((dev::csr_block_spmm_kernel<ValT, 2>), grid, dim3(256), 0, st, blk, rp, col, val, X, Y, k,
+                       n_blocks);
+  else
+    hipLaunchKernelGGL((dev::csr_block_spmm_kernel<ValT, 4>), grid, dim3(256), 0, st, blk, rp, col, val, X, Y, k,
+                       n_blocks);
+  return hipGetLastError();
+}
+
+template hipError_t launch_csr_block_spmm<double>(int32_t, const int32_t*, const int32_t*, const int32_t*,
+                                                  const double*, const double*, double*, int32_t, hipStream_t);
+template hipError_t launch_csr_block_spmm<float>(int32_t, const int32_t*, const int32_t*, const int32_t*,
+                                                 const float*, const double*, double*, int32_t, hipStream_t);
 
 void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk) {
   const int64_t cap = 256 * static_cast<int64_t>(per);

@@ -660,7 +660,20 @@ def test_batch_full_64(batch64, k):
             s.close()
 
 
+def _arrow(n, seed):
+    """Row 0 coupled to every row (a full row of n entries, longer than any
+    row block), the diagonal, and a random sparse upper part."""
+    rng = np.random.default_rng(seed)
+    r = rng.integers(1, n, size=4 * n)
+    c = rng.integers(1, n, size=4 * n)
+    lo, hi = np.minimum(r, c), np.maximum(r, c)
+    keys = np.unique(np.concatenate([np.arange(n) * n + np.arange(n), np.arange(1, n), lo * n + hi]))
+    rows, cols = keys // n, keys % n
+    return matgen._csr_from_sorted(n, rows, cols, rng.standard_normal(keys.shape[0]), f"arrow_{n}")
+
+
 EXPANDED = [
+    ("arrow_3000_expanded", lambda: _arrow(3000, 4), dict(n_workers=8, low_locality="expanded"), 1),
     ("banded_40k_w96_auto", lambda: matgen.banded_irregular(40000, seed=6, band=4000),
      dict(n_workers=16, window_max=96, low_locality="auto"), 1),
     ("3d27pt_24_auto", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=256, low_locality="auto"), 0),
