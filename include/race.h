@@ -137,6 +137,7 @@ typedef struct {
   int32_t product_path;      /* what race_symm_spmv runs: 0 the RACE kernels, 1 the expanded CRS product
                                 (race_params.low_locality) */
   int32_t expanded_per_thread; /* entries per thread of the expanded CRS product's row blocks (0 when not expanded) */
+  int32_t n_zero_tasks;      /* clearing tasks of a dataflow product: its first tickets, before the units */
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
@@ -317,6 +318,28 @@ int race_symm_poly(race_schedule_t s, int32_t degree, const double* coeffs, cons
  * units in *ptr (n_units + 1, host) and *idx (*count entries, host).  Pass
  * NULL ptr and idx to query *count first. */
 int race_schedule_read_deps(race_schedule_t s, int64_t* count, int32_t* ptr, int32_t* idx);
+
+/* Ticket order of race_symm_mpk (Section 7's matrix powers; the order is a
+ * list-scheduling choice made here, not the paper's).  lag_rows < 0 (the
+ * default): power-major, every unit of power p before any of power p + 1.
+ * lag_rows >= 0: after the launch's static tickets (the first units of
+ * power 0, in their own order), tickets in a topological order of all the
+ * launch's waits -- conflict edges within a power, read dependencies on the
+ * power before -- taking, among the tickets whose waits are all earlier,
+ * the one with the smallest first row of its unit + power * lag_rows: a
+ * unit's next power follows it after about lag_rows rows' worth of other
+ * work.  cache_matrix 1: the matrix stream is read with cacheable loads
+ * (0: non-temporal, as in a single product), so a unit that comes back
+ * soon may find its entries in the last-level cache.  RACE_EINVAL for
+ * cache_matrix outside 0..1.  Takes effect on the next race_symm_mpk.  (On
+ * the 3D 27-point 128^3 stencil no lag was faster than power-major.) */
+int race_schedule_set_mpk_order(race_schedule_t s, int64_t lag_rows, int32_t cache_matrix);
+
+/* The ticket order race_symm_mpk uses for `powers` powers when its launch
+ * has n_static static tickets (host; for inspection and tests): order[t] =
+ * p * (units + clearing tasks) + r, the power and position of ticket t, for
+ * powers * (units + clearing tasks) tickets. */
+int race_schedule_mpk_order(race_schedule_t s, int32_t powers, int32_t n_static, int32_t* order);
 
 /* Gauss-Seidel sweep on A x = b over a distance-1 schedule (dist_k = 1,
  * float64 values; the paper names Gauss-Seidel as the prime user of such

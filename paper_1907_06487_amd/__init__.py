@@ -175,6 +175,16 @@ class Schedule:
     def read_deps(self):
         return race_schedule_read_deps(self.handle, self.stats()["n_units"])
 
+    def set_mpk_order(self, lag_rows=-1, cache_matrix=False):
+        """Ticket order of mpk(): lag_rows < 0 power-major, else the
+        diagonal order with that lag; cache_matrix: cacheable matrix loads."""
+        _lib.race_schedule_set_mpk_order(self.handle, lag_rows, int(bool(cache_matrix)))
+
+    def mpk_order(self, powers, n_static):
+        """The matrix-power ticket order (power-major indices by ticket)."""
+        st = self.stats()
+        return _lib.race_schedule_mpk_order(self.handle, powers, n_static, st["n_units"] + st["n_zero_tasks"])
+
     def spmv_noalloc(self, x, y, stream=None):
         """The product through the entry point that allocates nothing."""
         race_symm_spmv_noalloc(self.handle, x, y, stream)

@@ -32,6 +32,7 @@ EXPORTS = [
     "race_symm_spmv_noalloc", "race_vendor_create", "race_vendor_spmv", "race_vendor_destroy", "race_stream_read",
     "race_stream_copy", "race_symm_gs", "race_schedule_set_ticket_order", "race_schedule_order_tickets",
     "race_schedule_ticket_order", "race_symm_mpk", "race_symm_poly", "race_schedule_read_deps",
+    "race_schedule_set_mpk_order", "race_schedule_mpk_order",
 ]
 
 MLP_INPUTS = 12
@@ -68,6 +69,7 @@ class race_stats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64), ("shared_touches", ctypes.c_int64),
         ("n_zeroed", ctypes.c_int64), ("product_path", ctypes.c_int32), ("expanded_per_thread", ctypes.c_int32),
+        ("n_zero_tasks", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -111,6 +113,8 @@ def lib():
         "race_symm_mpk": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_poly": ([_P, ctypes.c_int32, _DP, _P, _P, _P, _P], ctypes.c_int),
         "race_schedule_read_deps": ([_P, _I64P, _I32P, _I32P], ctypes.c_int),
+        "race_schedule_set_mpk_order": ([_P, ctypes.c_int64, ctypes.c_int32], ctypes.c_int),
+        "race_schedule_mpk_order": ([_P, ctypes.c_int32, ctypes.c_int32, _I32P], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
@@ -337,6 +341,16 @@ def race_schedule_read_deps(h, n_units):
     idx = np.empty(cnt.value, dtype=np.int32)
     check(lib().race_schedule_read_deps(h, ctypes.byref(cnt), _np_ptr(ptr, ctypes.c_int32), _np_ptr(idx, ctypes.c_int32)))
     return ptr, idx
+
+
+def race_schedule_set_mpk_order(h, lag_rows, cache_matrix):
+    check(lib().race_schedule_set_mpk_order(h, int(lag_rows), int(cache_matrix)))
+
+
+def race_schedule_mpk_order(h, powers, n_static, per_power):
+    out = np.empty(int(powers) * int(per_power), dtype=np.int32)
+    check(lib().race_schedule_mpk_order(h, int(powers), int(n_static), _np_ptr(out, ctypes.c_int32)))
+    return out
 
 
 def race_symm_spmv(h, x, y, stream=None):

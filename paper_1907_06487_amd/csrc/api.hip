@@ -122,6 +122,14 @@ struct race_schedule {
   DevBuf<int32_t> rdep_ptr, rdep_idx;
   DevBuf<uint32_t> mpk_state;
   uint64_t mpk_ticket_next = 0;
+  // matrix-power ticket order (race_schedule_set_mpk_order): lag < 0 is
+  // power-major; else the diagonal order, cached for one (powers, static
+  // tickets) pair
+  int64_t mpk_lag = -1;
+  int32_t mpk_cache = 0;
+  std::vector<int32_t> mpk_order_h;
+  int32_t mpk_order_P = 0, mpk_order_static = -1;
+  DevBuf<int32_t> mpk_order_d;
   // the full permuted matrix in CRS, when single-vector products run as a
   // CRS product (race_params.low_locality)
   bool expanded = false;
@@ -147,7 +155,7 @@ struct race_schedule {
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
     release(exp_rp); release(exp_col); release(exp_blk); release(exp_blk2); release(exp_val64); release(exp_val32);
-    release(rdep_ptr); release(rdep_idx); release(mpk_state);
+    release(rdep_ptr); release(rdep_idx); release(mpk_state); release(mpk_order_d);
     uploaded = false;
   }
 };
@@ -382,6 +390,7 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
                   (prm.low_locality == 2 || (prm.low_locality == 1 && 2 * st.shared_touches > touches));
     st.product_path = s->expanded ? 1 : 0;
     st.expanded_per_thread = s->expanded ? race::kExpandedPerThread : 0;
+    st.n_zero_tasks = L.n_zero_tasks;
     s->exp_per = st.expanded_per_thread;
   } catch (const std::bad_alloc&) {
     delete s;
@@ -703,6 +712,7 @@ int race_schedule_set_ticket_order(race_schedule_t s, const int32_t* ticket_unit
   } catch (const std::bad_alloc&) {
     return fail(RACE_ENOMEM, "out of host memory");
   }
+  s->mpk_order_P = 0;  // a cached matrix-power order follows the old ticket order
   return RACE_OK;
 }
 
@@ -1187,6 +1197,24 @@ static int ensure_read_deps(race_schedule_t s, bool device) {
   return RACE_OK;
 }
 
+// The diagonal matrix-power ticket order for P powers and n_static static
+// tickets (host).
+static int build_mpk_order(race_schedule_t s, int32_t P, int32_t n_static, std::vector<int32_t>& order) {
+  int rc = ensure_read_deps(s, false);
+  if (rc) return rc;
+  std::vector<int32_t> tu, ut;
+  ticket_arrays(s, tu, ut);
+  try {
+    race::mpk_ticket_order(s->L, tu, s->rdep_ptr_h, s->rdep_idx_h, P, n_static, std::max<int64_t>(0, s->mpk_lag),
+                           order);
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory while ordering the matrix-power tickets");
+  } catch (const std::exception& ex) {
+    return fail(RACE_EINTERNAL, ex.what());
+  }
+  return RACE_OK;
+}
+
 template <typename ValT>
 static int run_mpk(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t P, const double* x, double* Y,
                    hipStream_t st) {
@@ -1241,7 +1269,31 @@ static int run_mpk(race_schedule_t s, const race::UnitArgs<ValT>& a, int32_t P, 
                    s->claims.p, s->claims.p + claim_cap, n_static, s->late_stride, nullptr, n_tickets, n_units,
                    L.n_zero_tasks, race::kZeroChunk, s->zero_idx.p, static_cast<int64_t>(L.zero_idx.size()),
                    s->ticket_unit_d.p, s->unit_ticket_d.p};
-  race::MpkArgs m{s->rdep_ptr.p, s->rdep_idx.p, P, n_flags, static_cast<int64_t>(s->tree.n)};
+  const int32_t* order = nullptr;
+  if (s->mpk_lag >= 0) {
+    if (s->mpk_order_P != P || s->mpk_order_static != n_static) {
+      rc = build_mpk_order(s, P, n_static, s->mpk_order_h);
+      if (rc) return rc;
+      // the buffer may still be read by an earlier launch on this stream
+      e = hipStreamSynchronize(st);
+      if (e == hipSuccess && s->mpk_order_d.count < s->mpk_order_h.size()) {
+        release(s->mpk_order_d);
+        int64_t total = 0;
+        e = upload(s->mpk_order_d, s->mpk_order_h.data(), s->mpk_order_h.size(), &total);
+      } else if (e == hipSuccess) {
+        e = hipMemcpy(s->mpk_order_d.p, s->mpk_order_h.data(), sizeof(int32_t) * s->mpk_order_h.size(),
+                      hipMemcpyHostToDevice);
+      }
+      if (e != hipSuccess) {
+        s->mpk_order_P = 0;
+        return hip_fail(e, "upload of the matrix-power ticket order");
+      }
+      s->mpk_order_P = P;
+      s->mpk_order_static = n_static;
+    }
+    order = s->mpk_order_d.p;
+  }
+  race::MpkArgs m{s->rdep_ptr.p, s->rdep_idx.p, P, n_flags, static_cast<int64_t>(s->tree.n), order, s->mpk_cache};
   e = race::launch_race_mpk<ValT>(a, f, m, x, Y, wmax, s->params.block_threads, grid, s->epoch, ticket_base, st);
   if (e != hipSuccess) return hip_fail(e, "matrix-power launch");
   return RACE_OK;
@@ -1285,6 +1337,34 @@ int race_symm_poly(race_schedule_t s, int32_t degree, const double* coeffs, cons
   for (int32_t p = 0; p <= degree; ++p) c.c[p] = coeffs[p];
   const hipError_t e = race::launch_poly_combine(s->tree.n, degree, c, x, work, z, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "polynomial combination launch");
+  return RACE_OK;
+}
+
+int race_schedule_set_mpk_order(race_schedule_t s, int64_t lag_rows, int32_t cache_matrix) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, "a distance-1 schedule has no units");
+  if (cache_matrix != 0 && cache_matrix != 1) return fail(RACE_EINVAL, "cache_matrix must be 0 or 1");
+  s->mpk_lag = lag_rows < 0 ? -1 : lag_rows;
+  s->mpk_cache = cache_matrix;
+  s->mpk_order_P = 0;
+  return RACE_OK;
+}
+
+int race_schedule_mpk_order(race_schedule_t s, int32_t powers, int32_t n_static, int32_t* order) {
+  if (!s || !order) return fail(RACE_EINVAL, "NULL argument");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, "a distance-1 schedule has no units");
+  if (powers < 1 || powers > 64) return fail(RACE_EINVAL, "powers must be in 1..64");
+  const int32_t per = static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
+  if (n_static < 0 || n_static > per) return fail(RACE_EINVAL, "n_static must be in 0..units + clearing tasks");
+  const int64_t total = static_cast<int64_t>(powers) * per;
+  if (s->mpk_lag < 0) {
+    for (int64_t t = 0; t < total; ++t) order[t] = static_cast<int32_t>(t);
+    return RACE_OK;
+  }
+  std::vector<int32_t> o;
+  const int rc = build_mpk_order(s, powers, n_static, o);
+  if (rc) return rc;
+  std::copy(o.begin(), o.end(), order);
   return RACE_OK;
 }
 

@@ -86,6 +86,8 @@ struct MpkArgs {
   int32_t powers;
   int32_t per_power;
   int64_t n;
+  const int32_t* order;   // ticket -> power-major index (p * per_power + r); nullptr: power-major
+  int32_t cache_matrix;   // 1: cacheable matrix loads (the next power may find them in cache)
 };
 
 constexpr int kMaxPolyDegree = 32;

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <numeric>
+#include <queue>
+#include <stdexcept>
 
 #include "../../include/race.h"
 
@@ -338,6 +340,78 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
     L.phase_max_window[ph] = std::max(L.phase_max_window[ph], w);
   }
   return std::string();
+}
+
+void mpk_ticket_order(const Layout& L, const std::vector<int32_t>& ticket_unit, const std::vector<int32_t>& rdep_ptr,
+                      const std::vector<int32_t>& rdep_idx, int32_t powers, int32_t n_static, int64_t lag_rows,
+                      std::vector<int32_t>& order) {
+  const int32_t nu = static_cast<int32_t>(L.unit_lo.size());
+  const int32_t nz = L.n_zero_tasks;
+  const int32_t per = nu + nz;
+  const int64_t total = static_cast<int64_t>(per) * powers;
+  // position of each unit within a power (after the clearing tasks)
+  std::vector<int32_t> pos(static_cast<size_t>(nu));
+  for (int32_t i = 0; i < nu; ++i) pos[static_cast<size_t>(ticket_unit[static_cast<size_t>(i)])] = nz + i;
+  auto flag_pos = [&](int32_t v) { return v < nu ? pos[static_cast<size_t>(v)] : v - nu; };
+  // dependency counts and successor lists over power-major indices
+  std::vector<int32_t> indeg(static_cast<size_t>(total), 0);
+  std::vector<int64_t> succ_ptr(static_cast<size_t>(total) + 1, 0);
+  auto for_deps = [&](int64_t node, auto&& fn) {
+    const int32_t p = static_cast<int32_t>(node / per), r = static_cast<int32_t>(node % per);
+    if (r < nz) return;
+    const int32_t u = ticket_unit[static_cast<size_t>(r - nz)];
+    for (int32_t d = L.dep_ptr[static_cast<size_t>(u)]; d < L.dep_ptr[static_cast<size_t>(u) + 1]; ++d)
+      fn(static_cast<int64_t>(p) * per + flag_pos(L.dep_idx[static_cast<size_t>(d)]));
+    if (p > 0)
+      for (int32_t d = rdep_ptr[static_cast<size_t>(u)]; d < rdep_ptr[static_cast<size_t>(u) + 1]; ++d)
+        fn(static_cast<int64_t>(p - 1) * per + pos[static_cast<size_t>(rdep_idx[static_cast<size_t>(d)])]);
+  };
+  for (int64_t v = 0; v < total; ++v)
+    for_deps(v, [&](int64_t w) {
+      ++indeg[static_cast<size_t>(v)];
+      ++succ_ptr[static_cast<size_t>(w) + 1];
+    });
+  for (int64_t v = 0; v < total; ++v) succ_ptr[static_cast<size_t>(v) + 1] += succ_ptr[static_cast<size_t>(v)];
+  std::vector<int64_t> succ(static_cast<size_t>(succ_ptr.back()));
+  {
+    std::vector<int64_t> fill(succ_ptr.begin(), succ_ptr.end() - 1);
+    for (int64_t v = 0; v < total; ++v)
+      for_deps(v, [&](int64_t w) { succ[static_cast<size_t>(fill[static_cast<size_t>(w)]++)] = v; });
+  }
+  auto key = [&](int64_t v) {
+    const int32_t p = static_cast<int32_t>(v / per), r = static_cast<int32_t>(v % per);
+    const int64_t row = r < nz ? 0 : L.unit_lo[static_cast<size_t>(ticket_unit[static_cast<size_t>(r - nz)])];
+    return row + static_cast<int64_t>(p) * lag_rows;
+  };
+  using Item = std::pair<int64_t, int64_t>;  // (key, power-major index), smallest first
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
+  std::vector<char> done(static_cast<size_t>(total), 0);
+  order.clear();
+  order.reserve(static_cast<size_t>(total));
+  auto emit = [&](int64_t v) {
+    done[static_cast<size_t>(v)] = 1;
+    order.push_back(static_cast<int32_t>(v));
+    for (int64_t i = succ_ptr[static_cast<size_t>(v)]; i < succ_ptr[static_cast<size_t>(v) + 1]; ++i) {
+      const int64_t w = succ[static_cast<size_t>(i)];
+      if (--indeg[static_cast<size_t>(w)] == 0 && !(w < n_static)) ready.push({key(w), w});
+    }
+  };
+  // the static prefix: power 0 in its own order, a closed set (its waits
+  // point to smaller positions of power 0)
+  for (int64_t v = 0; v < n_static && v < total; ++v) {
+    if (indeg[static_cast<size_t>(v)] != 0) throw std::logic_error("static ticket waits outside the static prefix");
+    emit(v);
+  }
+  // everything else that waits for nothing (successors of the prefix that
+  // became ready are already queued; a repeat is skipped when popped)
+  for (int64_t v = n_static; v < total; ++v)
+    if (indeg[static_cast<size_t>(v)] == 0) ready.push({key(v), v});
+  while (!ready.empty()) {
+    const int64_t v = ready.top().second;
+    ready.pop();
+    if (!done[static_cast<size_t>(v)]) emit(v);
+  }
+  if (static_cast<int64_t>(order.size()) != total) throw std::logic_error("matrix-power waits form a cycle");
 }
 
 void build_read_deps(const Layout& L, std::vector<int32_t>& ptr, std::vector<int32_t>& idx) {

@@ -95,4 +95,20 @@ std::string build_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, 
 // touch set, which is final once these units have flushed power p - 1.
 void build_read_deps(const Layout& L, std::vector<int32_t>& ptr, std::vector<int32_t>& idx);
 
+// Ticket order of a P-power matrix-power launch.  Tickets are (power p,
+// position r) pairs, r over one power's sequence (the n_zero_tasks clearing
+// tasks, then the units in the order `ticket_unit`); order[t] is the
+// power-major index p * per_power + r of ticket t.  The first n_static
+// tickets stay the first n_static positions of power 0 (their owners claim
+// them by index); the rest follow a topological order of every wait -- a
+// unit's conflict edges within its power, and from power 1 on its read
+// dependencies (rdep_ptr/rdep_idx) in the power before -- emitted by
+// smallest key first, key = first row of the unit (0 for a clearing task)
+// + p * lag_rows, ties by the power-major index.  lag_rows large gives the
+// power-major order; small lets a unit's next power follow it closely, so
+// its part of the matrix may still be cached.
+void mpk_ticket_order(const Layout& L, const std::vector<int32_t>& ticket_unit, const std::vector<int32_t>& rdep_ptr,
+                      const std::vector<int32_t>& rdep_idx, int32_t powers, int32_t n_static, int64_t lag_rows,
+                      std::vector<int32_t>& order);
+
 }  // namespace race

@@ -3,8 +3,11 @@
 // powers and polynomials as the next users of RACE schedules), and the
 // combination of the powers into a polynomial.
 //
-// Tickets are (power, unit) pairs, power-major; inside a power the
-// schedule's own ticket order with its clearing tasks first.  A unit of
+// Tickets are (power, unit) pairs: power-major by default (inside a power
+// the schedule's own ticket order with its clearing tasks first), or any
+// order from a table that keeps the static tickets and every wait pointing
+// to a smaller ticket (a diagonal order lets a unit's next power follow it
+// while its part of the matrix may still be cached).  A unit of
 // power p first waits until every unit whose touch set meets its window has
 // flushed power p - 1 (its x is then final), computes, waits for the
 // conflict edges of power p like a single product, flushes into y_p and
@@ -40,7 +43,7 @@ __device__ __forceinline__ void wait_reads(const MpkArgs& m, int32_t u, const ui
   __syncthreads();
 }
 
-template <typename ValT>
+template <typename ValT, bool kNT>
 __global__ void __launch_bounds__(1024) race_mpk_kernel(UnitArgs<ValT> a, FlowArgs f, MpkArgs m,
                                                         const double* __restrict__ x, double* __restrict__ Y,
                                                         int32_t wmax, uint32_t epoch, uint64_t ticket_base) {
@@ -79,8 +82,9 @@ __global__ void __launch_bounds__(1024) race_mpk_kernel(UnitArgs<ValT> a, FlowAr
         if (t < 0) break;
       }
     }
-    const int32_t p = t / m.per_power;
-    const int32_t r = t - p * m.per_power;
+    const int32_t pm = m.order ? uniform_load(m.order, t) : t;
+    const int32_t p = pm / m.per_power;
+    const int32_t r = pm - p * m.per_power;
     FlowArgs fp = f;
     fp.done = f.done + static_cast<size_t>(p) * n_flags;
     double* yp = Y + static_cast<size_t>(p) * m.n;
@@ -94,12 +98,12 @@ __global__ void __launch_bounds__(1024) race_mpk_kernel(UnitArgs<ValT> a, FlowAr
     const int32_t u = uniform_load(f.ticket_unit, r - f.n_zero_tasks);
     const UnitDesc ud = uniform_load(a.unit_desc, u);
     if (p == 0) {
-      compute_unit<ValT, 1, false>(a, ud, x, 1, xw, yw, gw, tid, nthr);
+      compute_unit<ValT, 1, false, kNT>(a, ud, x, 1, xw, yw, gw, tid, nthr);
     } else {
       // x of this power is the previous power's y: final once every unit
       // touching the window has flushed it
       wait_reads(m, u, f.done + static_cast<size_t>(p - 1) * n_flags, f.status, epoch, tid, nthr);
-      compute_unit<ValT, 1, true>(a, ud, Y + static_cast<size_t>(p - 1) * m.n, 1, xw, yw, gw, tid, nthr);
+      compute_unit<ValT, 1, true, kNT>(a, ud, Y + static_cast<size_t>(p - 1) * m.n, 1, xw, yw, gw, tid, nthr);
     }
     // static tickets are all of power 0: only there can a waited-for
     // ticket lack a running owner
@@ -150,23 +154,35 @@ hipError_t launch_race_mpk(const UnitArgs<ValT>& a, const FlowArgs& f, const Mpk
                            int32_t wmax, int32_t threads, int32_t grid, uint32_t epoch, uint64_t ticket_base,
                            hipStream_t st) {
   static bool attr_done = false;
-  const void* fn = reinterpret_cast<const void*>(&dev::race_mpk_kernel<ValT>);
+  const void* fns[2] = {reinterpret_cast<const void*>(&dev::race_mpk_kernel<ValT, true>),
+                        reinterpret_cast<const void*>(&dev::race_mpk_kernel<ValT, false>)};
   if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
-    if (e != hipSuccess) return e;
+    for (const void* fn : fns) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
+      if (e != hipSuccess) return e;
+    }
     attr_done = true;
   }
-  hipLaunchKernelGGL(dev::race_mpk_kernel<ValT>, dim3(static_cast<uint32_t>(grid)), dim3(static_cast<uint32_t>(threads)),
-                     window_lds_bytes(wmax, 1), st, a, f, m, x, Y, wmax, epoch, ticket_base);
+  if (m.cache_matrix)
+    hipLaunchKernelGGL((dev::race_mpk_kernel<ValT, false>), dim3(static_cast<uint32_t>(grid)),
+                       dim3(static_cast<uint32_t>(threads)), window_lds_bytes(wmax, 1), st, a, f, m, x, Y, wmax, epoch,
+                       ticket_base);
+  else
+    hipLaunchKernelGGL((dev::race_mpk_kernel<ValT, true>), dim3(static_cast<uint32_t>(grid)),
+                       dim3(static_cast<uint32_t>(threads)), window_lds_bytes(wmax, 1), st, a, f, m, x, Y, wmax, epoch,
+                       ticket_base);
   return hipGetLastError();
 }
 
 template <typename ValT>
 hipError_t race_mpk_occupancy(int32_t threads, int32_t wmax, int32_t* blocks_per_cu) {
-  hipFuncAttributes attr{};
-  hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&dev::race_mpk_kernel<ValT>));
+  // both forms (non-temporal or cacheable matrix loads): the larger need
+  hipFuncAttributes attr{}, attr2{};
+  hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&dev::race_mpk_kernel<ValT, true>));
+  if (e == hipSuccess) e = hipFuncGetAttributes(&attr2, reinterpret_cast<const void*>(&dev::race_mpk_kernel<ValT, false>));
   if (e != hipSuccess) return e;
-  const int32_t regs = std::max(attr.numRegs, 1);
+  attr.sharedSizeBytes = std::max(attr.sharedSizeBytes, attr2.sharedSizeBytes);
+  const int32_t regs = std::max({attr.numRegs, attr2.numRegs, 1});
   const int32_t waves_per_block = std::max(1, threads / 64);
   const int32_t waves_per_simd = std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8)));
   const int32_t by_waves = (4 * waves_per_simd) / waves_per_block;

@@ -121,7 +121,15 @@ __device__ __forceinline__ void load_slice_head(const UnitArgs<ValT>& a, int32_t
 // is the same for the whole wavefront, and lanes past the slice's rows read
 // the last row's entries (in bounds, never applied), so the loads of a batch
 // are issued back to back with no per-lane branches between them.
-template <typename ValT>
+// kNT: non-temporal loads (the matrix streams once per product); false
+// keeps its lines cacheable (matrix powers that come back to a unit soon).
+template <bool kNT, typename T>
+__device__ __forceinline__ T matrix_load(const T* p) {
+  if constexpr (kNT) return stream_load(p);
+  else return *p;
+}
+
+template <typename ValT, bool kNT = true>
 __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane, int32_t j0, SliceRegs<ValT>& r) {
   const int32_t l = lane < r.width ? lane : r.width - 1;
   // a wave-uniform base and a 32-bit per-lane byte offset (a slice spans
@@ -133,8 +141,8 @@ __device__ __forceinline__ void load_batch(const UnitArgs<ValT>& a, int32_t lane
     const int32_t j = j0 + b;
     if (j < r.len) {
       const uint32_t e = static_cast<uint32_t>(l + j * r.width);
-      r.v[b] = stream_load(reinterpret_cast<const ValT*>(vp + e * static_cast<uint32_t>(sizeof(ValT))));
-      r.sl[b] = stream_load(reinterpret_cast<const uint16_t*>(sp + e * 2u));
+      r.v[b] = matrix_load<kNT>(reinterpret_cast<const ValT*>(vp + e * static_cast<uint32_t>(sizeof(ValT))));
+      r.sl[b] = matrix_load<kNT>(reinterpret_cast<const uint16_t*>(sp + e * 2u));
     } else {
       r.v[b] = zero_value<ValT>();
       r.sl[b] = r.rs;
@@ -230,7 +238,7 @@ __device__ __forceinline__ double x_load(const double* p) {
   else return *p;
 }
 
-template <typename ValT, int K, bool kCohX = false>
+template <typename ValT, int K, bool kCohX = false, bool kNT = true>
 __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const UnitDesc& ud,
                                              const double* __restrict__ x, int32_t ld, double* xw, double* yw,
                                              uint32_t* gw, int32_t tid, int32_t nthr) {
@@ -310,7 +318,7 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const Unit
       }
     }
   }
-  if (c < c1) load_batch(a, lane, 0, cur);
+  if (c < c1) load_batch<ValT, kNT>(a, lane, 0, cur);
   __syncthreads();
   // 2. slices: the next slice's descriptor is in flight during this slice's
   // arithmetic, its elements are requested right after
@@ -331,7 +339,7 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const Unit
       constexpr int B = SliceRegs<ValT>::kBatch;
       apply_batch<K, B>(cur.v, cur.sl, xw, yw, xr, acc);
       for (int32_t j0 = B; j0 < cur.len; j0 += B) {
-        load_batch(a, lane, j0, cur);
+        load_batch<ValT, kNT>(a, lane, j0, cur);
         apply_batch<K, B>(cur.v, cur.sl, xw, yw, xr, acc);
       }
 #pragma unroll
@@ -343,7 +351,7 @@ __device__ __forceinline__ void compute_unit(const UnitArgs<ValT>& a, const Unit
       cur.off = off_n;
       cur.rs = rs_n;
       cur.d = to_reg(d_n);
-      load_batch(a, lane, 0, cur);
+      load_batch<ValT, kNT>(a, lane, 0, cur);
     }
     c = cn;
   }

@@ -6,7 +6,8 @@ power's own magnitude:  ||y_p - y_p,ref||_inf / ||y_p,ref||_inf <= 1e-12.
 Cases cover shared-atomic units with clearing tasks, chained units, a
 schedule built for the phase mode, FP32 values (oracle on the same
 rounded values), workgroups forced to join late (static tickets taken
-over), a critical-path ticket order and repeated calls."""
+over), a critical-path ticket order, the diagonal ticket order with and
+without cacheable matrix loads, and repeated calls."""
 import numpy as np
 import pytest
 
@@ -70,6 +71,37 @@ def test_mpk_parity(name, make, params, powers):
         s.close()
 
 
+@pytest.mark.parametrize("lag,cache", [(0, True), (500, False), (4000, True)])
+@pytest.mark.parametrize("name,make,params", [CASES[0], CASES[1], CASES[3], CASES[4], CASES[6]],
+                         ids=[CASES[i][0] for i in (0, 1, 3, 4, 6)])
+def test_mpk_diagonal_order(name, make, params, lag, cache):
+    """The diagonal ticket order (race_schedule_set_mpk_order) with several
+    lags, cacheable or non-temporal matrix loads, 5 powers, two calls, and
+    a change of the number of powers in between (the order is rebuilt)."""
+    m = _scaled(make())
+    x = matgen.rhs(m.n, 53)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, **params)
+    try:
+        s.set_mpk_order(lag, cache)
+        perm = s.perm()
+        refs = P.powers(m.n, m.row_ptr, m.col, m.val, x, 5)
+        xd = torch.as_tensor(x, device=DEV)
+        xp = torch.empty_like(xd)
+        s.permute(xd, xp, True)
+        for powers in (5, 2, 5):
+            print(f"case mpk diagonal {name} lag={lag} cache={cache} powers={powers}: n={m.n}", flush=True)
+            Y = torch.full((powers, m.n), float("nan"), dtype=torch.float64, device=DEV)
+            s.mpk(xp, Y)
+            torch.cuda.synchronize()
+            s.check()
+            Yh = Y.cpu().numpy()
+            errs = [_err(Yh[p], refs[p][perm]) for p in range(powers)]
+            print(f"  errors {['%.2e' % e for e in errs]}", flush=True)
+            assert max(errs) <= 1e-12
+    finally:
+        s.close()
+
+
 def test_mpk_float32_values_late_workgroups_and_ticket_order():
     m = _scaled(matgen.stencil3d_27pt(40, seed=72))
     vals32 = m.val.astype(np.float32).astype(np.float64)
@@ -83,8 +115,10 @@ def test_mpk_float32_values_late_workgroups_and_ticket_order():
         s.permute(xd, xp, True)
         nu = s.stats()["n_units"]
         for tag, setup in (("late", lambda: s.test_late(3)),
-                           ("critical_order", lambda: (s.test_late(0),
-                                                       s.order_tickets(np.random.default_rng(3).uniform(1, 5, nu).astype(np.float32))))):
+                           ("late_diagonal", lambda: s.set_mpk_order(300, True)),
+                           ("critical_order", lambda: (s.test_late(0), s.set_mpk_order(-1, False),
+                                                       s.order_tickets(np.random.default_rng(3).uniform(1, 5, nu).astype(np.float32)))),
+                           ("critical_order_diagonal", lambda: s.set_mpk_order(0, False))):
             setup()
             before = s.takeovers()
             Y = torch.full((4, m.n), float("nan"), dtype=torch.float64, device=DEV)
@@ -94,7 +128,7 @@ def test_mpk_float32_values_late_workgroups_and_ticket_order():
             errs = [_err(Y[p].cpu().numpy(), refs[p][perm]) for p in range(4)]
             print(f"[mpk f32 {tag}] errors {['%.2e' % e for e in errs]} takeovers {s.takeovers() - before}", flush=True)
             assert max(errs) <= 1e-12
-            if tag == "late":
+            if tag in ("late", "late_diagonal"):
                 assert s.takeovers() - before > 0
     finally:
         s.close()
