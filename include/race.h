@@ -341,6 +341,16 @@ int race_schedule_set_mpk_order(race_schedule_t s, int64_t lag_rows, int32_t cac
  * powers * (units + clearing tasks) tickets. */
 int race_schedule_mpk_order(race_schedule_t s, int32_t powers, int32_t n_static, int32_t* order);
 
+/* Gauss-Seidel kernel choice per phase: phases with at least min_leaves
+ * leaves (and windows of at most 2048 entries) run four leaves per
+ * wavefront, 16 lanes each, the others one leaf per wavefront.  -1 (the
+ * default): 32 x the device's CUs, i.e. more leaves than the CUs hold
+ * wavefronts; -2: never; 0: always.  The results agree to rounding (a
+ * row's products are added in another order).
+ * RACE_EUNSUPPORTED for a schedule that is not distance-1; RACE_EINVAL for
+ * min_leaves < -2. */
+int race_schedule_set_gs_quad(race_schedule_t s, int32_t min_leaves);
+
 /* Gauss-Seidel sweep on A x = b over a distance-1 schedule (dist_k = 1,
  * float64 values; the paper names Gauss-Seidel as the prime user of such
  * colorings, Sections 1 and 4.2): every row i takes

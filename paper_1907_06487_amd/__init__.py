@@ -180,6 +180,11 @@ class Schedule:
         diagonal order with that lag; cache_matrix: cacheable matrix loads."""
         _lib.race_schedule_set_mpk_order(self.handle, lag_rows, int(bool(cache_matrix)))
 
+    def set_gs_quad(self, min_leaves=-1):
+        """Gauss-Seidel phases with at least min_leaves leaves run four leaves
+        per wavefront (-1: the default threshold, -2: never, 0: always)."""
+        _lib.race_schedule_set_gs_quad(self.handle, min_leaves)
+
     def mpk_order(self, powers, n_static):
         """The matrix-power ticket order (power-major indices by ticket)."""
         st = self.stats()

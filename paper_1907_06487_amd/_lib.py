@@ -32,7 +32,7 @@ EXPORTS = [
     "race_symm_spmv_noalloc", "race_vendor_create", "race_vendor_spmv", "race_vendor_destroy", "race_stream_read",
     "race_stream_copy", "race_symm_gs", "race_schedule_set_ticket_order", "race_schedule_order_tickets",
     "race_schedule_ticket_order", "race_symm_mpk", "race_symm_poly", "race_schedule_read_deps",
-    "race_schedule_set_mpk_order", "race_schedule_mpk_order",
+    "race_schedule_set_mpk_order", "race_schedule_mpk_order", "race_schedule_set_gs_quad",
 ]
 
 MLP_INPUTS = 12
@@ -115,6 +115,7 @@ def lib():
         "race_schedule_read_deps": ([_P, _I64P, _I32P, _I32P], ctypes.c_int),
         "race_schedule_set_mpk_order": ([_P, ctypes.c_int64, ctypes.c_int32], ctypes.c_int),
         "race_schedule_mpk_order": ([_P, ctypes.c_int32, ctypes.c_int32, _I32P], ctypes.c_int),
+        "race_schedule_set_gs_quad": ([_P, ctypes.c_int32], ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
@@ -351,6 +352,10 @@ def race_schedule_mpk_order(h, powers, n_static, per_power):
     out = np.empty(int(powers) * int(per_power), dtype=np.int32)
     check(lib().race_schedule_mpk_order(h, int(powers), int(n_static), _np_ptr(out, ctypes.c_int32)))
     return out
+
+
+def race_schedule_set_gs_quad(h, min_leaves):
+    check(lib().race_schedule_set_gs_quad(h, int(min_leaves)))
 
 
 def race_symm_spmv(h, x, y, stream=None):

@@ -109,6 +109,9 @@ struct race_schedule {
   uint32_t epoch = 0;
   uint64_t ticket_next = 0;
   int32_t n_cus = 0;
+  // Gauss-Seidel phases with at least this many leaves run four leaves per
+  // wavefront: -1 the default (32 x CUs), -2 never, >= 0 that count
+  int32_t gs_quad_min = -1;
   DevBuf<uint32_t> halo, row_flags, chunk_off;
   DevBuf<int32_t> zero_idx;
   DevBuf<uint16_t> lane_slot, sell_slot;
@@ -472,6 +475,11 @@ int race_schedule_upload(race_schedule_t s) {
     UP(gs_val, G.val)
     UP(gs_diag, G.diag)
     UP(new2old, s->tree.perm)
+    e = hipDeviceGetAttribute(&s->n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+      s->free_device();
+      return hip_fail(e, "hipDeviceGetAttribute");
+    }
     s->device = dev;
     s->uploaded = true;
     s->stats.device_bytes = total;
@@ -1379,6 +1387,14 @@ int race_schedule_read_deps(race_schedule_t s, int64_t* count, int32_t* ptr, int
   return RACE_OK;
 }
 
+int race_schedule_set_gs_quad(race_schedule_t s, int32_t min_leaves) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (min_leaves < -2) return fail(RACE_EINVAL, "min_leaves must be -2 (never), -1 (default) or >= 0");
+  s->gs_quad_min = min_leaves;
+  return RACE_OK;
+}
+
 int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t direction, void* stream) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
@@ -1393,7 +1409,10 @@ int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t directio
   const int32_t np = s->tree.n_phases;
   auto phase = [&](int32_t ph, bool backward) {
     const int32_t l0 = G.phase_leaf_ptr[ph], l1 = G.phase_leaf_ptr[ph + 1];
-    return race::launch_gs_phase(a, l0, l1 - l0, G.phase_max_window[ph], backward, b, x, st);
+    // four leaves per wavefront once a phase has more leaves than the CUs
+    // hold wavefronts (32 each)
+    const int32_t quad_min = s->gs_quad_min >= 0 ? s->gs_quad_min : (s->gs_quad_min == -1 ? 32 * s->n_cus : INT32_MAX);
+    return race::launch_gs_phase(a, l0, l1 - l0, G.phase_max_window[ph], backward, quad_min, b, x, st);
   };
   if (direction != 1)
     for (int32_t ph = 0; ph < np; ++ph) {

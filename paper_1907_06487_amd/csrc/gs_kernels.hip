@@ -1,6 +1,8 @@
 // gfx950 Gauss-Seidel sweep over a distance-1 RACE schedule: one launch per
-// phase, one wavefront per leaf (leaves of one phase share no edge, so they
-// run at the same time), the rows of a leaf in order.
+// phase, one wavefront per leaf or (phases of more leaves than the CUs can
+// hold wavefronts, windows up to kGsQuadMaxWindow entries) four leaves per
+// wavefront (leaves of one phase share no edge, so they run at the same
+// time), the rows of a leaf in order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -149,10 +151,122 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
   for (int32_t s = lane; s < R; s += kGsLanes) x[lo + s] = xw[s];
 }
 
+// Four leaves per wavefront: lanes 16 g .. 16 g + 15 run leaf 4 b + g of
+// the phase, so a phase of many small leaves needs a quarter of the
+// wavefronts (the wave slots of a CU, not the LDS, bound how many leaves run
+// at once with one leaf per wavefront).  The rows of the four leaves advance
+// together; a group past its leaf's last row computes on empty rows and
+// writes nothing.  A group's lanes take a row's entries 16 at a time (the
+// first 32 are loaded ahead, kQAhead rows in advance), reduce within the
+// group by four DPP steps (quad swaps, half-row and row mirrors, which stay
+// inside a row of 16 lanes) and get the row's metadata from the lane that
+// holds it (ds_bpermute).
+constexpr int kQLanes = 16;
+constexpr int kQAhead = 8;  // divides 16
+
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Rows t0 .. t0 + 15 of the group's leaf, one per lane j of the group.
+template <bool kBackward>
+__device__ __forceinline__ void gsq_load_meta(const GsArgs& a, const double* __restrict__ bvec, int32_t lo, int32_t R,
+                                              int32_t t0, int32_t j, GsMeta& m) {
+  m = GsMeta{};
+  const int32_t t = t0 + j;
+  if (t < R) {
+    const int32_t i = kBackward ? lo + R - 1 - t : lo + t;
+    m.e0 = a.row_ptr[i];
+    m.e1 = a.row_ptr[i + 1];
+    m.b = bvec[i];
+    m.d = a.diag[i];
+  }
+}
+
+struct GsQRow {
+  double v0 = 0.0, v1 = 0.0;
+  uint32_t s0 = 0, s1 = 0;
+};
+
+__device__ __forceinline__ void gsq_load_row(const GsArgs& a, const GsMeta& m, int32_t src, int32_t j, GsQRow& r) {
+  const int32_t e0 = __shfl(m.e0, src), e1 = __shfl(m.e1, src);
+  r = GsQRow{};
+  if (e0 + j < e1) {
+    r.v0 = a.val[e0 + j];
+    r.s0 = a.slot[e0 + j];
+  }
+  if (e0 + kQLanes + j < e1) {
+    r.v1 = a.val[e0 + kQLanes + j];
+    r.s1 = a.slot[e0 + kQLanes + j];
+  }
+}
+
+template <bool kBackward>
+__global__ void __launch_bounds__(kGsLanes) gs_quad_kernel(GsArgs a, int32_t leaf0, int32_t count, int32_t wmax,
+                                                          const double* __restrict__ bvec, double* __restrict__ x) {
+  extern __shared__ double smem[];
+  const int32_t lane = static_cast<int32_t>(threadIdx.x);
+  const int32_t g = lane / kQLanes, j = lane % kQLanes, base = lane - j;
+  const int32_t li = static_cast<int32_t>(blockIdx.x) * 4 + g;
+  const bool live = li < count;
+  const int32_t leaf = leaf0 + (live ? li : count - 1);
+  double* xw = smem + static_cast<size_t>(g) * wmax;
+  const int32_t lo = a.leaf_lo[leaf], h0 = a.halo_ptr[leaf];
+  const int32_t R = live ? a.leaf_hi[leaf] - lo : 0, H = live ? a.halo_ptr[leaf + 1] - h0 : 0;
+  for (int32_t s = j; s < R; s += kQLanes) xw[s] = x[lo + s];
+  for (int32_t s = j; s < H; s += kQLanes) xw[R + s] = x[a.halo[h0 + s]];
+  int32_t rmax = R;
+  rmax = max(rmax, __shfl_xor(rmax, 16));
+  rmax = max(rmax, __shfl_xor(rmax, 32));
+  rmax = __builtin_amdgcn_readfirstlane(rmax);
+  GsMeta cur, next;
+  gsq_load_meta<kBackward>(a, bvec, lo, R, 0, j, cur);
+  gsq_load_meta<kBackward>(a, bvec, lo, R, kQLanes, j, next);
+  GsQRow ring[kQAhead];
+#pragma unroll
+  for (int p = 0; p < kQAhead; ++p)
+    if (p < rmax) gsq_load_row(a, cur, base + p, j, ring[p]);
+  __syncthreads();
+  for (int32_t t0 = 0; t0 < rmax; t0 += kQAhead) {
+#pragma unroll
+    for (int p = 0; p < kQAhead; ++p) {
+      const int32_t t = t0 + p;
+      if (t < rmax) {
+        const int32_t l = t & (kQLanes - 1);
+        const int32_t src = base + l;
+        double s = ring[p].v0 * xw[ring[p].s0] + ring[p].v1 * xw[ring[p].s1];
+        // entries past the first 32 (long rows) are loaded when the row runs
+        const int32_t e1 = __shfl(cur.e1, src);
+        for (int32_t e = __shfl(cur.e0, src) + 2 * kQLanes + j; e < e1; e += kQLanes) s += a.val[e] * xw[a.slot[e]];
+        const double bi = __shfl(cur.b, src), di = __shfl(cur.d, src);
+        const int32_t tn = t + kQAhead;
+        // kQAhead divides 16, so row tn is in the current or the next chunk
+        if (tn < rmax) {
+          const int32_t ln = tn & (kQLanes - 1);
+          gsq_load_row(a, ln >= l ? cur : next, base + ln, j, ring[p]);
+        }
+        const double xi = (bi - group_sum(s)) / di;
+        if (t < R && j == 0) xw[kBackward ? R - 1 - t : t] = xi;
+        __syncthreads();
+        if (l == kQLanes - 1) {
+          // the chunk of rows t - 15 .. t is done: shift, fetch the one after next
+          cur = next;
+          gsq_load_meta<kBackward>(a, bvec, lo, R, t + 1 + kQLanes, j, next);
+        }
+      }
+    }
+  }
+  for (int32_t s = j; s < R; s += kQLanes) x[lo + s] = xw[s];
+}
+
 }  // namespace dev
 
 hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,
-                           const double* b, double* x, hipStream_t st) {
+                           int32_t quad_min_leaves, const double* b, double* x, hipStream_t st) {
   if (count == 0) return hipSuccess;
   static bool attr_done[2] = {false, false};
   const void* fn = backward ? reinterpret_cast<const void*>(&dev::gs_leaf_kernel<true>)
@@ -161,6 +275,18 @@ hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kGsMaxWindowBytes);
     if (e != hipSuccess) return e;
     attr_done[backward] = true;
+  }
+  if (wmax <= kGsQuadMaxWindow && count >= quad_min_leaves) {
+    // four leaves per wavefront
+    const size_t qlds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+    const dim3 grid(static_cast<uint32_t>((count + 3) / 4));
+    if (backward)
+      hipLaunchKernelGGL(dev::gs_quad_kernel<true>, grid, dim3(dev::kGsLanes), qlds, st, a, leaf0, count,
+                         wmax > 0 ? wmax : 1, b, x);
+    else
+      hipLaunchKernelGGL(dev::gs_quad_kernel<false>, grid, dim3(dev::kGsLanes), qlds, st, a, leaf0, count,
+                         wmax > 0 ? wmax : 1, b, x);
+    return hipGetLastError();
   }
   const size_t lds = static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
   if (backward)

@@ -8,6 +8,7 @@
 namespace race {
 
 constexpr int32_t kGsMaxWindowBytes = 16384 * 8;  // LDS of the largest leaf window
+constexpr int32_t kGsQuadMaxWindow = 2048;        // phases whose windows fit run four leaves per wavefront
 
 // Device copies of a GsLayout (gauss_seidel.hpp).
 struct GsArgs {
@@ -21,10 +22,13 @@ struct GsArgs {
   const double* diag;
 };
 
-// Leaves leaf0 .. leaf0 + count - 1 (one phase) on one wavefront each, with
-// windows of at most wmax entries; rows in order (backward: reversed).
+// Leaves leaf0 .. leaf0 + count - 1 (one phase), with windows of at most
+// wmax entries: four per wavefront (16 lanes each) when wmax <=
+// kGsQuadMaxWindow and count >= quad_min_leaves (more leaves than the
+// device holds wavefronts: then a quarter of the wavefronts run them in
+// fewer rounds), else one per wavefront; rows in order (backward: reversed).
 // b and x are device arrays of n in the permuted order; x is updated in place.
 hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,
-                           const double* b, double* x, hipStream_t st);
+                           int32_t quad_min_leaves, const double* b, double* x, hipStream_t st);
 
 }  // namespace race

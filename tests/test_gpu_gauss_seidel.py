@@ -5,7 +5,8 @@ phase concurrently, rows of a leaf ascending in the permuted numbering).
 The oracle runs the plain serial sweep over the same rows in the same
 order (the C oracle, bit-equal to the Python one pinned against dense
 triangular solves).  Summation order inside a row differs (the GPU sums a
-row's products across lanes), so the results agree within rounding:
+row's products across 64 or, with four leaves per wavefront, 16 lanes), so
+the results agree within rounding:
 ||x - x_ref||_inf / ||x_ref||_inf <= 1e-12 on diagonally dominant matrices,
 after one or several sweeps.
 """
@@ -42,9 +43,10 @@ def race_rows(s):
     return G.race_order(s.perm(), lo, hi, phase)
 
 
-def run_gs(m, b, x0, direction, sweeps, **params):
+def run_gs(m, b, x0, direction, sweeps, quad=-1, **params):
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, dist_k=1, **params)
     try:
+        s.set_gs_quad(quad)
         bd = torch.as_tensor(b, device=DEV)
         xd = torch.as_tensor(x0, device=DEV)
         bp, xp = torch.empty_like(bd), torch.empty_like(xd)
@@ -84,19 +86,24 @@ CASES = [
     ("one_row", lambda: matgen.UpperCSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])),
      dict(n_workers=4)),
     ("long_rows", lambda: dominant(matgen.random_symmetric(600, 0.3, seed=10)), dict(n_workers=4)),
+    # leaves of thousands of rows: windows past 2048 entries take one leaf per wavefront
+    ("3d27pt_24_big_leaves", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=2)),
+    # phases whose leaf count is not a multiple of four (four leaves per wavefront)
+    ("3d27pt_17", lambda: matgen.stencil3d_27pt(17, seed=7), dict(n_workers=333)),
 ]
 
 
+@pytest.mark.parametrize("quad", [-2, 0], ids=["one_leaf_per_wave", "four_leaves_per_wave"])
 @pytest.mark.parametrize("direction", ["forward", "backward", "symmetric"])
 @pytest.mark.parametrize("name,make,params", CASES, ids=[c[0] for c in CASES])
-def test_gauss_seidel_parity(name, make, params, direction):
+def test_gauss_seidel_parity(name, make, params, direction, quad):
     m = make()
     rng = np.random.default_rng(11)
     b = rng.uniform(-1, 1, m.n)
     x0 = rng.uniform(-1, 1, m.n)
     sweeps = 3 if direction == "symmetric" else 1
-    print(f"case gs {name} {direction} x{sweeps}: n={m.n} nnz={m.nnz} {params}", flush=True)
-    x, order, st = run_gs(m, b, x0, direction, sweeps, **params)
+    print(f"case gs {name} {direction} x{sweeps} quad={quad}: n={m.n} nnz={m.nnz} {params}", flush=True)
+    x, order, st = run_gs(m, b, x0, direction, sweeps, quad=quad, **params)
     ref = oracle(m, b, x0, order, direction, sweeps)
     err = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     print(f"[gs {name} {direction}] leaves={st['n_leaves']} phases={st['n_phases_used']} "
@@ -140,15 +147,18 @@ def test_gauss_seidel_converges_and_refuses_products():
 
 
 @pytest.mark.timeout(600)
-def test_gauss_seidel_full_size_3d27pt_128():
-    """The 128^3 stencil of the benchmark, one symmetric sweep, against the
-    C oracle over the same row order (about 2 s on one host core)."""
+@pytest.mark.parametrize("nt", [4096, 16384])
+def test_gauss_seidel_full_size_3d27pt_128(nt):
+    """The 128^3 stencil, one symmetric sweep, against the C oracle over
+    the same row order (about 2 s on one host core); N_t 16384 is the
+    benchmark's schedule, whose large phases run four leaves per wavefront
+    with the default threshold."""
     m = matgen.config_3d_128()
     rng = np.random.default_rng(14)
     b = rng.uniform(-1, 1, m.n)
     x0 = np.zeros(m.n)
-    print(f"case gs 3d27pt_128: n={m.n}", flush=True)
-    x, order, st = run_gs(m, b, x0, "symmetric", 1, n_workers=4096)
+    print(f"case gs 3d27pt_128 nt={nt}: n={m.n}", flush=True)
+    x, order, st = run_gs(m, b, x0, "symmetric", 1, n_workers=nt)
     ref = oracle(m, b, x0, order, "symmetric", 1)
     err = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     print(f"[gs 3d27pt_128] leaves={st['n_leaves']} window={st['max_window']} err_norm={err:.3e}", flush=True)

@@ -382,3 +382,20 @@ def test_matrix_power_read_deps(name, make, kw):
             assert idx[ptr[i]:ptr[i + 1]].tolist() == want, i
     finally:
         s.close()
+
+
+def test_gs_quad_knob_arguments():
+    """race_schedule_set_gs_quad: distance-1 schedules only, -2..any."""
+    g = matgen.config_2d_small()
+    s = R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, dist_k=1, n_workers=64)
+    s2 = R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, n_workers=64)
+    try:
+        for v in (-2, -1, 0, 100):
+            s.set_gs_quad(v)
+        with pytest.raises(_lib.RaceError):
+            s.set_gs_quad(-3)
+        with pytest.raises(_lib.RaceError):
+            s2.set_gs_quad(0)
+    finally:
+        s.close()
+        s2.close()
