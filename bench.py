@@ -181,6 +181,44 @@ def yardsticks(m, perm, flops, nnz_full, xs, ys, args, torch):
     return out
 
 
+def unit_trace(s, st, xs, ys, reps, torch):
+    """Per-unit device timestamps of `reps` traced products (race_symm_spmm_traced:
+    start, end of the arithmetic, end of the conflict-edge waits, end of the
+    flush, on the device's wall clock) summarised: the span of a product,
+    what an average unit spends in each part, how many workgroups hold a
+    unit over time, and the drain after the last unit starts."""
+    import numpy as np
+    nu = st["n_units"]
+    tr = torch.zeros(4 * nu, dtype=torch.int64, device=xs[0].device)
+    spans, parts, timelines, drains, idle = [], [], [], [], []
+    grid = s.flow_grid(1)
+    for rep in range(reps):
+        s.traced(xs[rep % len(xs)], ys[rep % len(ys)], tr)
+        torch.cuda.synchronize()
+        t = tr.cpu().numpy().reshape(nu, 4).astype(np.float64) * 1e6 / float(st["wall_clock_hz"])
+        t -= t[:, 0].min()
+        span = float(t[:, 3].max())
+        spans.append(span)
+        parts.append([float(np.mean(t[:, 1] - t[:, 0])), float(np.mean(t[:, 2] - t[:, 1])),
+                      float(np.mean(t[:, 3] - t[:, 2]))])
+        drains.append(span - float(t[:, 0].max()))
+        idle.append(1.0 - float(np.sum(t[:, 3] - t[:, 0])) / (grid * span))
+        edges = np.arange(0.0, span + 5.0, 5.0)
+        timelines.append([int(np.sum((t[:, 0] <= b) & (t[:, 3] > b))) for b in edges])
+    s.check()
+    k = int(np.argsort(spans)[len(spans) // 2])  # the median product
+    out = {"reps": reps, "workgroups": grid, "units": nu, "span_us_median": round(float(np.median(spans)), 2),
+           "unit_us_mean": {"compute": round(parts[k][0], 2), "wait": round(parts[k][1], 2),
+                            "flush": round(parts[k][2], 2)},
+           "drain_after_last_start_us": round(drains[k], 2), "idle_workgroup_time": round(idle[k], 3),
+           "units_in_flight_every_5us": timelines[k]}
+    log(f"unit trace ({reps} traced products, median span {out['span_us_median']} us on {grid} workgroups): "
+        f"a unit computes {parts[k][0]:.1f} us, waits {parts[k][1]:.1f} us, flushes {parts[k][2]:.1f} us; "
+        f"drain after the last start {drains[k]:.1f} us; workgroups idle {idle[k] * 100:.1f}% of the span; "
+        f"units in flight every 5 us: {timelines[k]}")
+    return out
+
+
 def cpu_baseline(m, budget_s):
     """The serial C oracle on one host core, the process pinned to that
     core while it runs: mean and median seconds per product."""
@@ -676,6 +714,8 @@ def main():
     ap.add_argument("--low-locality", default="auto", choices=["auto", "race", "expanded"],
                     help="single-vector products: the library's choice (auto: a CRS product of the expanded permuted "
                          "matrix when the schedule predicts no window reuse), the RACE kernels, or always expanded")
+    ap.add_argument("--unit-trace", type=int, default=0,
+                    help="also run this many traced products and summarise their per-unit timestamps")
     ap.add_argument("--mpk", type=int, default=0, help="matrix powers A^p x, p = 1..MPK, in one launch instead")
     ap.add_argument("--mpk-orders", default="-1:0",
                     help="matrix-power ticket orders to time, lag_rows:cache_matrix pairs (lag < 0: power-major), "
@@ -817,6 +857,9 @@ def main():
         f"algorithmic ({achieved / PEAK_HBM_GBS * 100:.1f}% of peak), kernel-format bytes "
         f"{bytes_fmt / (ms * 1e-3) / 1e9:.1f} GB/s")
 
+    trace_info = unit_trace(s, st, xs, ys, args.unit_trace, torch) if args.unit_trace and st["product_path"] == 0 \
+        and args.exec_mode == "flow" else None
+
     race_kernels = None
     if st["product_path"] == 1:
         # the schedule predicted no window reuse and runs the expanded CRS
@@ -949,6 +992,7 @@ def main():
                      "product_path": "expanded CRS" if st["product_path"] == 1 else "RACE kernels",
                      "expanded_per_thread": st["expanded_per_thread"]},
         "race_kernels": race_kernels,
+        "unit_trace": trace_info,
         "attainable": attain,
         "error": {"norm": err_norm, "componentwise": err_comp},
         "baselines": baselines,
