@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
 // inside a row of 16 lanes) and get the row's metadata from the lane that
 // holds it (ds_bpermute).
 constexpr int kQLanes = 16;
-constexpr int kQAhead = 8;  // divides 16
+constexpr int kQAhead = 4;  // divides 16
 
 __device__ __forceinline__ double group_sum(double v) {
   v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
