@@ -724,7 +724,7 @@ def main():
                     help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
     ap.add_argument("--gs-workers", type=int, default=65536,
                     help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 65536 measured fastest: "
-                         "732 us against 854 at 16384)")
+                         "717 us against 843 at 16384 and 1529 at 4096)")
     ap.add_argument("--order", default="default", choices=["default", "critical"],
                     help="dataflow ticket order: the layout's execution order, or the critical path of unit costs "
                          "measured by traced products on this device (part of the schedule's preparation)")

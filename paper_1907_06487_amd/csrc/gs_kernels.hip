@@ -13,7 +13,7 @@ namespace race {
 namespace dev {
 
 constexpr int kGsLanes = 64;
-constexpr int kGsAhead = 16;  // rows whose entries are in flight ahead of the running row (divides 64)
+constexpr int kGsAhead = 8;  // rows whose entries are in flight ahead of the running row (divides 64)
 
 // Load of a word no kernel writes, at an index that is the same in every
 // lane: a scalar load through the constant address space.
