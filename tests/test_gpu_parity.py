@@ -403,17 +403,20 @@ def _batch_mats():
             matgen.random_symmetric(300, 0.02, seed=55), matgen.stencil3d_27pt(9, seed=56)]
 
 
-@pytest.mark.parametrize("k,low_locality", [(1, "race"), (4, "race"), (16, "race"), (1, "auto"), (1, "expanded"),
-                                            (4, "expanded"), (4, "auto"), (16, "auto")])
-def test_batch_graph_replays(k, low_locality):
+@pytest.mark.parametrize("k,low_locality,value_type", [
+    (1, "race", "f64"), (4, "race", "f64"), (16, "race", "f64"), (1, "auto", "f64"), (1, "expanded", "f64"),
+    (4, "expanded", "f64"), (4, "auto", "f64"), (16, "auto", "f64"), (1, "auto", "f32"), (3, "expanded", "f32"),
+    (16, "expanded", "f32")])
+def test_batch_graph_replays(k, low_locality, value_type):
     """Graph replays and direct launches of a small batch against the oracle.
     Members whose product is the expanded CRS product (all of them with
     "expanded", the banded one with "auto") take no tickets: with k = 1 they
-    run the batched row-block launch, with k > 1 a CRS SpMM each."""
+    run the batched row-block launch, with k > 1 a CRS SpMM each.  FP32
+    values are checked against the oracle on the same rounded values."""
     mats = _batch_mats()
     window = min(3840, (159 * 1024) // (16 * k + 4) - 16)  # x, y windows of k doubles + the index, per entry
     scheds = [R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=max(4, m.n // 500), window_max=window,
-                         low_locality=low_locality) for m in mats]
+                         low_locality=low_locality, value_type=value_type) for m in mats]
     paths = [sc.stats()["product_path"] for sc in scheds]
     if low_locality == "expanded":
         assert all(p == 1 for p in paths)
@@ -440,8 +443,9 @@ def test_batch_graph_replays(k, low_locality):
             xp = x.cpu().numpy()
             x_orig = np.empty_like(xp)
             x_orig[perm] = xp
-            y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, m.val, x_orig)[perm]
-            absax = O.abs_product(m.n, m.row_ptr, m.col, m.val, np.abs(x_orig))[perm]
+            vals = m.val if value_type == "f64" else m.val.astype(np.float32).astype(np.float64)
+            y_ref = O.symm_spmv(m.n, m.row_ptr, m.col, vals, x_orig)[perm]
+            absax = O.abs_product(m.n, m.row_ptr, m.col, vals, np.abs(x_orig))[perm]
             yh = y.cpu().numpy()
             for j in range(k):
                 sl = (slice(None), j) if k > 1 else slice(None)
