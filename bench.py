@@ -566,8 +566,9 @@ def run_gs(args, torch):
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, dist_k=1, n_workers=args.gs_workers, root=args.root,
                    level_order=args.level_order)
     st = s.stats()
+    s.set_gs_exec(args.gs_exec)
     log(f"Gauss-Seidel schedule built in {time.perf_counter() - t0:.2f}s: leaves {st['n_leaves']}, phases "
-        f"{st['n_phases_used']}, largest window {st['max_window']}")
+        f"{st['n_phases_used']}, largest window {st['max_window']}, execution {args.gs_exec}")
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(5)
     b = rng.uniform(-1, 1, m.n)
@@ -579,12 +580,14 @@ def run_gs(args, torch):
     x = torch.empty_like(xp)
     s.permute(xp, x, False)
     torch.cuda.synchronize()
+    s.check()
     tr = s.tree()
     node, phase = s.leaves()
     order = G.race_order(s.perm(), np.asarray(tr["lo"])[node], np.asarray(tr["hi"])[node], phase)
     ref = G.symmetric_sweep_c(m.n, m.row_ptr, m.col, m.val, b, np.zeros(m.n), order)
     err = float(np.max(np.abs(x.cpu().numpy() - ref)) / np.max(np.abs(ref)))
     ms = time_ring(lambda x_, y_: s.gauss_seidel(bp, xp), [0], [0], args.steps, args.warmup, torch)
+    s.check()
     nnz_full = st["nnz_full"]
     flops = 2 * 2 * nnz_full  # both directions: a multiply-add per off-diagonal, the diagonal division
     bytes_min = 2 * (12 * (nnz_full - m.n) + 4 * (m.n + 1) + 32 * m.n)
@@ -597,7 +600,8 @@ def run_gs(args, torch):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload + "_dominant", "description": desc + ", diagonal 1 + row abs-sum",
-                   "n": m.n, "nnz_full": nnz_full, "n_workers": args.gs_workers, "leaves": st["n_leaves"],
+                   "n": m.n, "nnz_full": nnz_full, "n_workers": args.gs_workers, "execution": args.gs_exec,
+                   "leaves": st["n_leaves"],
                    "phases": st["n_phases_used"], "max_window": st["max_window"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_min},
@@ -722,9 +726,11 @@ def main():
                          "e.g. -1:0,0:1,500000:1; the fastest is reported")
     ap.add_argument("--gs", action="store_true",
                     help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
+    ap.add_argument("--gs-exec", default="flow", choices=["phases", "flow"],
+                    help="--gs: one launch per phase, or one dataflow launch per sweep (128^3, N_t 65536: 640 us "
+                         "against 718 us with phase launches)")
     ap.add_argument("--gs-workers", type=int, default=65536,
-                    help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 65536 measured fastest: "
-                         "717 us against 843 at 16384 and 1529 at 4096)")
+                    help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 65536 measured fastest)")
     ap.add_argument("--order", default="default", choices=["default", "critical"],
                     help="dataflow ticket order: the layout's execution order, or the critical path of unit costs "
                          "measured by traced products on this device (part of the schedule's preparation)")

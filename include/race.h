@@ -341,6 +341,29 @@ int race_schedule_set_mpk_order(race_schedule_t s, int64_t lag_rows, int32_t cac
  * powers * (units + clearing tasks) tickets. */
 int race_schedule_mpk_order(race_schedule_t s, int32_t powers, int32_t n_static, int32_t* order);
 
+/* Gauss-Seidel execution: mode 0 (the default) launches once per phase and
+ * direction; mode 1 runs a whole sweep in one cooperative launch
+ * (dataflow): tickets are groups of up to four leaves of one phase, in the
+ * sweep's phase order; a ticket waits until the tickets holding its halo
+ * rows that the serial sweep updates before it have published (bounded
+ * waits; race_schedule_check reports one that gave up), so the phases
+ * overlap and the result is the serial sweep's, up to rounding.  Mode 1
+ * needs leaf windows of at most 2048 entries (else the phase launches run)
+ * and cannot be captured into a graph (RACE_EUNSUPPORTED).  RACE_EINVAL for
+ * another mode, RACE_EUNSUPPORTED for a schedule that is not distance-1. */
+int race_schedule_set_gs_exec(race_schedule_t s, int32_t mode);
+
+/* The tickets of the dataflow sweep in `direction` (host; for inspection
+ * and tests): *n_tickets tickets, each up to four consecutive leaves
+ * (execution order, see race_schedule_leaves) ticket_leaf0[t] ..
+ * ticket_leaf0[t] + ticket_count[t] - 1 of the forward (ticket_back[t] 0)
+ * or backward sweep, waiting for the tickets dep_idx[dep_ptr[t] ..
+ * dep_ptr[t + 1]) (*n_deps in all, n_tickets + 1 pointers).  Pass NULL
+ * arrays to query the counts first. */
+int race_schedule_gs_flow_plan(race_schedule_t s, int32_t direction, int32_t* n_tickets, int64_t* n_deps,
+                               int32_t* ticket_leaf0, int32_t* ticket_count, int32_t* ticket_back, int32_t* dep_ptr,
+                               int32_t* dep_idx);
+
 /* Gauss-Seidel kernel choice per phase: phases with at least min_leaves
  * leaves (and windows of at most 2048 entries) run four leaves per
  * wavefront, 16 lanes each, the others one leaf per wavefront.  -1 (the

@@ -180,6 +180,15 @@ class Schedule:
         diagonal order with that lag; cache_matrix: cacheable matrix loads."""
         _lib.race_schedule_set_mpk_order(self.handle, lag_rows, int(bool(cache_matrix)))
 
+    def set_gs_exec(self, mode="phases"):
+        """Gauss-Seidel sweeps as one launch per phase ("phases") or one
+        dataflow launch per sweep ("flow")."""
+        _lib.race_schedule_set_gs_exec(self.handle, {"phases": 0, "flow": 1}[mode])
+
+    def gs_flow_plan(self, direction=2):
+        """Tickets and waits of the dataflow sweep (0 forward, 1 backward, 2 both)."""
+        return _lib.race_schedule_gs_flow_plan(self.handle, direction)
+
     def set_gs_quad(self, min_leaves=-1):
         """Gauss-Seidel phases with at least min_leaves leaves run four leaves
         per wavefront (-1: the default threshold, -2: never, 0: always)."""

@@ -32,7 +32,8 @@ EXPORTS = [
     "race_symm_spmv_noalloc", "race_vendor_create", "race_vendor_spmv", "race_vendor_destroy", "race_stream_read",
     "race_stream_copy", "race_symm_gs", "race_schedule_set_ticket_order", "race_schedule_order_tickets",
     "race_schedule_ticket_order", "race_symm_mpk", "race_symm_poly", "race_schedule_read_deps",
-    "race_schedule_set_mpk_order", "race_schedule_mpk_order", "race_schedule_set_gs_quad",
+    "race_schedule_set_mpk_order", "race_schedule_mpk_order", "race_schedule_set_gs_quad", "race_schedule_set_gs_exec",
+    "race_schedule_gs_flow_plan",
 ]
 
 MLP_INPUTS = 12
@@ -116,6 +117,9 @@ def lib():
         "race_schedule_set_mpk_order": ([_P, ctypes.c_int64, ctypes.c_int32], ctypes.c_int),
         "race_schedule_mpk_order": ([_P, ctypes.c_int32, ctypes.c_int32, _I32P], ctypes.c_int),
         "race_schedule_set_gs_quad": ([_P, ctypes.c_int32], ctypes.c_int),
+        "race_schedule_set_gs_exec": ([_P, ctypes.c_int32], ctypes.c_int),
+        "race_schedule_gs_flow_plan": ([_P, ctypes.c_int32, _I32P, _I64P, _I32P, _I32P, _I32P, _I32P, _I32P],
+                                       ctypes.c_int),
         "race_symm_spmv": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
         "race_symm_spmm_traced": ([_P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
@@ -352,6 +356,21 @@ def race_schedule_mpk_order(h, powers, n_static, per_power):
     out = np.empty(int(powers) * int(per_power), dtype=np.int32)
     check(lib().race_schedule_mpk_order(h, int(powers), int(n_static), _np_ptr(out, ctypes.c_int32)))
     return out
+
+
+def race_schedule_set_gs_exec(h, mode):
+    check(lib().race_schedule_set_gs_exec(h, int(mode)))
+
+
+def race_schedule_gs_flow_plan(h, direction):
+    nt, nd = ctypes.c_int32(), ctypes.c_int64()
+    check(lib().race_schedule_gs_flow_plan(h, int(direction), ctypes.byref(nt), ctypes.byref(nd), *([None] * 5)))
+    arrs = [np.empty(nt.value, dtype=np.int32) for _ in range(3)]
+    ptr = np.empty(nt.value + 1, dtype=np.int32)
+    idx = np.empty(nd.value, dtype=np.int32)
+    check(lib().race_schedule_gs_flow_plan(h, int(direction), ctypes.byref(nt), ctypes.byref(nd),
+                                           *[_np_ptr(a, ctypes.c_int32) for a in arrs + [ptr, idx]]))
+    return {"leaf0": arrs[0], "count": arrs[1], "back": arrs[2], "dep_ptr": ptr, "dep_idx": idx}
 
 
 def race_schedule_set_gs_quad(h, min_leaves):

@@ -112,6 +112,14 @@ struct race_schedule {
   // Gauss-Seidel phases with at least this many leaves run four leaves per
   // wavefront: -1 the default (32 x CUs), -2 never, >= 0 that count
   int32_t gs_quad_min = -1;
+  // Gauss-Seidel execution: 0 one launch per phase, 1 one dataflow launch
+  // per sweep (plans per direction, built on first use); flags of the
+  // tickets (set to the launch's epoch), then the status word
+  int32_t gs_exec = 0;
+  race::GsFlow gs_flow_h[3];
+  DevBuf<int32_t> gsf_item[3], gsf_back[3], gsf_leaf0[3], gsf_count[3], gsf_dptr[3], gsf_didx[3];
+  DevBuf<uint32_t> gsf_flags;
+  uint32_t gs_epoch = 0;
   DevBuf<uint32_t> halo, row_flags, chunk_off;
   DevBuf<int32_t> zero_idx;
   DevBuf<uint16_t> lane_slot, sell_slot;
@@ -152,6 +160,12 @@ struct race_schedule {
   void free_device() {
     release(gs_leaf_lo); release(gs_leaf_hi); release(gs_halo_ptr); release(gs_halo); release(gs_row_ptr);
     release(gs_slot); release(gs_val); release(gs_diag);
+    for (int d = 0; d < 3; ++d) {
+      release(gsf_item[d]); release(gsf_back[d]); release(gsf_leaf0[d]); release(gsf_count[d]);
+      release(gsf_dptr[d]); release(gsf_didx[d]);
+      gs_flow_h[d].direction = -1;
+    }
+    release(gsf_flags);
     release(leaf_units); release(unit_desc); release(ticket_unit_d); release(unit_ticket_d);
     release(chunk_len); release(new2old); release(halo); release(row_flags); release(chunk_off);
     release(zero_idx);
@@ -1040,14 +1054,21 @@ int race_schedule_check(race_schedule_t s) {
   if (!s->uploaded) return RACE_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-  if (s->gs) return RACE_OK;  // Gauss-Seidel sweeps have no bounded waits
-  const int32_t n_flags = static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
+  // the status word: after the dataflow state of a product, or after the
+  // ticket flags of a dataflow Gauss-Seidel sweep
+  uint32_t* status_at = nullptr;
+  if (s->gs) {
+    if (!s->gsf_flags.p) return RACE_OK;  // phase launches have no bounded waits
+    status_at = s->gsf_flags.p + s->gsf_flags.count - 1;
+  } else {
+    status_at = s->flow_state.p + static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
+  }
   uint32_t status = 0;
-  e = hipMemcpy(&status, s->flow_state.p + n_flags, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  e = hipMemcpy(&status, status_at, sizeof(uint32_t), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   if (status) {
     const uint32_t zero = 0;
-    e = hipMemcpy(s->flow_state.p + n_flags, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(status_at, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     return fail(RACE_EINTERNAL, "a dataflow wait gave up (bounded spin exceeded)");
   }
@@ -1387,6 +1408,111 @@ int race_schedule_read_deps(race_schedule_t s, int64_t* count, int32_t* ptr, int
   return RACE_OK;
 }
 
+}  // extern "C"
+
+// One dataflow launch for a whole sweep (race_schedule_set_gs_exec 1).
+static int run_gs_flow(race_schedule_t s, const race::GsArgs& a, int32_t direction, const double* b, double* x,
+                       hipStream_t st) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cap);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(RACE_EUNSUPPORTED, "a dataflow sweep cannot be captured into a graph (the launch epoch is an argument)");
+  race::GsFlow& f = s->gs_flow_h[direction];
+  if (f.direction != direction) {
+    try {
+      race::build_gs_flow(s->G, direction, f);
+    } catch (const std::bad_alloc&) {
+      f.direction = -1;
+      return fail(RACE_ENOMEM, "out of host memory while planning the dataflow sweep");
+    } catch (const std::exception& ex) {
+      f.direction = -1;
+      return fail(RACE_EINTERNAL, ex.what());
+    }
+    int64_t total = 0;
+    for (DevBuf<int32_t>* bf : {&s->gsf_item[direction], &s->gsf_back[direction], &s->gsf_leaf0[direction],
+                                &s->gsf_count[direction], &s->gsf_dptr[direction], &s->gsf_didx[direction]})
+      release(*bf);
+    e = upload(s->gsf_item[direction], f.ticket_item.data(), f.ticket_item.size(), &total);
+    if (e == hipSuccess) e = upload(s->gsf_back[direction], f.ticket_back.data(), f.ticket_back.size(), &total);
+    if (e == hipSuccess) e = upload(s->gsf_leaf0[direction], f.item_leaf0.data(), f.item_leaf0.size(), &total);
+    if (e == hipSuccess) e = upload(s->gsf_count[direction], f.item_count.data(), f.item_count.size(), &total);
+    if (e == hipSuccess) e = upload(s->gsf_dptr[direction], f.dep_ptr.data(), f.dep_ptr.size(), &total);
+    if (e == hipSuccess && !f.dep_idx.empty()) e = upload(s->gsf_didx[direction], f.dep_idx.data(), f.dep_idx.size(), &total);
+    if (e != hipSuccess) {
+      f.direction = -1;
+      return hip_fail(e, "upload of the dataflow sweep plan");
+    }
+  }
+  const int32_t nt = static_cast<int32_t>(f.ticket_item.size());
+  if (nt == 0) return RACE_OK;
+  // flags of every ticket, then the status word; a new allocation starts at
+  // epoch 0 everywhere
+  if (s->gsf_flags.count < static_cast<size_t>(nt) + 1) {
+    release(s->gsf_flags);
+    std::vector<uint32_t> zeros(static_cast<size_t>(nt) + 1, 0u);
+    int64_t total = 0;
+    e = upload(s->gsf_flags, zeros.data(), zeros.size(), &total);
+    if (e != hipSuccess) return hip_fail(e, "allocation of the dataflow sweep flags");
+    s->gs_epoch = 0;
+  }
+  if (++s->gs_epoch == 0) {
+    // the epoch wrapped: clear the flags (the status word keeps its value)
+    e = race::launch_clear_words(s->gsf_flags.p, static_cast<int64_t>(s->gsf_flags.count) - 1, st);
+    if (e != hipSuccess) return hip_fail(e, "flag reset");
+    s->gs_epoch = 1;
+  }
+  int32_t grid = 0;
+  e = race::gs_flow_grid(s->G.max_window, s->n_cus, &grid);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (grid < 1) return fail(RACE_EUNSUPPORTED, "the dataflow sweep does not fit a CU");
+  grid = std::min(grid, nt);
+  const race::GsFlowArgs fa{s->gsf_item[direction].p, s->gsf_back[direction].p, s->gsf_leaf0[direction].p,
+                            s->gsf_count[direction].p, s->gsf_dptr[direction].p, s->gsf_didx[direction].p,
+                            s->gsf_flags.p, s->gsf_flags.p + s->gsf_flags.count - 1, nt, s->gs_epoch};
+  e = race::launch_gs_flow(a, fa, s->G.max_window, grid, b, x, st);
+  if (e != hipSuccess) return hip_fail(e, "dataflow sweep launch");
+  return RACE_OK;
+}
+
+extern "C" {
+
+int race_schedule_set_gs_exec(race_schedule_t s, int32_t mode) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (mode != 0 && mode != 1) return fail(RACE_EINVAL, "mode must be 0 (a launch per phase) or 1 (one dataflow launch)");
+  s->gs_exec = mode;
+  return RACE_OK;
+}
+
+int race_schedule_gs_flow_plan(race_schedule_t s, int32_t direction, int32_t* n_tickets, int64_t* n_deps,
+                               int32_t* ticket_leaf0, int32_t* ticket_count, int32_t* ticket_back, int32_t* dep_ptr,
+                               int32_t* dep_idx) {
+  if (!s || !n_tickets || !n_deps) return fail(RACE_EINVAL, "NULL argument");
+  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (direction < 0 || direction > 2) return fail(RACE_EINVAL, "direction must be 0 (forward), 1 (backward) or 2 (both)");
+  race::GsFlow f;
+  try {
+    race::build_gs_flow(s->G, direction, f);
+  } catch (const std::bad_alloc&) {
+    return fail(RACE_ENOMEM, "out of host memory while planning the dataflow sweep");
+  } catch (const std::exception& ex) {
+    return fail(RACE_EINTERNAL, ex.what());
+  }
+  const int32_t nt = static_cast<int32_t>(f.ticket_item.size());
+  *n_tickets = nt;
+  *n_deps = static_cast<int64_t>(f.dep_idx.size());
+  for (int32_t t = 0; t < nt; ++t) {
+    const int32_t i = f.ticket_item[static_cast<size_t>(t)];
+    if (ticket_leaf0) ticket_leaf0[t] = f.item_leaf0[static_cast<size_t>(i)];
+    if (ticket_count) ticket_count[t] = f.item_count[static_cast<size_t>(i)];
+    if (ticket_back) ticket_back[t] = f.ticket_back[static_cast<size_t>(t)];
+  }
+  if (dep_ptr) std::copy(f.dep_ptr.begin(), f.dep_ptr.end(), dep_ptr);
+  if (dep_idx) std::copy(f.dep_idx.begin(), f.dep_idx.end(), dep_idx);
+  return RACE_OK;
+}
+
 int race_schedule_set_gs_quad(race_schedule_t s, int32_t min_leaves) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
   if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
@@ -1406,6 +1532,7 @@ int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t directio
   const race::GsArgs a{s->gs_leaf_lo.p, s->gs_leaf_hi.p, s->gs_halo_ptr.p, s->gs_halo.p,
                        s->gs_row_ptr.p, s->gs_slot.p,    s->gs_val.p,      s->gs_diag.p};
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->gs_exec == 1 && G.max_window <= race::kGsQuadMaxWindow) return run_gs_flow(s, a, direction, b, x, st);
   const int32_t np = s->tree.n_phases;
   auto phase = [&](int32_t ph, bool backward) {
     const int32_t l0 = G.phase_leaf_ptr[ph], l1 = G.phase_leaf_ptr[ph + 1];

@@ -2,6 +2,7 @@
 #include "gauss_seidel.hpp"
 
 #include <algorithm>
+#include <stdexcept>
 #include <string>
 
 #include "../../include/race.h"
@@ -113,6 +114,78 @@ std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* co
   for (int32_t p = 0; p < tree.n_phases; ++p) L.phase_leaf_ptr[p + 1] += L.phase_leaf_ptr[p];
   L.halo_total = static_cast<int64_t>(L.halo.size());
   return "";
+}
+
+void build_gs_flow(const GsLayout& G, int32_t direction, GsFlow& f) {
+  const int32_t nl = static_cast<int32_t>(G.leaf_lo.size());
+  const int32_t np = static_cast<int32_t>(G.phase_leaf_ptr.size()) - 1;
+  f = GsFlow{};
+  f.direction = direction;
+  // phase of every leaf; items of up to kGsFlowLeaves leaves inside a phase
+  std::vector<int32_t> leaf_phase(static_cast<size_t>(nl)), leaf_item(static_cast<size_t>(nl));
+  std::vector<int32_t> phase_item_ptr(static_cast<size_t>(np) + 1, 0);
+  for (int32_t p = 0; p < np; ++p) {
+    phase_item_ptr[static_cast<size_t>(p)] = static_cast<int32_t>(f.item_leaf0.size());
+    for (int32_t l = G.phase_leaf_ptr[static_cast<size_t>(p)]; l < G.phase_leaf_ptr[static_cast<size_t>(p) + 1];
+         l += kGsFlowLeaves) {
+      const int32_t cnt = std::min(kGsFlowLeaves, G.phase_leaf_ptr[static_cast<size_t>(p) + 1] - l);
+      for (int32_t i = 0; i < cnt; ++i) {
+        leaf_phase[static_cast<size_t>(l + i)] = p;
+        leaf_item[static_cast<size_t>(l + i)] = static_cast<int32_t>(f.item_leaf0.size());
+      }
+      f.item_leaf0.push_back(l);
+      f.item_count.push_back(cnt);
+    }
+  }
+  phase_item_ptr[static_cast<size_t>(np)] = static_cast<int32_t>(f.item_leaf0.size());
+  const int32_t ni = static_cast<int32_t>(f.item_leaf0.size());
+  // leaf of every row (leaves cover the rows as disjoint ranges)
+  std::vector<int32_t> row_leaf(static_cast<size_t>(G.n), -1);
+  for (int32_t l = 0; l < nl; ++l)
+    for (int32_t r = G.leaf_lo[static_cast<size_t>(l)]; r < G.leaf_hi[static_cast<size_t>(l)]; ++r)
+      row_leaf[static_cast<size_t>(r)] = l;
+  // tickets
+  std::vector<int32_t> fwd_ticket(static_cast<size_t>(ni), -1), bwd_ticket(static_cast<size_t>(ni), -1);
+  if (direction != 1)
+    for (int32_t i = 0; i < ni; ++i) {
+      fwd_ticket[static_cast<size_t>(i)] = static_cast<int32_t>(f.ticket_item.size());
+      f.ticket_item.push_back(i);
+      f.ticket_back.push_back(0);
+    }
+  if (direction != 0)
+    for (int32_t p = np - 1; p >= 0; --p)
+      for (int32_t i = phase_item_ptr[static_cast<size_t>(p)]; i < phase_item_ptr[static_cast<size_t>(p) + 1]; ++i) {
+        bwd_ticket[static_cast<size_t>(i)] = static_cast<int32_t>(f.ticket_item.size());
+        f.ticket_item.push_back(i);
+        f.ticket_back.push_back(1);
+      }
+  // waits
+  const int32_t nt = static_cast<int32_t>(f.ticket_item.size());
+  f.dep_ptr.assign(static_cast<size_t>(nt) + 1, 0);
+  std::vector<int32_t> deps;
+  for (int32_t t = 0; t < nt; ++t) {
+    const int32_t i = f.ticket_item[static_cast<size_t>(t)];
+    const bool back = f.ticket_back[static_cast<size_t>(t)] != 0;
+    deps.clear();
+    if (back && direction == 2) deps.push_back(fwd_ticket[static_cast<size_t>(i)]);
+    for (int32_t l = f.item_leaf0[static_cast<size_t>(i)];
+         l < f.item_leaf0[static_cast<size_t>(i)] + f.item_count[static_cast<size_t>(i)]; ++l) {
+      const int32_t p = leaf_phase[static_cast<size_t>(l)];
+      for (int32_t h = G.halo_ptr[static_cast<size_t>(l)]; h < G.halo_ptr[static_cast<size_t>(l) + 1]; ++h) {
+        const int32_t m = row_leaf[static_cast<size_t>(G.halo[static_cast<size_t>(h)])];
+        const int32_t q = leaf_phase[static_cast<size_t>(m)];
+        if (q == p) throw std::logic_error("Gauss-Seidel dataflow: two leaves of one phase share an edge");
+        if (!back && q < p) deps.push_back(fwd_ticket[static_cast<size_t>(leaf_item[static_cast<size_t>(m)])]);
+        if (back && q > p) deps.push_back(bwd_ticket[static_cast<size_t>(leaf_item[static_cast<size_t>(m)])]);
+      }
+    }
+    std::sort(deps.begin(), deps.end());
+    deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+    for (const int32_t d : deps)
+      if (d < 0 || d >= t) throw std::logic_error("Gauss-Seidel dataflow: a wait that does not point backwards");
+    f.dep_idx.insert(f.dep_idx.end(), deps.begin(), deps.end());
+    f.dep_ptr[static_cast<size_t>(t) + 1] = static_cast<int32_t>(f.dep_idx.size());
+  }
 }
 
 }  // namespace race

@@ -44,4 +44,25 @@ struct GsLayout {
 std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                             const Tree& tree, GsLayout& out, int* code);
 
+// Dataflow plan of a sweep in one persistent launch.  Items are up to
+// kGsFlowLeaves consecutive leaves of one phase; tickets are the items of
+// the forward sweep in phase order, or of the backward sweep in reverse
+// phase order, or both (symmetric: forward, then backward).  A forward
+// ticket waits for the forward tickets of the items holding its leaves'
+// halo rows in earlier phases (their new x); a backward ticket for the
+// backward tickets of those in later phases and, in a symmetric sweep, for
+// its own forward ticket.  Leaves of one phase share no edge, so these are
+// all the orderings the serial sweep fixes: every later reader or writer
+// of a row this ticket reads or writes waits for it in turn, and every wait
+// points to an earlier ticket.
+constexpr int32_t kGsFlowLeaves = 4;
+struct GsFlow {
+  int32_t direction = -1;
+  std::vector<int32_t> item_leaf0, item_count;  // items in execution order
+  std::vector<int32_t> ticket_item;             // per ticket
+  std::vector<int32_t> ticket_back;             // per ticket: 1 for the backward sweep
+  std::vector<int32_t> dep_ptr, dep_idx;        // per ticket: the earlier tickets it waits for
+};
+void build_gs_flow(const GsLayout& G, int32_t direction, GsFlow& f);
+
 }  // namespace race

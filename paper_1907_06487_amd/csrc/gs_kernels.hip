@@ -161,6 +161,7 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
 // group by four DPP steps (quad swaps, half-row and row mirrors, which stay
 // inside a row of 16 lanes) and get the row's metadata from the lane that
 // holds it (ds_bpermute).
+constexpr uint32_t kGsSpinLimit = 1u << 16;  // bounded wait of the dataflow sweep (about 2^16 sleeps)
 constexpr int kQLanes = 16;
 constexpr int kQAhead = 4;  // divides 16
 
@@ -205,20 +206,35 @@ __device__ __forceinline__ void gsq_load_row(const GsArgs& a, const GsMeta& m, i
   }
 }
 
-template <bool kBackward>
-__global__ void __launch_bounds__(kGsLanes) gs_quad_kernel(GsArgs a, int32_t leaf0, int32_t count, int32_t wmax,
-                                                          const double* __restrict__ bvec, double* __restrict__ x) {
-  extern __shared__ double smem[];
+// x as the sweep reads and writes it: plain, or (kCoherent: several
+// workgroups of one launch update x) agent-scope loads and stores, which are
+// coherent across the XCDs.
+template <bool kCoherent>
+__device__ __forceinline__ double gs_x_load(const double* p) {
+  if constexpr (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool kCoherent>
+__device__ __forceinline__ void gs_x_store(double* p, double v) {
+  if constexpr (kCoherent) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+// Leaves first .. first + cnt - 1 (cnt <= 4) on the wavefront, group g on
+// leaf first + g; smem holds 4 windows of wmax entries.
+template <bool kBackward, bool kCoherent>
+__device__ __forceinline__ void gs_quad_leaves(const GsArgs& a, int32_t first, int32_t cnt, int32_t wmax,
+                                               const double* __restrict__ bvec, double* __restrict__ x,
+                                               double* smem) {
   const int32_t lane = static_cast<int32_t>(threadIdx.x);
   const int32_t g = lane / kQLanes, j = lane % kQLanes, base = lane - j;
-  const int32_t li = static_cast<int32_t>(blockIdx.x) * 4 + g;
-  const bool live = li < count;
-  const int32_t leaf = leaf0 + (live ? li : count - 1);
+  const bool live = g < cnt;
+  const int32_t leaf = first + (live ? g : cnt - 1);
   double* xw = smem + static_cast<size_t>(g) * wmax;
   const int32_t lo = a.leaf_lo[leaf], h0 = a.halo_ptr[leaf];
   const int32_t R = live ? a.leaf_hi[leaf] - lo : 0, H = live ? a.halo_ptr[leaf + 1] - h0 : 0;
-  for (int32_t s = j; s < R; s += kQLanes) xw[s] = x[lo + s];
-  for (int32_t s = j; s < H; s += kQLanes) xw[R + s] = x[a.halo[h0 + s]];
+  for (int32_t s = j; s < R; s += kQLanes) xw[s] = gs_x_load<kCoherent>(x + lo + s);
+  for (int32_t s = j; s < H; s += kQLanes) xw[R + s] = gs_x_load<kCoherent>(x + a.halo[h0 + s]);
   int32_t rmax = R;
   rmax = max(rmax, __shfl_xor(rmax, 16));
   rmax = max(rmax, __shfl_xor(rmax, 32));
@@ -260,10 +276,80 @@ __global__ void __launch_bounds__(kGsLanes) gs_quad_kernel(GsArgs a, int32_t lea
       }
     }
   }
-  for (int32_t s = j; s < R; s += kQLanes) x[lo + s] = xw[s];
+  for (int32_t s = j; s < R; s += kQLanes) gs_x_store<kCoherent>(x + lo + s, xw[s]);
+}
+
+template <bool kBackward>
+__global__ void __launch_bounds__(kGsLanes) gs_quad_kernel(GsArgs a, int32_t leaf0, int32_t count, int32_t wmax,
+                                                          const double* __restrict__ bvec, double* __restrict__ x) {
+  extern __shared__ double smem[];
+  const int32_t first = static_cast<int32_t>(blockIdx.x) * 4;
+  gs_quad_leaves<kBackward, false>(a, leaf0 + first, min(4, count - first), wmax, bvec, x, smem);
+}
+
+// A whole sweep in one launch (dataflow, see GsFlowArgs): workgroup w runs
+// tickets w, w + grid, ... in order; before a ticket it waits until every
+// ticket in its list has published (bounded; a wait that gives up sets
+// *status and goes on, so the grid always drains), after it every x store
+// has completed before the ticket's flag is set.  The launch is cooperative
+// (every workgroup resident), so the lowest unfinished ticket always has a
+// running owner whose own earlier tickets are done.
+__global__ void __launch_bounds__(kGsLanes) gs_flow_kernel(GsArgs a, GsFlowArgs f, int32_t wmax,
+                                                          const double* __restrict__ bvec, double* __restrict__ x) {
+  extern __shared__ double smem[];
+  const int32_t lane = static_cast<int32_t>(threadIdx.x);
+  for (int32_t t = static_cast<int32_t>(blockIdx.x); t < f.n_tickets; t += static_cast<int32_t>(gridDim.x)) {
+    const int32_t d0 = gs_uniform(f.dep_ptr, t), d1 = gs_uniform(f.dep_ptr, t + 1);
+    for (int32_t i = d0 + lane; i < d1; i += kGsLanes) {
+      const uint32_t* flag = f.flags + f.dep_idx[i];
+      uint32_t spins = 0;
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kGsSpinLimit) {
+          atomicOr(f.status, 1u);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    const int32_t item = gs_uniform(f.ticket_item, t);
+    const int32_t first = gs_uniform(f.item_leaf0, item), cnt = gs_uniform(f.item_count, item);
+    if (gs_uniform(f.ticket_back, t))
+      gs_quad_leaves<true, true>(a, first, cnt, wmax, bvec, x, smem);
+    else
+      gs_quad_leaves<false, true>(a, first, cnt, wmax, bvec, x, smem);
+    // every lane's x stores complete before the flag
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (lane == 0) __hip_atomic_store(f.flags + t, f.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 }  // namespace dev
+
+hipError_t gs_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
+  const size_t lds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&dev::gs_flow_kernel),
+                                                              dev::kGsLanes, lds);
+  if (e != hipSuccess) return e;
+  *grid = per_cu * n_cus;
+  return hipSuccess;
+}
+
+hipError_t launch_gs_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, int32_t grid, const double* b, double* x,
+                          hipStream_t st) {
+  if (f.n_tickets == 0) return hipSuccess;
+  const size_t lds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  GsArgs aa = a;
+  GsFlowArgs ff = f;
+  int32_t ww = wmax > 0 ? wmax : 1;
+  void* args[] = {&aa, &ff, &ww, const_cast<double**>(&b), &x};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&dev::gs_flow_kernel), dim3(static_cast<uint32_t>(grid)),
+                                    dim3(dev::kGsLanes), args, static_cast<unsigned int>(lds), st);
+}
 
 hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,
                            int32_t quad_min_leaves, const double* b, double* x, hipStream_t st) {

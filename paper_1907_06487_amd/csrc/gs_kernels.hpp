@@ -22,6 +22,27 @@ struct GsArgs {
   const double* diag;
 };
 
+// A whole sweep in one cooperative launch over the tickets of a GsFlow
+// (gauss_seidel.hpp): device copies of its arrays, one completion flag per
+// ticket (set to epoch when done), a status word (bit 0: a bounded wait gave
+// up).
+struct GsFlowArgs {
+  const int32_t* ticket_item;
+  const int32_t* ticket_back;
+  const int32_t* item_leaf0;
+  const int32_t* item_count;
+  const int32_t* dep_ptr;
+  const int32_t* dep_idx;
+  uint32_t* flags;
+  uint32_t* status;
+  int32_t n_tickets;
+  uint32_t epoch;
+};
+// Workgroups of the cooperative launch: as many as the CUs hold at once.
+hipError_t gs_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid);
+hipError_t launch_gs_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, int32_t grid, const double* b, double* x,
+                          hipStream_t st);
+
 // Leaves leaf0 .. leaf0 + count - 1 (one phase), with windows of at most
 // wmax entries: four per wavefront (16 lanes each) when wmax <=
 // kGsQuadMaxWindow and count >= quad_min_leaves (more leaves than the

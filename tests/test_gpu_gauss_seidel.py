@@ -43,10 +43,11 @@ def race_rows(s):
     return G.race_order(s.perm(), lo, hi, phase)
 
 
-def run_gs(m, b, x0, direction, sweeps, quad=-1, **params):
+def run_gs(m, b, x0, direction, sweeps, quad=-1, exec_mode="phases", **params):
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, dist_k=1, **params)
     try:
         s.set_gs_quad(quad)
+        s.set_gs_exec(exec_mode)
         bd = torch.as_tensor(b, device=DEV)
         xd = torch.as_tensor(x0, device=DEV)
         bp, xp = torch.empty_like(bd), torch.empty_like(xd)
@@ -57,6 +58,7 @@ def run_gs(m, b, x0, direction, sweeps, quad=-1, **params):
         out = torch.empty_like(xd)
         s.permute(xp, out, to_permuted=False)
         torch.cuda.synchronize()
+        s.check()  # a dataflow wait that gave up
         return out.cpu().numpy(), race_rows(s), s.stats()
     finally:
         s.close()
@@ -93,17 +95,19 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("quad", [-2, 0], ids=["one_leaf_per_wave", "four_leaves_per_wave"])
+@pytest.mark.parametrize("quad,exec_mode", [(-2, "phases"), (0, "phases"), (-1, "flow")],
+                         ids=["one_leaf_per_wave", "four_leaves_per_wave", "dataflow"])
 @pytest.mark.parametrize("direction", ["forward", "backward", "symmetric"])
 @pytest.mark.parametrize("name,make,params", CASES, ids=[c[0] for c in CASES])
-def test_gauss_seidel_parity(name, make, params, direction, quad):
+def test_gauss_seidel_parity(name, make, params, direction, quad, exec_mode):
     m = make()
     rng = np.random.default_rng(11)
     b = rng.uniform(-1, 1, m.n)
     x0 = rng.uniform(-1, 1, m.n)
     sweeps = 3 if direction == "symmetric" else 1
-    print(f"case gs {name} {direction} x{sweeps} quad={quad}: n={m.n} nnz={m.nnz} {params}", flush=True)
-    x, order, st = run_gs(m, b, x0, direction, sweeps, quad=quad, **params)
+    print(f"case gs {name} {direction} x{sweeps} quad={quad} exec={exec_mode}: n={m.n} nnz={m.nnz} {params}",
+          flush=True)
+    x, order, st = run_gs(m, b, x0, direction, sweeps, quad=quad, exec_mode=exec_mode, **params)
     ref = oracle(m, b, x0, order, direction, sweeps)
     err = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     print(f"[gs {name} {direction}] leaves={st['n_leaves']} phases={st['n_phases_used']} "
@@ -147,8 +151,8 @@ def test_gauss_seidel_converges_and_refuses_products():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("nt", [4096, 16384])
-def test_gauss_seidel_full_size_3d27pt_128(nt):
+@pytest.mark.parametrize("nt,exec_mode", [(4096, "phases"), (16384, "phases"), (65536, "flow")])
+def test_gauss_seidel_full_size_3d27pt_128(nt, exec_mode):
     """The 128^3 stencil, one symmetric sweep, against the C oracle over
     the same row order (about 2 s on one host core); N_t 16384 is the
     benchmark's schedule, whose large phases run four leaves per wavefront
@@ -157,8 +161,8 @@ def test_gauss_seidel_full_size_3d27pt_128(nt):
     rng = np.random.default_rng(14)
     b = rng.uniform(-1, 1, m.n)
     x0 = np.zeros(m.n)
-    print(f"case gs 3d27pt_128 nt={nt}: n={m.n}", flush=True)
-    x, order, st = run_gs(m, b, x0, "symmetric", 1, n_workers=nt)
+    print(f"case gs 3d27pt_128 nt={nt} exec={exec_mode}: n={m.n}", flush=True)
+    x, order, st = run_gs(m, b, x0, "symmetric", 1, n_workers=nt, exec_mode=exec_mode)
     ref = oracle(m, b, x0, order, "symmetric", 1)
     err = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     print(f"[gs 3d27pt_128] leaves={st['n_leaves']} window={st['max_window']} err_norm={err:.3e}", flush=True)
