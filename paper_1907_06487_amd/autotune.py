@@ -24,10 +24,20 @@ def max_window(k: int) -> int:
 
 def candidates(n: int, k: int, block: int, window: int = 0, low_locality: str = "race"):
     """Worker counts of 8000, 4000 and 2000 rows per worker at the given
-    window (0: the largest that holds all k columns)."""
+    window (0: the largest that holds all k columns).  With low_locality
+    "auto" and four or more right-hand sides the expanded CRS product is one
+    more candidate, so the choice between it and the RACE kernels is
+    measured per matrix: from four columns on, a full-matrix CRS SpMM can
+    beat passes of RACE windows even where the windows have reuse.  With one
+    or two columns the schedule's own prediction decides; a matrix timed
+    alone there favours the expanded product more than the same matrix in a
+    batch, where the RACE members share one persistent launch."""
     wm = window or max_window(k)
     nts = sorted({int(min(4096, max(4, n // r))) for r in (8000, 4000, 2000)})
-    return [dict(n_workers=nt, window_max=wm, block_threads=block, low_locality=low_locality) for nt in nts]
+    out = [dict(n_workers=nt, window_max=wm, block_threads=block, low_locality=low_locality) for nt in nts]
+    if low_locality == "auto" and k >= 4:
+        out.append(dict(n_workers=nts[len(nts) // 2], window_max=wm, block_threads=block, low_locality="expanded"))
+    return out
 
 
 def _time(fn, reps):
