@@ -45,11 +45,13 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_source_hash():
-    """Hash of the sources that decide what the RACE kernel moves."""
+def kernel_source_hash(product_path=0):
+    """Hash of the sources that decide what the product kernel moves: the
+    RACE kernels (path 0) or the expanded CRS kernels (path 1)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ["race_kernels.hip", "unit_device.hpp", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp"]:
+    kern = "race_kernels.hip" if product_path == 0 else "csr_kernels.hip"
+    for f in [kern, "unit_device.hpp", "kernels.hpp", "layout.cpp", "layout.hpp", "schedule.cpp"]:
         with open(os.path.join(ROOT, "paper_1907_06487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -963,7 +965,8 @@ def main():
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if os.path.exists(tpath):
         tr = json.load(open(tpath))
-        same = (tr.get("source_hash") == kernel_source_hash() and tr.get("bytes_kernel") == st["bytes_kernel"]
+        same = (tr.get("source_hash") == kernel_source_hash(st["product_path"])
+                and tr.get("bytes_kernel") == st["bytes_kernel"]
                 and tr.get("n_workers") == args.n_workers and tr.get("block_threads") == args.block
                 and tr.get("window_max") == args.window and tr.get("exec_mode") == args.exec_mode
                 and tr.get("max_stages", 4) == args.max_stages

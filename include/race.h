@@ -97,7 +97,7 @@ typedef struct {
                               matrix over row blocks, as race_csr_create with lanes_per_row -8 (the schedule then
                               also holds the expanded matrix; value_type 0 or 1; stats product_path 1); 2 = the
                               CRS product always (tests).  On such schedules race_symm_spmm with k > 1 runs a CRS
-                              SpMM of the expanded matrix (row blocks for k <= 4, a lane per column above) and
+                              SpMM of the expanded matrix (row blocks, the matrix read once for all k columns) and
                               batches run them outside the persistent launch; traced products always run the RACE kernels */
 } race_params;
 

@@ -15,8 +15,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librace.so")
 
 HOST_SRC = ["schedule.cpp", "layout.cpp", "costmodel.cpp", "gauss_seidel.cpp"]
-HIP_SRC = ["race_kernels.hip", "mpk_kernels.hip", "mlp_kernels.hip", "bandwidth.hip", "vendor.hip", "gs_kernels.hip",
-           "api.hip"]
+HIP_SRC = ["race_kernels.hip", "csr_kernels.hip", "mpk_kernels.hip", "mlp_kernels.hip", "bandwidth.hip", "vendor.hip",
+           "gs_kernels.hip", "api.hip"]
 ARCH = os.environ.get("RACE_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]

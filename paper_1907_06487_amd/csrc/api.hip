@@ -147,7 +147,8 @@ struct race_schedule {
   int32_t exp_per = 0;   // entries per thread of its row blocks
   int32_t exp_nblk = 0;  // row blocks
   int32_t exp_nblk2 = 0; // row blocks of the SpMM with 2..4 columns
-  DevBuf<int32_t> exp_rp, exp_col, exp_blk, exp_blk2;
+  int32_t exp_nblk3 = 0; // row blocks of the SpMM with 5..16 columns
+  DevBuf<int32_t> exp_rp, exp_col, exp_blk, exp_blk2, exp_blk3;
   DevBuf<double> exp_val64;
   DevBuf<float> exp_val32;
   // distance-1 schedules: the Gauss-Seidel layout and its device copies
@@ -171,7 +172,7 @@ struct race_schedule {
     release(zero_idx);
     release(lane_slot); release(sell_slot); release(lane_diag64); release(sell_val64); release(lane_diag32);
     release(sell_val32); release(lane_diagc); release(sell_valc); release(dep_idx); release(flow_state); release(claims); release(tiles_x); release(tiles_y);
-    release(exp_rp); release(exp_col); release(exp_blk); release(exp_blk2); release(exp_val64); release(exp_val32);
+    release(exp_rp); release(exp_col); release(exp_blk); release(exp_blk2); release(exp_blk3); release(exp_val64); release(exp_val32);
     release(rdep_ptr); release(rdep_idx); release(mpk_state); release(mpk_order_d);
     uploaded = false;
   }
@@ -542,9 +543,12 @@ int race_schedule_upload(race_schedule_t s) {
       race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), s->exp_per, blk);
       s->exp_nblk = static_cast<int32_t>(blk.size()) - 1;
       UP(exp_blk, blk)
-      race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), race::kSpmmBlockPer, blk);
+      race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), race::csr_spmm_block_per(2), blk);
       s->exp_nblk2 = static_cast<int32_t>(blk.size()) - 1;
       UP(exp_blk2, blk)
+      race::csr_row_blocks(static_cast<int32_t>(erp.size()) - 1, erp.data(), race::csr_spmm_block_per(16), blk);
+      s->exp_nblk3 = static_cast<int32_t>(blk.size()) - 1;
+      UP(exp_blk3, blk)
     }
     UP(exp_rp, erp)
     UP(exp_col, ecol)
@@ -950,15 +954,13 @@ static int run_expanded(race_schedule_t s, const double* x, double* y, hipStream
 // Y = A X (k >= 2 columns, row-major) as a CRS SpMM of the expanded
 // permuted matrix.
 static hipError_t expanded_spmm(race_schedule_t s, int32_t k, const double* x, double* y, hipStream_t st) {
-  if (k <= 4)  // row blocks, k products per entry in LDS
-    return s->params.value_type == 0
-               ? race::launch_csr_block_spmm<double>(s->exp_nblk2, s->exp_blk2.p, s->exp_rp.p, s->exp_col.p,
-                                                     s->exp_val64.p, x, y, k, st)
-               : race::launch_csr_block_spmm<float>(s->exp_nblk2, s->exp_blk2.p, s->exp_rp.p, s->exp_col.p,
-                                                    s->exp_val32.p, x, y, k, st);
+  // row blocks, k products per entry in LDS: blocks of 512 entries up to 4
+  // columns, of 256 above
+  const int32_t nb = k <= 4 ? s->exp_nblk2 : s->exp_nblk3;
+  const int32_t* blk = k <= 4 ? s->exp_blk2.p : s->exp_blk3.p;
   return s->params.value_type == 0
-             ? race::launch_csr_spmm<double>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, st)
-             : race::launch_csr_spmm<float>(s->tree.n, k, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, st);
+             ? race::launch_csr_block_spmm<double>(nb, blk, s->exp_rp.p, s->exp_col.p, s->exp_val64.p, x, y, k, st)
+             : race::launch_csr_block_spmm<float>(nb, blk, s->exp_rp.p, s->exp_col.p, s->exp_val32.p, x, y, k, st);
 }
 
 static int run_expanded_spmm(race_schedule_t s, int32_t k, const double* x, double* y, hipStream_t st) {

@@ -223,16 +223,12 @@ struct BlockMat {
 template <typename ValT>
 hipError_t launch_csr_block_batch(const BlockMat<ValT>* mats, const int32_t* blk_mat, int32_t n_blocks,
                                   hipStream_t st);
-// Full-matrix CRS SpMM over row blocks of at most kSpmmBlockPer * 256
-// entries (csr_row_blocks with per = kSpmmBlockPer), 2 <= k <= 4.
-constexpr int32_t kSpmmBlockPer = 2;
+// Full-matrix CRS SpMM over row blocks of at most 256 * csr_spmm_block_per(k)
+// entries (csr_row_blocks with that per), 2 <= k <= 16.
+constexpr int32_t csr_spmm_block_per(int32_t k) { return k <= 4 ? 2 : 1; }
 template <typename ValT>
 hipError_t launch_csr_block_spmm(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
                                  const ValT* val, const double* X, double* Y, int32_t k, hipStream_t st);
-// Full-matrix CRS SpMM Y = A X, X and Y row-major n x k, 2 <= k <= 16.
-template <typename ValT>
-hipError_t launch_csr_spmm(int32_t n, int32_t k, const int32_t* rp, const int32_t* col, const ValT* val,
-                           const double* X, double* Y, hipStream_t st);
 // CRS SpMV over those blocks (per = 4, 8 or 16 entries per thread).
 template <typename ValT>
 hipError_t launch_csr_block(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,

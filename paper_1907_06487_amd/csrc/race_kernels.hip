@@ -1,5 +1,5 @@
-// gfx950 kernels: RACE SymmSpMV / SymmSpMM, the full-CRS SpMV and the
-// global-atomic SymmSpMV baselines, and the permutation kernel.
+// gfx950 kernels: RACE SymmSpMV / SymmSpMM (phases, dataflow, batch), the
+// tile and permutation kernels.  The CRS kernels are in csr_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -212,264 +212,6 @@ __global__ void __launch_bounds__(1024) race_batch_kernel(const BatchMat<ValT>* 
     flow_unit<ValT, K>(mm.a, lt - mm.n_zero_tasks, mm.dep_idx, mm.done, status, nullptr, 1u, xp, yp, b.ld,
                        xw, yw, gw, tid, nthr, wave0);
   }
-}
-
-// Full-matrix CRS SpMV (Algorithm "SpMV"), LPR lanes per row; values
-// float64 or float32 (promoted, float64 arithmetic).
-template <int LPR, typename ValT>
-__global__ void __launch_bounds__(256) csr_spmv_kernel(int32_t n, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col, const ValT* __restrict__ val,
-                                                       const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t row = gid / LPR;
-  const int32_t l = static_cast<int32_t>(gid % LPR);
-  if (row >= n) return;  // whole lane groups leave together
-  double s = 0.0;
-  const int32_t e = rp[row + 1];
-  // plain loads: a lane group takes a row's entries a part of a cache line
-  // at a time, so a line that is not kept would be fetched again
-  for (int32_t i = rp[row] + l; i < e; i += LPR) s += static_cast<double>(val[i]) * x[col[i]];
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-  if (l == 0) y[row] = s;
-}
-
-// Full-matrix CRS SpMV over row blocks (Algorithm "SpMV" with the entries
-// of consecutive rows streamed together).  Block b covers rows
-// [blk[b], blk[b+1]); their entries, at most 256 * PER, are consecutive in
-// the CRS arrays, so thread t loads entries t, t + 256, ... with unit
-// stride across the workgroup (every load instruction takes whole cache
-// lines, read non-temporally), multiplies each by its x entry and keeps the
-// product in LDS; after a barrier one thread per row adds its row's
-// products in entry order.  A block of a single row longer than 256 * PER
-// strides over the row and reduces across the workgroup instead.  Loads of
-// the lanes past the block's last entry repeat that entry (no per-lane
-// branch around the loads) and their products are dropped.  Workgroups are
-// dealt to the 8 XCDs in turn, so workgroup g runs block (g % 8) * G8 + g / 8
-// (G8 = grid / 8, the grid padded to a multiple of 8): each XCD streams a
-// contiguous eighth of the rows, and the x entries its rows gather stay in
-// its own L2 instead of being fetched by all eight.
-// One row block (rows r0..r1 of one matrix) of the row-block product, run
-// by a 256-thread workgroup with `prod` its LDS array of 256 * PER doubles.
-template <typename ValT, int PER>
-__device__ __forceinline__ void csr_block_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                               const ValT* __restrict__ val, const double* __restrict__ x,
-                                               double* __restrict__ y, int32_t r0, int32_t r1, double* prod) {
-  constexpr int32_t kCap = 256 * PER;
-  const int32_t t = static_cast<int32_t>(threadIdx.x);
-  const int32_t e0 = uniform_load(rp, r0);
-  const int32_t ne = uniform_load(rp, r1) - e0;
-  if (ne > kCap) {
-    // one long row (the partition gives such a row a block of its own)
-    double s = 0.0;
-    for (int32_t i = e0 + t; i < e0 + ne; i += 256) s += static_cast<double>(val[i]) * x[col[i]];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((t & 63) == 0) prod[t >> 6] = s;
-    __syncthreads();
-    if (t == 0) y[r0] = (prod[0] + prod[1]) + (prod[2] + prod[3]);
-    return;
-  }
-  if (ne > 0) {
-    int32_t c[PER];
-    ValT v[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int32_t i = e0 + min(t + k * 256, ne - 1);
-      c[k] = stream_load(col + i);
-      v[k] = stream_load(val + i);
-    }
-    double xv[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) xv[k] = x[c[k]];
-#pragma unroll
-    for (int k = 0; k < PER; ++k)
-      if (t + k * 256 < ne) prod[t + k * 256] = static_cast<double>(v[k]) * xv[k];
-  }
-  __syncthreads();
-  for (int32_t r = r0 + t; r < r1; r += 256) {
-    const int32_t a = rp[r] - e0, b = rp[r + 1] - e0;
-    double s = 0.0;
-    for (int32_t j = a; j < b; ++j) s += prod[j];
-    y[r] = s;
-  }
-}
-
-// Workgroup g of a grid padded to a multiple of 8 runs block
-// (g % 8) * (grid / 8) + g / 8 (see above).
-__device__ __forceinline__ int32_t xcd_block() {
-  const uint32_t g8 = gridDim.x / 8u;
-  return static_cast<int32_t>((blockIdx.x % 8u) * g8 + blockIdx.x / 8u);
-}
-
-template <typename ValT, int PER>
-__global__ void __launch_bounds__(256) csr_block_kernel(const int32_t* __restrict__ blk,
-                                                        const int32_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ col,
-                                                        const ValT* __restrict__ val,
-                                                        const double* __restrict__ x, double* __restrict__ y,
-                                                        int32_t n_blocks) {
-  __shared__ double prod[256 * PER];
-  const int32_t b = xcd_block();
-  if (b >= n_blocks) return;  // padding of the grid (uniform per workgroup)
-  csr_block_rows<ValT, PER>(rp, col, val, x, y, uniform_load(blk, b), uniform_load(blk, b + 1), prod);
-}
-
-// The row-block product of several matrices in one launch (the members of a
-// batch that run it): global block g belongs to matrix blk_mat[g] and is
-// block g - base of that matrix.
-template <typename ValT, int PER>
-__global__ void __launch_bounds__(256) csr_block_batch_kernel(const BlockMat<ValT>* __restrict__ mats,
-                                                              const int32_t* __restrict__ blk_mat,
-                                                              int32_t n_blocks) {
-  __shared__ double prod[256 * PER];
-  const int32_t g = xcd_block();
-  if (g >= n_blocks) return;
-  const BlockMat<ValT> m = mats[uniform_load(blk_mat, g)];
-  const int32_t b = g - m.base;
-  csr_block_rows<ValT, PER>(m.rp, m.col, m.val, m.x, m.y, uniform_load(m.blk, b), uniform_load(m.blk, b + 1), prod);
-}
-
-// Full-matrix CRS SpMM over row blocks for k = 2..KB columns (KB = 2 or 4;
-// X, Y row-major n x k): blocks of at most 512 entries (two per thread),
-// each entry's k products kept in LDS (entry-major, KB per entry), then one
-// thread per (row, column) adds its row's products in entry order.  Column
-// indices past k are computed on column k - 1 and never stored.  A block
-// of one row longer than 512 entries strides over it and reduces across
-// the workgroup per column.  Blocks go to the XCDs in contiguous eighths.
-template <typename ValT, int KB>
-__global__ void __launch_bounds__(256) csr_block_spmm_kernel(const int32_t* __restrict__ blk,
-                                                             const int32_t* __restrict__ rp,
-                                                             const int32_t* __restrict__ col,
-                                                             const ValT* __restrict__ val,
-                                                             const double* __restrict__ X, double* __restrict__ Y,
-                                                             int32_t k, int32_t n_blocks) {
-  constexpr int32_t kPer = 2, kCap = 256 * kPer;
-  __shared__ double prod[kCap * KB];
-  const int32_t t = static_cast<int32_t>(threadIdx.x);
-  const int32_t b = xcd_block();
-  if (b >= n_blocks) return;  // padding of the grid (uniform per workgroup)
-  const int32_t r0 = uniform_load(blk, b), r1 = uniform_load(blk, b + 1);
-  const int32_t e0 = uniform_load(rp, r0);
-  const int32_t ne = uniform_load(rp, r1) - e0;
-  if (ne > kCap) {
-    double s[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) s[j] = 0.0;
-    for (int32_t i = e0 + t; i < e0 + ne; i += 256) {
-      const double a = static_cast<double>(val[i]);
-      const int64_t c = static_cast<int64_t>(col[i]) * k;
-#pragma unroll
-      for (int j = 0; j < KB; ++j) s[j] += a * X[c + (j < k ? j : k - 1)];
-    }
-#pragma unroll
-    for (int j = 0; j < KB; ++j)
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
-    if ((t & 63) == 0)
-#pragma unroll
-      for (int j = 0; j < KB; ++j) prod[(t >> 6) * KB + j] = s[j];
-    __syncthreads();
-    if (t < k) Y[static_cast<int64_t>(r0) * k + t] = (prod[t] + prod[KB + t]) + (prod[2 * KB + t] + prod[3 * KB + t]);
-    return;
-  }
-  if (ne > 0) {
-    int32_t c[kPer];
-    ValT v[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int32_t i = e0 + min(t + u * 256, ne - 1);
-      c[u] = stream_load(col + i);
-      v[u] = stream_load(val + i);
-    }
-    double xv[kPer][KB];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u)
-#pragma unroll
-      for (int j = 0; j < KB; ++j) xv[u][j] = X[static_cast<int64_t>(c[u]) * k + (j < k ? j : k - 1)];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u)
-      if (t + u * 256 < ne)
-#pragma unroll
-        for (int j = 0; j < KB; ++j) prod[(t + u * 256) * KB + j] = static_cast<double>(v[u]) * xv[u][j];
-  }
-  __syncthreads();
-  const int32_t pairs = (r1 - r0) * KB;
-  for (int32_t p = t; p < pairs; p += 256) {
-    const int32_t r = r0 + p / KB, j = p % KB;
-    if (j >= k) continue;
-    const int32_t a = rp[r] - e0, e = rp[r + 1] - e0;
-    double s = 0.0;
-    for (int32_t q = a; q < e; ++q) s += prod[q * KB + j];
-    Y[static_cast<int64_t>(r) * k + j] = s;
-  }
-}
-
-// Full-matrix CRS SpMM Y = A X (Algorithm "SpMV" for k columns; X, Y
-// row-major n x k, 2 <= k <= KC): a group of KC lanes per row, lane j owns
-// column j.  The group steps through its row four entries at a time; every
-// lane loads the same value and column (one address per group) and its own
-// X entry, so the k entries of an X row arrive as one contiguous segment.
-// Lanes j >= k compute on column k - 1 and store nothing.
-template <typename ValT, int KC>
-__global__ void __launch_bounds__(256) csr_spmm_kernel(int32_t n, int32_t k, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col,
-                                                       const ValT* __restrict__ val,
-                                                       const double* __restrict__ X, double* __restrict__ Y) {
-  constexpr int kU = 4;
-  const int64_t gid = static_cast<int64_t>(xcd_block()) * blockDim.x + threadIdx.x;
-  const int64_t row = gid / KC;
-  const int32_t j = static_cast<int32_t>(gid % KC);
-  if (row >= n) return;  // whole lane groups leave together
-  const int32_t jj = j < k ? j : k - 1;
-  const int32_t b = rp[row], e = rp[row + 1];
-  double s = 0.0;
-  for (int32_t i = b; i < e; i += kU) {
-    int32_t c[kU];
-    ValT v[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int32_t ii = i + u < e ? i + u : e - 1;
-      c[u] = col[ii];
-      v[u] = val[ii];
-    }
-    double xv[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) xv[u] = X[static_cast<int64_t>(c[u]) * k + jj];
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (i + u < e) s += static_cast<double>(v[u]) * xv[u];
-  }
-  if (j < k) Y[row * k + j] = s;
-}
-
-// SymmSpMV with device-wide float64 atomics for every update of y.
-template <int LPR>
-__global__ void __launch_bounds__(256) atomic_symm_kernel(int32_t n, const int32_t* __restrict__ rp,
-                                                          const int32_t* __restrict__ col,
-                                                          const double* __restrict__ val,
-                                                          const double* __restrict__ x, double* y) {
-  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t row = gid / LPR;
-  const int32_t l = static_cast<int32_t>(gid % LPR);
-  if (row >= n) return;
-  const double xr = x[row];
-  double s = 0.0;
-  const int32_t e = rp[row + 1];
-  for (int32_t i = rp[row] + l; i < e; i += LPR) {
-    const int32_t c = col[i];
-    const double v = val[i];
-    s += v * x[c];
-    if (c != row) unsafeAtomicAdd(&y[c], v * xr);
-  }
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-  if (l == 0) unsafeAtomicAdd(&y[row], s);
-}
-
-__global__ void __launch_bounds__(256) fill_zero_kernel(double* __restrict__ y, int64_t n) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = 0.0;
 }
 
 // Row-major n x k <-> column tiles: tile t holds columns [t kt, t kt + kc)
@@ -722,143 +464,6 @@ template hipError_t launch_race_batch<float>(const BatchMat<float>*, const Batch
 hipError_t launch_clear_words(uint32_t* p, int64_t words, hipStream_t st) {
   if (words == 0) return hipSuccess;
   hipLaunchKernelGGL(dev::batch_reset_kernel, fill_grid(words), dim3(256), 0, st, p, words);
-  return hipGetLastError();
-}
-
-template <typename ValT>
-hipError_t launch_csr_spmv(int32_t n, const int32_t* rp, const int32_t* col, const ValT* val, const double* x,
-                           double* y, int32_t lpr, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  const int64_t threads = static_cast<int64_t>(n) * lpr;
-  const dim3 grid(static_cast<uint32_t>((threads + 255) / 256));
-  switch (lpr) {
-#define CSR_L(L)                                                                                         \
-  case L:                                                                                                \
-    hipLaunchKernelGGL((dev::csr_spmv_kernel<L, ValT>), grid, dim3(256), 0, st, n, rp, col, val, x, y); \
-    break;
-    CSR_L(1) CSR_L(2) CSR_L(4) CSR_L(8) CSR_L(16) CSR_L(32) CSR_L(64)
-#undef CSR_L
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template hipError_t launch_csr_spmv<double>(int32_t, const int32_t*, const int32_t*, const double*, const double*,
-                                            double*, int32_t, hipStream_t);
-template hipError_t launch_csr_spmv<float>(int32_t, const int32_t*, const int32_t*, const float*, const double*,
-                                           double*, int32_t, hipStream_t);
-
-template <typename ValT>
-hipError_t launch_csr_block(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
-                            const ValT* val, const double* x, double* y, int32_t per, hipStream_t st) {
-  if (n_blocks == 0) return hipSuccess;
-  const dim3 grid(static_cast<uint32_t>((static_cast<int64_t>(n_blocks) + 7) / 8 * 8));
-  switch (per) {
-#define CSR_B(P)                                                                                         \
-  case P:                                                                                                \
-    hipLaunchKernelGGL((dev::csr_block_kernel<ValT, P>), grid, dim3(256), 0, st, blk, rp, col, val, x, y, n_blocks); \
-    break;
-    CSR_B(4) CSR_B(8) CSR_B(16)
-#undef CSR_B
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template hipError_t launch_csr_block<double>(int32_t, const int32_t*, const int32_t*, const int32_t*, const double*,
-                                             const double*, double*, int32_t, hipStream_t);
-template hipError_t launch_csr_block<float>(int32_t, const int32_t*, const int32_t*, const int32_t*, const float*,
-                                            const double*, double*, int32_t, hipStream_t);
-
-template <typename ValT>
-hipError_t launch_csr_block_batch(const BlockMat<ValT>* mats, const int32_t* blk_mat, int32_t n_blocks,
-                                  hipStream_t st) {
-  if (n_blocks == 0) return hipSuccess;
-  const dim3 grid(static_cast<uint32_t>((static_cast<int64_t>(n_blocks) + 7) / 8 * 8));
-  hipLaunchKernelGGL((dev::csr_block_batch_kernel<ValT, kExpandedPerThread>), grid, dim3(256), 0, st, mats, blk_mat,
-                     n_blocks);
-  return hipGetLastError();
-}
-
-template hipError_t launch_csr_block_batch<double>(const BlockMat<double>*, const int32_t*, int32_t, hipStream_t);
-template hipError_t launch_csr_block_batch<float>(const BlockMat<float>*, const int32_t*, int32_t, hipStream_t);
-
-template <typename ValT>
-hipError_t launch_csr_spmm(int32_t n, int32_t k, const int32_t* rp, const int32_t* col, const ValT* val,
-                           const double* X, double* Y, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (k < 2 || k > 16) return hipErrorInvalidValue;
-  const int32_t kc = k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-  const int64_t blocks = (static_cast<int64_t>(n) * kc + 255) / 256;
-  const dim3 grid(static_cast<uint32_t>((blocks + 7) / 8 * 8));
-  switch (kc) {
-#define CSR_M(C)                                                                                           \
-  case C:                                                                                                  \
-    hipLaunchKernelGGL((dev::csr_spmm_kernel<ValT, C>), grid, dim3(256), 0, st, n, k, rp, col, val, X, Y); \
-    break;
-    CSR_M(2) CSR_M(4) CSR_M(8) CSR_M(16)
-#undef CSR_M
-  }
-  return hipGetLastError();
-}
-
-template hipError_t launch_csr_spmm<double>(int32_t, int32_t, const int32_t*, const int32_t*, const double*,
-                                            const double*, double*, hipStream_t);
-template hipError_t launch_csr_spmm<float>(int32_t, int32_t, const int32_t*, const int32_t*, const float*,
-                                           const double*, double*, hipStream_t);
-
-template <typename ValT>
-hipError_t launch_csr_block_spmm(int32_t n_blocks, const int32_t* blk, const int32_t* rp, const int32_t* col,
-                                 const ValT* val, const double* X, double* Y, int32_t k, hipStream_t st) {
-  if (n_blocks == 0) return hipSuccess;
-  if (k < 2 || k > 4) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<uint32_t>((static_cast<int64_t>(n_blocks) + 7) / 8 * 8));
-  if (k == 2)
-    hipLaunchKernelGGL((dev::csr_block_spmm_kernel<ValT, 2>), grid, dim3(256), 0, st, blk, rp, col, val, X, Y, k,
-                       n_blocks);
-  else
-    hipLaunchKernelGGL((dev::csr_block_spmm_kernel<ValT, 4>), grid, dim3(256), 0, st, blk, rp, col, val, X, Y, k,
-                       n_blocks);
-  return hipGetLastError();
-}
-
-template hipError_t launch_csr_block_spmm<double>(int32_t, const int32_t*, const int32_t*, const int32_t*,
-                                                  const double*, const double*, double*, int32_t, hipStream_t);
-template hipError_t launch_csr_block_spmm<float>(int32_t, const int32_t*, const int32_t*, const int32_t*,
-                                                 const float*, const double*, double*, int32_t, hipStream_t);
-
-void csr_row_blocks(int32_t n, const int32_t* rp, int32_t per, std::vector<int32_t>& blk) {
-  const int64_t cap = 256 * static_cast<int64_t>(per);
-  blk.clear();
-  blk.push_back(0);
-  int32_t r = 0;
-  while (r < n) {
-    int32_t e = r + 1;  // a row longer than cap still gets a block of its own
-    while (e < n && e - r < kCsrBlockRows && rp[e + 1] - rp[r] <= cap) ++e;
-    blk.push_back(e);
-    r = e;
-  }
-}
-
-hipError_t launch_atomic_symm(int32_t n, const int32_t* rp, const int32_t* col, const double* val, const double* x,
-                              double* y, int32_t lpr, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::fill_zero_kernel, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, y,
-                     static_cast<int64_t>(n));
-  const int64_t threads = static_cast<int64_t>(n) * lpr;
-  const dim3 grid(static_cast<uint32_t>((threads + 255) / 256));
-  switch (lpr) {
-#define ATO_L(L)                                                                                      \
-  case L:                                                                                             \
-    hipLaunchKernelGGL(dev::atomic_symm_kernel<L>, grid, dim3(256), 0, st, n, rp, col, val, x, y); \
-    break;
-    ATO_L(1) ATO_L(2) ATO_L(4) ATO_L(8) ATO_L(16) ATO_L(32) ATO_L(64)
-#undef ATO_L
-    default:
-      return hipErrorInvalidValue;
-  }
   return hipGetLastError();
 }
 
