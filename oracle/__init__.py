@@ -17,6 +17,11 @@ Hardware-Efficient Symmetric Sparse Matrix-Vector Multiplication"):
 * ``perfmodel`` -- the roofline intensities of Section 3 (Eqs. SpMV and
   SymmSpMV intensity).
 * ``mlp``       -- float64 forward/backward of the small cost-model network.
+* ``gauss_seidel`` -- Gauss-Seidel sweeps over a row order (distance-1
+  schedules), and the order a schedule runs its rows in.
+* ``kaczmarz``  -- Kaczmarz sweeps (row projections) over a row order
+  (distance-2 schedules).
+* ``powers``    -- matrix powers and polynomials built from products.
 
 Only the tests, the smoke entry and the benchmark's CPU-baseline leg may
 import this package.  The product path never calls it.

@@ -9,7 +9,7 @@ def build(force=True):
     out = os.path.join(HERE, "liboracle.so")
     if not force and os.path.exists(out):
         return out
-    srcs = [os.path.join(HERE, f) for f in ("symmspmv.c", "gauss_seidel.c")]
+    srcs = [os.path.join(HERE, f) for f in ("symmspmv.c", "gauss_seidel.c", "kaczmarz.c")]
     tmp = out + ".tmp"
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, *srcs], check=True)
     os.replace(tmp, out)

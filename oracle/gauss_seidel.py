@@ -1,8 +1,8 @@
 """Gauss-Seidel sweeps -- test infrastructure only ("parity" reference for the
 GPU sweep kernel; never called by the product path).
 
-The paper names Gauss-Seidel and Kaczmarz as the prime users of
-distance-1 colorings (Section 1 and Section 4.2): a sweep updates row i
+The paper names Gauss-Seidel as a prime user of colorings (Section 1 and
+Section 4.2; its row dependencies need distance 1): a sweep updates row i
 with the newest values of all other unknowns,
 
     x_i <- (b_i - sum_{j != i} a_ij x_j) / a_ii,
