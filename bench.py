@@ -613,6 +613,68 @@ def run_gs(args, torch):
     s.close()
 
 
+def run_kacz(args, torch):
+    """Symmetric Kaczmarz sweeps (forward then backward, omega 1) over a
+    distance-2 RACE schedule of the workload's matrix: time per symmetric
+    sweep, checked against the serial C oracle over the same row order.
+    One JSON line.  A sweep direction reads every entry of the full matrix
+    (value + column, diagonal included), b and x, and writes x: at least
+    12 nnz_full + 4 (N + 1) + 24 N bytes in CRS (squared row norms
+    recomputed; the library keeps them, 8 N more)."""
+    import numpy as np
+
+    import paper_1907_06487_amd as R
+    from oracle import gauss_seidel as G
+    from oracle import kaczmarz as K
+    m, desc = workload(args.workload)
+    t0 = time.perf_counter()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, n_workers=args.kacz_workers, max_stages=args.kacz_stages,
+                   root=args.root, level_order=args.level_order, kaczmarz=True)
+    s.set_gs_quad(args.kacz_quad)
+    st = s.stats()
+    log(f"Kaczmarz schedule built in {time.perf_counter() - t0:.2f}s: leaves {st['n_leaves']}, phases "
+        f"{st['n_phases_used']}, largest window {st['kacz_max_window']}")
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    b = rng.uniform(-1, 1, m.n)
+    bd = torch.as_tensor(b, device=dev)
+    bp = torch.empty_like(bd)
+    s.permute(bd, bp, True)
+    xp = torch.zeros_like(bp)
+    s.kaczmarz(bp, xp)
+    x = torch.empty_like(xp)
+    s.permute(xp, x, False)
+    torch.cuda.synchronize()
+    tr = s.tree()
+    node, phase = s.leaves()
+    order = G.race_order(s.perm(), np.asarray(tr["lo"])[node], np.asarray(tr["hi"])[node], phase)
+    ref = K.symmetric_sweep_c(m.n, m.row_ptr, m.col, m.val, b, np.zeros(m.n), order)
+    err = float(np.max(np.abs(x.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    ms = time_ring(lambda x_, y_: s.kaczmarz(bp, xp), [0], [0], args.steps, args.warmup, torch)
+    nnz_full = st["nnz_full"]
+    flops = 2 * 4 * nnz_full  # both directions: a multiply-add per entry for the dot product and for the update
+    bytes_min = 2 * (12 * nnz_full + 4 * (m.n + 1) + 24 * m.n)
+    achieved = bytes_min / (ms * 1e-3) / 1e9
+    log(f"Kaczmarz {args.workload}: {ms * 1e3:.1f} us per symmetric sweep, {flops / (ms * 1e-3) / 1e9:.1f} GFLOP/s, "
+        f"{achieved:.1f} GB/s algorithmic, error vs oracle {err:.2e}")
+    out = {
+        "metric": "symmetric Kaczmarz sweeps over a distance-2 RACE schedule, GFLOP/s",
+        "value": round(flops / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": m.n, "nnz_full": nnz_full,
+                   "n_workers": args.kacz_workers, "max_stages": args.kacz_stages, "omega": 1.0,
+                   "quad_min_leaves": args.kacz_quad,
+                   "leaves": st["n_leaves"], "phases": st["n_phases_used"],
+                   "max_window": st["kacz_max_window"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_step": bytes_min},
+        "error": {"norm": err}, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def run_mpk(args, torch):
     """Matrix powers y_p = A^p x, p = 1..P, of the workload's matrix scaled
     by its largest absolute row sum: one race_symm_mpk launch against P
@@ -733,6 +795,13 @@ def main():
                          "against 718 us with phase launches)")
     ap.add_argument("--gs-workers", type=int, default=65536,
                     help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 65536 measured fastest)")
+    ap.add_argument("--kacz", action="store_true",
+                    help="symmetric Kaczmarz sweeps over a distance-2 schedule of the workload instead")
+    ap.add_argument("--kacz-workers", type=int, default=4096, help="--kacz: n_workers of the schedule")
+    ap.add_argument("--kacz-stages", type=int, default=3, help="--kacz: recursion stages of the schedule")
+    ap.add_argument("--kacz-quad", type=int, default=-1,
+                    help="--kacz: phases of at least this many leaves run four per wavefront (-1 library default, "
+                         "-2 never, 0 always)")
     ap.add_argument("--order", default="default", choices=["default", "critical"],
                     help="dataflow ticket order: the layout's execution order, or the critical path of unit costs "
                          "measured by traced products on this device (part of the schedule's preparation)")
@@ -779,6 +848,9 @@ def main():
         return
     if args.gs:
         run_gs(args, torch)
+        return
+    if args.kacz:
+        run_kacz(args, torch)
         return
     if args.mpk:
         run_mpk(args, torch)

@@ -99,6 +99,9 @@ typedef struct {
                               CRS product always (tests).  On such schedules race_symm_spmm with k > 1 runs a CRS
                               SpMM of the expanded matrix (row blocks, the matrix read once for all k columns) and
                               batches run them outside the persistent launch; traced products always run the RACE kernels */
+  int32_t kaczmarz;        /* 1: also build the layout of Kaczmarz sweeps (race_symm_kacz; dist_k >= 2, value_type 0 or
+                              1, values given): every leaf's window of the full rows, at most 16,384 entries
+                              (RACE_EUNSUPPORTED otherwise: raise n_workers), checked disjoint within each phase */
 } race_params;
 
 /* Summary of a built schedule (Section 5 terms where they exist). */
@@ -138,6 +141,7 @@ typedef struct {
                                 (race_params.low_locality) */
   int32_t expanded_per_thread; /* entries per thread of the expanded CRS product's row blocks (0 when not expanded) */
   int32_t n_zero_tasks;      /* clearing tasks of a dataflow product: its first tickets, before the units */
+  int32_t kacz_max_window;   /* largest leaf window of the Kaczmarz layout (0 without one) */
 } race_stats;
 
 /* Fill *p with defaults: dist_k 2, n_workers 1024, max_stages 4, balance by
@@ -391,6 +395,25 @@ int race_schedule_set_gs_quad(race_schedule_t s, int32_t min_leaves);
  * (RACE_EUNSUPPORTED at build time: raise n_workers).  RACE_EUNSUPPORTED for
  * a schedule with dist_k != 1. */
 int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t direction, void* stream);
+
+/* Kaczmarz sweep on A x = b over a distance-2 schedule built with
+ * race_params.kaczmarz = 1 (the paper names the Kaczmarz method beside
+ * Gauss-Seidel among the solvers parallelised by colorings, Sections 1 and
+ * 4.2): every row i projects x onto its equation,
+ *     x <- x + omega (b_i - a_i . x) / |a_i|^2  a_i,
+ * a_i the full row of the symmetric matrix (diagonal included; a row with no
+ * value is skipped), in the schedule's order: phase by phase, leaves of one
+ * phase at the same time (their rows are at distance 3 or more, so they
+ * share no column and the result equals running them one after another),
+ * the rows of a leaf in ascending permuted order.  direction 0: forward;
+ * 1: backward (phases and rows reversed); 2: symmetric (forward, then
+ * backward).  omega in (0, 2) (1: plain projections).  b (read) and x
+ * (updated in place): device float64 arrays of n in permuted order.  One
+ * launch per non-empty phase and direction on `stream`, no allocation (it
+ * can be captured into a graph).  RACE_EUNSUPPORTED on a distance-1
+ * schedule, RACE_ESTATE on one built without race_params.kaczmarz, RACE_EINVAL
+ * for direction or omega out of range. */
+int race_symm_kacz(race_schedule_t s, const double* b, double* x, int32_t direction, double omega, void* stream);
 
 /* Reorder device float64 row-major n x k arrays between input order and the
  * permuted order: to_permuted != 0: out[i] = in[new2old[i]]; else

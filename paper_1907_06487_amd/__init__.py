@@ -18,7 +18,7 @@ from ._lib import (RaceError, race_atomic_create, race_batch_bind, race_batch_ch
                    race_schedule_read_deps,
                    race_schedule_leaves, race_schedule_perm, race_schedule_stats, race_schedule_tree,
                    race_schedule_units, race_schedule_upload, race_schedule_zero_list, race_symm_spmm, race_symm_spmm_traced, race_symm_spmv,
-                   race_symm_gs, race_symm_spmv_atomic, race_symm_spmv_noalloc, race_stream_copy, race_stream_read,
+                   race_symm_gs, race_symm_kacz, race_symm_spmv_atomic, race_symm_spmv_noalloc, race_stream_copy, race_stream_read,
                    race_vendor_create, race_vendor_destroy, race_vendor_spmv)
 
 BALANCE = {"nnz": 0, "rows": 1, "model": 2}
@@ -27,7 +27,7 @@ BALANCE = {"nnz": 0, "rows": 1, "model": 2}
 def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, value_type="f64", window_max=3840,
                 block_threads=256, eps=(0.8, 0.8, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5), exec_mode="flow",
                 shared_atomics=True, cost_model=None, rhs_tile=0, root="first", level_order="input", dist_k=2,
-                low_locality="race"):
+                low_locality="race", kaczmarz=False):
     """race_params from keywords.  balance="model" needs cost_model: the
     network's MLP_PARAMS float32 weights (kept alive on the returned struct).
     root: "first" (stage-0 islands start at their first vertex in the input
@@ -35,7 +35,8 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     "input" or "cm" (Cuthill-McKee discovery order inside stage-0 levels).
     low_locality: "race" (always the RACE kernels), "auto" (single-vector
     products switch to a full-matrix CRS product of the permuted matrix when
-    the layout predicts no window reuse) or "expanded" (always that)."""
+    the layout predicts no window reuse) or "expanded" (always that).
+    kaczmarz: also build the Kaczmarz sweep layout (distance >= 2)."""
     p = race_params_default()
     p.dist_k = int(dist_k)
     p.n_workers = int(n_workers)
@@ -51,6 +52,7 @@ def make_params(n_workers=1024, max_stages=4, balance="nnz", global_lb=False, va
     p.root_mode = {"first": 0, "peripheral": 1}[root]
     p.level_order = {"input": 0, "cm": 1}[level_order]
     p.low_locality = {"race": 0, "auto": 1, "expanded": 2}[low_locality]
+    p.kaczmarz = int(bool(kaczmarz))
     if cost_model is not None:
         import ctypes
 
@@ -163,6 +165,11 @@ class Schedule:
     def gauss_seidel(self, b, x, direction="symmetric", stream=None):
         """Gauss-Seidel sweep(s) on A x = b in place (distance-1 schedules)."""
         race_symm_gs(self.handle, b, x, direction, stream)
+
+    def kaczmarz(self, b, x, direction="symmetric", omega=1.0, stream=None):
+        """Kaczmarz sweep(s) on A x = b in place (schedules built with
+        kaczmarz=True); omega in (0, 2)."""
+        race_symm_kacz(self.handle, b, x, direction, omega, stream)
 
     def mpk(self, x, Y, stream=None):
         """Y[p] = A^(p+1) x for p < Y.shape[0] (Y: powers x n) in one launch."""

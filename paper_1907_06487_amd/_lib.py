@@ -33,7 +33,7 @@ EXPORTS = [
     "race_stream_copy", "race_symm_gs", "race_schedule_set_ticket_order", "race_schedule_order_tickets",
     "race_schedule_ticket_order", "race_symm_mpk", "race_symm_poly", "race_schedule_read_deps",
     "race_schedule_set_mpk_order", "race_schedule_mpk_order", "race_schedule_set_gs_quad", "race_schedule_set_gs_exec",
-    "race_schedule_gs_flow_plan",
+    "race_schedule_gs_flow_plan", "race_symm_kacz",
 ]
 
 MLP_INPUTS = 12
@@ -55,6 +55,7 @@ class race_params(ctypes.Structure):
         ("cost_model", ctypes.POINTER(ctypes.c_float)), ("cost_model_len", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("shared_atomics", ctypes.c_int32), ("rhs_tile", ctypes.c_int32),
         ("root_mode", ctypes.c_int32), ("level_order", ctypes.c_int32), ("low_locality", ctypes.c_int32),
+        ("kaczmarz", ctypes.c_int32),
     ]
 
 
@@ -70,7 +71,7 @@ class race_stats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("n_deps", ctypes.c_int64), ("flow_grid", ctypes.c_int32),
         ("exec_mode", ctypes.c_int32), ("wall_clock_hz", ctypes.c_int64), ("shared_touches", ctypes.c_int64),
         ("n_zeroed", ctypes.c_int64), ("product_path", ctypes.c_int32), ("expanded_per_thread", ctypes.c_int32),
-        ("n_zero_tasks", ctypes.c_int32),
+        ("n_zero_tasks", ctypes.c_int32), ("kacz_max_window", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -130,6 +131,7 @@ def lib():
                                ctypes.c_int),
         "race_symm_spmv_noalloc": ([_P, _P, _P, _P], ctypes.c_int),
         "race_symm_gs": ([_P, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+        "race_symm_kacz": ([_P, _P, _P, ctypes.c_int32, ctypes.c_double, _P], ctypes.c_int),
         "race_vendor_create": ([ctypes.c_int32, _I32P, _I32P, _DP, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(_P)], ctypes.c_int),
         "race_vendor_spmv": ([_P, _P, _P, _P], ctypes.c_int),
@@ -422,6 +424,11 @@ GS_DIRECTIONS = {"forward": 0, "backward": 1, "symmetric": 2}
 def race_symm_gs(h, b, x, direction="symmetric", stream=None):
     check(lib().race_symm_gs(h, _dev_ptr(b), _dev_ptr(x), GS_DIRECTIONS.get(direction, direction),
                              _stream_ptr(stream)))
+
+
+def race_symm_kacz(h, b, x, direction="symmetric", omega=1.0, stream=None):
+    check(lib().race_symm_kacz(h, _dev_ptr(b), _dev_ptr(x), GS_DIRECTIONS.get(direction, direction), float(omega),
+                               _stream_ptr(stream)))
 
 
 def race_symm_spmv_noalloc(h, x, y, stream=None):

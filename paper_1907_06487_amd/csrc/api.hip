@@ -120,6 +120,13 @@ struct race_schedule {
   DevBuf<int32_t> gsf_item[3], gsf_back[3], gsf_leaf0[3], gsf_count[3], gsf_dptr[3], gsf_didx[3];
   DevBuf<uint32_t> gsf_flags;
   uint32_t gs_epoch = 0;
+  // distance-2 schedules built with race_params.kaczmarz: the Kaczmarz
+  // sweep layout and its device copies
+  bool kz = false;
+  race::GsLayout KG;
+  DevBuf<int32_t> kz_leaf_lo, kz_leaf_hi, kz_halo_ptr, kz_halo, kz_row_ptr;
+  DevBuf<uint16_t> kz_slot;
+  DevBuf<double> kz_val, kz_diag, kz_nrm;
   DevBuf<uint32_t> halo, row_flags, chunk_off;
   DevBuf<int32_t> zero_idx;
   DevBuf<uint16_t> lane_slot, sell_slot;
@@ -161,6 +168,8 @@ struct race_schedule {
   void free_device() {
     release(gs_leaf_lo); release(gs_leaf_hi); release(gs_halo_ptr); release(gs_halo); release(gs_row_ptr);
     release(gs_slot); release(gs_val); release(gs_diag);
+    release(kz_leaf_lo); release(kz_leaf_hi); release(kz_halo_ptr); release(kz_halo); release(kz_row_ptr);
+    release(kz_slot); release(kz_val); release(kz_diag); release(kz_nrm);
     for (int d = 0; d < 3; ++d) {
       release(gsf_item[d]); release(gsf_back[d]); release(gsf_leaf0[d]); release(gsf_count[d]);
       release(gsf_dptr[d]); release(gsf_didx[d]);
@@ -245,6 +254,7 @@ int race_params_default(race_params* p) {
   p->root_mode = 0;
   p->level_order = 0;
   p->low_locality = 0;
+  p->kaczmarz = 0;
   return RACE_OK;
 }
 
@@ -274,6 +284,9 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
   if (prm.root_mode < 0 || prm.root_mode > 1) return fail(RACE_EINVAL, "root_mode must be 0 or 1");
   if (prm.level_order < 0 || prm.level_order > 1) return fail(RACE_EINVAL, "level_order must be 0 or 1");
   if (prm.low_locality < 0 || prm.low_locality > 2) return fail(RACE_EINVAL, "low_locality must be 0, 1 or 2");
+  if (prm.kaczmarz < 0 || prm.kaczmarz > 1) return fail(RACE_EINVAL, "kaczmarz must be 0 or 1");
+  if (prm.kaczmarz && (prm.dist_k < 2 || prm.value_type > 1))
+    return fail(RACE_EUNSUPPORTED, "Kaczmarz sweeps need a distance-2 (or wider) schedule of real values");
   if (prm.window_max == 0) prm.window_max = 3840;
   if (prm.window_max < 2 || prm.window_max > 8000) return fail(RACE_EINVAL, "window_max must be in 2..8000");
   if (prm.block_threads == 0) prm.block_threads = 256;
@@ -339,6 +352,17 @@ int race_build_schedule(int32_t n, const int32_t* row_ptr, const int32_t* col, c
     if (!err.empty()) {
       delete s;
       return fail(code, err);
+    }
+    if (prm.kaczmarz && val) {
+      // rows of one distance-2 phase share no column, so their Kaczmarz
+      // projections commute
+      err = race::build_gs_layout(n, row_ptr, col, val, s->tree, s->KG, &code, true);
+      if (!err.empty()) {
+        delete s;
+        return fail(code, err);
+      }
+      s->kz = true;
+      s->stats.kacz_max_window = s->KG.max_window;
     }
     s->has_values = val != nullptr;
     s->params.cost_model = nullptr;  // borrowed for the build only
@@ -488,7 +512,12 @@ int race_schedule_upload(race_schedule_t s) {
     UP(gs_row_ptr, G.row_ptr)
     UP(gs_slot, G.slot)
     UP(gs_val, G.val)
-    UP(gs_diag, G.diag)
+    {
+      // the sweep multiplies by the reciprocal diagonal
+      std::vector<double> inv(G.diag.size());
+      for (size_t i = 0; i < inv.size(); ++i) inv[i] = 1.0 / G.diag[i];
+      UP(gs_diag, inv)
+    }
     UP(new2old, s->tree.perm)
     e = hipDeviceGetAttribute(&s->n_cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) {
@@ -499,6 +528,22 @@ int race_schedule_upload(race_schedule_t s) {
     s->uploaded = true;
     s->stats.device_bytes = total;
     return RACE_OK;
+  }
+  if (s->kz) {
+    const race::GsLayout& K = s->KG;
+    UP(kz_leaf_lo, K.leaf_lo)
+    UP(kz_leaf_hi, K.leaf_hi)
+    UP(kz_halo_ptr, K.halo_ptr)
+    UP(kz_halo, K.halo)
+    UP(kz_row_ptr, K.row_ptr)
+    UP(kz_slot, K.slot)
+    UP(kz_val, K.val)
+    UP(kz_diag, K.diag)
+    {
+      std::vector<double> inv(K.nrm.size());
+      for (size_t i = 0; i < inv.size(); ++i) inv[i] = K.nrm[i] > 0.0 ? 1.0 / K.nrm[i] : 0.0;
+      UP(kz_nrm, inv)
+    }
   }
   UP(leaf_units, L.leaf_units)
   {
@@ -1517,7 +1562,8 @@ int race_schedule_gs_flow_plan(race_schedule_t s, int32_t direction, int32_t* n_
 
 int race_schedule_set_gs_quad(race_schedule_t s, int32_t min_leaves) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
-  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (!s->gs && !s->kz)
+    return fail(RACE_EUNSUPPORTED, "sweeps need a distance-1 schedule or one built with race_params.kaczmarz");
   if (min_leaves < -2) return fail(RACE_EINVAL, "min_leaves must be -2 (never), -1 (default) or >= 0");
   s->gs_quad_min = min_leaves;
   return RACE_OK;
@@ -1552,6 +1598,40 @@ int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t directio
     for (int32_t ph = np - 1; ph >= 0; --ph) {
       hipError_t e = phase(ph, true);
       if (e != hipSuccess) return hip_fail(e, "Gauss-Seidel phase launch");
+    }
+  return RACE_OK;
+}
+
+int race_symm_kacz(race_schedule_t s, const double* b, double* x, int32_t direction, double omega, void* stream) {
+  if (!s) return fail(RACE_EINVAL, "schedule is NULL");
+  if (s->gs) return fail(RACE_EUNSUPPORTED, "Kaczmarz sweeps need a distance-2 schedule (dist_k >= 2)");
+  if (!s->kz) return fail(RACE_ESTATE, "the schedule was built without race_params.kaczmarz = 1");
+  if (!s->uploaded) return fail(RACE_ESTATE, "race_schedule_upload has not been called");
+  if (direction < 0 || direction > 2) return fail(RACE_EINVAL, "direction must be 0 (forward), 1 (backward) or 2 (both)");
+  if (!(omega > 0.0 && omega < 2.0)) return fail(RACE_EINVAL, "omega must be in (0, 2)");
+  if (s->tree.n == 0) return RACE_OK;
+  if (!b || !x) return fail(RACE_EINVAL, "b or x is NULL");
+  const race::GsLayout& K = s->KG;
+  const race::GsArgs a{s->kz_leaf_lo.p, s->kz_leaf_hi.p, s->kz_halo_ptr.p, s->kz_halo.p, s->kz_row_ptr.p,
+                       s->kz_slot.p,    s->kz_val.p,     s->kz_diag.p,     s->kz_nrm.p};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t np = s->tree.n_phases;
+  // four leaves per wavefront once a phase has more leaves than the CUs
+  // hold wavefronts (32 each)
+  const int32_t quad_min = s->gs_quad_min >= 0 ? s->gs_quad_min : (s->gs_quad_min == -1 ? 32 * s->n_cus : INT32_MAX);
+  auto phase = [&](int32_t ph, bool backward) {
+    const int32_t l0 = K.phase_leaf_ptr[ph], l1 = K.phase_leaf_ptr[ph + 1];
+    return race::launch_kacz_phase(a, l0, l1 - l0, K.phase_max_window[ph], backward, omega, quad_min, b, x, st);
+  };
+  if (direction != 1)
+    for (int32_t ph = 0; ph < np; ++ph) {
+      hipError_t e = phase(ph, false);
+      if (e != hipSuccess) return hip_fail(e, "Kaczmarz phase launch");
+    }
+  if (direction != 0)
+    for (int32_t ph = np - 1; ph >= 0; --ph) {
+      hipError_t e = phase(ph, true);
+      if (e != hipSuccess) return hip_fail(e, "Kaczmarz phase launch");
     }
   return RACE_OK;
 }

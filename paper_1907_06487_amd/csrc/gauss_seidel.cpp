@@ -10,7 +10,7 @@
 namespace race {
 
 std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                            const Tree& tree, GsLayout& L, int* code) {
+                            const Tree& tree, GsLayout& L, int* code, bool kaczmarz) {
   L = GsLayout();
   L.n = n;
   *code = RACE_OK;
@@ -32,7 +32,7 @@ std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* co
         ++cnt[inv[col[k]] + 1];
       }
     }
-  for (int32_t i = 0; i < n; ++i)
+  for (int32_t i = 0; i < n && !kaczmarz; ++i)
     if (!has_diag[i] || L.diag[i] == 0.0) {
       *code = RACE_EINVAL;
       return "Gauss-Seidel needs a nonzero stored diagonal in every row (row " + std::to_string(tree.perm[i]) +
@@ -113,6 +113,42 @@ std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* co
   }
   for (int32_t p = 0; p < tree.n_phases; ++p) L.phase_leaf_ptr[p + 1] += L.phase_leaf_ptr[p];
   L.halo_total = static_cast<int64_t>(L.halo.size());
+  if (kaczmarz) {
+    L.nrm.assign(static_cast<size_t>(n), 0.0);
+    for (int32_t i = 0; i < n; ++i) {
+      double q = 0.0;
+      bool diag_done = !has_diag[i];
+      for (int64_t k = cnt[i]; k < cnt[i + 1]; ++k) {
+        if (!diag_done && pcol[k] > i) {
+          q += L.diag[i] * L.diag[i];
+          diag_done = true;
+        }
+        q += L.val[k] * L.val[k];
+      }
+      if (!diag_done) q += L.diag[i] * L.diag[i];
+      L.nrm[i] = q;
+    }
+    // windows of one phase must not overlap (leaves are sorted by phase)
+    std::vector<int32_t> owner(static_cast<size_t>(n), -1);
+    for (int32_t p = 0; p < tree.n_phases; ++p) {
+      const int32_t l0 = L.phase_leaf_ptr[p], l1 = L.phase_leaf_ptr[p + 1];
+      auto claim = [&](int32_t r, int32_t t) {
+        if (owner[r] >= l0 && owner[r] != t) return false;
+        owner[r] = t;
+        return true;
+      };
+      for (int32_t t = l0; t < l1; ++t) {
+        bool ok = true;
+        for (int32_t r = L.leaf_lo[t]; r < L.leaf_hi[t] && ok; ++r) ok = claim(r, t);
+        for (int32_t h = L.halo_ptr[t]; h < L.halo_ptr[t + 1] && ok; ++h) ok = claim(L.halo[h], t);
+        if (!ok) {
+          *code = RACE_EINTERNAL;
+          return "two leaves of phase " + std::to_string(p) +
+                 " share a row of their windows: the schedule is not distance-2 independent";
+        }
+      }
+    }
+  }
   return "";
 }
 

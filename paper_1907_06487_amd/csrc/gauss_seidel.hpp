@@ -31,7 +31,8 @@ struct GsLayout {
   std::vector<int32_t> row_ptr;           // n + 1: off-diagonal entries of the full permuted rows
   std::vector<uint16_t> slot;             // window slot of each entry (columns ascending within a row)
   std::vector<double> val;
-  std::vector<double> diag;               // n
+  std::vector<double> diag;               // n (0 where none is stored: Kaczmarz layouts only)
+  std::vector<double> nrm;                // Kaczmarz layouts: squared norm of every full row, diagonal included
   int32_t max_window = 0;
   int32_t max_row = 0;                    // longest row (off-diagonals)
   int64_t halo_total = 0;
@@ -41,8 +42,16 @@ struct GsLayout {
 // *code receives RACE_EINVAL (a zero or missing diagonal) or
 // RACE_EUNSUPPORTED (a leaf window above kGsMaxWindow, or more than 2^31
 // entries).
+//
+// kaczmarz: the layout of Kaczmarz sweeps over a distance-2 schedule.  A
+// Kaczmarz row reads and writes x at every column it holds, so a leaf's
+// whole window (own rows and halo) is written back, a missing or zero
+// diagonal is allowed, every row's squared norm is kept (summed in
+// ascending column order), and the build checks that the windows of the
+// leaves of one phase are disjoint (the rows of a distance-2 phase are at
+// distance 3 or more; *code RACE_EINTERNAL otherwise).
 std::string build_gs_layout(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                            const Tree& tree, GsLayout& out, int* code);
+                            const Tree& tree, GsLayout& out, int* code, bool kaczmarz = false);
 
 // Dataflow plan of a sweep in one persistent launch.  Items are up to
 // kGsFlowLeaves consecutive leaves of one phase; tickets are the items of

@@ -2,7 +2,9 @@
 // phase, one wavefront per leaf or (phases of more leaves than the CUs can
 // hold wavefronts, windows up to kGsQuadMaxWindow entries) four leaves per
 // wavefront (leaves of one phase share no edge, so they run at the same
-// time), the rows of a leaf in order.
+// time), the rows of a leaf in order; or one dataflow launch per sweep.
+// The Kaczmarz sweep over a distance-2 schedule runs the same way, one leaf
+// per wavefront.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -73,6 +75,57 @@ __device__ __forceinline__ void gs_load_meta(const GsArgs& a, const double* __re
   }
 }
 
+// Stages a leaf's window in LDS: x of its own rows lo .. lo + R - 1 into
+// slots 0 .. R - 1, x of its halo rows (halo[0 .. H - 1]) into slots R ..
+// R + H - 1; kLanes lanes (lane j), kStage loads per lane in flight before
+// their LDS writes (one HBM round trip per kLanes * kStage entries, two for
+// the halo: indices, then values).  kCoherent: agent-scope loads (x is
+// updated by other workgroups of the same launch).
+template <int kLanes, bool kCoherent>
+__device__ __forceinline__ void stage_window(const double* __restrict__ x, const int32_t* __restrict__ halo,
+                                             int32_t lo, int32_t R, int32_t H, int32_t j, double* xw) {
+  constexpr int kStage = 8;
+  auto load = [](const double* p) {
+    if constexpr (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  };
+  for (int32_t s0 = 0; s0 < R; s0 += kLanes * kStage) {
+    double v[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int32_t s = s0 + u * kLanes + j;
+      v[u] = s < R ? load(x + lo + s) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int32_t s = s0 + u * kLanes + j;
+      if (s < R) xw[s] = v[u];
+    }
+  }
+  for (int32_t s0 = 0; s0 < H; s0 += kLanes * kStage) {
+    int32_t r[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int32_t s = s0 + u * kLanes + j;
+      r[u] = s < H ? halo[s] : -1;
+    }
+    double v[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) v[u] = r[u] >= 0 ? load(x + r[u]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int32_t s = s0 + u * kLanes + j;
+      if (s < H) xw[R + s] = v[u];
+    }
+  }
+}
+
+// Between two rows of a sweep inside a one-wavefront workgroup: the LDS
+// runs a wavefront's instructions in the order they issue, so the next
+// row's reads see this row's writes without a wait; the signal fence keeps
+// the compiler from moving LDS accesses across the row boundary.
+__device__ __forceinline__ void lds_row_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
 __device__ __forceinline__ int32_t lane_value(int32_t v, int32_t l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ double lane_value(double v, int32_t l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
@@ -112,8 +165,7 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
   const int32_t lo = gs_uniform(a.leaf_lo, leaf), hi = gs_uniform(a.leaf_hi, leaf);
   const int32_t h0 = gs_uniform(a.halo_ptr, leaf), h1 = gs_uniform(a.halo_ptr, leaf + 1);
   const int32_t R = hi - lo, H = h1 - h0;
-  for (int32_t s = lane; s < R; s += kGsLanes) xw[s] = x[lo + s];
-  for (int32_t s = lane; s < H; s += kGsLanes) xw[R + s] = x[a.halo[h0 + s]];
+  stage_window<kGsLanes, false>(x, a.halo + h0, lo, R, H, lane, xw);
   GsMeta cur, next;
   gs_load_meta<kBackward>(a, bvec, lo, hi, 0, lane, cur);
   gs_load_meta<kBackward>(a, bvec, lo, hi, kGsLanes, lane, next);
@@ -137,9 +189,9 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
         const int32_t tn = t + kGsAhead;
         // kGsAhead divides 64, so row tn is in the current or the next chunk
         if (tn < R) gs_load_row(a, (tn & (kGsLanes - 1)) >= l ? cur : next, tn & (kGsLanes - 1), lane, ring[p]);
-        const double xi = (bi - wave_sum(s)) / di;
+        const double xi = (bi - wave_sum(s)) * di;
         if (lane == 0) xw[i - lo] = xi;
-        __syncthreads();
+        lds_row_order();
         if (l == kGsLanes - 1) {
           // the chunk of rows t - 63 .. t is done: shift, fetch the one after next
           cur = next;
@@ -149,6 +201,99 @@ __global__ void __launch_bounds__(kGsLanes) gs_leaf_kernel(GsArgs a, int32_t lea
     }
   }
   for (int32_t s = lane; s < R; s += kGsLanes) x[lo + s] = xw[s];
+}
+
+// Kaczmarz sweep of one leaf (a distance-2 phase: the windows of its leaves
+// are disjoint, so they run at the same time): stage the window in LDS,
+// then for every row in order (backward: last row first)
+//   c = omega (b_i - a_i . x) / |a_i|^2   (0 for a row with no value; the
+//       layout holds the reciprocal squared norms),
+//   x_j += c a_ij for every stored column j of the full row, x_i += c a_ii,
+// and store the whole window back.  The dot product is summed across the
+// lanes (one off-diagonal entry each, 64 at a time) plus the diagonal term;
+// each lane then updates the slot of its own entry (the columns of a row
+// are distinct, so no two lanes write one slot).  The entries of the next
+// kGsAhead rows are in flight while a row runs, as in the Gauss-Seidel
+// kernel.
+struct KzMeta {
+  int32_t e0 = 0, e1 = 0;
+  double b = 0.0, d = 0.0, q = 0.0;
+};
+
+template <bool kBackward>
+__device__ __forceinline__ void kz_load_meta(const GsArgs& a, const double* __restrict__ bvec, int32_t lo, int32_t hi,
+                                             int32_t t0, int32_t lane, KzMeta& m) {
+  const int32_t t = t0 + lane;
+  if (t < hi - lo) {
+    const int32_t i = kBackward ? hi - 1 - t : lo + t;
+    m.e0 = a.row_ptr[i];
+    m.e1 = a.row_ptr[i + 1];
+    m.b = bvec[i];
+    m.d = a.diag[i];
+    m.q = a.nrm[i];
+  }
+}
+
+__device__ __forceinline__ void kz_load_row(const GsArgs& a, const KzMeta& m, int32_t l, int32_t lane, GsRow& r) {
+  const int32_t e = lane_value(m.e0, l) + lane;
+  r.v = 0.0;
+  r.sl = 0u;
+  if (e < lane_value(m.e1, l)) {
+    r.v = a.val[e];
+    r.sl = a.slot[e];
+  }
+}
+
+template <bool kBackward>
+__global__ void __launch_bounds__(kGsLanes) kacz_leaf_kernel(GsArgs a, int32_t leaf0, double omega,
+                                                            const double* __restrict__ bvec, double* __restrict__ x) {
+  extern __shared__ double xw[];
+  const int32_t leaf = leaf0 + static_cast<int32_t>(blockIdx.x);
+  const int32_t lane = static_cast<int32_t>(threadIdx.x);
+  const int32_t lo = gs_uniform(a.leaf_lo, leaf), hi = gs_uniform(a.leaf_hi, leaf);
+  const int32_t h0 = gs_uniform(a.halo_ptr, leaf), h1 = gs_uniform(a.halo_ptr, leaf + 1);
+  const int32_t R = hi - lo, H = h1 - h0;
+  stage_window<kGsLanes, false>(x, a.halo + h0, lo, R, H, lane, xw);
+  KzMeta cur, next;
+  kz_load_meta<kBackward>(a, bvec, lo, hi, 0, lane, cur);
+  kz_load_meta<kBackward>(a, bvec, lo, hi, kGsLanes, lane, next);
+  GsRow ring[kGsAhead];
+#pragma unroll
+  for (int p = 0; p < kGsAhead; ++p)
+    if (p < R) kz_load_row(a, cur, p, lane, ring[p]);
+  __syncthreads();
+  for (int32_t t0 = 0; t0 < R; t0 += kGsAhead) {
+#pragma unroll
+    for (int p = 0; p < kGsAhead; ++p) {
+      const int32_t t = t0 + p;
+      if (t < R) {
+        const int32_t i = kBackward ? hi - 1 - t : lo + t;
+        const int32_t l = t & (kGsLanes - 1);
+        const int32_t e0 = lane_value(cur.e0, l), e1 = lane_value(cur.e1, l);
+        const GsRow row = ring[p];
+        const double bi = lane_value(cur.b, l), di = lane_value(cur.d, l), qi = lane_value(cur.q, l);
+        // the diagonal term rides in lane 0 of the sum
+        const double xd = xw[i - lo];
+        double s = row.v * xw[row.sl] + (lane == 0 ? di * xd : 0.0);
+        // entries past the first 64 (long rows) are loaded when the row runs
+        for (int32_t e = e0 + kGsLanes + lane; e < e1; e += kGsLanes) s += a.val[e] * xw[a.slot[e]];
+        const int32_t tn = t + kGsAhead;
+        // kGsAhead divides 64, so row tn is in the current or the next chunk
+        if (tn < R) kz_load_row(a, (tn & (kGsLanes - 1)) >= l ? cur : next, tn & (kGsLanes - 1), lane, ring[p]);
+        const double c = omega * (bi - wave_sum(s)) * qi;  // qi = 1 / |a_i|^2, 0 for a row with no value
+        if (lane < e1 - e0) xw[row.sl] += c * row.v;
+        for (int32_t e = e0 + kGsLanes + lane; e < e1; e += kGsLanes) xw[a.slot[e]] += c * a.val[e];
+        if (lane == 0) xw[i - lo] = xd + c * di;
+        lds_row_order();
+        if (l == kGsLanes - 1) {
+          cur = next;
+          kz_load_meta<kBackward>(a, bvec, lo, hi, t + 1 + kGsLanes, lane, next);
+        }
+      }
+    }
+  }
+  for (int32_t s = lane; s < R; s += kGsLanes) x[lo + s] = xw[s];
+  for (int32_t s = lane; s < H; s += kGsLanes) x[a.halo[h0 + s]] = xw[R + s];
 }
 
 // Four leaves per wavefront: lanes 16 g .. 16 g + 15 run leaf 4 b + g of
@@ -233,8 +378,7 @@ __device__ __forceinline__ void gs_quad_leaves(const GsArgs& a, int32_t first, i
   double* xw = smem + static_cast<size_t>(g) * wmax;
   const int32_t lo = a.leaf_lo[leaf], h0 = a.halo_ptr[leaf];
   const int32_t R = live ? a.leaf_hi[leaf] - lo : 0, H = live ? a.halo_ptr[leaf + 1] - h0 : 0;
-  for (int32_t s = j; s < R; s += kQLanes) xw[s] = gs_x_load<kCoherent>(x + lo + s);
-  for (int32_t s = j; s < H; s += kQLanes) xw[R + s] = gs_x_load<kCoherent>(x + a.halo[h0 + s]);
+  stage_window<kQLanes, kCoherent>(x, a.halo + h0, lo, R, H, j, xw);
   int32_t rmax = R;
   rmax = max(rmax, __shfl_xor(rmax, 16));
   rmax = max(rmax, __shfl_xor(rmax, 32));
@@ -265,9 +409,9 @@ __device__ __forceinline__ void gs_quad_leaves(const GsArgs& a, int32_t first, i
           const int32_t ln = tn & (kQLanes - 1);
           gsq_load_row(a, ln >= l ? cur : next, base + ln, j, ring[p]);
         }
-        const double xi = (bi - group_sum(s)) / di;
+        const double xi = (bi - group_sum(s)) * di;
         if (t < R && j == 0) xw[kBackward ? R - 1 - t : t] = xi;
-        __syncthreads();
+        lds_row_order();
         if (l == kQLanes - 1) {
           // the chunk of rows t - 15 .. t is done: shift, fetch the one after next
           cur = next;
@@ -285,6 +429,99 @@ __global__ void __launch_bounds__(kGsLanes) gs_quad_kernel(GsArgs a, int32_t lea
   extern __shared__ double smem[];
   const int32_t first = static_cast<int32_t>(blockIdx.x) * 4;
   gs_quad_leaves<kBackward, false>(a, leaf0 + first, min(4, count - first), wmax, bvec, x, smem);
+}
+
+// Four Kaczmarz leaves per wavefront, as gs_quad_leaves: lanes 16 g .. 16 g
+// + 15 run leaf first + g, rows advance together, a group past its leaf's
+// last row computes on an empty row (coefficient 0) and writes nothing.
+template <bool kBackward>
+__global__ void __launch_bounds__(kGsLanes) kacz_quad_kernel(GsArgs a, int32_t leaf0, int32_t count, int32_t wmax,
+                                                            double omega, const double* __restrict__ bvec,
+                                                            double* __restrict__ x) {
+  extern __shared__ double smem[];
+  const int32_t first = leaf0 + static_cast<int32_t>(blockIdx.x) * 4;
+  const int32_t cnt = min(4, leaf0 + count - first);
+  const int32_t lane = static_cast<int32_t>(threadIdx.x);
+  const int32_t g = lane / kQLanes, j = lane % kQLanes, base = lane - j;
+  const bool live = g < cnt;
+  const int32_t leaf = first + (live ? g : cnt - 1);
+  double* xw = smem + static_cast<size_t>(g) * wmax;
+  const int32_t lo = a.leaf_lo[leaf], h0 = a.halo_ptr[leaf];
+  const int32_t R = live ? a.leaf_hi[leaf] - lo : 0, H = live ? a.halo_ptr[leaf + 1] - h0 : 0;
+  stage_window<kQLanes, false>(x, a.halo + h0, lo, R, H, j, xw);
+  int32_t rmax = R;
+  rmax = max(rmax, __shfl_xor(rmax, 16));
+  rmax = max(rmax, __shfl_xor(rmax, 32));
+  rmax = __builtin_amdgcn_readfirstlane(rmax);
+  // per-row metadata, lane j of the group holding row t0 + j of its leaf
+  KzMeta cur, next;
+  auto load_meta = [&](int32_t t0, KzMeta& m) {
+    m = KzMeta{};
+    const int32_t t = t0 + j;
+    if (t < R) {
+      const int32_t i = kBackward ? lo + R - 1 - t : lo + t;
+      m.e0 = a.row_ptr[i];
+      m.e1 = a.row_ptr[i + 1];
+      m.b = bvec[i];
+      m.d = a.diag[i];
+      m.q = a.nrm[i];
+    }
+  };
+  auto load_row = [&](const KzMeta& m, int32_t src, GsQRow& r) {
+    const int32_t e0 = __shfl(m.e0, src), e1 = __shfl(m.e1, src);
+    r = GsQRow{};
+    if (e0 + j < e1) {
+      r.v0 = a.val[e0 + j];
+      r.s0 = a.slot[e0 + j];
+    }
+    if (e0 + kQLanes + j < e1) {
+      r.v1 = a.val[e0 + kQLanes + j];
+      r.s1 = a.slot[e0 + kQLanes + j];
+    }
+  };
+  load_meta(0, cur);
+  load_meta(kQLanes, next);
+  GsQRow ring[kQAhead];
+#pragma unroll
+  for (int p = 0; p < kQAhead; ++p)
+    if (p < rmax) load_row(cur, base + p, ring[p]);
+  __syncthreads();
+  for (int32_t t0 = 0; t0 < rmax; t0 += kQAhead) {
+#pragma unroll
+    for (int p = 0; p < kQAhead; ++p) {
+      const int32_t t = t0 + p;
+      if (t < rmax) {
+        const int32_t l = t & (kQLanes - 1);
+        const int32_t src = base + l;
+        const int32_t e0 = __shfl(cur.e0, src), e1 = __shfl(cur.e1, src);
+        const double bi = __shfl(cur.b, src), di = __shfl(cur.d, src), qi = __shfl(cur.q, src);
+        const GsQRow row = ring[p];
+        const int32_t il = kBackward ? R - 1 - t : t;  // the row's slot (t < R)
+        const double xd = t < R ? xw[il] : 0.0;
+        double s = row.v0 * xw[row.s0] + row.v1 * xw[row.s1] + (j == 0 ? di * xd : 0.0);
+        // entries past the first 32 (long rows) are loaded when the row runs
+        for (int32_t e = e0 + 2 * kQLanes + j; e < e1; e += kQLanes) s += a.val[e] * xw[a.slot[e]];
+        const int32_t tn = t + kQAhead;
+        // kQAhead divides 16, so row tn is in the current or the next chunk
+        if (tn < rmax) {
+          const int32_t ln = tn & (kQLanes - 1);
+          load_row(ln >= l ? cur : next, base + ln, ring[p]);
+        }
+        const double c = omega * (bi - group_sum(s)) * qi;
+        if (e0 + j < e1) xw[row.s0] += c * row.v0;
+        if (e0 + kQLanes + j < e1) xw[row.s1] += c * row.v1;
+        for (int32_t e = e0 + 2 * kQLanes + j; e < e1; e += kQLanes) xw[a.slot[e]] += c * a.val[e];
+        if (t < R && j == 0) xw[il] = xd + c * di;
+        lds_row_order();
+        if (l == kQLanes - 1) {
+          cur = next;
+          load_meta(t + 1 + kQLanes, next);
+        }
+      }
+    }
+  }
+  for (int32_t s = j; s < R; s += kQLanes) x[lo + s] = xw[s];
+  for (int32_t s = j; s < H; s += kQLanes) x[a.halo[h0 + s]] = xw[R + s];
 }
 
 // A whole sweep in one launch (dataflow, see GsFlowArgs): workgroup w runs
@@ -349,6 +586,39 @@ hipError_t launch_gs_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, in
   void* args[] = {&aa, &ff, &ww, const_cast<double**>(&b), &x};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&dev::gs_flow_kernel), dim3(static_cast<uint32_t>(grid)),
                                     dim3(dev::kGsLanes), args, static_cast<unsigned int>(lds), st);
+}
+
+hipError_t launch_kacz_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward, double omega,
+                             int32_t quad_min_leaves, const double* b, double* x, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  if (wmax <= kGsQuadMaxWindow && count >= quad_min_leaves) {
+    // four leaves per wavefront
+    const size_t qlds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+    const dim3 grid(static_cast<uint32_t>((count + 3) / 4));
+    if (backward)
+      hipLaunchKernelGGL(dev::kacz_quad_kernel<true>, grid, dim3(dev::kGsLanes), qlds, st, a, leaf0, count,
+                         wmax > 0 ? wmax : 1, omega, b, x);
+    else
+      hipLaunchKernelGGL(dev::kacz_quad_kernel<false>, grid, dim3(dev::kGsLanes), qlds, st, a, leaf0, count,
+                         wmax > 0 ? wmax : 1, omega, b, x);
+    return hipGetLastError();
+  }
+  static bool attr_done[2] = {false, false};
+  const void* fn = backward ? reinterpret_cast<const void*>(&dev::kacz_leaf_kernel<true>)
+                            : reinterpret_cast<const void*>(&dev::kacz_leaf_kernel<false>);
+  if (!attr_done[backward]) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kGsMaxWindowBytes);
+    if (e != hipSuccess) return e;
+    attr_done[backward] = true;
+  }
+  const size_t lds = static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  if (backward)
+    hipLaunchKernelGGL(dev::kacz_leaf_kernel<true>, dim3(static_cast<uint32_t>(count)), dim3(dev::kGsLanes), lds, st,
+                       a, leaf0, omega, b, x);
+  else
+    hipLaunchKernelGGL(dev::kacz_leaf_kernel<false>, dim3(static_cast<uint32_t>(count)), dim3(dev::kGsLanes), lds, st,
+                       a, leaf0, omega, b, x);
+  return hipGetLastError();
 }
 
 hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,

@@ -19,7 +19,8 @@ struct GsArgs {
   const int32_t* row_ptr;
   const uint16_t* slot;
   const double* val;
-  const double* diag;
+  const double* diag;  // Gauss-Seidel: 1 / a_ii; Kaczmarz: a_ii (0 where none is stored)
+  const double* nrm;   // Kaczmarz: 1 / |a_i|^2 of the full row (0 for a row with no value); else unused
 };
 
 // A whole sweep in one cooperative launch over the tickets of a GsFlow
@@ -51,5 +52,15 @@ hipError_t launch_gs_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, in
 // b and x are device arrays of n in the permuted order; x is updated in place.
 hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,
                            int32_t quad_min_leaves, const double* b, double* x, hipStream_t st);
+
+// Kaczmarz sweep over leaves leaf0 .. leaf0 + count - 1 of one phase of a
+// distance-2 schedule (GsArgs of a Kaczmarz layout, nrm set): one leaf per
+// wavefront, or four (16 lanes each) when wmax <= kGsQuadMaxWindow and
+// count >= quad_min_leaves; a leaf's window (own rows and halo) is staged in
+// LDS, updated row by row with x <- x + omega (b_i - a_i . x) / |a_i|^2 a_i
+// in order (backward: reversed) and written back whole.  b and x: device
+// arrays of n in the permuted order; x is updated in place.
+hipError_t launch_kacz_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward, double omega,
+                             int32_t quad_min_leaves, const double* b, double* x, hipStream_t st);
 
 }  // namespace race

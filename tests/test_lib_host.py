@@ -399,3 +399,30 @@ def test_gs_quad_knob_arguments():
     finally:
         s.close()
         s2.close()
+
+
+def test_kaczmarz_layout_and_refusals():
+    """race_params.kaczmarz: built on distance-2 schedules of real values
+    (windows reported in the stats), refused with dist_k 1 or complex
+    values; race_symm_kacz refuses schedules without the layout and
+    schedules not uploaded before touching any device."""
+    g = matgen.config_2d_small()
+    s = R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, n_workers=64, kaczmarz=True)
+    s0 = R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, n_workers=64)
+    try:
+        s.set_gs_quad(0)  # the four-leaves-per-wavefront threshold serves Kaczmarz sweeps too
+        w = s.stats()["kacz_max_window"]
+        assert 0 < w <= 16384
+        assert s0.stats()["kacz_max_window"] == 0
+        assert _lib.lib().race_symm_kacz(s.handle, None, None, 2, 1.0, None) == -5  # not uploaded
+        assert _lib.lib().race_symm_kacz(s0.handle, None, None, 2, 1.0, None) == -5  # no layout
+        for kw in (dict(dist_k=1), dict(value_type="c128")):
+            with pytest.raises(_lib.RaceError):
+                R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, n_workers=64, kaczmarz=True, **kw)
+        # windows too large for the LDS of one wavefront
+        big = matgen.stencil3d_27pt(40, seed=1)
+        with pytest.raises(_lib.RaceError):
+            R.Schedule(big.n, big.row_ptr, big.col, big.val, upload=False, n_workers=1, max_stages=1, kaczmarz=True)
+    finally:
+        s.close()
+        s0.close()
