@@ -791,8 +791,8 @@ def main():
     ap.add_argument("--gs", action="store_true",
                     help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
     ap.add_argument("--gs-exec", default="flow", choices=["phases", "flow"],
-                    help="--gs: one launch per phase, or one dataflow launch per sweep (128^3, N_t 65536: 640 us "
-                         "against 718 us with phase launches)")
+                    help="--gs: one launch per phase, or one dataflow launch per sweep (128^3, N_t 65536: 609 us "
+                         "against 652 us with phase launches)")
     ap.add_argument("--gs-workers", type=int, default=65536,
                     help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 65536 measured fastest)")
     ap.add_argument("--kacz", action="store_true",
