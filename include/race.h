@@ -345,20 +345,25 @@ int race_schedule_set_mpk_order(race_schedule_t s, int64_t lag_rows, int32_t cac
  * powers * (units + clearing tasks) tickets. */
 int race_schedule_mpk_order(race_schedule_t s, int32_t powers, int32_t n_static, int32_t* order);
 
-/* Gauss-Seidel execution: mode 0 (the default) launches once per phase and
- * direction; mode 1 runs a whole sweep in one cooperative launch
- * (dataflow): tickets are groups of up to four leaves of one phase, in the
- * sweep's phase order; a ticket waits until the tickets holding its halo
- * rows that the serial sweep updates before it have published (bounded
- * waits; race_schedule_check reports one that gave up), so the phases
- * overlap and the result is the serial sweep's, up to rounding.  Mode 1
- * needs leaf windows of at most 2048 entries (else the phase launches run)
- * and cannot be captured into a graph (RACE_EUNSUPPORTED).  RACE_EINVAL for
- * another mode, RACE_EUNSUPPORTED for a schedule that is not distance-1. */
+/* Sweep execution (Gauss-Seidel on distance-1 schedules, Kaczmarz on
+ * schedules built with race_params.kaczmarz): mode 0 (the default)
+ * launches once per phase and direction; mode 1 runs a whole sweep in one
+ * cooperative launch (dataflow), tickets in the sweep's phase order.
+ * Gauss-Seidel: tickets are groups of up to four leaves of one phase; a
+ * ticket waits until the tickets holding its halo rows that the serial
+ * sweep updates before it have published (needs leaf windows of at most
+ * 2048 entries, else the phase launches run).  Kaczmarz: one leaf per
+ * ticket; a ticket waits for the latest earlier ticket whose window holds
+ * each row of its own window.  Waits are bounded (race_schedule_check
+ * reports one that gave up), the phases overlap and the result is the
+ * serial sweep's, up to rounding.  Mode 1 cannot be captured into a graph
+ * (RACE_EUNSUPPORTED).  RACE_EINVAL for another mode, RACE_EUNSUPPORTED for
+ * a schedule without a sweep layout. */
 int race_schedule_set_gs_exec(race_schedule_t s, int32_t mode);
 
 /* The tickets of the dataflow sweep in `direction` (host; for inspection
- * and tests): *n_tickets tickets, each up to four consecutive leaves
+ * and tests; the Kaczmarz plan on a schedule built with
+ * race_params.kaczmarz): *n_tickets tickets, each up to four consecutive leaves
  * (execution order, see race_schedule_leaves) ticket_leaf0[t] ..
  * ticket_leaf0[t] + ticket_count[t] - 1 of the forward (ticket_back[t] 0)
  * or backward sweep, waiting for the tickets dep_idx[dep_ptr[t] ..
@@ -368,13 +373,14 @@ int race_schedule_gs_flow_plan(race_schedule_t s, int32_t direction, int32_t* n_
                                int32_t* ticket_leaf0, int32_t* ticket_count, int32_t* ticket_back, int32_t* dep_ptr,
                                int32_t* dep_idx);
 
-/* Gauss-Seidel kernel choice per phase: phases with at least min_leaves
+/* Sweep kernel choice per phase (Gauss-Seidel, and Kaczmarz in its phase
+ * launches): phases with at least min_leaves
  * leaves (and windows of at most 2048 entries) run four leaves per
  * wavefront, 16 lanes each, the others one leaf per wavefront.  -1 (the
  * default): 32 x the device's CUs, i.e. more leaves than the CUs hold
  * wavefronts; -2: never; 0: always.  The results agree to rounding (a
  * row's products are added in another order).
- * RACE_EUNSUPPORTED for a schedule that is not distance-1; RACE_EINVAL for
+ * RACE_EUNSUPPORTED for a schedule without a sweep layout; RACE_EINVAL for
  * min_leaves < -2. */
 int race_schedule_set_gs_quad(race_schedule_t s, int32_t min_leaves);
 
@@ -410,7 +416,8 @@ int race_symm_gs(race_schedule_t s, const double* b, double* x, int32_t directio
  * backward).  omega in (0, 2) (1: plain projections).  b (read) and x
  * (updated in place): device float64 arrays of n in permuted order.  One
  * launch per non-empty phase and direction on `stream`, no allocation (it
- * can be captured into a graph).  RACE_EUNSUPPORTED on a distance-1
+ * can be captured into a graph); or, after race_schedule_set_gs_exec(s, 1),
+ * one dataflow launch per sweep (not capturable).  RACE_EUNSUPPORTED on a distance-1
  * schedule, RACE_ESTATE on one built without race_params.kaczmarz, RACE_EINVAL
  * for direction or omega out of range. */
 int race_symm_kacz(race_schedule_t s, const double* b, double* x, int32_t direction, double omega, void* stream);

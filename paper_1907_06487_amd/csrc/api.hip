@@ -1101,24 +1101,27 @@ int race_schedule_check(race_schedule_t s) {
   if (!s->uploaded) return RACE_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-  // the status word: after the dataflow state of a product, or after the
-  // ticket flags of a dataflow Gauss-Seidel sweep
-  uint32_t* status_at = nullptr;
-  if (s->gs) {
-    if (!s->gsf_flags.p) return RACE_OK;  // phase launches have no bounded waits
-    status_at = s->gsf_flags.p + s->gsf_flags.count - 1;
-  } else {
-    status_at = s->flow_state.p + static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
-  }
-  uint32_t status = 0;
-  e = hipMemcpy(&status, status_at, sizeof(uint32_t), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-  if (status) {
-    const uint32_t zero = 0;
-    e = hipMemcpy(status_at, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
+  // the status words: after the dataflow state of a product, and after the
+  // ticket flags of a dataflow sweep (Gauss-Seidel or Kaczmarz; phase
+  // launches have no bounded waits)
+  uint32_t* words[2] = {nullptr, nullptr};
+  if (!s->gs && s->flow_state.p)
+    words[0] = s->flow_state.p + static_cast<int32_t>(s->L.unit_lo.size()) + s->L.n_zero_tasks;
+  if (s->gsf_flags.p) words[1] = s->gsf_flags.p + s->gsf_flags.count - 1;
+  bool gave_up = false;
+  for (uint32_t* status_at : words) {
+    if (!status_at) continue;
+    uint32_t status = 0;
+    e = hipMemcpy(&status, status_at, sizeof(uint32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-    return fail(RACE_EINTERNAL, "a dataflow wait gave up (bounded spin exceeded)");
+    if (status) {
+      const uint32_t zero = 0;
+      e = hipMemcpy(status_at, &zero, sizeof(uint32_t), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+      gave_up = true;
+    }
   }
+  if (gave_up) return fail(RACE_EINTERNAL, "a dataflow wait gave up (bounded spin exceeded)");
   return RACE_OK;
 }
 
@@ -1458,8 +1461,11 @@ int race_schedule_read_deps(race_schedule_t s, int64_t* count, int32_t* ptr, int
 }  // extern "C"
 
 // One dataflow launch for a whole sweep (race_schedule_set_gs_exec 1).
+// kacz: a Kaczmarz sweep over the schedule's Kaczmarz layout (one leaf
+// per ticket) with relaxation omega.  A schedule holds one of the two
+// layouts, so both share the plan caches, flags and epoch.
 static int run_gs_flow(race_schedule_t s, const race::GsArgs& a, int32_t direction, const double* b, double* x,
-                       hipStream_t st) {
+                       hipStream_t st, bool kacz = false, double omega = 1.0) {
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(st, &cap);
   if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
@@ -1468,7 +1474,10 @@ static int run_gs_flow(race_schedule_t s, const race::GsArgs& a, int32_t directi
   race::GsFlow& f = s->gs_flow_h[direction];
   if (f.direction != direction) {
     try {
-      race::build_gs_flow(s->G, direction, f);
+      if (kacz)
+        race::build_kacz_flow(s->KG, direction, f);
+      else
+        race::build_gs_flow(s->G, direction, f);
     } catch (const std::bad_alloc&) {
       f.direction = -1;
       return fail(RACE_ENOMEM, "out of host memory while planning the dataflow sweep");
@@ -1510,14 +1519,15 @@ static int run_gs_flow(race_schedule_t s, const race::GsArgs& a, int32_t directi
     s->gs_epoch = 1;
   }
   int32_t grid = 0;
-  e = race::gs_flow_grid(s->G.max_window, s->n_cus, &grid);
+  const int32_t wmax = kacz ? s->KG.max_window : s->G.max_window;
+  e = kacz ? race::kacz_flow_grid(wmax, s->n_cus, &grid) : race::gs_flow_grid(wmax, s->n_cus, &grid);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (grid < 1) return fail(RACE_EUNSUPPORTED, "the dataflow sweep does not fit a CU");
   grid = std::min(grid, nt);
   const race::GsFlowArgs fa{s->gsf_item[direction].p, s->gsf_back[direction].p, s->gsf_leaf0[direction].p,
                             s->gsf_count[direction].p, s->gsf_dptr[direction].p, s->gsf_didx[direction].p,
                             s->gsf_flags.p, s->gsf_flags.p + s->gsf_flags.count - 1, nt, s->gs_epoch};
-  e = race::launch_gs_flow(a, fa, s->G.max_window, grid, b, x, st);
+  e = kacz ? race::launch_kacz_flow(a, fa, wmax, grid, omega, b, x, st) : race::launch_gs_flow(a, fa, wmax, grid, b, x, st);
   if (e != hipSuccess) return hip_fail(e, "dataflow sweep launch");
   return RACE_OK;
 }
@@ -1526,7 +1536,8 @@ extern "C" {
 
 int race_schedule_set_gs_exec(race_schedule_t s, int32_t mode) {
   if (!s) return fail(RACE_EINVAL, "schedule is NULL");
-  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (!s->gs && !s->kz)
+    return fail(RACE_EUNSUPPORTED, "sweeps need a distance-1 schedule or one built with race_params.kaczmarz");
   if (mode != 0 && mode != 1) return fail(RACE_EINVAL, "mode must be 0 (a launch per phase) or 1 (one dataflow launch)");
   s->gs_exec = mode;
   return RACE_OK;
@@ -1536,11 +1547,15 @@ int race_schedule_gs_flow_plan(race_schedule_t s, int32_t direction, int32_t* n_
                                int32_t* ticket_leaf0, int32_t* ticket_count, int32_t* ticket_back, int32_t* dep_ptr,
                                int32_t* dep_idx) {
   if (!s || !n_tickets || !n_deps) return fail(RACE_EINVAL, "NULL argument");
-  if (!s->gs) return fail(RACE_EUNSUPPORTED, "Gauss-Seidel sweeps need a distance-1 schedule (dist_k = 1)");
+  if (!s->gs && !s->kz)
+    return fail(RACE_EUNSUPPORTED, "sweeps need a distance-1 schedule or one built with race_params.kaczmarz");
   if (direction < 0 || direction > 2) return fail(RACE_EINVAL, "direction must be 0 (forward), 1 (backward) or 2 (both)");
   race::GsFlow f;
   try {
-    race::build_gs_flow(s->G, direction, f);
+    if (s->gs)
+      race::build_gs_flow(s->G, direction, f);
+    else
+      race::build_kacz_flow(s->KG, direction, f);
   } catch (const std::bad_alloc&) {
     return fail(RACE_ENOMEM, "out of host memory while planning the dataflow sweep");
   } catch (const std::exception& ex) {
@@ -1615,6 +1630,7 @@ int race_symm_kacz(race_schedule_t s, const double* b, double* x, int32_t direct
   const race::GsArgs a{s->kz_leaf_lo.p, s->kz_leaf_hi.p, s->kz_halo_ptr.p, s->kz_halo.p, s->kz_row_ptr.p,
                        s->kz_slot.p,    s->kz_val.p,     s->kz_diag.p,     s->kz_nrm.p};
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->gs_exec == 1) return run_gs_flow(s, a, direction, b, x, st, true, omega);
   const int32_t np = s->tree.n_phases;
   // four leaves per wavefront once a phase has more leaves than the CUs
   // hold wavefronts (32 each)

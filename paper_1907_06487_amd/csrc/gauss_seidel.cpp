@@ -224,4 +224,47 @@ void build_gs_flow(const GsLayout& G, int32_t direction, GsFlow& f) {
   }
 }
 
+void build_kacz_flow(const GsLayout& K, int32_t direction, GsFlow& f) {
+  const int32_t nl = static_cast<int32_t>(K.leaf_lo.size());
+  const int32_t np = static_cast<int32_t>(K.phase_leaf_ptr.size()) - 1;
+  f = GsFlow{};
+  f.direction = direction;
+  for (int32_t l = 0; l < nl; ++l) {
+    f.item_leaf0.push_back(l);
+    f.item_count.push_back(1);
+  }
+  if (direction != 1)
+    for (int32_t l = 0; l < nl; ++l) {
+      f.ticket_item.push_back(l);
+      f.ticket_back.push_back(0);
+    }
+  if (direction != 0)
+    for (int32_t p = np - 1; p >= 0; --p)
+      for (int32_t l = K.phase_leaf_ptr[static_cast<size_t>(p)]; l < K.phase_leaf_ptr[static_cast<size_t>(p) + 1]; ++l) {
+        f.ticket_item.push_back(l);
+        f.ticket_back.push_back(1);
+      }
+  const int32_t nt = static_cast<int32_t>(f.ticket_item.size());
+  f.dep_ptr.assign(static_cast<size_t>(nt) + 1, 0);
+  std::vector<int32_t> last(static_cast<size_t>(K.n), -1), deps;
+  for (int32_t t = 0; t < nt; ++t) {
+    const int32_t l = f.ticket_item[static_cast<size_t>(t)];
+    deps.clear();
+    auto touch = [&](int32_t r) {
+      int32_t& w = last[static_cast<size_t>(r)];
+      if (w >= 0) deps.push_back(w);
+      w = t;
+    };
+    for (int32_t r = K.leaf_lo[static_cast<size_t>(l)]; r < K.leaf_hi[static_cast<size_t>(l)]; ++r) touch(r);
+    for (int32_t h = K.halo_ptr[static_cast<size_t>(l)]; h < K.halo_ptr[static_cast<size_t>(l) + 1]; ++h)
+      touch(K.halo[static_cast<size_t>(h)]);
+    std::sort(deps.begin(), deps.end());
+    deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+    for (const int32_t d : deps)
+      if (d >= t) throw std::logic_error("Kaczmarz dataflow: a wait that does not point backwards");
+    f.dep_idx.insert(f.dep_idx.end(), deps.begin(), deps.end());
+    f.dep_ptr[static_cast<size_t>(t) + 1] = static_cast<int32_t>(f.dep_idx.size());
+  }
+}
+
 }  // namespace race

@@ -74,4 +74,13 @@ struct GsFlow {
 };
 void build_gs_flow(const GsLayout& G, int32_t direction, GsFlow& f);
 
+// Dataflow plan of a Kaczmarz sweep over a Kaczmarz layout: one leaf per
+// item and ticket, tickets in the serial sweep's order (forward: phases
+// ascending; backward: descending; symmetric: both).  A leaf reads and
+// writes its whole window, so a ticket waits for the latest earlier ticket
+// whose window holds each of its window's rows: every pair of tickets that
+// share a row then runs in the serial order (leaves of one phase share
+// none).
+void build_kacz_flow(const GsLayout& K, int32_t direction, GsFlow& f);
+
 }  // namespace race

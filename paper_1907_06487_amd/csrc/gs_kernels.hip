@@ -75,6 +75,20 @@ __device__ __forceinline__ void gs_load_meta(const GsArgs& a, const double* __re
   }
 }
 
+// x as the sweep reads and writes it: plain, or (kCoherent: several
+// workgroups of one launch update x) agent-scope loads and stores, which are
+// coherent across the XCDs.
+template <bool kCoherent>
+__device__ __forceinline__ double gs_x_load(const double* p) {
+  if constexpr (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool kCoherent>
+__device__ __forceinline__ void gs_x_store(double* p, double v) {
+  if constexpr (kCoherent) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 // Stages a leaf's window in LDS: x of its own rows lo .. lo + R - 1 into
 // slots 0 .. R - 1, x of its halo rows (halo[0 .. H - 1]) into slots R ..
 // R + H - 1; kLanes lanes (lane j), kStage loads per lane in flight before
@@ -85,10 +99,7 @@ template <int kLanes, bool kCoherent>
 __device__ __forceinline__ void stage_window(const double* __restrict__ x, const int32_t* __restrict__ halo,
                                              int32_t lo, int32_t R, int32_t H, int32_t j, double* xw) {
   constexpr int kStage = 8;
-  auto load = [](const double* p) {
-    if constexpr (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else return *p;
-  };
+  auto load = [](const double* p) { return gs_x_load<kCoherent>(p); };
   for (int32_t s0 = 0; s0 < R; s0 += kLanes * kStage) {
     double v[kStage];
 #pragma unroll
@@ -244,16 +255,16 @@ __device__ __forceinline__ void kz_load_row(const GsArgs& a, const KzMeta& m, in
   }
 }
 
-template <bool kBackward>
-__global__ void __launch_bounds__(kGsLanes) kacz_leaf_kernel(GsArgs a, int32_t leaf0, double omega,
-                                                            const double* __restrict__ bvec, double* __restrict__ x) {
-  extern __shared__ double xw[];
-  const int32_t leaf = leaf0 + static_cast<int32_t>(blockIdx.x);
+// One leaf on the wavefront (kCoherent: x through agent-scope loads and
+// stores, for the dataflow launch).
+template <bool kBackward, bool kCoherent>
+__device__ __forceinline__ void kacz_leaf(const GsArgs& a, int32_t leaf, double omega, const double* __restrict__ bvec,
+                                          double* __restrict__ x, double* xw) {
   const int32_t lane = static_cast<int32_t>(threadIdx.x);
   const int32_t lo = gs_uniform(a.leaf_lo, leaf), hi = gs_uniform(a.leaf_hi, leaf);
   const int32_t h0 = gs_uniform(a.halo_ptr, leaf), h1 = gs_uniform(a.halo_ptr, leaf + 1);
   const int32_t R = hi - lo, H = h1 - h0;
-  stage_window<kGsLanes, false>(x, a.halo + h0, lo, R, H, lane, xw);
+  stage_window<kGsLanes, kCoherent>(x, a.halo + h0, lo, R, H, lane, xw);
   KzMeta cur, next;
   kz_load_meta<kBackward>(a, bvec, lo, hi, 0, lane, cur);
   kz_load_meta<kBackward>(a, bvec, lo, hi, kGsLanes, lane, next);
@@ -292,8 +303,15 @@ __global__ void __launch_bounds__(kGsLanes) kacz_leaf_kernel(GsArgs a, int32_t l
       }
     }
   }
-  for (int32_t s = lane; s < R; s += kGsLanes) x[lo + s] = xw[s];
-  for (int32_t s = lane; s < H; s += kGsLanes) x[a.halo[h0 + s]] = xw[R + s];
+  for (int32_t s = lane; s < R; s += kGsLanes) gs_x_store<kCoherent>(x + lo + s, xw[s]);
+  for (int32_t s = lane; s < H; s += kGsLanes) gs_x_store<kCoherent>(x + a.halo[h0 + s], xw[R + s]);
+}
+
+template <bool kBackward>
+__global__ void __launch_bounds__(kGsLanes) kacz_leaf_kernel(GsArgs a, int32_t leaf0, double omega,
+                                                            const double* __restrict__ bvec, double* __restrict__ x) {
+  extern __shared__ double xw[];
+  kacz_leaf<kBackward, false>(a, leaf0 + static_cast<int32_t>(blockIdx.x), omega, bvec, x, xw);
 }
 
 // Four leaves per wavefront: lanes 16 g .. 16 g + 15 run leaf 4 b + g of
@@ -349,20 +367,6 @@ __device__ __forceinline__ void gsq_load_row(const GsArgs& a, const GsMeta& m, i
     r.v1 = a.val[e0 + kQLanes + j];
     r.s1 = a.slot[e0 + kQLanes + j];
   }
-}
-
-// x as the sweep reads and writes it: plain, or (kCoherent: several
-// workgroups of one launch update x) agent-scope loads and stores, which are
-// coherent across the XCDs.
-template <bool kCoherent>
-__device__ __forceinline__ double gs_x_load(const double* p) {
-  if constexpr (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else return *p;
-}
-template <bool kCoherent>
-__device__ __forceinline__ void gs_x_store(double* p, double v) {
-  if constexpr (kCoherent) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else *p = v;
 }
 
 // Leaves first .. first + cnt - 1 (cnt <= 4) on the wavefront, group g on
@@ -564,7 +568,68 @@ __global__ void __launch_bounds__(kGsLanes) gs_flow_kernel(GsArgs a, GsFlowArgs 
   }
 }
 
+// A whole Kaczmarz sweep in one launch: as gs_flow_kernel, one leaf per
+// ticket (GsFlowArgs items of one leaf), its window read and written with
+// agent-scope loads and stores.
+__global__ void __launch_bounds__(kGsLanes) kacz_flow_kernel(GsArgs a, GsFlowArgs f, double omega,
+                                                            const double* __restrict__ bvec, double* __restrict__ x) {
+  extern __shared__ double xw[];
+  const int32_t lane = static_cast<int32_t>(threadIdx.x);
+  for (int32_t t = static_cast<int32_t>(blockIdx.x); t < f.n_tickets; t += static_cast<int32_t>(gridDim.x)) {
+    const int32_t d0 = gs_uniform(f.dep_ptr, t), d1 = gs_uniform(f.dep_ptr, t + 1);
+    for (int32_t i = d0 + lane; i < d1; i += kGsLanes) {
+      const uint32_t* flag = f.flags + f.dep_idx[i];
+      uint32_t spins = 0;
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kGsSpinLimit) {
+          atomicOr(f.status, 1u);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    const int32_t leaf = gs_uniform(f.item_leaf0, gs_uniform(f.ticket_item, t));
+    if (gs_uniform(f.ticket_back, t))
+      kacz_leaf<true, true>(a, leaf, omega, bvec, x, xw);
+    else
+      kacz_leaf<false, true>(a, leaf, omega, bvec, x, xw);
+    // every lane's x stores complete before the flag
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (lane == 0) __hip_atomic_store(f.flags + t, f.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 }  // namespace dev
+
+hipError_t kacz_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
+  const size_t lds = static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  int per_cu = 0;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::kacz_flow_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kGsMaxWindowBytes);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&dev::kacz_flow_kernel),
+                                                   dev::kGsLanes, lds);
+  if (e != hipSuccess) return e;
+  *grid = per_cu * n_cus;
+  return hipSuccess;
+}
+
+hipError_t launch_kacz_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, int32_t grid, double omega,
+                            const double* b, double* x, hipStream_t st) {
+  if (f.n_tickets == 0) return hipSuccess;
+  const size_t lds = static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  GsArgs aa = a;
+  GsFlowArgs ff = f;
+  double om = omega;
+  void* args[] = {&aa, &ff, &om, const_cast<double**>(&b), &x};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&dev::kacz_flow_kernel),
+                                    dim3(static_cast<uint32_t>(grid)), dim3(dev::kGsLanes), args,
+                                    static_cast<unsigned int>(lds), st);
+}
 
 hipError_t gs_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
   const size_t lds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);

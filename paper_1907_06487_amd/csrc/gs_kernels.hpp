@@ -53,6 +53,13 @@ hipError_t launch_gs_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, in
 hipError_t launch_gs_phase(const GsArgs& a, int32_t leaf0, int32_t count, int32_t wmax, bool backward,
                            int32_t quad_min_leaves, const double* b, double* x, hipStream_t st);
 
+// A whole Kaczmarz sweep in one cooperative launch over the tickets of a
+// plan from build_kacz_flow (one leaf per ticket); wmax: the largest leaf
+// window.
+hipError_t kacz_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid);
+hipError_t launch_kacz_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, int32_t grid, double omega,
+                            const double* b, double* x, hipStream_t st);
+
 // Kaczmarz sweep over leaves leaf0 .. leaf0 + count - 1 of one phase of a
 // distance-2 schedule (GsArgs of a Kaczmarz layout, nrm set): one leaf per
 // wavefront, or four (16 lanes each) when wmax <= kGsQuadMaxWindow and

@@ -32,10 +32,11 @@ def race_rows(s):
     return G.race_order(s.perm(), lo, hi, phase)
 
 
-def run_kacz(m, b, x0, direction, sweeps, omega, quad=-1, **params):
+def run_kacz(m, b, x0, direction, sweeps, omega, quad=-1, exec_mode="phases", **params):
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, kaczmarz=True, **params)
     try:
         s.set_gs_quad(quad)
+        s.set_gs_exec(exec_mode)
         bd = torch.as_tensor(b, device=DEV)
         xd = torch.as_tensor(x0, device=DEV)
         bp, xp = torch.empty_like(bd), torch.empty_like(xd)
@@ -46,6 +47,7 @@ def run_kacz(m, b, x0, direction, sweeps, omega, quad=-1, **params):
         out = torch.empty_like(xd)
         s.permute(xp, out, to_permuted=False)
         torch.cuda.synchronize()
+        s.check()  # a dataflow wait that gave up
         return out.cpu().numpy(), race_rows(s), s.stats()
     finally:
         s.close()
@@ -92,19 +94,20 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("quad", [-2, 0], ids=["one_leaf_per_wave", "four_leaves_per_wave"])
+@pytest.mark.parametrize("quad,exec_mode", [(-2, "phases"), (0, "phases"), (-2, "flow")],
+                         ids=["one_leaf_per_wave", "four_leaves_per_wave", "dataflow"])
 @pytest.mark.parametrize("omega", [1.0, 1.4])
 @pytest.mark.parametrize("direction", ["forward", "backward", "symmetric"])
 @pytest.mark.parametrize("name,make,params", CASES, ids=[c[0] for c in CASES])
-def test_kaczmarz_parity(name, make, params, direction, omega, quad):
+def test_kaczmarz_parity(name, make, params, direction, omega, quad, exec_mode):
     m = make()
     rng = np.random.default_rng(11)
     b = rng.uniform(-1, 1, m.n)
     x0 = rng.uniform(-1, 1, m.n)
     sweeps = 2 if direction == "symmetric" else 1
-    print(f"case kacz {name} {direction} x{sweeps} omega={omega} quad={quad}: n={m.n} nnz={m.nnz} {params}",
-          flush=True)
-    x, order, st = run_kacz(m, b, x0, direction, sweeps, omega, quad, **params)
+    print(f"case kacz {name} {direction} x{sweeps} omega={omega} quad={quad} exec={exec_mode}: n={m.n} nnz={m.nnz} "
+          f"{params}", flush=True)
+    x, order, st = run_kacz(m, b, x0, direction, sweeps, omega, quad, exec_mode, **params)
     ref = oracle(m, b, x0, order, direction, sweeps, omega)
     err = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     print(f"[kacz {name} {direction}] leaves={st['n_leaves']} phases={st['n_phases_used']} "
@@ -167,16 +170,16 @@ def test_kaczmarz_converges_captures_and_refuses():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("quad", [-1, 0])
-def test_kaczmarz_full_size_3d27pt_128(quad):
+@pytest.mark.parametrize("quad,exec_mode", [(-1, "phases"), (0, "phases"), (-1, "flow")])
+def test_kaczmarz_full_size_3d27pt_128(quad, exec_mode):
     """The 128^3 stencil at the benchmark's schedule (N_t 4096, 3 stages),
     one symmetric sweep, against the C oracle over the same row order."""
     m = matgen.config_3d_128()
     rng = np.random.default_rng(14)
     b = rng.uniform(-1, 1, m.n)
     x0 = np.zeros(m.n)
-    print(f"case kacz 3d27pt_128: n={m.n}", flush=True)
-    x, order, st = run_kacz(m, b, x0, "symmetric", 1, 1.0, quad, n_workers=4096, max_stages=3)
+    print(f"case kacz 3d27pt_128 quad={quad} exec={exec_mode}: n={m.n}", flush=True)
+    x, order, st = run_kacz(m, b, x0, "symmetric", 1, 1.0, quad, exec_mode, n_workers=4096, max_stages=3)
     ref = oracle(m, b, x0, order, "symmetric", 1, 1.0)
     err = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     print(f"[kacz 3d27pt_128] leaves={st['n_leaves']} window={st['kacz_max_window']} err_norm={err:.3e}", flush=True)

@@ -1,4 +1,4 @@
-"""Host checks of the dataflow plan of a Gauss-Seidel sweep
+"""Host checks of the dataflow plans of Gauss-Seidel and Kaczmarz sweeps
 (race_schedule_gs_flow_plan).  The orderings are rederived from the matrix
 and the leaves' row ranges alone: two leaves of different phases that hold
 adjacent rows (a stored entry between them) must run in the serial sweep's
@@ -6,7 +6,10 @@ order -- forward: the leaf of the earlier phase first; backward: the leaf
 of the later phase first; symmetric: every leaf's forward update before
 its backward one.  The plan must make each such pair reachable through its
 waits, every wait must point to an earlier ticket, every leaf must appear
-once per direction, and the leaves of a ticket must share a phase."""
+once per direction, and the leaves of a ticket must share a phase.
+A Kaczmarz ticket (one leaf) reads and writes its leaf's window, the rows
+of the leaf and their neighbours: every two tickets whose windows share a
+row must run in the serial sweep's order."""
 import numpy as np
 import pytest
 
@@ -106,6 +109,76 @@ def test_gs_exec_arguments():
             s2.set_gs_exec("flow")
         with pytest.raises(R.RaceError):
             s2.gs_flow_plan(0)
+        s3 = R.Schedule(g.n, g.row_ptr, g.col, g.val, upload=False, n_workers=64, kaczmarz=True)
+        s3.set_gs_exec("flow")
+        assert s3.gs_flow_plan(2)["leaf0"].size == 2 * s3.stats()["n_leaves"]
+        s3.close()
     finally:
         s.close()
         s2.close()
+
+
+def _windows(m, perm, lo, hi):
+    """Rows (permuted numbering) of every leaf's Kaczmarz window: its own
+    rows and their neighbours in the full matrix."""
+    inv = np.empty(m.n, dtype=np.int64)
+    inv[perm] = np.arange(m.n)
+    nb = [set() for _ in range(m.n)]
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    for r, c in zip(inv[rows].tolist(), inv[m.col].tolist()):
+        nb[r].add(c)
+        nb[c].add(r)
+    out = []
+    for a, b in zip(lo, hi):
+        w = set(range(a, b))
+        for r in range(a, b):
+            w |= nb[r]
+        out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("direction", [0, 1, 2])
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_kacz_flow_plan_orders_every_shared_row(name, make, kw, direction):
+    m = make()
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, kaczmarz=True, **kw)
+    try:
+        tr = s.tree()
+        node, phase = s.leaves()
+        lo, hi = np.asarray(tr["lo"])[node], np.asarray(tr["hi"])[node]
+        win = _windows(m, s.perm(), lo, hi)
+        plan = s.gs_flow_plan(direction)
+        nt = plan["leaf0"].size
+        ptr, idx = plan["dep_ptr"], plan["dep_idx"]
+        assert np.all(plan["count"] == 1)
+        seen = set()
+        for t in range(nt):
+            assert np.all(idx[ptr[t]:ptr[t + 1]] < t)
+            key = (int(plan["back"][t]), int(plan["leaf0"][t]))
+            assert key not in seen
+            seen.add(key)
+        dirs = {0: [0], 1: [1], 2: [0, 1]}[direction]
+        assert len(seen) == len(dirs) * len(phase)
+        # the serial order: forward phases ascending, then backward descending
+        ph = [int(phase[int(l)]) for l in plan["leaf0"]]
+        bk = plan["back"].tolist()
+        for t in range(1, nt):
+            if bk[t] == bk[t - 1]:
+                assert ph[t] >= ph[t - 1] if bk[t] == 0 else ph[t] <= ph[t - 1]
+            else:
+                assert bk[t - 1] == 0 and bk[t] == 1
+        reach = _reach(nt, ptr, idx)
+        holders = {}
+        for t in range(nt):
+            for r in win[int(plan["leaf0"][t])]:
+                holders.setdefault(r, []).append(t)
+        for r, ts in holders.items():
+            for a, b in zip(ts, ts[1:]):
+                assert a in reach[b], (r, a, b)
+        # leaves of one phase share no window row
+        for p in set(ph):
+            ls = [l for l in range(len(phase)) if int(phase[l]) == p]
+            allrows = [r for l in ls for r in win[l]]
+            assert len(allrows) == len(set(allrows))
+    finally:
+        s.close()
