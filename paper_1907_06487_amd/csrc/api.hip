@@ -1502,18 +1502,19 @@ static int run_gs_flow(race_schedule_t s, const race::GsArgs& a, int32_t directi
   }
   const int32_t nt = static_cast<int32_t>(f.ticket_item.size());
   if (nt == 0) return RACE_OK;
-  // flags of every ticket, then the status word; a new allocation starts at
-  // epoch 0 everywhere
-  if (s->gsf_flags.count < static_cast<size_t>(nt) + 1) {
+  // flags of every ticket, the drain word, then the status word; a new
+  // allocation starts at epoch 0 everywhere
+  if (s->gsf_flags.count < static_cast<size_t>(nt) + 2) {
     release(s->gsf_flags);
-    std::vector<uint32_t> zeros(static_cast<size_t>(nt) + 1, 0u);
+    std::vector<uint32_t> zeros(static_cast<size_t>(nt) + 2, 0u);
     int64_t total = 0;
     e = upload(s->gsf_flags, zeros.data(), zeros.size(), &total);
     if (e != hipSuccess) return hip_fail(e, "allocation of the dataflow sweep flags");
     s->gs_epoch = 0;
   }
   if (++s->gs_epoch == 0) {
-    // the epoch wrapped: clear the flags (the status word keeps its value)
+    // the epoch wrapped: clear the flags and the drain word (the status
+    // word keeps its value)
     e = race::launch_clear_words(s->gsf_flags.p, static_cast<int64_t>(s->gsf_flags.count) - 1, st);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
     s->gs_epoch = 1;
@@ -1526,7 +1527,8 @@ static int run_gs_flow(race_schedule_t s, const race::GsArgs& a, int32_t directi
   grid = std::min(grid, nt);
   const race::GsFlowArgs fa{s->gsf_item[direction].p, s->gsf_back[direction].p, s->gsf_leaf0[direction].p,
                             s->gsf_count[direction].p, s->gsf_dptr[direction].p, s->gsf_didx[direction].p,
-                            s->gsf_flags.p, s->gsf_flags.p + s->gsf_flags.count - 1, nt, s->gs_epoch};
+                            s->gsf_flags.p, s->gsf_flags.p + s->gsf_flags.count - 1,
+                            s->gsf_flags.p + s->gsf_flags.count - 2, nt, s->gs_epoch};
   e = kacz ? race::launch_kacz_flow(a, fa, wmax, grid, omega, b, x, st) : race::launch_gs_flow(a, fa, wmax, grid, b, x, st);
   if (e != hipSuccess) return hip_fail(e, "dataflow sweep launch");
   return RACE_OK;

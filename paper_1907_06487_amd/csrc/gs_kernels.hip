@@ -324,7 +324,10 @@ __global__ void __launch_bounds__(kGsLanes) kacz_leaf_kernel(GsArgs a, int32_t l
 // group by four DPP steps (quad swaps, half-row and row mirrors, which stay
 // inside a row of 16 lanes) and get the row's metadata from the lane that
 // holds it (ds_bpermute).
-constexpr uint32_t kGsSpinLimit = 1u << 16;  // bounded wait of the dataflow sweep (about 2^16 sleeps)
+// Bounded wait of the dataflow sweeps: about one second of the 100 MHz
+// wall clock for one ticket's list (a chain of long leaves can legitimately
+// take tens of milliseconds).
+constexpr uint64_t kGsWaitTicks = 100000000ull;
 constexpr int kQLanes = 16;
 constexpr int kQAhead = 4;  // divides 16
 
@@ -528,31 +531,43 @@ __global__ void __launch_bounds__(kGsLanes) kacz_quad_kernel(GsArgs a, int32_t l
   for (int32_t s = j; s < H; s += kQLanes) x[a.halo[h0 + s]] = xw[R + s];
 }
 
+// Waits until every ticket in ticket t's list has published.  A wait that
+// runs past kGsWaitTicks sets *status (reported to the host) and *drain to
+// the launch's epoch and goes on; every other wait of the same launch then
+// stops at once, so the grid drains quickly.
+__device__ __forceinline__ void wait_tickets(const GsFlowArgs& f, int32_t t, int32_t lane) {
+  const int32_t d0 = gs_uniform(f.dep_ptr, t), d1 = gs_uniform(f.dep_ptr, t + 1);
+  for (int32_t i = d0 + lane; i < d1; i += kGsLanes) {
+    const uint32_t* flag = f.flags + f.dep_idx[i];
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__hip_atomic_load(f.drain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == f.epoch) break;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kGsWaitTicks) {
+        atomicOr(f.status, 1u);
+        __hip_atomic_store(f.drain, f.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // A whole sweep in one launch (dataflow, see GsFlowArgs): workgroup w runs
 // tickets w, w + grid, ... in order; before a ticket it waits until every
-// ticket in its list has published (bounded; a wait that gives up sets
-// *status and goes on, so the grid always drains), after it every x store
-// has completed before the ticket's flag is set.  The launch is cooperative
-// (every workgroup resident), so the lowest unfinished ticket always has a
-// running owner whose own earlier tickets are done.
+// ticket in its list has published (bounded, see wait_tickets, so the grid
+// always drains), after it every x store has completed before the ticket's
+// flag is set.  The launch is cooperative (every workgroup resident), so the
+// lowest unfinished ticket always has a running owner whose own earlier
+// tickets are done.  (Claiming tickets from one atomic counter instead
+// serialises the claims at that address: 3.6 ms per 128^3 sweep against
+// 0.61 ms.)
 __global__ void __launch_bounds__(kGsLanes) gs_flow_kernel(GsArgs a, GsFlowArgs f, int32_t wmax,
                                                           const double* __restrict__ bvec, double* __restrict__ x) {
   extern __shared__ double smem[];
   const int32_t lane = static_cast<int32_t>(threadIdx.x);
   for (int32_t t = static_cast<int32_t>(blockIdx.x); t < f.n_tickets; t += static_cast<int32_t>(gridDim.x)) {
-    const int32_t d0 = gs_uniform(f.dep_ptr, t), d1 = gs_uniform(f.dep_ptr, t + 1);
-    for (int32_t i = d0 + lane; i < d1; i += kGsLanes) {
-      const uint32_t* flag = f.flags + f.dep_idx[i];
-      uint32_t spins = 0;
-      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kGsSpinLimit) {
-          atomicOr(f.status, 1u);
-          break;
-        }
-      }
-    }
-    __syncthreads();
+    wait_tickets(f, t, lane);
     const int32_t item = gs_uniform(f.ticket_item, t);
     const int32_t first = gs_uniform(f.item_leaf0, item), cnt = gs_uniform(f.item_count, item);
     if (gs_uniform(f.ticket_back, t))
@@ -576,19 +591,7 @@ __global__ void __launch_bounds__(kGsLanes) kacz_flow_kernel(GsArgs a, GsFlowArg
   extern __shared__ double xw[];
   const int32_t lane = static_cast<int32_t>(threadIdx.x);
   for (int32_t t = static_cast<int32_t>(blockIdx.x); t < f.n_tickets; t += static_cast<int32_t>(gridDim.x)) {
-    const int32_t d0 = gs_uniform(f.dep_ptr, t), d1 = gs_uniform(f.dep_ptr, t + 1);
-    for (int32_t i = d0 + lane; i < d1; i += kGsLanes) {
-      const uint32_t* flag = f.flags + f.dep_idx[i];
-      uint32_t spins = 0;
-      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kGsSpinLimit) {
-          atomicOr(f.status, 1u);
-          break;
-        }
-      }
-    }
-    __syncthreads();
+    wait_tickets(f, t, lane);
     const int32_t leaf = gs_uniform(f.item_leaf0, gs_uniform(f.ticket_item, t));
     if (gs_uniform(f.ticket_back, t))
       kacz_leaf<true, true>(a, leaf, omega, bvec, x, xw);

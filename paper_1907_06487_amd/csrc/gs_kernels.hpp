@@ -26,7 +26,7 @@ struct GsArgs {
 // A whole sweep in one cooperative launch over the tickets of a GsFlow
 // (gauss_seidel.hpp): device copies of its arrays, one completion flag per
 // ticket (set to epoch when done), a status word (bit 0: a bounded wait gave
-// up).
+// up) and a drain word.
 struct GsFlowArgs {
   const int32_t* ticket_item;
   const int32_t* ticket_back;
@@ -36,6 +36,7 @@ struct GsFlowArgs {
   const int32_t* dep_idx;
   uint32_t* flags;
   uint32_t* status;
+  uint32_t* drain;  // set to epoch when a wait of this launch gave up
   int32_t n_tickets;
   uint32_t epoch;
 };
