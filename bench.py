@@ -793,16 +793,17 @@ def main():
     ap.add_argument("--gs", action="store_true",
                     help="symmetric Gauss-Seidel sweeps over a distance-1 schedule of the workload instead")
     ap.add_argument("--gs-exec", default="flow", choices=["phases", "flow"],
-                    help="--gs: one launch per phase, or one dataflow launch per sweep (128^3, N_t 65536: 609 us "
-                         "against 652 us with phase launches)")
-    ap.add_argument("--gs-workers", type=int, default=65536,
-                    help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 65536 measured fastest)")
+                    help="--gs: one launch per phase, or one dataflow launch per sweep (128^3, N_t 16384: 527 us "
+                         "against 712 us with phase launches)")
+    ap.add_argument("--gs-workers", type=int, default=16384,
+                    help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 16384 measured fastest with "
+                         "the dataflow launch: 527 us against 585 us at 65536)")
     ap.add_argument("--kacz", action="store_true",
                     help="symmetric Kaczmarz sweeps over a distance-2 schedule of the workload instead")
     ap.add_argument("--kacz-workers", type=int, default=4096, help="--kacz: n_workers of the schedule")
     ap.add_argument("--kacz-stages", type=int, default=3, help="--kacz: recursion stages of the schedule")
     ap.add_argument("--kacz-exec", default="flow", choices=["phases", "flow"],
-                    help="--kacz: one launch per phase, or one dataflow launch per sweep (128^3, N_t 4096: 981 us "
+                    help="--kacz: one launch per phase, or one dataflow launch per sweep (128^3, N_t 4096: 930 us "
                          "against 1,398 us with phase launches)")
     ap.add_argument("--kacz-quad", type=int, default=-1,
                     help="--kacz: phases of at least this many leaves run four per wavefront (-1 library default, "

@@ -7,6 +7,7 @@
 // per wavefront.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "gs_kernels.hpp"
@@ -608,14 +609,36 @@ __global__ void __launch_bounds__(kGsLanes) kacz_flow_kernel(GsArgs a, GsFlowArg
 
 }  // namespace dev
 
+// LDS of a dataflow sweep's workgroup.
+static size_t flow_lds(size_t bytes) { return std::max<size_t>(bytes, 1); }
+
+// Workgroups per CU of a dataflow sweep.  The tickets are dealt round robin
+// and every workgroup must be resident (a ticket whose owner never starts
+// stalls its dependents, until the bounded waits give up).  On this device
+// the count the occupancy query reports was not always all resident:
+// Gauss-Seidel, N_t 16384: 11 x 14,336 B of LDS per CU stalled, 12 x
+// 12,800 B ran; so the count is capped at 144 KiB of LDS per CU.  The
+// Kaczmarz kernel stalled at N_t 8192 with 24 x 6,656 B, 20 x 8,192 B and
+// 22 x 6,656 B per CU, and ran with 12 or 13; the cause is not identified,
+// so its query asks for its LDS rounded up to 2 KiB plus 4 KiB (13 per CU
+// at 6,656 B), the largest count measured to run.
+static hipError_t flow_per_cu(const void* fn, size_t lds, size_t query_lds, int* per_cu) {
+  constexpr size_t kCuLdsUsable = 144 * 1024;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, dev::kGsLanes, query_lds);
+  if (e != hipSuccess) return e;
+  const int cap = static_cast<int>(kCuLdsUsable / lds);
+  if (*per_cu > cap) *per_cu = cap;
+  return hipSuccess;
+}
+
 hipError_t kacz_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
-  const size_t lds = static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  const size_t lds = flow_lds(static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double));
   int per_cu = 0;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::kacz_flow_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kGsMaxWindowBytes);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&dev::kacz_flow_kernel),
-                                                   dev::kGsLanes, lds);
+  e = flow_per_cu(reinterpret_cast<const void*>(&dev::kacz_flow_kernel), lds, (lds + 2047) / 2048 * 2048 + 4096,
+                  &per_cu);
   if (e != hipSuccess) return e;
   *grid = per_cu * n_cus;
   return hipSuccess;
@@ -624,7 +647,7 @@ hipError_t kacz_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
 hipError_t launch_kacz_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, int32_t grid, double omega,
                             const double* b, double* x, hipStream_t st) {
   if (f.n_tickets == 0) return hipSuccess;
-  const size_t lds = static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  const size_t lds = flow_lds(static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double));
   GsArgs aa = a;
   GsFlowArgs ff = f;
   double om = omega;
@@ -635,10 +658,9 @@ hipError_t launch_kacz_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, 
 }
 
 hipError_t gs_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
-  const size_t lds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  const size_t lds = flow_lds(4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double));
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&dev::gs_flow_kernel),
-                                                              dev::kGsLanes, lds);
+  hipError_t e = flow_per_cu(reinterpret_cast<const void*>(&dev::gs_flow_kernel), lds, lds, &per_cu);
   if (e != hipSuccess) return e;
   *grid = per_cu * n_cus;
   return hipSuccess;
@@ -647,7 +669,7 @@ hipError_t gs_flow_grid(int32_t wmax, int32_t n_cus, int32_t* grid) {
 hipError_t launch_gs_flow(const GsArgs& a, const GsFlowArgs& f, int32_t wmax, int32_t grid, const double* b, double* x,
                           hipStream_t st) {
   if (f.n_tickets == 0) return hipSuccess;
-  const size_t lds = 4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double);
+  const size_t lds = flow_lds(4 * static_cast<size_t>(wmax > 0 ? wmax : 1) * sizeof(double));
   GsArgs aa = a;
   GsFlowArgs ff = f;
   int32_t ww = wmax > 0 ? wmax : 1;
