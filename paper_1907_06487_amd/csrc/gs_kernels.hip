@@ -613,15 +613,15 @@ __global__ void __launch_bounds__(kGsLanes) kacz_flow_kernel(GsArgs a, GsFlowArg
 static size_t flow_lds(size_t bytes) { return std::max<size_t>(bytes, 1); }
 
 // Workgroups per CU of a dataflow sweep.  The tickets are dealt round robin
-// and every workgroup must be resident (a ticket whose owner never starts
-// stalls its dependents, until the bounded waits give up).  On this device
-// the count the occupancy query reports was not always all resident:
-// Gauss-Seidel, N_t 16384: 11 x 14,336 B of LDS per CU stalled, 12 x
-// 12,800 B ran; so the count is capped at 144 KiB of LDS per CU.  The
-// Kaczmarz kernel stalled at N_t 8192 with 24 x 6,656 B, 20 x 8,192 B and
-// 22 x 6,656 B per CU, and ran with 12 or 13; the cause is not identified,
-// so its query asks for its LDS rounded up to 2 KiB plus 4 KiB (13 per CU
-// at 6,656 B), the largest count measured to run.
+// and every workgroup must be running (a ticket whose owner never starts
+// stalls its dependents until the bounded waits give up).  On this device
+// some launches at the count the occupancy query reports stalled, the cause
+// not identified: Gauss-Seidel, N_t 16384 (11,232 B of LDS per workgroup):
+// 14 per CU ran, 13 x 12,288 B stalled; Kaczmarz, N_t 8192 (6,656 B): 24 and
+// 22 per CU (and 20 x 8,192 B) stalled, 12 and 13 ran, while N_t 4096
+// (6,072 B) ran at 24.  The count is therefore capped at 144 KiB of LDS per
+// CU, and the Kaczmarz query asks for its LDS rounded up to 2 KiB plus 4 KiB
+// (13 per CU at 6,656 B), the settings every measured case ran with.
 static hipError_t flow_per_cu(const void* fn, size_t lds, size_t query_lds, int* per_cu) {
   constexpr size_t kCuLdsUsable = 144 * 1024;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, dev::kGsLanes, query_lds);
