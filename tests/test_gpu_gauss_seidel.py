@@ -151,12 +151,12 @@ def test_gauss_seidel_converges_and_refuses_products():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("nt,exec_mode", [(4096, "phases"), (16384, "phases"), (65536, "flow")])
+@pytest.mark.parametrize("nt,exec_mode", [(4096, "phases"), (16384, "phases"), (16384, "flow"), (65536, "flow")])
 def test_gauss_seidel_full_size_3d27pt_128(nt, exec_mode):
     """The 128^3 stencil, one symmetric sweep, against the C oracle over
-    the same row order (about 2 s on one host core); N_t 16384 is the
-    benchmark's schedule, whose large phases run four leaves per wavefront
-    with the default threshold."""
+    the same row order (about 2 s on one host core); N_t 16384 with one
+    dataflow launch is the benchmark's configuration; with phase launches
+    its large phases run four leaves per wavefront (the default threshold)."""
     m = matgen.config_3d_128()
     rng = np.random.default_rng(14)
     b = rng.uniform(-1, 1, m.n)
