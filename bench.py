@@ -565,8 +565,8 @@ def run_gs(args, torch):
     v[d] = 1.0 + absrow[rows[d]] - np.abs(m.val[d])
     m = matgen.UpperCSR(m.n, m.row_ptr, m.col, v, m.name + "_dominant")
     t0 = time.perf_counter()
-    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, dist_k=1, n_workers=args.gs_workers, root=args.root,
-                   level_order=args.level_order)
+    s = R.Schedule(m.n, m.row_ptr, m.col, m.val, dist_k=1, n_workers=args.gs_workers, max_stages=args.gs_stages,
+                   root=args.root, level_order=args.level_order)
     st = s.stats()
     s.set_gs_exec(args.gs_exec)
     log(f"Gauss-Seidel schedule built in {time.perf_counter() - t0:.2f}s: leaves {st['n_leaves']}, phases "
@@ -602,7 +602,8 @@ def run_gs(args, torch):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload + "_dominant", "description": desc + ", diagonal 1 + row abs-sum",
-                   "n": m.n, "nnz_full": nnz_full, "n_workers": args.gs_workers, "execution": args.gs_exec,
+                   "n": m.n, "nnz_full": nnz_full, "n_workers": args.gs_workers, "max_stages": args.gs_stages,
+                   "execution": args.gs_exec,
                    "leaves": st["n_leaves"],
                    "phases": st["n_phases_used"], "max_window": st["max_window"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -795,6 +796,7 @@ def main():
     ap.add_argument("--gs-exec", default="flow", choices=["phases", "flow"],
                     help="--gs: one launch per phase, or one dataflow launch per sweep (128^3, N_t 16384: 527 us "
                          "against 712 us with phase launches)")
+    ap.add_argument("--gs-stages", type=int, default=4, help="--gs: recursion stages of the distance-1 schedule")
     ap.add_argument("--gs-workers", type=int, default=16384,
                     help="--gs: n_workers of the distance-1 schedule (on the 128^3 stencil 16384 measured fastest with "
                          "the dataflow launch: 527 us against 585 us at 65536)")
