@@ -3,8 +3,9 @@
 // hold wavefronts, windows up to kGsQuadMaxWindow entries) four leaves per
 // wavefront (leaves of one phase share no edge, so they run at the same
 // time), the rows of a leaf in order; or one dataflow launch per sweep.
-// The Kaczmarz sweep over a distance-2 schedule runs the same way, one leaf
-// per wavefront.
+// The Kaczmarz sweep over a distance-2 schedule runs the same ways (one or
+// four leaves per wavefront in phase launches, one leaf per ticket in the
+// dataflow launch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
