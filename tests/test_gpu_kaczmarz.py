@@ -91,6 +91,8 @@ CASES = [
     # leaves of thousands of rows
     ("3d27pt_24_big_leaves", lambda: matgen.stencil3d_27pt(24, seed=5), dict(n_workers=8, max_stages=2)),
     ("3d27pt_17", lambda: matgen.stencil3d_27pt(17, seed=7), dict(n_workers=333, max_stages=3)),
+    # a distance-3 schedule (rows of one phase further apart than needed)
+    ("3d27pt_17_dist3", lambda: matgen.stencil3d_27pt(17, seed=7), dict(n_workers=64, dist_k=3)),
 ]
 
 

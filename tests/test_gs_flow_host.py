@@ -137,8 +137,11 @@ def _windows(m, perm, lo, hi):
     return out
 
 
+KACZ_CASES = CASES + [("3d27pt_10_dist3", lambda: matgen.stencil3d_27pt(10, seed=4), dict(n_workers=64, dist_k=3))]
+
+
 @pytest.mark.parametrize("direction", [0, 1, 2])
-@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("name,make,kw", KACZ_CASES, ids=[c[0] for c in KACZ_CASES])
 def test_kacz_flow_plan_orders_every_shared_row(name, make, kw, direction):
     m = make()
     s = R.Schedule(m.n, m.row_ptr, m.col, m.val, upload=False, kaczmarz=True, **kw)
