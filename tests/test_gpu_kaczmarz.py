@@ -93,6 +93,9 @@ CASES = [
     ("3d27pt_17", lambda: matgen.stencil3d_27pt(17, seed=7), dict(n_workers=333, max_stages=3)),
     # a distance-3 schedule (rows of one phase further apart than needed)
     ("3d27pt_17_dist3", lambda: matgen.stencil3d_27pt(17, seed=7), dict(n_workers=64, dist_k=3)),
+    # a schedule whose products store float32 values: the sweep keeps float64
+    ("3d27pt_17_f32_products", lambda: matgen.stencil3d_27pt(17, seed=7),
+     dict(n_workers=333, max_stages=3, value_type="f32")),
 ]
 
 
